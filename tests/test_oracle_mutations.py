@@ -1,0 +1,111 @@
+"""The pins are strong enough: each plausible mistake planted in the oracle
+(a transposed factor, a dropped sketch mode, a wrong index, a Frobenius norm
+where the sketched norm belongs, a wrong filter factor, an unsquared target)
+makes at least one pin fail.  Mistakes are planted on the CPU only, by
+monkeypatching oracle functions for the duration of one test."""
+import math
+
+import numpy as np
+import pytest
+
+import test_oracle_pins as pins
+import oracle.operator as opm
+import oracle.sketch as skm
+import oracle.projected as pm
+import oracle.arnoldi as am
+import oracle.gmres as gm
+from oracle.tensor_algebra import mode_product, frobenius
+
+
+def expect_failure(fn, *args):
+    with pytest.raises(Exception):
+        fn(*args)
+
+
+def test_pins_pass_unmutated():
+    pins.test_phi_matches_literal_einstein_form_and_kronecker()
+    pins.test_sketch_vectorised_form()
+    pins.test_arnoldi_relation_and_theta_orthonormality("tiny")
+
+
+def test_untransposed_b_is_caught(monkeypatch):
+    def bad_phi(X, A1, A2, B):
+        return mode_product(mode_product(mode_product(X, A1, 0), A2, 1), B, 2)
+    monkeypatch.setattr(opm, "phi", bad_phi)
+    expect_failure(pins.test_phi_matches_literal_einstein_form_and_kronecker)
+
+
+def test_transposed_blur_factor_is_caught(monkeypatch):
+    good = opm.phi
+
+    def bad_phi(X, A1, A2, B):
+        return good(X, np.asarray(A1).T, A2, B)
+    monkeypatch.setattr(opm, "phi", bad_phi)
+    monkeypatch.setattr(pins, "phi", bad_phi)
+    expect_failure(pins.test_phi_is_psf_convolution_with_zero_boundary)
+    expect_failure(pins.test_phi_matches_literal_einstein_form_and_kronecker)
+
+
+def test_dropped_sketch_mode_is_caught(monkeypatch):
+    def bad_call(self, X):
+        Y = np.asarray(X, np.float64)
+        for k, om in enumerate(self.om[:2]):
+            if om is not None:
+                Y = mode_product(Y, om, k)
+        return Y
+    monkeypatch.setattr(skm.Sketch, "__call__", bad_call)
+    expect_failure(pins.test_sketch_vectorised_form)
+
+
+def _mutated_arnoldi(kind):
+    def arnoldi(phi, sketch, R0, m, reorth=True, bd_tol=1e-12, stop_res=None):
+        R0 = np.asarray(R0, dtype=np.float64)
+        s0 = sketch(R0)
+        beta = math.sqrt(frobenius(s0, s0))
+        V = [R0 / beta]
+        SV = [sketch(V[0])]
+        H = np.zeros((m + 1, m))
+        for j in range(m):
+            W = phi(V[j])
+            s = sketch(W)
+            for _ in range(2):
+                for i in range(j + 1):
+                    h = frobenius(SV[i], s)
+                    H[i, j] += h
+                    s = s - h * SV[i]
+                    W = W - h * (V[j] if kind == "index" else V[i])
+            hn = math.sqrt(frobenius(W, W)) if kind == "frobenius" else math.sqrt(frobenius(s, s))
+            H[j + 1, j] = hn
+            V.append(W / hn)
+            SV.append(sketch(V[-1]))
+        return am.ArnoldiResult(V, SV, H, beta, m, 0, np.zeros(m))
+    return arnoldi
+
+
+@pytest.mark.parametrize("kind", ["index", "frobenius"])
+def test_arnoldi_mistakes_are_caught(monkeypatch, kind):
+    monkeypatch.setattr(pins, "sketched_global_arnoldi", _mutated_arnoldi(kind))
+    expect_failure(pins.test_arnoldi_relation_and_theta_orthonormality, "tiny")
+
+
+def test_wrong_filter_factor_is_caught(monkeypatch):
+    monkeypatch.setattr(pm.SVDProblem, "y",
+                        lambda self, mu: self.W @ (self.s ** 2 / (self.s ** 2 + mu) * self.ghat))
+    expect_failure(pins.test_eq13_eq14_and_svd_filter_agree)
+
+
+def test_unsquared_discrepancy_target_is_caught(monkeypatch):
+    good = pm.discrepancy_mu
+    monkeypatch.setattr(pm, "discrepancy_mu", lambda P, target, iters=200: good(P, math.sqrt(target), iters))
+    expect_failure(pins.test_discrepancy_root_and_monotonicity)
+
+
+def test_reversed_assembly_is_caught(monkeypatch):
+    good = gm.projected_tikhonov
+
+    def bad(H, beta, **kw):
+        out = good(H, beta, **kw)
+        out["y"] = out["y"][::-1].copy()
+        return out
+    monkeypatch.setattr(gm, "projected_tikhonov", bad)
+    expect_failure(pins.test_matches_dense_direct_solve_on_krylov_space, 5)

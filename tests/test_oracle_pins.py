@@ -1,0 +1,428 @@
+"""Pins of the float64 oracle against facts fixed by the paper and by
+mathematics (no GPU).  Each test names the passage it checks.
+
+The oracle is only trusted because of these tests: closed forms, brute-force
+sums, textbook special cases and dense direct solves on tiny sizes.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2603_00839_amd import synth
+from oracle import tensor_algebra as ta
+from oracle.operator import (Operator, phi, phi_einstein, band_to_dense,
+                             convolve_psf_zero_bc, make_observation, blur_tensor)
+from oracle.sketch import Sketch, identity_sketch
+from oracle.arnoldi import sketched_global_arnoldi, FLAG_BREAKDOWN
+from oracle.projected import (projected_tikhonov, givens_residuals, solve_13,
+                              solve_14, ls_solve, SVDProblem, discrepancy_mu,
+                              FLAG_DISCREP_UNREACHABLE, FLAG_MU_INF)
+from oracle.gmres import rtg_gmres
+from oracle.metrics import relative_error, psnr_paper, psnr_peak
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def tiny_problem(seed=0, dims=(6, 5, 3), r=(2, 1, 1), ls=(4, 3, 2)):
+    """Non-symmetric operator and a full (non-identity) sketch on every mode."""
+    p = synth.small_problem(seed, dims[0], dims[1], dims[2], r[0], r[1], r[2],
+                            ls[0], ls[1], ls[2], m=5, random_bands=True)
+    return p, Operator(p.a1_band, p.a2_band, p.b_band), Sketch(p.om1, p.om2, p.om3)
+
+
+# --------------------------------------------------------------------------
+# Sec. 2.1 / Sec. 4.1: Einstein product and the unfolding identity
+# --------------------------------------------------------------------------
+def test_einstein_product_matches_explicit_sums():
+    rng = np.random.default_rng(1)
+    A = rng.standard_normal((2, 3, 4, 2))
+    B = rng.standard_normal((4, 2, 3))
+    np.testing.assert_allclose(ta.einstein_product(A, B, 2),
+                               ta.einstein_product_loops(A, B, 2), rtol=1e-13, atol=1e-13)
+
+
+def test_einstein_golden_hand_computed():
+    """A 2x2x2 by 2x2 Einstein product evaluated by hand (tests/golden)."""
+    with open(os.path.join(GOLDEN, "einstein_2x2.json")) as f:
+        g = json.load(f)
+    A = np.array(g["A"], dtype=float)
+    B = np.array(g["B"], dtype=float)
+    np.testing.assert_allclose(ta.einstein_product(A, B, g["N"]), np.array(g["AB"]), atol=0)
+
+
+def test_unfolding_turns_einstein_into_matrix_product():
+    """Psi_IJ(A *_N B) = Psi_IK(A) Psi_KJ(B) with the ivec ordering (Sec. 4.1)."""
+    rng = np.random.default_rng(2)
+    A = rng.standard_normal((3, 2, 4, 3))      # I = (3,2), K = (4,3)
+    B = rng.standard_normal((4, 3, 2, 2))      # K = (4,3), J = (2,2)
+    lhs = ta.unfold(ta.einstein_product(A, B, 2), 2)
+    rhs = ta.unfold(A, 2) @ ta.unfold(B, 2)
+    np.testing.assert_allclose(lhs, rhs, rtol=1e-13, atol=1e-13)
+    # ivec: first index fastest
+    assert ta.ivec((1, 0), (3, 2)) == 1 and ta.ivec((0, 1), (3, 2)) == 3
+
+
+def test_unfolded_blur_is_kron_a2_a1():
+    """With a[i1,i2,k1,k2] = A1[i1,k1] A2[i2,k2], Psi(A) = A2 (x) A1."""
+    rng = np.random.default_rng(3)
+    A1 = rng.standard_normal((4, 4))
+    A2 = rng.standard_normal((3, 3))
+    np.testing.assert_allclose(ta.unfold(blur_tensor(A1, A2), 2), np.kron(A2, A1), rtol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# eq. (2), Sec. 5.1-5.2: the operator
+# --------------------------------------------------------------------------
+def test_phi_matches_literal_einstein_form_and_kronecker():
+    p, op, _ = tiny_problem()
+    X = p.x_true.astype(np.float64)
+    ref = phi_einstein(X, op.A1, op.A2, op.B)             # (A *_2 X) *_1 B
+    np.testing.assert_allclose(op(X), ref, rtol=1e-13, atol=1e-13)
+    # vec(Phi(X)) = (B^T (x) A2 (x) A1) vec(X)
+    np.testing.assert_allclose(ta.vec(op(X)), op.dense() @ ta.vec(X), rtol=1e-13, atol=1e-13)
+    # unfolding form: Psi(Phi(X)) = Psi(A) Psi(X) B
+    np.testing.assert_allclose(ta.unfold(op(X), 2),
+                               np.kron(op.A2, op.A1) @ ta.unfold(X, 2) @ op.B,
+                               rtol=1e-13, atol=1e-13)
+    # B is non-symmetric here, so B and B^T are distinguishable
+    assert np.abs(op.B - op.B.T).max() > 1e-3
+
+
+def test_band_layout():
+    band = np.array([[9.0, 1.0, 2.0], [3.0, 4.0, 5.0], [6.0, 7.0, 9.0]])
+    M = band_to_dense(band)
+    np.testing.assert_array_equal(M, [[1, 2, 0], [3, 4, 5], [0, 6, 7]])
+
+
+def test_phi_is_psf_convolution_with_zero_boundary():
+    """Separable PSF P = t1 t2^T applied by direct 2-D convolution with zero
+    boundary conditions (eq. (57) generalised) equals Phi with B = I."""
+    rng = np.random.default_rng(4)
+    t1 = rng.uniform(0.1, 1.0, 5)             # non-symmetric taps pin orientation
+    t2 = rng.uniform(0.1, 1.0, 3)
+    X = rng.standard_normal((7, 6, 2))
+    A1 = band_to_dense(synth.toeplitz_band(7, t1))
+    A2 = band_to_dense(synth.toeplitz_band(6, t2))
+    P = np.zeros((5, 5))
+    P[:, 1:4] = np.outer(t1, t2)              # embed 5x3 PSF in a 5x5 array
+    np.testing.assert_allclose(phi(X, A1, A2, np.eye(2)), convolve_psf_zero_bc(X, P),
+                               rtol=1e-13, atol=1e-13)
+
+
+def test_psf_3x3_golden():
+    """Eq. (57) with a 3x3 PSF on a 3x3 single-channel image, by hand."""
+    with open(os.path.join(GOLDEN, "psf3x3.json")) as f:
+        g = json.load(f)
+    X = np.array(g["X"], dtype=float)[:, :, None]
+    P = np.array(g["P"], dtype=float)
+    np.testing.assert_allclose(convolve_psf_zero_bc(X, P)[:, :, 0], np.array(g["C"]), atol=1e-12)
+
+
+def test_gaussian_band_rows_and_radius():
+    """Normalised truncated Gaussian taps: interior rows sum to 1; r = round(3 sigma)."""
+    band = synth.gaussian_band(32, 1.5, 4)
+    assert synth.half_bandwidth(1.5) == 4 and synth.half_bandwidth(2.5) == 8 \
+        and synth.half_bandwidth(2.0) == 6
+    M = band_to_dense(band)
+    np.testing.assert_allclose(M[10].sum(), 1.0, rtol=1e-12)
+    assert M[0].sum() < 1.0                       # boundary row truncated (zero BC)
+    np.testing.assert_allclose(M, M.T, atol=1e-15)
+
+
+def test_observation_noise_level():
+    """eq. (59): ||N|| / ||C_hat|| = nu exactly."""
+    p, op, _ = tiny_problem()
+    C, delta, chat = make_observation(op, p.x_true, p.noise_dir, 0.03)
+    np.testing.assert_allclose(np.linalg.norm(C - chat) / np.linalg.norm(chat), 0.03, rtol=1e-12)
+    np.testing.assert_allclose(delta, np.linalg.norm(C - chat), rtol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Sec. 3: the sketch
+# --------------------------------------------------------------------------
+def test_sketch_vectorised_form():
+    """vec(S(X)) = (Om3 (x) Om2 (x) Om1) vec(X) (Sec. 3.1.2), all modes sketched."""
+    p, _, sk = tiny_problem()
+    X = p.x_true.astype(np.float64)
+    np.testing.assert_allclose(ta.vec(sk(X)), sk.dense(X.shape) @ ta.vec(X), rtol=1e-13, atol=1e-13)
+    assert sk(X).shape == (4, 3, 2)
+
+
+def test_sketch_brute_force_sum():
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((3, 4, 2))
+    O1, O2, O3 = rng.standard_normal((2, 3)), rng.standard_normal((3, 4)), rng.standard_normal((2, 2))
+    S = Sketch(O1, O2, O3)(X)
+    ref = np.zeros((2, 3, 2))
+    for a in range(2):
+        for b in range(3):
+            for c in range(2):
+                ref[a, b, c] = sum(O1[a, i] * O2[b, k] * O3[c, j] * X[i, k, j]
+                                   for i in range(3) for k in range(4) for j in range(2))
+    np.testing.assert_allclose(S, ref, rtol=1e-13, atol=1e-13)
+
+
+def test_identity_sketch_and_theta_product():
+    p, _, sk = tiny_problem()
+    X = p.x_true.astype(np.float64)
+    Y = p.noise_dir.astype(np.float64)
+    np.testing.assert_array_equal(identity_sketch()(X), X)
+    Th = sk.dense(X.shape)
+    np.testing.assert_allclose(sk.inner(X, Y), ta.vec(X) @ Th.T @ Th @ ta.vec(Y), rtol=1e-12)
+
+
+def test_gaussian_sketch_is_unbiased_embedding():
+    """E[Om^T Om] = I for Om ~ N(0, 1/l): the average sketched norm of a fixed
+    tensor over many draws is its Frobenius norm (Sec. 3, inner-product
+    approximation)."""
+    rng = np.random.default_rng(6)
+    X = rng.standard_normal((8, 8, 1))
+    vals = []
+    for _ in range(400):
+        sk = Sketch(synth.sketch_matrix(rng, 4, 8), synth.sketch_matrix(rng, 4, 8), None)
+        vals.append(sk.norm(X) ** 2)
+    np.testing.assert_allclose(np.mean(vals), ta.fro_norm(X) ** 2, rtol=0.08)
+
+
+# --------------------------------------------------------------------------
+# Sec. 4.3: sketched global Arnoldi
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("which", ["tiny", "cfg1"])
+def test_arnoldi_relation_and_theta_orthonormality(which):
+    if which == "tiny":
+        p, op, sk = tiny_problem()
+        m = 6
+    else:
+        p = synth.cfg1(0)
+        op, sk, m = Operator(p.a1_band, p.a2_band, p.b_band), Sketch(p.om1, p.om2, p.om3), 20
+    R0 = p.x_true.astype(np.float64)
+    ar = sketched_global_arnoldi(op, sk, R0, m)
+    assert ar.m_eff == m and ar.flags == 0
+    H = ar.H
+    # Phi(V_j) = sum_{i <= j+1} h_ij V_i  (Arnoldi relation (7S)/(7))
+    for j in range(m):
+        lhs = op(ar.V[j])
+        rhs = sum(H[i, j] * ar.V[i] for i in range(j + 2))
+        assert rel(rhs, lhs) < 1e-12
+    # Theta-orthonormal basis
+    SV = np.stack([s.ravel() for s in ar.SV], axis=1)
+    assert np.abs(SV.T @ SV - np.eye(m + 1)).max() < 1e-12
+    # upper Hessenberg, positive subdiagonal
+    assert np.all(np.tril(H, -2) == 0)
+    assert np.all(np.diag(H, -1) > 0)
+    np.testing.assert_allclose(ar.beta, sk.norm(R0), rtol=1e-13)
+
+
+def test_single_pass_mgs_gives_same_basis_in_exact_arithmetic():
+    """Reorthogonalisation only corrects rounding: on a small, well-conditioned
+    problem the printed single-pass MGS and the two-pass variant agree."""
+    p, op, sk = tiny_problem()
+    R0 = p.x_true.astype(np.float64)
+    a = sketched_global_arnoldi(op, sk, R0, 5, reorth=True)
+    b = sketched_global_arnoldi(op, sk, R0, 5, reorth=False)
+    np.testing.assert_allclose(a.H, b.H, rtol=1e-9, atol=1e-11)
+
+
+# --------------------------------------------------------------------------
+# Omega = I: classical tensor global GMRES = textbook GMRES on vec(Phi)
+# --------------------------------------------------------------------------
+def krylov_basis(A, r0, m):
+    K = np.empty((r0.size, m))
+    v = r0.copy()
+    for j in range(m):
+        K[:, j] = v
+        v = A @ v
+    Q, _ = np.linalg.qr(K)
+    return Q
+
+
+def test_identity_sketch_reduces_to_gmres():
+    p, op, _ = tiny_problem(seed=3)
+    A = op.dense()
+    c = ta.vec(p.x_true) + 0.3
+    x0 = 0.1 * ta.vec(p.noise_dir)
+    m = 6
+    C = c.reshape(p.dims, order="F")
+    X0 = x0.reshape(p.dims, order="F")
+    res = rtg_gmres(op, identity_sketch(), C, m, X0=X0, mu=0.0)
+    Q = krylov_basis(A, c - A @ x0, m)
+    z, *_ = np.linalg.lstsq(A @ Q, c - A @ x0, rcond=None)
+    x_ref = x0 + Q @ z
+    assert rel(ta.vec(res.X), x_ref) < 1e-10
+    # identity sketch: the Theta-norm is the Frobenius norm
+    np.testing.assert_allclose(res.beta, np.linalg.norm(c - A @ x0), rtol=1e-13)
+    # minimal-residual property: residual equals the LS value
+    np.testing.assert_allclose(np.linalg.norm(c - A @ ta.vec(res.X)), res.res_proj, rtol=1e-9)
+
+
+# --------------------------------------------------------------------------
+# dense direct solve of the sketched projected Tikhonov problem
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("m", [3, 5])
+def test_matches_dense_direct_solve_on_krylov_space(m):
+    """x_m = argmin_{x in x0 + K_m} ||Th(c - A x)||^2 + mu ||Th(x - x0)||^2."""
+    p, op, sk = tiny_problem(seed=7)
+    A = op.dense()
+    Th = sk.dense(p.dims)
+    c = ta.vec(p.x_true)
+    x0 = 0.05 * ta.vec(p.noise_dir)
+    mu = 0.37
+    res = rtg_gmres(op, sk, c.reshape(p.dims, order="F"), m,
+                    X0=x0.reshape(p.dims, order="F"), mu=mu)
+    r0 = c - A @ x0
+    Q = krylov_basis(A, r0, m)
+    M = Th @ A @ Q
+    N = Th @ Q
+    z = np.linalg.solve(M.T @ M + mu * N.T @ N, M.T @ (Th @ r0))
+    assert rel(ta.vec(res.X), x0 + Q @ z) < 1e-9
+
+
+def test_full_space_tikhonov_closed_forms():
+    """m = n: with Omega = I the iterate is the Tikhonov solution of eq. (5);
+    with a square invertible sketch it is (A^T Th^T Th A + mu Th^T Th)^-1 A^T Th^T Th c."""
+    p = synth.small_problem(11, 4, 3, 2, 1, 1, 1, 4, 3, 2, m=24, random_bands=True)
+    op = Operator(p.a1_band, p.a2_band, p.b_band)
+    A = op.dense()
+    n = A.shape[0]
+    c = ta.vec(p.x_true)
+    mu = 0.05
+    res = rtg_gmres(op, identity_sketch(), c.reshape(p.dims, order="F"), n, mu=mu, bd_tol=1e-10)
+    x_ref = np.linalg.solve(A.T @ A + mu * np.eye(n), A.T @ c)
+    assert rel(ta.vec(res.X), x_ref) < 1e-8
+    rng = np.random.default_rng(12)
+    sk = Sketch(rng.standard_normal((4, 4)), rng.standard_normal((3, 3)), rng.standard_normal((2, 2)))
+    Th = sk.dense(p.dims)
+    res2 = rtg_gmres(op, sk, c.reshape(p.dims, order="F"), n, mu=mu, bd_tol=1e-10)
+    G = Th.T @ Th
+    x_ref2 = np.linalg.solve(A.T @ G @ A + mu * G, A.T @ G @ c)
+    assert rel(ta.vec(res2.X), x_ref2) < 1e-7
+
+
+# --------------------------------------------------------------------------
+# projected problem: (11S), (12)-(14), discrepancy principle
+# --------------------------------------------------------------------------
+def random_hessenberg(k, seed=0):
+    rng = np.random.default_rng(seed)
+    H = np.triu(rng.standard_normal((k + 1, k)), -1)
+    H[np.arange(1, k + 1), np.arange(k)] = np.abs(H[np.arange(1, k + 1), np.arange(k)]) + 0.1
+    return H
+
+
+def test_eq13_eq14_and_svd_filter_agree():
+    H = random_hessenberg(8)
+    beta, mu = 2.5, 0.3
+    y13 = solve_13(H, beta, mu)
+    y14 = solve_14(H, beta, mu)
+    ysvd = SVDProblem(H, beta).y(mu)
+    np.testing.assert_allclose(y13, y14, rtol=1e-11)
+    np.testing.assert_allclose(ysvd, y13, rtol=1e-11)
+
+
+def test_m1_closed_form():
+    h11, h21, beta, mu = 0.8, 0.3, 2.0, 0.1
+    H = np.array([[h11], [h21]])
+    out = projected_tikhonov(H, beta, mu=mu)
+    np.testing.assert_allclose(out["y"][0], beta * h11 / (h11 ** 2 + h21 ** 2 + mu), rtol=1e-14)
+
+
+def test_givens_residual_equals_least_squares_residual():
+    H = random_hessenberg(7, seed=2)
+    beta = 1.7
+    res = givens_residuals(H, beta)
+    for j in range(1, 8):
+        Hj = H[:j + 1, :j]
+        y = ls_solve(Hj, beta)
+        g = np.zeros(j + 1)
+        g[0] = beta
+        np.testing.assert_allclose(res[j - 1], np.linalg.norm(g - Hj @ y), rtol=1e-10)
+    np.testing.assert_allclose(res[-1] ** 2, SVDProblem(H, beta).gperp2, rtol=1e-10)
+
+
+def test_discrepancy_root_and_monotonicity():
+    H = random_hessenberg(6, seed=4)
+    H[-1, -1] = 0.5
+    beta = 3.0
+    P = SVDProblem(H, beta)
+    grid = np.logspace(-6, 4, 50)
+    vals = [P.residual2(m) for m in grid]
+    assert np.all(np.diff(vals) >= -1e-15)
+    target = math.sqrt(0.5 * (P.gperp2 + beta ** 2))
+    out = projected_tikhonov(H, beta, delta=target / 1.01, eta=1.01)
+    assert out["flags"] == 0
+    np.testing.assert_allclose(out["res_proj"] ** 2, target ** 2, rtol=1e-10)
+    y_direct = solve_14(H, beta, out["mu"])
+    np.testing.assert_allclose(out["y"], y_direct, rtol=1e-9)
+
+
+def test_discrepancy_edge_cases():
+    H = random_hessenberg(4, seed=5)
+    beta = 1.0
+    P = SVDProblem(H, beta)
+    out = projected_tikhonov(H, beta, delta=0.5 * math.sqrt(P.gperp2), eta=1.0)
+    assert out["flags"] == FLAG_DISCREP_UNREACHABLE and out["mu"] == 0.0
+    np.testing.assert_allclose(out["y"], ls_solve(H, beta), rtol=1e-10)
+    out = projected_tikhonov(H, beta, delta=2.0, eta=1.0)
+    assert out["flags"] == FLAG_MU_INF and np.all(out["y"] == 0)
+
+
+# --------------------------------------------------------------------------
+# residual identity in the Theta-norm (Sec. 4.4), special cases
+# --------------------------------------------------------------------------
+def test_sketched_residual_identity():
+    """||S(C - Phi(X0 + V_m y))|| = ||beta e1 - H y|| for any y."""
+    p, op, sk = tiny_problem(seed=9)
+    C = p.x_true.astype(np.float64)
+    res = rtg_gmres(op, sk, C, 5, mu=0.2)
+    rng = np.random.default_rng(0)
+    for y in [res.y, rng.standard_normal(5)]:
+        X = sum(y[j] * res.arnoldi.V[j] for j in range(5))
+        g = np.zeros(6)
+        g[0] = res.beta
+        np.testing.assert_allclose(sk.norm(C - op(X)), np.linalg.norm(g - res.arnoldi.H @ y), rtol=1e-11)
+
+
+def test_scaled_identity_breaks_down_and_is_exact():
+    """Phi = c Id: happy breakdown at j = 1 and X = X0 + R0 / c."""
+    p, _, sk = tiny_problem(seed=10)
+    c = 2.5
+    op = lambda X: c * X  # noqa: E731
+    C = p.x_true.astype(np.float64)
+    X0 = 0.1 * p.noise_dir.astype(np.float64)
+    res = rtg_gmres(op, sk, C, 4, X0=X0, mu=0.0)
+    assert res.m_eff == 1 and res.flags & FLAG_BREAKDOWN
+    assert rel(res.X, X0 + (C - c * X0) / c) < 1e-13
+
+
+def test_zero_initial_residual_returns_x0():
+    p, op, sk = tiny_problem(seed=11)
+    X0 = p.x_true.astype(np.float64)
+    res = rtg_gmres(op, sk, op(X0), 4, X0=X0, mu=0.0)
+    assert res.m_eff == 0
+    np.testing.assert_array_equal(res.X, X0)
+
+
+# --------------------------------------------------------------------------
+# Sec. 5.5 metrics
+# --------------------------------------------------------------------------
+def test_metrics_closed_forms():
+    rng = np.random.default_rng(13)
+    xt = rng.uniform(0, 1, (5, 4, 3))
+    e = rng.standard_normal(xt.shape)
+    e *= 0.1 * np.linalg.norm(xt) / np.linalg.norm(e)
+    np.testing.assert_allclose(relative_error(xt, xt + e), 0.1, rtol=1e-12)
+    var = np.sum((xt - xt.mean()) ** 2)
+    np.testing.assert_allclose(psnr_paper(xt, xt + e), 10 * np.log10(var / np.sum(e ** 2)), rtol=1e-12)
+    # PSNR = 10 log10(c / RE^2) with c = ||X - E(X)||^2 / ||X||^2 (image constant)
+    c = var / np.sum(xt ** 2)
+    np.testing.assert_allclose(psnr_paper(xt, xt + e), 10 * np.log10(c / 0.01), rtol=1e-12)
+    mse = np.mean(e ** 2)
+    np.testing.assert_allclose(psnr_peak(xt, xt + e, peak=1.0), -10 * np.log10(mse), rtol=1e-12)
