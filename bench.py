@@ -1,0 +1,263 @@
+#!/usr/bin/env python3
+"""RTG-GMRES throughput on one MI355X: solves/s at 512x512x3, m = 50.
+
+A step is one call of the batched solver over a batch of B independent
+512x512x3 colour deblurring problems (the paper's Example-1 setting at the
+sizes of the headline workload: Gaussian blur sigma 2.5 with half-bandwidth
+8, 3x3 channel mix, noise 1e-3, sketch 64x64x3, discrepancy-principle mu).
+Inputs are synthetic and resident in HBM before the timed region.
+
+Variants (each timed over the same number of steps):
+  fp32_plain     float32 basis and MFMA, X0 = 0, m = 50 (the plain solver)
+  bf16_warm      bfloat16 basis and MFMA, started from a warm start X0;
+                 --x0 learned uses the trained warm-start network (if its
+                 weights exist), --x0 observation uses X0 = C.
+The JSON line reports the headline variant in "value" and both variants
+under "variants", with restoration errors against the ground truth.
+
+Live measurement: the multi-AXPY + sketch tile kernel (the dominant byte
+mover) is bracketed by HIP events on its launch stream inside the library;
+its algorithmic bytes (tensor reads and writes the method needs) over its
+measured time give the roofline entry.  The CPU baseline times the float64
+oracle on one problem of the same workload on the host cores.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "RTG-GMRES solves/s at 512²×3, m=50: plain FP32 vs BF16+learned X₀ at equal rel err"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--m", type=int, default=50)
+    ap.add_argument("--m-warm", type=int, default=30, help="max steps of the warm-started BF16 solve")
+    ap.add_argument("--x0", choices=["learned", "observation"], default="learned")
+    ap.add_argument("--headline", choices=["auto", "fp32_plain", "bf16_warm"], default="auto")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["fp32_plain", "bf16_warm"], default=None,
+                    help="time one variant only (profiling runs)")
+    return ap.parse_args()
+
+
+def make_batch(B, device):
+    """B cfg2 problems (seeds 0..B-1): ground truth, observation C formed on
+    the GPU with the library's operator plus scaled Gaussian noise."""
+    import numpy as np
+    import torch
+    from paper_2603_00839_amd import rtg, synth
+    probs = []
+    op = None
+    for b in range(B):
+        p = synth.cfg2(b)
+        if op is None:
+            op = rtg.setup_operator(*p.dims, p.a1_band, p.a2_band, p.b_band)
+        sk = rtg.setup_sketch(*p.dims, p.om1, p.om2, p.om3)
+        xt = torch.from_numpy(synth.to_device_layout(p.x_true)).to(device)
+        g = torch.from_numpy(synth.to_device_layout(p.noise_dir)).to(device)
+        chat = rtg.apply_operator(op, xt)
+        delta = p.nu * float(torch.linalg.vector_norm(chat.double()))
+        C = (chat + g * (delta / float(torch.linalg.vector_norm(g.double())))).contiguous()
+        probs.append(dict(p=p, sk=sk, xt=xt, C=C, delta=delta))
+    return op, probs
+
+
+def rel_err(x, xt):
+    import torch
+    return float(torch.linalg.vector_norm((x - xt).double()) / torch.linalg.vector_norm(xt.double()))
+
+
+def tile_bytes(n, es, m_eff, has_x0, m_run):
+    """Algorithmic HBM bytes of the multi-AXPY + sketch tile launches of one
+    solve (tensor traffic only): sketch of R0, V1 = R0/beta, per step the
+    sketch of W and the orthogonalisation/normalisation that reads W and
+    V_1..V_j and writes V_{j+1}, and the final assembly."""
+    b = 4 * n                                   # sketch of R0
+    b += 4 * n + es * n                         # V1
+    for j in range(1, m_eff + 1):
+        b += 4 * n                              # sketch of W = Phi(V_j)
+        if j < m_run and j < m_eff:
+            b += 4 * n + j * es * n + es * n    # V_{j+1}
+    b += (4 * n if has_x0 else 0) + m_eff * es * n + 4 * n   # X = X0 + V y
+    return b
+
+
+def time_variant(plan, steps, warmup, rtg, torch, n, es, m_run, has_x0):
+    for _ in range(warmup):
+        plan.run()
+    torch.cuda.synchronize()
+    rtg.event_timing_read()                     # clear
+    rtg.event_timing_enable(1 << rtg.KIND_TILE)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.run()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rtg.event_timing_enable(0)
+    ev = rtg.event_timing_read()
+    infos = plan.infos()
+    tb = sum(tile_bytes(n, es, inf.iters, has_x0, m_run) for inf in infos) * steps
+    tile_ms, tile_launches = ev[rtg.KIND_TILE]
+    return {
+        "seconds": t1 - t0,
+        "tile_ms": tile_ms,
+        "tile_launches": tile_launches,
+        "tile_bytes": tb,
+        "infos": infos,
+    }
+
+
+def cpu_baseline(problem0):
+    """Float64 oracle, one cfg2 solve on the host cores."""
+    import numpy as np
+    from oracle.operator import Operator, make_observation
+    from oracle.sketch import Sketch
+    from oracle.gmres import rtg_gmres
+    from oracle.metrics import relative_error
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    p = problem0
+    op = Operator(p.a1_band, p.a2_band, p.b_band)
+    sk = Sketch(p.om1, p.om2, p.om3)
+    C, delta, _ = make_observation(op, p.x_true, p.noise_dir, p.nu)
+    C = C.astype(np.float32)
+    # repeat the same solve until about 10 s of CPU work (at most 20 solves)
+    nsolve = 0
+    t0 = time.perf_counter()
+    while True:
+        r = rtg_gmres(op, sk, C, p.m, delta=delta, eta=1.01)
+        nsolve += 1
+        dt = time.perf_counter() - t0
+        if dt >= 10.0 or nsolve >= 20:
+            break
+    return {"value": nsolve / dt, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{nsolve} repeated 512x512x3 solves, m=50, seed 0 (float64 NumPy oracle)",
+            "seconds": dt, "re": relative_error(p.x_true, r.X), "mu": r.mu}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design "
+                                   "note (independent problems per GPU), not implemented"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2603_00839_amd import rtg
+    if not os.path.exists(rtg.LIB_PATH):
+        from paper_2603_00839_amd import build_lib
+        build_lib.build()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    B = args.batch
+    op, probs = make_batch(B, dev)
+    p0 = probs[0]["p"]
+    I1, I2, J = p0.dims
+    n = I1 * I2 * J
+
+    # warm start
+    x0_kind = args.x0
+    X0s = None
+    if x0_kind == "learned":
+        try:
+            from paper_2603_00839_amd import warmstart
+            net = warmstart.load_default(dev)
+        except Exception as e:      # weights not trained yet
+            print(f"[bench] learned warm start unavailable ({e}); using X0 = C", file=sys.stderr)
+            net = None
+        if net is not None:
+            with torch.no_grad():
+                X0s = [net.infer(q["C"]) for q in probs]
+        else:
+            x0_kind = "observation"
+    if X0s is None:
+        X0s = [q["C"] for q in probs]
+    torch.cuda.synchronize()
+
+    results = {}
+    variants = [args.only] if args.only else ["fp32_plain", "bf16_warm"]
+    for v in variants:
+        if v == "fp32_plain":
+            prm = [rtg.make_params(args.m, rtg.F32, delta=q["delta"], eta=1.01) for q in probs]
+            plan = rtg.BatchPlan([op] * B, [q["sk"] for q in probs], [q["C"] for q in probs], [None] * B, prm)
+            r = time_variant(plan, args.steps, args.warmup, rtg, torch, n, 4, args.m, False)
+        else:
+            prm = [rtg.make_params(args.m_warm, rtg.BF16, delta=q["delta"], eta=1.01) for q in probs]
+            plan = rtg.BatchPlan([op] * B, [q["sk"] for q in probs], [q["C"] for q in probs], X0s, prm)
+            r = time_variant(plan, args.steps, args.warmup, rtg, torch, n, 2, args.m_warm, True)
+        res = [rel_err(plan.outs[b], probs[b]["xt"]) for b in range(B)]
+        r["re_mean"] = float(np.mean(res))
+        r["re_p0"] = res[0]
+        r["iters_mean"] = float(np.mean([i.iters for i in r["infos"]]))
+        r["flags"] = sorted({i.flags for i in r["infos"]})
+        r["solves_per_s"] = B * args.steps / r["seconds"]
+        r["ms_per_step"] = 1e3 * r["seconds"] / args.steps
+        results[v] = r
+        del plan
+        torch.cuda.empty_cache()
+
+    if args.headline == "auto":
+        head = "bf16_warm" if (x0_kind == "learned" and "bf16_warm" in results) else variants[0]
+        if "fp32_plain" in results and head == "bf16_warm":
+            pass
+    else:
+        head = args.headline
+    if head not in results:
+        head = variants[0]
+    H = results[head]
+    gbs = H["tile_bytes"] / (H["tile_ms"] * 1e-3) / 1e9 if H["tile_ms"] > 0 else 0.0
+    out = {
+        "metric": METRIC,
+        "value": H["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": H["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if head == "fp32_plain" else "bf16",
+        "data": "synthetic",
+        "config": {
+            "workload": "cfg2: 512x512x3 colour deblurring (200 rectangles + Gaussian random field, "
+                        "sigma 2.5, r 8, nu 1e-3), sketch 64x64x3, discrepancy mu",
+            "problems_per_step": B, "m": args.m if head == "fp32_plain" else args.m_warm,
+            "variant": head, "x0": "zero" if head == "fp32_plain" else x0_kind,
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "k_tile (multi-AXPY + store + MFMA mode-1/2 sketch)",
+            "launches": H["tile_launches"],
+            "avg_launch_us": 1e3 * H["tile_ms"] / max(H["tile_launches"], 1),
+            "bytes_per_launch": H["tile_bytes"] / max(H["tile_launches"], 1),
+        },
+        "variants": {k: {"solves_per_s": v["solves_per_s"], "ms_per_step": v["ms_per_step"],
+                         "re_mean": v["re_mean"], "re_problem0": v["re_p0"], "iters_mean": v["iters_mean"],
+                         "flags": v["flags"]} for k, v in results.items()},
+    }
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(p0)
+        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        out["oracle_re_problem0"] = cb["re"]
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,183 @@
+/*
+ * rtg.h -- C ABI of the MI355X (gfx950) RTG-GMRES library (librtg.so).
+ *
+ * RTG-GMRES solves  min || Phi(X) - C ||_F  (eq. (1)) for third-order tensors
+ * X, C in R^{I1 x I2 x J} with the operator of eq. (2),
+ *
+ *     Phi(X) = A *_2 X *_1 B,     a[i1,i2,k1,k2] = A1[i1,k1] A2[i2,k2],
+ *
+ * i.e. Phi(X) = X x_1 A1 x_2 A2 x_3 B^T, by the sketched tensor global
+ * Arnoldi process (Sec. 4.3) whose inner products are the sketched Einstein
+ * inner products <X,Y>_Theta = <S(X), S(Y)>_F with the mode-wise sketch
+ * S(X) = X x_1 Om1 x_2 Om2 x_3 Om3 (Sec. 3.1), followed by the projected
+ * Tikhonov problem  min ||beta e1 - H y||^2 + mu ||y||^2  (eqs. (12)-(13)),
+ * mu fixed or chosen by the discrepancy principle, and X = X0 + sum_j y_j V_j
+ * (algorithm "Block GMRES via Sketched Einstein Product", Sec. 4.4).
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ * - Tensors are device arrays of I1*I2*J elements in column-major order,
+ *   i1 fastest: offset(i1,i2,j) = i1 + I1*(i2 + I2*j) (the ivec order of
+ *   Sec. 4.1).  I1 must be a multiple of 8 and device pointers 16-byte
+ *   aligned.
+ * - A banded factor M (I x I, half-bandwidth r) is a HOST array of
+ *   I*(2r+1) floats, row-major: band[i*(2r+1) + d + r] = M[i, i+d] for
+ *   -r <= d <= r; entries whose column leaves [0, I) are ignored (zero
+ *   boundary conditions, Sec. 5.1).
+ * - Sketch factors Om_k are HOST arrays, row-major l_k x I_k; NULL means the
+ *   identity (then l_k must equal I_k).
+ * - "stream" is a hipStream_t passed as void* (NULL = default stream).
+ *   Compute calls only enqueue work; they return after argument checks.
+ * - Return codes (synchronous, host-side): RTG_OK or a negative RTG_E_*.
+ *   Numerical outcomes are reported in device-resident rtg_info.flags.
+ * - Ownership: all tensors and workspaces are caller-owned device memory.
+ *   Handles own small device copies of the bands and sketch factors and are
+ *   immutable after setup: one handle may be used concurrently on several
+ *   streams with separate workspaces.  Compute calls never allocate.
+ */
+#ifndef RTG_H
+#define RTG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rtg_op_s* rtg_op;
+typedef struct rtg_sk_s* rtg_sk;
+
+/* element types of tensors the library reads (X inputs, the Krylov basis) */
+enum { RTG_F32 = 0, RTG_BF16 = 1 };
+
+/* return codes */
+enum {
+    RTG_OK = 0,
+    RTG_E_ARG = -1,        /* null pointer, bad enum, misaligned pointer  */
+    RTG_E_SHAPE = -2,      /* inconsistent or unsupported sizes           */
+    RTG_E_HIP = -3,        /* a HIP runtime call failed                   */
+    RTG_E_NOMEM = -4,      /* device allocation in a setup call failed    */
+    RTG_E_WORKSPACE = -5   /* workspace smaller than required             */
+};
+
+/* numerical outcome flags (rtg_info.flags, device side) */
+enum {
+    RTG_F_BREAKDOWN = 1,           /* h_{j+1,j} <= bd_tol ||S(Phi(V_j))||: solved at j  */
+    RTG_F_DISCREP_UNREACHABLE = 2, /* LS residual already above eta*delta: mu = 0      */
+    RTG_F_MU_INF = 4,              /* eta*delta >= beta: y = 0, X = X0                  */
+    RTG_F_NONFINITE = 8,           /* NaN/Inf met in a coefficient                     */
+    RTG_F_NOT_CONVERGED = 16       /* stop_res requested and not reached within m      */
+};
+
+/* Solver parameters. */
+typedef struct {
+    int m;            /* maximum number of Arnoldi steps, 1 <= m <= 96            */
+    int basis_dtype;  /* RTG_F32 or RTG_BF16: storage of V_j (and MFMA precision) */
+    double mu;        /* >= 0: fixed Tikhonov parameter; < 0: discrepancy principle */
+    double delta;     /* absolute noise-norm estimate ||E||_F (discrepancy)       */
+    double eta;       /* discrepancy safety factor (1.01 is customary)            */
+    double stop_res;  /* > 0: stop at the first j whose projected LS residual is
+                         <= stop_res; <= 0: run m steps                          */
+    double bd_tol;    /* breakdown threshold relative to ||S(Phi(V_j))||          */
+} rtg_params;
+
+/* Result summary, written by the device at the end of a solve. */
+typedef struct {
+    int iters;        /* number of Arnoldi steps taken (m_eff)                    */
+    int flags;        /* RTG_F_* bits                                            */
+    double mu;        /* Tikhonov parameter used (inf if RTG_F_MU_INF)            */
+    double beta;      /* ||R0||_Theta                                            */
+    double res_proj;  /* ||beta e1 - H y||_2 = ||S(C - Phi(X))||_F (Sec. 4.4)     */
+    double res_ls;    /* least-squares residual of the projected problem (11S)    */
+} rtg_info;
+
+/* One problem of a batch (rtg_solve_batched). */
+typedef struct {
+    rtg_op op;
+    rtg_sk sk;
+    const float* C;   /* device, observation                                      */
+    const float* X0;  /* device initial guess, or NULL for X0 = 0                 */
+    float* X;         /* device output                                            */
+    rtg_params params;
+    rtg_info* info;   /* device pointer                                           */
+} rtg_problem;
+
+/* ---- operator (eq. (2); Sec. 5.1-5.2) ------------------------------------
+ * Phi(X) = X x_1 A1 x_2 A2 x_3 B^T.  b_band is the band of B as it appears in
+ * X *_1 B, (X *_1 B)[:,:,j] = sum_k X[:,:,k] B[k,j]; the library applies B^T
+ * along mode 3 itself.  Requires 0 <= r1 < I1, 0 <= r2 < I2 (r <= 12),
+ * 0 <= rB < J (rB <= 8).  Copies the bands to the device. */
+int rtg_setup_operator(int I1, int I2, int J,
+                       const float* a1_band, int r1,
+                       const float* a2_band, int r2,
+                       const float* b_band, int rB, rtg_op* out);
+/* Y = Phi(X)  (C == NULL)  or  Y = C - Phi(X)  (C != NULL); X of x_dtype. */
+int rtg_apply_operator(rtg_op op, int x_dtype, const void* X, const float* C,
+                       float* Y, void* stream);
+int rtg_destroy_operator(rtg_op op);
+
+/* ---- sketch (Sec. 3.1, global tensor sketching operator) ------------------
+ * S(X) = X x_1 Om1 x_2 Om2 x_3 Om3 with Om_k in R^{l_k x I_k}.  Requires
+ * 1 <= l1 <= min(I1, 128), 1 <= l2 <= min(I2, 128), 1 <= l3 <= min(J, 16)
+ * when Om3 is given.  The device keeps float32 copies and a bfloat16 copy of
+ * Om1 (used by the BF16 path). */
+int rtg_setup_sketch(int I1, int I2, int J, int l1, int l2, int l3,
+                     const float* om1, const float* om2, const float* om3,
+                     rtg_sk* out);
+size_t rtg_sketch_workspace_bytes(rtg_sk sk);
+/* SX = S(X), L = l1*l2*l3 floats in column-major order (a fastest):
+ * SX[a + l1*(b + l2*c)].  x_dtype RTG_F32 uses float32 MFMA; RTG_BF16 reads a
+ * bfloat16 X and uses bfloat16 MFMA with float32 accumulation. */
+int rtg_sketch(rtg_sk sk, int x_dtype, const void* X, float* SX,
+               void* ws, size_t ws_bytes, void* stream);
+int rtg_destroy_sketch(rtg_sk sk);
+
+/* ---- Arnoldi and solve ----------------------------------------------------- */
+/* Workspace of one problem with at most m steps and the given basis type. */
+size_t rtg_workspace_bytes(rtg_op op, rtg_sk sk, int m, int basis_dtype);
+
+/* m steps of the sketched global Arnoldi process from R0 (Sec. 4.3):
+ * beta = ||R0||_Theta, V1 = R0/beta, h_ij = <V_i, Phi(V_j)>_Theta (classical
+ * Gram-Schmidt with one reorthogonalisation, evaluated in sketch space),
+ * h_{j+1,j} = ||.||_Theta.  Outputs (device): H, (m+1) x m column-major
+ * float64 (zero below the computed part); *beta; *m_done (< m after a
+ * breakdown).  The basis stays in ws (see rtg_workspace_layout). */
+int rtg_arnoldi(rtg_op op, rtg_sk sk, const float* R0, int m, int basis_dtype,
+                double bd_tol, void* ws, size_t ws_bytes,
+                double* H, double* beta, int* m_done, void* stream);
+
+/* Offsets (bytes from ws) of the basis V_1..V_{m+1} (consecutive tensors of
+ * basis_dtype) and of the sketched basis S(V_1)..S(V_{m+1}) (consecutive
+ * float32 vectors of L entries, internal order (a*l2 + b)*l3 + c). */
+int rtg_workspace_layout(rtg_op op, rtg_sk sk, int m, int basis_dtype,
+                         size_t* v_offset, size_t* sv_offset);
+
+/* Full RTG-GMRES solve of one problem; info is a device pointer. */
+int rtg_solve(rtg_op op, rtg_sk sk, const float* C, const float* X0,
+              const rtg_params* params, void* ws, size_t ws_bytes,
+              float* X, rtg_info* info, void* stream);
+
+/* Many independent problems (uneven sizes allowed) solved together: every
+ * stage is one launch over the tiles of all problems.  probs is a HOST array. */
+size_t rtg_batch_workspace_bytes(int count, const rtg_problem* probs);
+int rtg_solve_batched(int count, const rtg_problem* probs, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/* ---- measurement ----------------------------------------------------------
+ * When enabled, every launch of the selected kernel kinds made by the solver
+ * calls (bit k of kind_mask: 0 operator Phi, 1 multi-AXPY + sketch tile,
+ * 2 sketched Gram / Hessenberg update, 3 projected Tikhonov solve) is
+ * bracketed by two hipEvents recorded on the launch stream.
+ * rtg_event_timing_read waits for those events and returns, per kind, the
+ * summed duration in milliseconds and the number of launches, then clears
+ * the record.  Host-side state shared by the process (not thread-safe); a
+ * kind_mask of 0 disables recording. */
+int rtg_event_timing_enable(int kind_mask);
+int rtg_event_timing_read(double* ms, long long* launches, int nkinds);
+
+const char* rtg_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RTG_H */

@@ -1,0 +1,303 @@
+// Sketched inner products and the Hessenberg update of one Arnoldi step.
+//
+// Each workgroup owns a chunk of (a, b) index pairs of the sketch.  It
+//  1. finishes the sketch for its chunk: sums the per-tile partials written
+//     by k_tile over the i2 tiles, and applies mode 3,
+//        s[a,b,c'] = sum_c Om3[c',c] sum_tiles P_(tile,c)[a,b]
+//     (Om3 = identity when absent) -- for s = S(Phi(V_j)) and, in a step,
+//     for S(V_j), the sketch of the newest stored basis tensor;
+//  2. computes its share of the inner products <S(V_i), s> and
+//     <S(V_i), S(V_j)> (i <= j) and of ||s||^2 in float64;
+//  3. the last workgroup of a problem to finish sums the shares in a fixed
+//     order and performs the small, float64 part of the step (Sec. 4.3):
+//        h1 = S(V)^T s,  h = h1 + (h1 - G h1)        (classical Gram-Schmidt
+//                                                     with one reorthogonal-
+//                                                     isation, G = S(V)^T S(V))
+//        h_{j+1,j} = ||s - S(V) h|| = sqrt(||s||^2 - 2 h^T h1 + h^T G h)
+//     then the breakdown test, the Givens update of the least-squares
+//     problem (11S) and the stopping decision.  It writes the coefficients
+//     for the next multi-AXPY (k_tile).
+// In the start mode it returns beta = ||S(R0)||; in the sketch-output mode it
+// writes the finished sketch in the column-major order of the C ABI.
+#include "rtg_internal.h"
+
+namespace rtg {
+
+__device__ __forceinline__ double load_coherent(const double* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// s_out[e] for the pairs [q0, q0 + qn): e = (q - q0) * l3 + c'
+__device__ __forceinline__ void finish_sketch(const Desc& d, const float* __restrict__ Pbuf, int q0,
+                                              int qn, float* s_out) {
+    const int tid = threadIdx.x;
+    const int L12 = d.l1 * d.l2;
+    const int J = d.J, nt2 = d.n_i2t, l3 = d.l3;
+    for (int t = tid; t < qn; t += blockDim.x) {
+        const int q = q0 + t;
+        float acc3[LMAX_3];
+#pragma unroll
+        for (int c3 = 0; c3 < LMAX_3; ++c3) acc3[c3] = 0.f;
+        for (int c = 0; c < J; ++c) {
+            // partials of the i2 tiles of channel c (independent loads in flight)
+            const float* pc = Pbuf + (size_t)c * nt2 * L12 + q;
+            float Qp[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) Qp[u] = 0.f;
+            int t2 = 0;
+            for (; t2 + 8 <= nt2; t2 += 8) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) Qp[u] += pc[(size_t)(t2 + u) * L12];
+            }
+            for (; t2 < nt2; ++t2) Qp[0] += pc[(size_t)t2 * L12];
+            const float Q = ((Qp[0] + Qp[1]) + (Qp[2] + Qp[3])) + ((Qp[4] + Qp[5]) + (Qp[6] + Qp[7]));
+            if (d.has_om3) {
+#pragma unroll
+                for (int c3 = 0; c3 < LMAX_3; ++c3)
+                    if (c3 < l3) acc3[c3] = fmaf(d.om3[(size_t)c3 * J + c], Q, acc3[c3]);
+            } else {
+                s_out[t * l3 + c] = Q;
+            }
+        }
+        if (d.has_om3) {
+#pragma unroll
+            for (int c3 = 0; c3 < LMAX_3; ++c3)
+                if (c3 < l3) s_out[t * l3 + c3] = acc3[c3];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
+                                              const int* __restrict__ starts, int count, int mode,
+                                              int j, float* sketch_out) {
+    __shared__ float s_s[4096];
+    __shared__ float s_v[4096];
+    __shared__ double ds[2 * (MMAX + 2)];
+    __shared__ double h1s[MMAX], hs[MMAX], gnew[MMAX], Gh1[MMAX], Gh[MMAX];
+    __shared__ int s_last;
+
+    const int b = blockIdx.x;
+    const int p = find_problem(starts, count, b);
+    const Desc& d = descs[p];
+    const int wgi = b - starts[p];
+    const int nwg = d.ntile[KIND_GRAM];
+    if (mode == GM_STEP && d.state[ST_ACTIVE] == 0) return;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int L12 = d.l1 * d.l2, l3 = d.l3;
+    const int CH = gram_pairs_per_block(l3);
+    const int q0 = wgi * CH;
+    const int qn = min(CH, L12 - q0);
+    const int E = qn * l3;
+
+    finish_sketch(d, d.PW, q0, qn, s_s);
+    if (mode == GM_STEP) finish_sketch(d, d.PV, q0, qn, s_v);
+    __syncthreads();
+
+    if (mode == GM_SKETCH_OUT) {
+        const int l1 = d.l1, l2 = d.l2;
+        for (int e = tid; e < E; e += 256) {
+            const int q = q0 + e / l3, c3 = e % l3;
+            const int a = q / l2, bb = q % l2;
+            sketch_out[(size_t)a + (size_t)l1 * (bb + (size_t)l2 * c3)] = s_s[e];
+        }
+        return;
+    }
+    const size_t Lsz = (size_t)d.L;
+    if (mode == GM_STEP) {
+        float* svj = d.SV + (size_t)(j - 1) * Lsz + (size_t)q0 * l3;
+        for (int e = tid; e < E; e += 256) svj[e] = s_v[e];
+    }
+
+    // ---- shares of the inner products (float64).  Items: <S(V_i), s> and
+    // <S(V_i), S(V_j)> for i < j, and ||s||^2.  Each wave takes groups of eight
+    // items (and unrolls over elements) so that many independent loads are in
+    // flight.
+    const int nitems = (mode == GM_STEP) ? j + 1 : 1;
+    constexpr int IG = 8;
+    for (int it0 = wave * IG; it0 < nitems; it0 += 4 * IG) {
+        double as[IG], av[IG];
+#pragma unroll
+        for (int u = 0; u < IG; ++u) { as[u] = 0.0; av[u] = 0.0; }
+#pragma unroll 4
+        for (int e = lane; e < E; e += 64) {
+            const double se = s_s[e];
+            const double ve = (mode == GM_STEP) ? (double)s_v[e] : 0.0;
+#pragma unroll
+            for (int u = 0; u < IG; ++u) {
+                const int it = it0 + u;
+                if (it >= nitems) break;
+                double x;
+                if (it == nitems - 1) { as[u] += se * se; continue; }
+                if (it == j - 1) x = ve;
+                else x = d.SV[(size_t)it * Lsz + (size_t)q0 * l3 + e];
+                as[u] += x * se;
+                av[u] += x * ve;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < IG; ++u) {
+            const int it = it0 + u;
+            if (it >= nitems) break;
+            const double ra = wave_sum(as[u]);
+            const double rv = wave_sum(av[u]);
+            if (lane == 0) {
+                d.dots[((size_t)wgi * (MMAX + 2) + it) * 2 + 0] = ra;
+                d.dots[((size_t)wgi * (MMAX + 2) + it) * 2 + 1] = rv;
+            }
+        }
+    }
+
+    // ---- the last workgroup of this problem finishes the step
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) {
+        const int old = __hip_atomic_fetch_add(d.state + ST_COUNTER, 1, __ATOMIC_ACQ_REL,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+        s_last = (old == nwg - 1);
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    for (int x = tid; x < 2 * nitems; x += 256) {
+        double sum = 0.0;
+        for (int w = 0; w < nwg; ++w) sum += load_coherent(d.dots + ((size_t)w * (MMAX + 2) + x / 2) * 2 + (x & 1));
+        ds[x] = sum;
+    }
+    __syncthreads();
+    int* st = d.state;
+    double* sc = d.scal;
+    const int m = d.m;
+    double* gvec = d.gv + 2 * m;       // rotated right-hand side g[0..m]
+    if (mode == GM_START) {
+        if (tid == 0) {
+            st[ST_COUNTER] = 0;
+            const double beta = sqrt(ds[0]);
+            sc[SC_BETA] = beta;
+            gvec[0] = beta;
+            if (!(beta > 0.0) || !isfinite(beta)) {
+                st[ST_ACTIVE] = 0;
+                st[ST_MEFF] = 0;
+                st[ST_FLAGS] |= isfinite(beta) ? RTG_F_BREAKDOWN : RTG_F_NONFINITE;
+                d.coef[MMAX + 1] = 0.f;
+            } else {
+                d.coef[MMAX + 1] = (float)(1.0 / beta);
+            }
+        }
+        return;
+    }
+
+    // ---- step j: classical Gram-Schmidt + reorthogonalisation in sketch space
+    const int jm = j - 1;              // column index, also index of the newest basis tensor
+    const int ldg = m + 1;
+    if (tid < j) {
+        h1s[tid] = ds[2 * tid];
+        gnew[tid] = ds[2 * tid + 1];
+    }
+    __syncthreads();
+    if (tid < j) {
+        d.G[(size_t)tid * ldg + jm] = gnew[tid];
+        d.G[(size_t)jm * ldg + tid] = gnew[tid];
+    }
+    // Gh1 = G h1 and then Gh = G h with h = 2 h1 - G h1: each wave takes four
+    // rows at a time, lanes run along the row (coalesced), wave reductions.
+    auto gmatvec = [&](const double* v, double* out, bool make_h) {
+        for (int i0 = wave * 4; i0 < j; i0 += 16) {
+            double acc4[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int k = lane; k < j; k += 64) {
+                const double vk = v[k];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int i = i0 + u;
+                    if (i >= j) break;
+                    const double gik = (i == jm) ? gnew[k] : (k == jm ? gnew[i] : d.G[(size_t)i * ldg + k]);
+                    acc4[u] += gik * vk;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = i0 + u;
+                if (i >= j) break;
+                const double r = wave_sum(acc4[u]);
+                if (lane == 0) {
+                    out[i] = r;
+                    if (make_h) hs[i] = 2.0 * h1s[i] - r;
+                }
+            }
+        }
+    };
+    gmatvec(h1s, Gh1, true);
+    __syncthreads();
+    gmatvec(hs, Gh, false);
+    __syncthreads();
+    if (tid == 0) {
+        st[ST_COUNTER] = 0;
+        const double nrm2 = ds[2 * j];
+        double hth1 = 0.0, hGh = 0.0;
+        bool finite = isfinite(nrm2);
+        for (int i = 0; i < j; ++i) {
+            hth1 += hs[i] * h1s[i];
+            hGh += hs[i] * Gh[i];
+            finite = finite && isfinite(hs[i]);
+        }
+        const double hn2 = nrm2 - 2.0 * hth1 + hGh;
+        const double hn = sqrt(hn2 > 0.0 ? hn2 : 0.0);
+        const double rho = sqrt(nrm2);
+        finite = finite && isfinite(hn);
+        // Hessenberg column
+        double* Hc = d.H + (size_t)jm * (m + 1);
+        for (int i = 0; i < j; ++i) Hc[i] = hs[i];
+        Hc[j] = hn;
+        // Givens update of the projected least-squares problem
+        double* cs = d.gv;
+        double* sn = d.gv + m;
+        double* Rc = d.R + (size_t)jm * m;
+        double r_prev = hs[0];
+        for (int i = 0; i < jm; ++i) {
+            const double a = r_prev, bnext = hs[i + 1];
+            Rc[i] = cs[i] * a + sn[i] * bnext;
+            r_prev = -sn[i] * a + cs[i] * bnext;
+        }
+        const double rr = hypot(r_prev, hn);
+        const double cj = rr > 0.0 ? r_prev / rr : 1.0;
+        const double sj = rr > 0.0 ? hn / rr : 0.0;
+        cs[jm] = cj;
+        sn[jm] = sj;
+        Rc[jm] = rr;
+        const double gj = gvec[jm];
+        gvec[jm] = cj * gj;
+        gvec[j] = -sj * gj;
+        const double res_ls = fabs(gvec[j]);
+        sc[SC_RESLS] = res_ls;
+        // coefficients of the orthogonalisation / normalisation
+        for (int i = 0; i < j; ++i) d.coef[i] = (float)hs[i];
+        d.coef[MMAX + 1] = hn > 0.0 ? (float)(1.0 / hn) : 0.f;
+        // stopping decisions
+        if (!finite) {
+            st[ST_FLAGS] |= RTG_F_NONFINITE;
+            st[ST_MEFF] = jm;
+            st[ST_ACTIVE] = 0;
+        } else if (hn <= d.bd_tol * rho) {
+            st[ST_FLAGS] |= RTG_F_BREAKDOWN;
+            st[ST_MEFF] = j;
+            st[ST_ACTIVE] = 0;
+        } else if (d.stop_res > 0.0 && res_ls <= d.stop_res) {
+            st[ST_MEFF] = j;
+            st[ST_ACTIVE] = 0;
+        } else if (j >= m && !d.keep_last) {
+            st[ST_MEFF] = j;
+            st[ST_ACTIVE] = 0;
+            if (d.stop_res > 0.0) st[ST_FLAGS] |= RTG_F_NOT_CONVERGED;
+        } else {
+            st[ST_MEFF] = j;
+        }
+    }
+}
+
+hipError_t launch_gram(const Desc* d, const int* starts, int count, int total_tiles, int mode, int j,
+                       float* sketch_out, hipStream_t s) {
+    hipLaunchKernelGGL(k_gram, dim3(total_tiles), dim3(256), 0, s, d, starts, count, mode, j, sketch_out);
+    return hipGetLastError();
+}
+
+}  // namespace rtg

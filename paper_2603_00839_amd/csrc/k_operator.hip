@@ -1,0 +1,260 @@
+// Banded Einstein-product operator (eq. (2); Sec. 5.1-5.2):
+//
+//   Y[i1,i2,j] = sum_k B[k,j] sum_{k2} A2[i2,k2] sum_{k1} A1[i1,k1] X[k1,k2,k]
+//             = (X x_1 A1 x_2 A2 x_3 B^T)[i1,i2,j],
+//
+// with A1, A2, B banded (half-bandwidths r1, r2, rB) and zero boundary
+// conditions.  Mode products on different modes commute, so each input
+// channel k is blurred spatially once and scattered into the (at most
+// 2 rB + 1) output channels it feeds.
+//
+// Tile: 64 rows (i1) x 32 columns (i2) x up to 8 output channels.  For every
+// input channel the workgroup stages a (64 + 2R) x (32 + 2R) slab in LDS
+// (zeros outside the image), runs the i1 pass with lanes across columns
+// (band coefficients are wave-uniform), then the i2 pass with lanes across
+// rows (again wave-uniform coefficients), and accumulates B-weighted results
+// in registers.  Global loads and stores run along i1, the contiguous mode.
+// R (a template tier 4/8/12) bounds r1, r2; actual widths are runtime.
+#include "rtg_internal.h"
+
+namespace rtg {
+
+struct PhiArgs {
+    int I1, I2, J, r1, r2, rB;
+    const float* a1;
+    const float* a2;
+    const float* bb;
+    const void* src;
+    const float* C;   // residual mode when non-null: Y = C - Phi(X)
+    float* dst;
+};
+
+__device__ __forceinline__ int xcd_remap(int b, int G) {
+    // Consecutive workgroups are dispatched round-robin over the 8 XCDs;
+    // remap so that each XCD receives a contiguous range of logical tiles
+    // (neighbouring tiles share halos through that XCD's L2).
+    const int X = 8;
+    int x = b % X, slot = b / X;
+    int q = G / X, rem = G % X;
+    return x * q + min(x, rem) + slot;
+}
+
+template <int R, bool BF16IN>
+__device__ __forceinline__ void phi_tile(const PhiArgs& a, int tile, float* smem) {
+    constexpr int T1 = PHI_T1, T2 = PHI_T2, JT = PHI_JT;
+    constexpr int SR = T1 + 2 * R;       // slab rows
+    constexpr int SRP = SR + 1;          // padded (odd) row stride
+    constexpr int SC = T2 + 2 * R;       // slab columns (<= 64)
+    constexpr int ZRP = T1 + 1;
+    constexpr int WP = ((2 * R + 1) + 3) / 4 * 4;   // padded taps per band row
+    constexpr int NKB = PHI_JT + 2 * RMAX_B;        // input channels per tile (max)
+    float* S = smem;                     // [SC][SRP]
+    float* Z = S + SC * SRP;             // [SC][ZRP]
+    float* A1c = Z + SC * ZRP;           // [T1][WP]: A1[i1, i1 + d], d = t - R (0 outside the band)
+    float* A2c = A1c + T1 * WP;          // [T2][WP]
+    float* Bc = A2c + T2 * WP;           // [NKB][JT]: B[k, j0 + jj]
+
+    const int I1 = a.I1, I2 = a.I2, J = a.J;
+    const int nt1 = (I1 + T1 - 1) / T1, nt2 = (I2 + T2 - 1) / T2;
+    const int t1 = tile % nt1;
+    const int rest = tile / nt1;
+    const int t2 = rest % nt2;
+    const int tj = rest / nt2;
+    const int i10 = t1 * T1, i20 = t2 * T2, j0 = tj * JT;
+    const int jn = min(JT, J - j0);
+    const int r1 = a.r1, r2 = a.r2, rB = a.rB;
+    const int w1 = 2 * r1 + 1, w2 = 2 * r2 + 1, wB = 2 * rB + 1;
+    const int klo = max(0, j0 - rB), khi = min(J, j0 + jn + rB);
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const size_t plane = (size_t)I1 * I2;
+
+    // band coefficients of this tile, zero-padded to R taps (no branches in
+    // the passes; reads are LDS broadcasts)
+    for (int e = tid; e < T1 * WP; e += 256) {
+        const int row = e / WP, t = e % WP, dd = t - R;
+        const int i1 = i10 + row;
+        A1c[e] = (t <= 2 * R && dd >= -r1 && dd <= r1 && i1 < I1) ? a.a1[(size_t)i1 * w1 + r1 + dd] : 0.f;
+    }
+    for (int e = tid; e < T2 * WP; e += 256) {
+        const int col = e / WP, t = e % WP, dd = t - R;
+        const int i2 = i20 + col;
+        A2c[e] = (t <= 2 * R && dd >= -r2 && dd <= r2 && i2 < I2) ? a.a2[(size_t)i2 * w2 + r2 + dd] : 0.f;
+    }
+    for (int e = tid; e < NKB * JT; e += 256) {
+        const int kk = e / JT, jj = e % JT;
+        const int k = klo + kk, j = j0 + jj, dd = j - k;
+        Bc[e] = (k < khi && jj < jn && dd >= -rB && dd <= rB) ? a.bb[(size_t)k * wB + dd + rB] : 0.f;
+    }
+
+    float acc[JT][8];
+#pragma unroll
+    for (int jj = 0; jj < JT; ++jj)
+#pragma unroll
+        for (int o = 0; o < 8; ++o) acc[jj][o] = 0.f;
+
+    // The slab of the next input channel is loaded into registers while the
+    // current one is processed (all loads of a slab are issued together).
+    constexpr int NLD = (SR * SC + 255) / 256;
+    const float* srcf = (const float*)a.src;
+    const bf16_t* srch = (const bf16_t*)a.src;
+    float pre[NLD];
+    auto load_slab = [&](int k) {
+#pragma unroll
+        for (int it = 0; it < NLD; ++it) {
+            const int e = tid + 256 * it;
+            const int row = e % SR, c = e / SR;
+            const int i1 = i10 - R + row, i2 = i20 - R + c;
+            float v = 0.f;
+            if (e < SR * SC && i1 >= 0 && i1 < I1 && i2 >= 0 && i2 < I2) {
+                const size_t off = (size_t)k * plane + (size_t)i2 * I1 + i1;
+                v = BF16IN ? bf2f(srch[off]) : srcf[off];
+            }
+            pre[it] = v;
+        }
+    };
+    load_slab(klo);
+    for (int k = klo; k < khi; ++k) {
+        __syncthreads();
+        // ---- stage the slab of channel k (zero boundary conditions)
+#pragma unroll
+        for (int it = 0; it < NLD; ++it) {
+            const int e = tid + 256 * it;
+            if (e < SR * SC) S[(e / SR) * SRP + e % SR] = pre[it];
+        }
+        if (k + 1 < khi) load_slab(k + 1);
+        __syncthreads();
+        // ---- i1 pass: Z[c][row] = sum_d A1[i1, i1+d] S[c][row + R + d]
+        // lanes across slab columns, wave handles rows [16 wave, 16 wave + 16)
+        if (lane < SC) {
+#pragma unroll
+            for (int blk = 0; blk < 2; ++blk) {
+                const int rbase = wave * 16 + blk * 8;
+                float in[8 + 2 * R];
+#pragma unroll
+                for (int e = 0; e < 8 + 2 * R; ++e) in[e] = S[lane * SRP + rbase + e];
+#pragma unroll
+                for (int o = 0; o < 8; ++o) {
+                    const float* cr = A1c + (rbase + o) * WP;
+                    float s = 0.f;
+#pragma unroll
+                    for (int t = 0; t <= 2 * R; ++t) s = fmaf(cr[t], in[o + t], s);
+                    Z[lane * ZRP + rbase + o] = s;
+                }
+            }
+        }
+        __syncthreads();
+        // ---- i2 pass: U[row][o] = sum_d A2[i2, i2+d] Z[8 wave + o + R + d][row]
+        float in2[8 + 2 * R];
+#pragma unroll
+        for (int e = 0; e < 8 + 2 * R; ++e) in2[e] = Z[(wave * 8 + e) * ZRP + lane];
+        float u[8];
+#pragma unroll
+        for (int o = 0; o < 8; ++o) {
+            const float* cr = A2c + (wave * 8 + o) * WP;
+            float s = 0.f;
+#pragma unroll
+            for (int t = 0; t <= 2 * R; ++t) s = fmaf(cr[t], in2[o + t], s);
+            u[o] = s;
+        }
+        // ---- mode 3: output channel j receives B[k, j] * U (|j - k| <= rB)
+#pragma unroll
+        for (int jj = 0; jj < JT; ++jj) {
+            const float bkj = Bc[(k - klo) * JT + jj];
+#pragma unroll
+            for (int o = 0; o < 8; ++o) acc[jj][o] = fmaf(bkj, u[o], acc[jj][o]);
+        }
+    }
+    // ---- store (lanes along i1: coalesced)
+    const int i1 = i10 + lane;
+    if (i1 < I1) {
+#pragma unroll
+        for (int jj = 0; jj < JT; ++jj) {
+            if (jj >= jn) break;
+#pragma unroll
+            for (int o = 0; o < 8; ++o) {
+                const int i2 = i20 + wave * 8 + o;
+                if (i2 < I2) {
+                    size_t off = (size_t)(j0 + jj) * plane + (size_t)i2 * I1 + i1;
+                    float v = acc[jj][o];
+                    if (a.C) v = a.C[off] - v;
+                    a.dst[off] = v;
+                }
+            }
+        }
+    }
+}
+
+template <int R>
+constexpr int phi_smem_floats() {
+    return (PHI_T2 + 2 * R) * (PHI_T1 + 2 * R + 1) + (PHI_T2 + 2 * R) * (PHI_T1 + 1) +
+           (PHI_T1 + PHI_T2) * (((2 * R + 1) + 3) / 4 * 4) + (PHI_JT + 2 * RMAX_B) * PHI_JT;
+}
+
+template <int R, bool BF16IN>
+__global__ void __launch_bounds__(256) k_phi_single(PhiArgs a) {
+    __shared__ float smem[phi_smem_floats<R>()];
+    phi_tile<R, BF16IN>(a, xcd_remap(blockIdx.x, gridDim.x), smem);
+}
+
+template <int R, bool BF16IN>
+__global__ void __launch_bounds__(256) k_phi_batched(const Desc* __restrict__ descs,
+                                                     const int* __restrict__ starts, int count,
+                                                     int src_sel, int src_index) {
+    __shared__ float smem[phi_smem_floats<R>()];
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int p = find_problem(starts, count, b);
+    const Desc& d = descs[p];
+    if (src_sel == PS_BASIS && d.state[ST_ACTIVE] == 0) return;
+    PhiArgs a;
+    a.I1 = d.I1; a.I2 = d.I2; a.J = d.J; a.r1 = d.r1; a.r2 = d.r2; a.rB = d.rB;
+    a.a1 = d.a1; a.a2 = d.a2; a.bb = d.bb;
+    if (src_sel == PS_BASIS) {
+        const size_t es = d.bf16 ? 2 : 4;
+        a.src = (const char*)d.V + (size_t)src_index * d.n * es;
+        a.C = nullptr;
+    } else {
+        if (d.X0 == nullptr) return;      // R0 = C needs no operator application
+        a.src = d.X0;
+        a.C = d.C;
+    }
+    a.dst = d.W;
+    phi_tile<R, BF16IN>(a, b - starts[p], smem);
+}
+
+static int phi_tier(int r) { return r <= 4 ? 4 : (r <= 8 ? 8 : 12); }
+
+int phi_tiles(int I1, int I2, int J) {
+    return ((I1 + PHI_T1 - 1) / PHI_T1) * ((I2 + PHI_T2 - 1) / PHI_T2) * ((J + PHI_JT - 1) / PHI_JT);
+}
+
+hipError_t launch_phi_single(int I1, int I2, int J, int r1, int r2, int rB, const float* a1,
+                             const float* a2, const float* bb, const void* src, int bf16_in,
+                             const float* C, float* dst, hipStream_t s) {
+    PhiArgs a{I1, I2, J, r1, r2, rB, a1, a2, bb, src, C, dst};
+    const int tiles = phi_tiles(I1, I2, J);
+    const int tier = phi_tier(r1 > r2 ? r1 : r2);
+#define RTG_PHI_SINGLE(RR)                                                          \
+    if (bf16_in) hipLaunchKernelGGL((k_phi_single<RR, true>), dim3(tiles), dim3(256), 0, s, a); \
+    else hipLaunchKernelGGL((k_phi_single<RR, false>), dim3(tiles), dim3(256), 0, s, a);
+    if (tier == 4) { RTG_PHI_SINGLE(4) } else if (tier == 8) { RTG_PHI_SINGLE(8) } else { RTG_PHI_SINGLE(12) }
+#undef RTG_PHI_SINGLE
+    return hipGetLastError();
+}
+
+hipError_t launch_phi(const Desc* d, const int* starts, int count, int total_tiles, int src_sel,
+                      int src_index, int rmax, int bf16_in, hipStream_t s) {
+    const int tier = phi_tier(rmax);
+#define RTG_PHI_BATCH(RR)                                                                   \
+    if (bf16_in) hipLaunchKernelGGL((k_phi_batched<RR, true>), dim3(total_tiles), dim3(256), 0, s, \
+                                    d, starts, count, src_sel, src_index);                 \
+    else hipLaunchKernelGGL((k_phi_batched<RR, false>), dim3(total_tiles), dim3(256), 0, s, \
+                            d, starts, count, src_sel, src_index);
+    if (tier == 4) { RTG_PHI_BATCH(4) } else if (tier == 8) { RTG_PHI_BATCH(8) } else { RTG_PHI_BATCH(12) }
+#undef RTG_PHI_BATCH
+    return hipGetLastError();
+}
+
+}  // namespace rtg

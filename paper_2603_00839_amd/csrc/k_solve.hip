@@ -1,0 +1,251 @@
+// Projected Tikhonov problem of RTG-GMRES in float64, one workgroup per
+// problem (eqs. (12)-(13), with mu fixed or chosen by the discrepancy
+// principle).
+//
+// The Arnoldi steps already reduced H (the (k+1) x k Hessenberg matrix) by
+// Givens rotations to H = Q [R; 0] with Q^T beta e1 = [g_R; gamma], so
+//   ||beta e1 - H y||^2 + mu ||y||^2 = ||g_R - R y||^2 + gamma^2 + mu ||y||^2.
+// With the SVD R = U diag(s) W^T (one-sided Jacobi: plane rotations of the
+// columns of R accumulated in W, in LDS) and ghat = U^T g_R,
+//   phi(mu) = sum_i (mu / (s_i^2 + mu))^2 ghat_i^2 + gamma^2
+// is the projected residual; it increases from gamma^2 to beta^2 and the
+// discrepancy principle takes the root of phi(mu) = (eta delta)^2, found by
+// bisection in log(mu).  Then y = W diag(s / (s^2 + mu)) ghat, the filter
+// form of the stacked least-squares problem (13).  The kernel writes the
+// coefficients -y_j of the solution update and the result summary.
+#include "rtg_internal.h"
+
+namespace rtg {
+
+// A pair of columns counts as orthogonal once |a_p . a_q| <= tol ||a_p|| ||a_q||;
+// below about n * eps the inner product is rounding noise and rotations stop
+// making progress.
+constexpr double JACOBI_TOL = 1e-13;
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// phi(mu) evaluated by one wave (k <= 128 terms, two per lane)
+__device__ __forceinline__ double proj_res2(const double* sig, const double* gh, int k, double mu,
+                                            double gp2, int lane) {
+    double s = 0.0;
+    for (int i = lane; i < k; i += 64) {
+        const double f = mu / (sig[i] * sig[i] + mu);
+        s += f * f * gh[i] * gh[i];
+    }
+    return wave_sum(s) + gp2;
+}
+
+__global__ void __launch_bounds__(1024) k_solve(const Desc* __restrict__ descs) {
+    constexpr int LD = MMAX + 1;
+    __shared__ double As[MMAX * LD];
+    __shared__ double Ws[MMAX * LD];
+    __shared__ double gR[MMAX], sig[MMAX], gh[MMAX], fco[MMAX];
+    __shared__ int s_rot;
+    __shared__ double s_mu;
+    __shared__ int s_flags;
+
+    const Desc& d = descs[blockIdx.x];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nwave = blockDim.x >> 6;
+    const int k = d.state[ST_MEFF];
+    const int m = d.m;
+    const double beta = d.scal[SC_BETA];
+    const double* gvec = d.gv + 2 * m;
+
+    if (k == 0) {
+        if (tid == 0) {
+            d.coef[MMAX + 1] = 1.f;
+            rtg_info inf;
+            inf.iters = 0;
+            inf.flags = d.state[ST_FLAGS];
+            inf.mu = 0.0;
+            inf.beta = beta;
+            inf.res_proj = beta;
+            inf.res_ls = beta;
+            *d.info = inf;
+        }
+        return;
+    }
+    // ---- load R (upper triangular, column-major, leading dimension m) and W = I
+    for (int e = tid; e < k * k; e += blockDim.x) {
+        const int c = e / k, r = e % k;
+        As[c * LD + r] = (r <= c) ? d.R[(size_t)c * m + r] : 0.0;
+        Ws[c * LD + r] = (r == c) ? 1.0 : 0.0;
+    }
+    if (tid < k) gR[tid] = gvec[tid];
+    const double gam = fabs(gvec[k]);
+    __syncthreads();
+
+    // ---- one-sided Jacobi, round-robin (circle) ordering of column pairs
+    const int nb = k + (k & 1);
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        if (tid == 0) s_rot = 0;
+        __syncthreads();
+        for (int rd = 0; rd < nb - 1; ++rd) {
+            for (int pi = wave; pi < nb / 2; pi += nwave) {
+                const int pos_a = pi, pos_b = nb - 1 - pi;
+                const int pa = pos_a == 0 ? 0 : 1 + (pos_a - 1 + rd) % (nb - 1);
+                const int pb = pos_b == 0 ? 0 : 1 + (pos_b - 1 + rd) % (nb - 1);
+                if (pa >= k || pb >= k) continue;
+                double* ca = As + pa * LD;
+                double* cb = As + pb * LD;
+                double al = 0.0, be = 0.0, ga = 0.0;
+                for (int r = lane; r < k; r += 64) {
+                    const double x = ca[r], y = cb[r];
+                    al += x * x; be += y * y; ga += x * y;
+                }
+                al = wave_sum(al); be = wave_sum(be); ga = wave_sum(ga);
+                if (ga != 0.0 && fabs(ga) > JACOBI_TOL * sqrt(al * be)) {
+                    const double zeta = (be - al) / (2.0 * ga);
+                    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                    const double cth = 1.0 / sqrt(1.0 + t * t), sth = cth * t;
+                    double* wa = Ws + pa * LD;
+                    double* wb = Ws + pb * LD;
+                    for (int r = lane; r < k; r += 64) {
+                        const double x = ca[r], y = cb[r];
+                        ca[r] = cth * x - sth * y;
+                        cb[r] = sth * x + cth * y;
+                        const double u = wa[r], v = wb[r];
+                        wa[r] = cth * u - sth * v;
+                        wb[r] = sth * u + cth * v;
+                    }
+                    if (lane == 0) s_rot = 1;
+                }
+            }
+            __syncthreads();
+        }
+        const int rot = s_rot;
+        __syncthreads();
+        if (!rot) break;
+    }
+    // ---- singular values and ghat = U^T g_R
+    for (int i = wave; i < k; i += nwave) {
+        double nn = 0.0, gg = 0.0;
+        for (int r = lane; r < k; r += 64) {
+            const double x = As[i * LD + r];
+            nn += x * x;
+            gg += x * gR[r];
+        }
+        nn = wave_sum(nn);
+        gg = wave_sum(gg);
+        if (lane == 0) {
+            const double s = sqrt(nn);
+            sig[i] = s;
+            gh[i] = s > 0.0 ? gg / s : 0.0;
+        }
+    }
+    __syncthreads();
+    // ---- mu: fixed, or the discrepancy principle (wave 0)
+    if (wave == 0) {
+        const double gp2 = gam * gam;
+        double mu = d.mu;
+        int flags = 0;
+        if (!d.mu_fixed) {
+            const double t = d.eta * d.delta;
+            const double t2 = t * t;
+            if (t2 <= gp2) {
+                mu = 0.0;
+                flags |= RTG_F_DISCREP_UNREACHABLE;
+            } else if (t2 >= beta * beta) {
+                mu = INFINITY;
+                flags |= RTG_F_MU_INF;
+            } else {
+                double smax = 0.0;
+                for (int i = lane; i < k; i += 64) smax = fmax(smax, sig[i]);
+                smax = wave_max(smax);
+                const double smax2 = smax > 0.0 ? smax * smax : 1.0;
+                double lo = log(smax2) - 80.0, hi = log(smax2) + 80.0;
+                for (int it = 0; it < 40 && proj_res2(sig, gh, k, exp(lo), gp2, lane) > t2; ++it) lo -= 40.0;
+                for (int it = 0; it < 40 && proj_res2(sig, gh, k, exp(hi), gp2, lane) < t2; ++it) hi += 40.0;
+                for (int it = 0; it < 200; ++it) {
+                    const double mid = 0.5 * (lo + hi);
+                    if (proj_res2(sig, gh, k, exp(mid), gp2, lane) < t2) lo = mid; else hi = mid;
+                }
+                mu = exp(0.5 * (lo + hi));
+            }
+        }
+        if (lane == 0) {
+            s_mu = mu;
+            s_flags = flags;
+        }
+    }
+    __syncthreads();
+    const double mu = s_mu;
+    if (tid < k) {
+        const double s = sig[tid];
+        fco[tid] = isinf(mu) ? 0.0 : (s > 0.0 ? s / (s * s + mu) * gh[tid] : 0.0);
+    }
+    __syncthreads();
+    // ---- y = W f; coefficients of X = X0 + sum_j y_j V_j
+    bool ok = true;
+    if (tid < k) {
+        double yv = 0.0;
+        for (int i = 0; i < k; ++i) yv += Ws[i * LD + tid] * fco[i];
+        d.y[tid] = yv;
+        d.coef[tid] = (float)(-yv);
+        ok = isfinite(yv);
+    }
+    const int allok = __syncthreads_and(ok ? 1 : 0);
+    if (wave == 0) {
+        const double gp2 = gam * gam;
+        const double rp2 = isinf(mu) ? beta * beta : proj_res2(sig, gh, k, mu, gp2, lane);
+        if (lane == 0) {
+            int flags = d.state[ST_FLAGS] | s_flags;
+            if (!allok) flags |= RTG_F_NONFINITE;
+            d.state[ST_FLAGS] = flags;
+            d.coef[MMAX + 1] = 1.f;
+            d.scal[SC_MU] = mu;
+            d.scal[SC_RESPROJ] = sqrt(rp2);
+            rtg_info inf;
+            inf.iters = k;
+            inf.flags = flags;
+            inf.mu = mu;
+            inf.beta = beta;
+            inf.res_proj = sqrt(rp2);
+            inf.res_ls = gam;
+            *d.info = inf;
+        }
+    }
+}
+
+__global__ void k_init(const Desc* __restrict__ descs) {
+    const Desc& d = descs[blockIdx.x];
+    const int tid = threadIdx.x;
+    if (tid < NSTATE) d.state[tid] = (tid == ST_ACTIVE) ? 1 : 0;
+    if (tid < NSCAL) d.scal[tid] = 0.0;
+    const int m = d.m;
+    for (int e = tid; e < (m + 1) * m; e += blockDim.x) d.H[e] = 0.0;
+    for (int e = tid; e < 3 * m + 1; e += blockDim.x) d.gv[e] = 0.0;
+}
+
+__global__ void k_finish_arnoldi(const Desc* __restrict__ descs, double* H, double* beta,
+                                 int* m_done, int m) {
+    const Desc& d = descs[0];
+    for (int e = threadIdx.x; e < (m + 1) * m; e += blockDim.x) H[e] = d.H[e];
+    if (threadIdx.x == 0) {
+        *beta = d.scal[SC_BETA];
+        *m_done = d.state[ST_MEFF];
+    }
+}
+
+hipError_t launch_solve(const Desc* d, int count, hipStream_t s) {
+    hipLaunchKernelGGL(k_solve, dim3(count), dim3(1024), 0, s, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(const Desc* d, int count, hipStream_t s) {
+    hipLaunchKernelGGL(k_init, dim3(count), dim3(256), 0, s, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish_arnoldi(const Desc* d, double* H, double* beta, int* m_done, int m,
+                                 hipStream_t s) {
+    hipLaunchKernelGGL(k_finish_arnoldi, dim3(1), dim3(256), 0, s, d, H, beta, m_done, m);
+    return hipGetLastError();
+}
+
+}  // namespace rtg

@@ -1,0 +1,567 @@
+// C ABI of librtg.so (declared in include/rtg.h): handles, workspace layout,
+// argument checks and the launch sequence of an RTG-GMRES solve
+// (algorithm "Block GMRES via Sketched Einstein Product", Sec. 4.4, with the
+// sketched global Arnoldi process of Sec. 4.3).
+//
+// Per problem the sequence is
+//   R0 = C - Phi(X0)                       k_phi   (skipped when X0 = 0)
+//   partial sketches of R0                 k_tile  (sketch)
+//   beta = ||S(R0)||                       k_gram  (start)
+//   V1 = R0 / beta, partial S(V1)          k_tile  (new basis tensor)
+//   for j = 1..m:
+//     W = Phi(V_j)                         k_phi
+//     partial S(W)                         k_tile  (sketch)
+//     S(V_j), h_{:,j}, h_{j+1,j}, Givens   k_gram  (step)
+//     V_{j+1} = (W - sum h_ij V_i) / h_{j+1,j}, partial S(V_{j+1})   k_tile
+//   projected Tikhonov problem, mu         k_solve
+//   X = X0 + sum y_j V_j                   k_tile  (assemble)
+// Every launch covers all problems of a batch; the host never waits.
+#include "rtg_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+struct rtg_op_s {
+    int I1, I2, J, r1, r2, rB;
+    float* a1;
+    float* a2;
+    float* bb;
+};
+
+struct rtg_sk_s {
+    int I1, I2, J, l1, l2, l3, has_om3;
+    float* om1;
+    float* om2;
+    float* om3;
+    rtg::bf16_t* om1h;
+};
+
+namespace {
+
+using namespace rtg;
+
+size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+struct Layout {
+    size_t V, W, PW, PV, SV, dots, G, H, R, gv, coef, y, state, scal, total;
+    int n_i2t, ntile_tile, ntile_gram, ntile_phi;
+};
+
+Layout problem_layout(const rtg_op_s* op, const rtg_sk_s* sk, int m, int bf16) {
+    Layout L{};
+    const size_t n = (size_t)op->I1 * op->I2 * op->J;
+    const size_t Ls = (size_t)sk->l1 * sk->l2 * sk->l3;
+    const size_t es = bf16 ? 2 : 4;
+    L.n_i2t = (op->I2 + TILE_TC - 1) / TILE_TC;
+    L.ntile_tile = op->J * L.n_i2t;
+    const int ch = gram_pairs_per_block(sk->l3);
+    L.ntile_gram = (sk->l1 * sk->l2 + ch - 1) / ch;
+    L.ntile_phi = phi_tiles(op->I1, op->I2, op->J);
+    const size_t part = (size_t)L.ntile_tile * sk->l1 * sk->l2 * sizeof(float);
+    size_t off = 0;
+    auto take = [&](size_t bytes) { off = align_up(off); size_t at = off; off += bytes; return at; };
+    L.V = take((size_t)(m + 1) * n * es);
+    L.W = take(n * sizeof(float));
+    L.PW = take(part);
+    L.PV = take(part);
+    L.SV = take((size_t)(m + 1) * Ls * sizeof(float));
+    L.dots = take((size_t)L.ntile_gram * (MMAX + 2) * 2 * sizeof(double));
+    L.G = take((size_t)(m + 1) * (m + 1) * sizeof(double));
+    L.H = take((size_t)(m + 1) * m * sizeof(double));
+    L.R = take((size_t)m * m * sizeof(double));
+    L.gv = take((size_t)(3 * m + 1) * sizeof(double));
+    L.coef = take((MMAX + 2) * sizeof(float));
+    L.y = take((size_t)m * sizeof(double));
+    L.state = take(NSTATE * sizeof(int));
+    L.scal = take(NSCAL * sizeof(double));
+    L.total = align_up(off);
+    return L;
+}
+
+size_t plan_bytes(int count) {
+    return align_up((size_t)count * sizeof(Desc)) + align_up((size_t)NKIND * (count + 1) * sizeof(int));
+}
+
+int check_pair(const rtg_op_s* op, const rtg_sk_s* sk) {
+    if (!op || !sk) return RTG_E_ARG;
+    if (op->I1 != sk->I1 || op->I2 != sk->I2 || op->J != sk->J) return RTG_E_SHAPE;
+    return RTG_OK;
+}
+
+int check_m(const rtg_sk_s* sk, int m) {
+    const long long L = (long long)sk->l1 * sk->l2 * sk->l3;
+    if (m < 1 || m > MMAX || m + 1 > L) return RTG_E_SHAPE;
+    return RTG_OK;
+}
+
+void fill_desc(Desc& d, const rtg_op_s* op, const rtg_sk_s* sk, int m, int bf16, char* base,
+               const Layout& L) {
+    std::memset(&d, 0, sizeof(d));
+    d.I1 = op->I1; d.I2 = op->I2; d.J = op->J;
+    d.l1 = sk->l1; d.l2 = sk->l2; d.l3 = sk->l3;
+    d.r1 = op->r1; d.r2 = op->r2; d.rB = op->rB;
+    d.m = m;
+    d.bf16 = bf16;
+    d.has_om3 = sk->has_om3;
+    d.n_i2t = L.n_i2t;
+    d.ntile[KIND_PHI] = L.ntile_phi;
+    d.ntile[KIND_TILE] = L.ntile_tile;
+    d.ntile[KIND_GRAM] = L.ntile_gram;
+    d.n = (long long)op->I1 * op->I2 * op->J;
+    d.L = (long long)sk->l1 * sk->l2 * sk->l3;
+    d.a1 = op->a1; d.a2 = op->a2; d.bb = op->bb;
+    d.om1 = sk->om1; d.om1h = sk->om1h; d.om2 = sk->om2; d.om3 = sk->om3;
+    if (base) {
+        d.V = base + L.V;
+        d.W = (float*)(base + L.W);
+        d.PW = (float*)(base + L.PW);
+        d.PV = (float*)(base + L.PV);
+        d.SV = (float*)(base + L.SV);
+        d.dots = (double*)(base + L.dots);
+        d.G = (double*)(base + L.G);
+        d.H = (double*)(base + L.H);
+        d.R = (double*)(base + L.R);
+        d.gv = (double*)(base + L.gv);
+        d.coef = (float*)(base + L.coef);
+        d.y = (double*)(base + L.y);
+        d.state = (int*)(base + L.state);
+        d.scal = (double*)(base + L.scal);
+    }
+}
+
+// Kernel arguments are copied at launch, so host-side staging can be
+// released as soon as the launch call returns (and the copies are
+// capturable in a graph).
+struct Blob {
+    unsigned char b[3072];
+};
+
+__global__ void k_store(Blob blob, unsigned char* dst, int nbytes) {
+    for (int i = threadIdx.x; i < nbytes; i += blockDim.x) dst[i] = blob.b[i];
+}
+
+int upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
+    const unsigned char* p = (const unsigned char*)src;
+    for (size_t off = 0; off < bytes; off += sizeof(Blob)) {
+        Blob blob;
+        const size_t nb = bytes - off < sizeof(Blob) ? bytes - off : sizeof(Blob);
+        std::memcpy(blob.b, p + off, nb);
+        hipLaunchKernelGGL(k_store, dim3(1), dim3(256), 0, s, blob, (unsigned char*)dst + off, (int)nb);
+    }
+    return hipGetLastError() == hipSuccess ? RTG_OK : RTG_E_HIP;
+}
+
+struct Plan {
+    Desc* d_desc;
+    int* d_starts;   // NKIND x (count + 1)
+    int total[NKIND];
+    int rmax;
+    int l1max;
+};
+
+int build_plan(std::vector<Desc>& descs, void* ws, hipStream_t s, Plan& plan) {
+    const int count = (int)descs.size();
+    std::vector<int> starts((size_t)NKIND * (count + 1), 0);
+    plan.rmax = 1;
+    for (int k = 0; k < NKIND; ++k) {
+        int acc = 0;
+        for (int p = 0; p < count; ++p) {
+            starts[(size_t)k * (count + 1) + p] = acc;
+            acc += descs[p].ntile[k];
+        }
+        starts[(size_t)k * (count + 1) + count] = acc;
+        plan.total[k] = acc;
+    }
+    plan.l1max = 1;
+    for (auto& d : descs) {
+        plan.rmax = std::max(plan.rmax, std::max(d.r1, d.r2));
+        plan.l1max = std::max(plan.l1max, d.l1);
+    }
+    char* base = (char*)ws;
+    plan.d_desc = (Desc*)base;
+    plan.d_starts = (int*)(base + align_up((size_t)count * sizeof(Desc)));
+    int rc = upload(plan.d_desc, descs.data(), descs.size() * sizeof(Desc), s);
+    if (rc) return rc;
+    return upload(plan.d_starts, starts.data(), starts.size() * sizeof(int), s);
+}
+
+const int* starts_of(const Plan& plan, int kind, int count) {
+    return plan.d_starts + (size_t)kind * (count + 1);
+}
+
+#define RTG_HIP(call)                                   \
+    do {                                                \
+        if ((call) != hipSuccess) return RTG_E_HIP;     \
+    } while (0)
+
+// ---- optional event timing of launches (measurement facility)
+constexpr int NTIMED = 4;   // 0 phi, 1 tile, 2 gram, 3 solve
+struct EventTiming {
+    int mask = 0;
+    std::vector<hipEvent_t> pool;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> rec[NTIMED];
+    hipEvent_t get() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+};
+EventTiming g_timing;
+
+struct TimedLaunch {
+    int kind;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    TimedLaunch(int k, hipStream_t st) : kind(k), s(st) {
+        if (g_timing.mask & (1 << kind)) {
+            a = g_timing.get();
+            b = g_timing.get();
+            if (a && b) (void)hipEventRecord(a, s);
+        }
+    }
+    ~TimedLaunch() {
+        if (a && b) {
+            (void)hipEventRecord(b, s);
+            g_timing.rec[kind].push_back({a, b});
+        }
+    }
+};
+#define RTG_TIMED(kind, call)                            \
+    do {                                                 \
+        TimedLaunch _tl((kind), s);                      \
+        if ((call) != hipSuccess) return RTG_E_HIP;      \
+    } while (0)
+
+// Arnoldi loop + (optionally) solve and assembly for a prepared plan.
+int run_solver(const Plan& plan, int count, int mmax, int bf16, bool any_x0, bool solve,
+               bool last_newv, hipStream_t s) {
+    const int* sp = starts_of(plan, KIND_PHI, count);
+    const int* st = starts_of(plan, KIND_TILE, count);
+    const int* sg = starts_of(plan, KIND_GRAM, count);
+    RTG_HIP(launch_init(plan.d_desc, count, s));
+    if (any_x0) RTG_TIMED(0, launch_phi(plan.d_desc, sp, count, plan.total[KIND_PHI], PS_X0, 0, plan.rmax, 0, s));
+    RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_SKETCH_SRC, 0, 0, bf16, 0, plan.l1max, s));
+    RTG_TIMED(2, launch_gram(plan.d_desc, sg, count, plan.total[KIND_GRAM], GM_START, 0, nullptr, s));
+    RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_NEWV, 0, 0, bf16, 0, plan.l1max, s));
+    for (int j = 1; j <= mmax; ++j) {
+        RTG_TIMED(0, launch_phi(plan.d_desc, sp, count, plan.total[KIND_PHI], PS_BASIS, j - 1, plan.rmax, bf16, s));
+        RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_SKETCH, 0, 0, bf16, 0, plan.l1max, s));
+        RTG_TIMED(2, launch_gram(plan.d_desc, sg, count, plan.total[KIND_GRAM], GM_STEP, j, nullptr, s));
+        if (j < mmax || last_newv)
+            RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_NEWV, j, j, bf16, 0, plan.l1max, s));
+    }
+    if (solve) {
+        RTG_TIMED(3, launch_solve(plan.d_desc, count, s));
+        RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_ASSEMBLE, 0, 0, bf16, 0, plan.l1max, s));
+    }
+    return RTG_OK;
+}
+
+int validate_params(const rtg_params* prm) {
+    if (!prm) return RTG_E_ARG;
+    if (prm->basis_dtype != RTG_F32 && prm->basis_dtype != RTG_BF16) return RTG_E_ARG;
+    if (prm->mu < 0.0 && !(prm->delta >= 0.0 && prm->eta > 0.0)) return RTG_E_ARG;
+    if (!(prm->bd_tol >= 0.0)) return RTG_E_ARG;
+    return RTG_OK;
+}
+
+void set_params(Desc& d, const rtg_params* prm) {
+    d.mu_fixed = prm->mu >= 0.0 ? 1 : 0;
+    d.mu = prm->mu >= 0.0 ? prm->mu : 0.0;
+    d.delta = prm->delta;
+    d.eta = prm->eta;
+    d.stop_res = prm->stop_res;
+    d.bd_tol = prm->bd_tol;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rtg_status_string(int status) {
+    switch (status) {
+        case RTG_OK: return "ok";
+        case RTG_E_ARG: return "invalid argument";
+        case RTG_E_SHAPE: return "inconsistent or unsupported sizes";
+        case RTG_E_HIP: return "HIP runtime error";
+        case RTG_E_NOMEM: return "device allocation failed";
+        case RTG_E_WORKSPACE: return "workspace too small";
+        default: return "unknown status";
+    }
+}
+
+int rtg_setup_operator(int I1, int I2, int J, const float* a1_band, int r1, const float* a2_band,
+                       int r2, const float* b_band, int rB, rtg_op* out) {
+    if (!out || !a1_band || !a2_band || !b_band) return RTG_E_ARG;
+    *out = nullptr;
+    if (I1 < 8 || I2 < 1 || J < 1 || (I1 % 8) != 0) return RTG_E_SHAPE;
+    if (r1 < 0 || r2 < 0 || rB < 0 || r1 > RMAX_SPATIAL || r2 > RMAX_SPATIAL || rB > RMAX_B) return RTG_E_SHAPE;
+    if (r1 >= I1 || (r2 >= I2 && I2 > 1) || (rB >= J && J > 1)) return RTG_E_SHAPE;
+    rtg_op_s* op = new rtg_op_s{I1, I2, J, r1, r2, rB, nullptr, nullptr, nullptr};
+    const size_t n1 = (size_t)I1 * (2 * r1 + 1), n2 = (size_t)I2 * (2 * r2 + 1), nb = (size_t)J * (2 * rB + 1);
+    if (hipMalloc(&op->a1, n1 * 4) != hipSuccess || hipMalloc(&op->a2, n2 * 4) != hipSuccess ||
+        hipMalloc(&op->bb, nb * 4) != hipSuccess) {
+        rtg_destroy_operator(op);
+        return RTG_E_NOMEM;
+    }
+    if (hipMemcpy(op->a1, a1_band, n1 * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(op->a2, a2_band, n2 * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(op->bb, b_band, nb * 4, hipMemcpyHostToDevice) != hipSuccess) {
+        rtg_destroy_operator(op);
+        return RTG_E_HIP;
+    }
+    *out = op;
+    return RTG_OK;
+}
+
+int rtg_destroy_operator(rtg_op op) {
+    if (!op) return RTG_OK;
+    if (op->a1) (void)hipFree(op->a1);
+    if (op->a2) (void)hipFree(op->a2);
+    if (op->bb) (void)hipFree(op->bb);
+    delete op;
+    return RTG_OK;
+}
+
+int rtg_apply_operator(rtg_op op, int x_dtype, const void* X, const float* C, float* Y, void* stream) {
+    if (!op || !X || !Y) return RTG_E_ARG;
+    if (x_dtype != RTG_F32 && x_dtype != RTG_BF16) return RTG_E_ARG;
+    if (launch_phi_single(op->I1, op->I2, op->J, op->r1, op->r2, op->rB, op->a1, op->a2, op->bb, X,
+                          x_dtype == RTG_BF16, C, Y, (hipStream_t)stream) != hipSuccess)
+        return RTG_E_HIP;
+    return RTG_OK;
+}
+
+static bf16_t host_f2bf(float f) {
+    uint32_t x;
+    std::memcpy(&x, &f, 4);
+    if ((x & 0x7fffffffu) > 0x7f800000u) return (bf16_t)((x >> 16) | 0x40u);
+    x += 0x7fffu + ((x >> 16) & 1u);
+    return (bf16_t)(x >> 16);
+}
+
+int rtg_setup_sketch(int I1, int I2, int J, int l1, int l2, int l3, const float* om1,
+                     const float* om2, const float* om3, rtg_sk* out) {
+    if (!out) return RTG_E_ARG;
+    *out = nullptr;
+    if (I1 < 8 || I2 < 1 || J < 1 || (I1 % 8) != 0) return RTG_E_SHAPE;
+    if (l1 < 1 || l1 > I1 || l1 > LMAX_SPATIAL || l2 < 1 || l2 > I2 || l2 > LMAX_SPATIAL) return RTG_E_SHAPE;
+    if ((!om1 && l1 != I1) || (!om2 && l2 != I2) || (!om3 && l3 != J)) return RTG_E_SHAPE;
+    if (om3 && (l3 < 1 || l3 > J || l3 > LMAX_3)) return RTG_E_SHAPE;
+    if (!om3 && J > 4096) return RTG_E_SHAPE;
+    rtg_sk_s* sk = new rtg_sk_s{I1, I2, J, l1, l2, l3, om3 ? 1 : 0, nullptr, nullptr, nullptr, nullptr};
+    // identity factors are stored explicitly for modes 1 and 2
+    std::vector<float> h1((size_t)l1 * I1, 0.f), h2((size_t)l2 * I2, 0.f);
+    if (om1) std::memcpy(h1.data(), om1, h1.size() * 4);
+    else for (int i = 0; i < I1; ++i) h1[(size_t)i * I1 + i] = 1.f;
+    if (om2) std::memcpy(h2.data(), om2, h2.size() * 4);
+    else for (int i = 0; i < I2; ++i) h2[(size_t)i * I2 + i] = 1.f;
+    std::vector<bf16_t> h1h(h1.size());
+    for (size_t i = 0; i < h1.size(); ++i) h1h[i] = host_f2bf(h1[i]);
+    bool ok = hipMalloc(&sk->om1, h1.size() * 4) == hipSuccess &&
+              hipMalloc(&sk->om2, h2.size() * 4) == hipSuccess &&
+              hipMalloc(&sk->om1h, h1h.size() * 2) == hipSuccess &&
+              (!om3 || hipMalloc(&sk->om3, (size_t)l3 * J * 4) == hipSuccess);
+    if (!ok) {
+        rtg_destroy_sketch(sk);
+        return RTG_E_NOMEM;
+    }
+    ok = hipMemcpy(sk->om1, h1.data(), h1.size() * 4, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(sk->om2, h2.data(), h2.size() * 4, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(sk->om1h, h1h.data(), h1h.size() * 2, hipMemcpyHostToDevice) == hipSuccess &&
+         (!om3 || hipMemcpy(sk->om3, om3, (size_t)l3 * J * 4, hipMemcpyHostToDevice) == hipSuccess);
+    if (!ok) {
+        rtg_destroy_sketch(sk);
+        return RTG_E_HIP;
+    }
+    *out = sk;
+    return RTG_OK;
+}
+
+int rtg_destroy_sketch(rtg_sk sk) {
+    if (!sk) return RTG_OK;
+    if (sk->om1) (void)hipFree(sk->om1);
+    if (sk->om2) (void)hipFree(sk->om2);
+    if (sk->om3) (void)hipFree(sk->om3);
+    if (sk->om1h) (void)hipFree(sk->om1h);
+    delete sk;
+    return RTG_OK;
+}
+
+size_t rtg_sketch_workspace_bytes(rtg_sk sk) {
+    if (!sk) return 0;
+    const int n_i2t = (sk->I2 + TILE_TC - 1) / TILE_TC;
+    return plan_bytes(1) + align_up((size_t)sk->J * n_i2t * sk->l1 * sk->l2 * sizeof(float));
+}
+
+int rtg_sketch(rtg_sk sk, int x_dtype, const void* X, float* SX, void* ws, size_t ws_bytes, void* stream) {
+    if (!sk || !X || !SX || !ws) return RTG_E_ARG;
+    if (x_dtype != RTG_F32 && x_dtype != RTG_BF16) return RTG_E_ARG;
+    if (!aligned16(X) || !aligned16(ws)) return RTG_E_ARG;
+    if (ws_bytes < rtg_sketch_workspace_bytes(sk)) return RTG_E_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    rtg_op_s dummy{sk->I1, sk->I2, sk->J, 0, 0, 0, nullptr, nullptr, nullptr};
+    Layout L = problem_layout(&dummy, sk, 1, x_dtype == RTG_BF16);
+    std::vector<Desc> descs(1);
+    fill_desc(descs[0], &dummy, sk, 1, x_dtype == RTG_BF16, nullptr, L);
+    descs[0].PW = (float*)((char*)ws + plan_bytes(1));
+    descs[0].R0src = X;
+    descs[0].src_bf16 = x_dtype == RTG_BF16;
+    descs[0].ntile[KIND_PHI] = 0;
+    Plan plan;
+    int rc = build_plan(descs, ws, s, plan);
+    if (rc) return rc;
+    RTG_HIP(launch_tile(plan.d_desc, starts_of(plan, KIND_TILE, 1), 1, plan.total[KIND_TILE], TM_SKETCH_SRC,
+                        0, 0, x_dtype == RTG_BF16, x_dtype == RTG_BF16, plan.l1max, s));
+    RTG_HIP(launch_gram(plan.d_desc, starts_of(plan, KIND_GRAM, 1), 1, plan.total[KIND_GRAM], GM_SKETCH_OUT,
+                        0, SX, s));
+    return RTG_OK;
+}
+
+size_t rtg_workspace_bytes(rtg_op op, rtg_sk sk, int m, int basis_dtype) {
+    if (check_pair(op, sk) || check_m(sk, m)) return 0;
+    return plan_bytes(1) + problem_layout(op, sk, m, basis_dtype == RTG_BF16).total;
+}
+
+int rtg_workspace_layout(rtg_op op, rtg_sk sk, int m, int basis_dtype, size_t* v_offset, size_t* sv_offset) {
+    int rc = check_pair(op, sk);
+    if (rc) return rc;
+    if ((rc = check_m(sk, m))) return rc;
+    Layout L = problem_layout(op, sk, m, basis_dtype == RTG_BF16);
+    if (v_offset) *v_offset = plan_bytes(1) + L.V;
+    if (sv_offset) *sv_offset = plan_bytes(1) + L.SV;
+    return RTG_OK;
+}
+
+int rtg_arnoldi(rtg_op op, rtg_sk sk, const float* R0, int m, int basis_dtype, double bd_tol, void* ws,
+                size_t ws_bytes, double* H, double* beta, int* m_done, void* stream) {
+    int rc = check_pair(op, sk);
+    if (rc) return rc;
+    if ((rc = check_m(sk, m))) return rc;
+    if (!R0 || !ws || !H || !beta || !m_done) return RTG_E_ARG;
+    if (basis_dtype != RTG_F32 && basis_dtype != RTG_BF16) return RTG_E_ARG;
+    if (!aligned16(R0) || !aligned16(ws) || !(bd_tol >= 0.0)) return RTG_E_ARG;
+    const int bf16 = basis_dtype == RTG_BF16;
+    if (ws_bytes < rtg_workspace_bytes(op, sk, m, basis_dtype)) return RTG_E_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    Layout L = problem_layout(op, sk, m, bf16);
+    std::vector<Desc> descs(1);
+    fill_desc(descs[0], op, sk, m, bf16, (char*)ws + plan_bytes(1), L);
+    descs[0].R0src = R0;
+    descs[0].bd_tol = bd_tol;
+    descs[0].m = m;
+    descs[0].keep_last = 1;
+    Plan plan;
+    if ((rc = build_plan(descs, ws, s, plan))) return rc;
+    // the last step also forms V_{m+1} (used by the Arnoldi relation):
+    // run one more normalisation than a solve needs
+    if ((rc = run_solver(plan, 1, m, bf16, false, false, true, s))) return rc;
+    RTG_HIP(launch_finish_arnoldi(plan.d_desc, H, beta, m_done, m, s));
+    return RTG_OK;
+}
+
+size_t rtg_batch_workspace_bytes(int count, const rtg_problem* probs) {
+    if (count < 1 || !probs) return 0;
+    size_t total = plan_bytes(count);
+    for (int p = 0; p < count; ++p) {
+        const rtg_problem& q = probs[p];
+        if (check_pair(q.op, q.sk) || check_m(q.sk, q.params.m)) return 0;
+        total += problem_layout(q.op, q.sk, q.params.m, q.params.basis_dtype == RTG_BF16).total;
+    }
+    return total;
+}
+
+int rtg_solve_batched(int count, const rtg_problem* probs, void* ws, size_t ws_bytes, void* stream) {
+    if (count < 1 || !probs || !ws || !aligned16(ws)) return RTG_E_ARG;
+    int bf16 = -1;
+    for (int p = 0; p < count; ++p) {
+        const rtg_problem& q = probs[p];
+        int rc = check_pair(q.op, q.sk);
+        if (rc) return rc;
+        if ((rc = check_m(q.sk, q.params.m))) return rc;
+        if ((rc = validate_params(&q.params))) return rc;
+        if (!q.C || !q.X || !q.info) return RTG_E_ARG;
+        if (!aligned16(q.C) || !aligned16(q.X) || (q.X0 && !aligned16(q.X0))) return RTG_E_ARG;
+        const int b = q.params.basis_dtype == RTG_BF16;
+        if (bf16 >= 0 && b != bf16) return RTG_E_ARG;     // one basis type per batch
+        bf16 = b;
+    }
+    const size_t need = rtg_batch_workspace_bytes(count, probs);
+    if (need == 0) return RTG_E_SHAPE;
+    if (ws_bytes < need) return RTG_E_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<Desc> descs(count);
+    size_t off = plan_bytes(count);
+    int mmax = 0;
+    bool any_x0 = false;
+    for (int p = 0; p < count; ++p) {
+        const rtg_problem& q = probs[p];
+        Layout L = problem_layout(q.op, q.sk, q.params.m, bf16);
+        Desc& d = descs[p];
+        fill_desc(d, q.op, q.sk, q.params.m, bf16, (char*)ws + off, L);
+        set_params(d, &q.params);
+        d.C = q.C;
+        d.X0 = q.X0;
+        d.X = q.X;
+        d.info = q.info;
+        d.R0src = q.X0 ? (const void*)d.W : (const void*)q.C;
+        off += L.total;
+        mmax = std::max(mmax, q.params.m);
+        any_x0 = any_x0 || q.X0 != nullptr;
+    }
+    Plan plan;
+    int rc = build_plan(descs, ws, s, plan);
+    if (rc) return rc;
+    return run_solver(plan, count, mmax, bf16, any_x0, true, false, s);
+}
+
+int rtg_event_timing_enable(int kind_mask) {
+    if (kind_mask < 0 || kind_mask >= (1 << NTIMED)) return RTG_E_ARG;
+    g_timing.mask = kind_mask;
+    return RTG_OK;
+}
+
+int rtg_event_timing_read(double* ms, long long* launches, int nkinds) {
+    if (nkinds < 0 || (nkinds > 0 && (!ms || !launches))) return RTG_E_ARG;
+    int rc = RTG_OK;
+    for (int k = 0; k < NTIMED; ++k) {
+        double total = 0.0;
+        long long cnt = 0;
+        for (auto& pr : g_timing.rec[k]) {
+            float t = 0.f;
+            if (hipEventSynchronize(pr.second) != hipSuccess ||
+                hipEventElapsedTime(&t, pr.first, pr.second) != hipSuccess)
+                rc = RTG_E_HIP;
+            total += t;
+            ++cnt;
+            g_timing.pool.push_back(pr.first);
+            g_timing.pool.push_back(pr.second);
+        }
+        g_timing.rec[k].clear();
+        if (k < nkinds) {
+            ms[k] = total;
+            launches[k] = cnt;
+        }
+    }
+    return rc;
+}
+
+int rtg_solve(rtg_op op, rtg_sk sk, const float* C, const float* X0, const rtg_params* params, void* ws,
+              size_t ws_bytes, float* X, rtg_info* info, void* stream) {
+    if (!params) return RTG_E_ARG;
+    rtg_problem q;
+    q.op = op; q.sk = sk; q.C = C; q.X0 = X0; q.X = X; q.params = *params; q.info = info;
+    return rtg_solve_batched(1, &q, ws, ws_bytes, stream);
+}
+
+}  // extern "C"
