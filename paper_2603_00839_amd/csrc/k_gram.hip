@@ -47,7 +47,7 @@ __device__ __forceinline__ void finish_sketch(const Desc& d, const float* __rest
             int t2 = 0;
             for (; t2 + 8 <= nt2; t2 += 8) {
 #pragma unroll
-                for (int u = 0; u < 8; ++u) Qp[u] += pc[(size_t)(t2 + u) * L12];
+                for (int u = 0; u < 8; ++u) Qp[u] += *gptr(pc + (size_t)(t2 + u) * L12);
             }
             for (; t2 < nt2; ++t2) Qp[0] += pc[(size_t)t2 * L12];
             const float Q = ((Qp[0] + Qp[1]) + (Qp[2] + Qp[3])) + ((Qp[4] + Qp[5]) + (Qp[6] + Qp[7]));
@@ -73,7 +73,7 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
     __shared__ float s_s[4096];
     __shared__ float s_v[4096];
     __shared__ double ds[2 * (MMAX + 2)];
-    __shared__ double h1s[MMAX], hs[MMAX], gnew[MMAX], Gh1[MMAX], Gh[MMAX];
+    __shared__ double h1s[MMAX], hs[MMAX], gnew[MMAX], Gh1[MMAX], Gh[MMAX], cs_s[MMAX], sn_s[MMAX];
     __shared__ int s_last;
 
     const int b = blockIdx.x;
@@ -109,41 +109,56 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
         for (int e = tid; e < E; e += 256) svj[e] = s_v[e];
     }
 
-    // ---- shares of the inner products (float64).  Items: <S(V_i), s> and
-    // <S(V_i), S(V_j)> for i < j, and ||s||^2.  Each wave takes groups of eight
-    // items (and unrolls over elements) so that many independent loads are in
-    // flight.
+    // ---- shares of the inner products (float64): <S(V_i), s> and
+    // <S(V_i), S(V_j)> for the stored S(V_i), i < j - 1 (from global memory,
+    // eight items per wave pass, branch-free so the loads overlap), then the
+    // newest tensor S(V_j) and ||s||^2 from LDS.
     const int nitems = (mode == GM_STEP) ? j + 1 : 1;
+    const int nglob = (mode == GM_STEP) ? j - 1 : 0;
     constexpr int IG = 8;
-    for (int it0 = wave * IG; it0 < nitems; it0 += 4 * IG) {
+    for (int it0 = wave * IG; it0 < nglob; it0 += 4 * IG) {
+        const float* svb = d.SV + (size_t)q0 * l3;
         double as[IG], av[IG];
 #pragma unroll
         for (int u = 0; u < IG; ++u) { as[u] = 0.0; av[u] = 0.0; }
-#pragma unroll 4
         for (int e = lane; e < E; e += 64) {
-            const double se = s_s[e];
-            const double ve = (mode == GM_STEP) ? (double)s_v[e] : 0.0;
+            const double se = s_s[e], ve = s_v[e];
+            float xv[IG];
+#pragma unroll
+            for (int u = 0; u < IG; ++u) xv[u] = *gptr(svb + (size_t)min(it0 + u, nglob - 1) * Lsz + e);
 #pragma unroll
             for (int u = 0; u < IG; ++u) {
-                const int it = it0 + u;
-                if (it >= nitems) break;
-                double x;
-                if (it == nitems - 1) { as[u] += se * se; continue; }
-                if (it == j - 1) x = ve;
-                else x = d.SV[(size_t)it * Lsz + (size_t)q0 * l3 + e];
-                as[u] += x * se;
-                av[u] += x * ve;
+                as[u] += (double)xv[u] * se;
+                av[u] += (double)xv[u] * ve;
             }
         }
 #pragma unroll
         for (int u = 0; u < IG; ++u) {
-            const int it = it0 + u;
-            if (it >= nitems) break;
             const double ra = wave_sum(as[u]);
             const double rv = wave_sum(av[u]);
-            if (lane == 0) {
-                d.dots[((size_t)wgi * (MMAX + 2) + it) * 2 + 0] = ra;
-                d.dots[((size_t)wgi * (MMAX + 2) + it) * 2 + 1] = rv;
+            if (lane == 0 && it0 + u < nglob) {
+                d.dots[((size_t)wgi * (MMAX + 2) + it0 + u) * 2 + 0] = ra;
+                d.dots[((size_t)wgi * (MMAX + 2) + it0 + u) * 2 + 1] = rv;
+            }
+        }
+    }
+    if (wave == 3) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+        for (int e = lane; e < E; e += 64) {
+            const double se = s_s[e], ve = s_v[e];
+            a0 += se * se;
+            a1 += ve * se;
+            a2 += ve * ve;
+        }
+        a0 = wave_sum(a0);
+        a1 = wave_sum(a1);
+        a2 = wave_sum(a2);
+        if (lane == 0) {
+            d.dots[((size_t)wgi * (MMAX + 2) + nitems - 1) * 2 + 0] = a0;
+            d.dots[((size_t)wgi * (MMAX + 2) + nitems - 1) * 2 + 1] = 0.0;
+            if (mode == GM_STEP) {
+                d.dots[((size_t)wgi * (MMAX + 2) + j - 1) * 2 + 0] = a1;
+                d.dots[((size_t)wgi * (MMAX + 2) + j - 1) * 2 + 1] = a2;
             }
         }
     }
@@ -160,9 +175,18 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
     if (!s_last) return;
     __threadfence();
     for (int x = tid; x < 2 * nitems; x += 256) {
-        double sum = 0.0;
-        for (int w = 0; w < nwg; ++w) sum += load_coherent(d.dots + ((size_t)w * (MMAX + 2) + x / 2) * 2 + (x & 1));
-        ds[x] = sum;
+        // fixed order over workgroups (deterministic); 8 loads in flight
+        double part[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) part[u] = 0.0;
+        const double* base = d.dots + (size_t)(x / 2) * 2 + (x & 1);
+        int w = 0;
+        for (; w + 8 <= nwg; w += 8) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) part[u] += load_coherent(base + (size_t)(w + u) * (MMAX + 2) * 2);
+        }
+        for (; w < nwg; ++w) part[0] += load_coherent(base + (size_t)w * (MMAX + 2) * 2);
+        ds[x] = ((part[0] + part[1]) + (part[2] + part[3])) + ((part[4] + part[5]) + (part[6] + part[7]));
     }
     __syncthreads();
     int* st = d.state;
@@ -206,20 +230,21 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
             double acc4[4] = {0.0, 0.0, 0.0, 0.0};
             for (int k = lane; k < j; k += 64) {
                 const double vk = v[k];
+                double gl[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) gl[u] = *gptr(d.G + (size_t)min(i0 + u, j - 1) * ldg + k);
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const int i = i0 + u;
-                    if (i >= j) break;
-                    const double gik = (i == jm) ? gnew[k] : (k == jm ? gnew[i] : d.G[(size_t)i * ldg + k]);
+                    const int i = min(i0 + u, j - 1);
+                    const double gik = (i == jm) ? gnew[k] : (k == jm ? gnew[i] : gl[u]);
                     acc4[u] += gik * vk;
                 }
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int i = i0 + u;
-                if (i >= j) break;
                 const double r = wave_sum(acc4[u]);
-                if (lane == 0) {
+                if (lane == 0 && i < j) {
                     out[i] = r;
                     if (make_h) hs[i] = 2.0 * h1s[i] - r;
                 }
@@ -227,6 +252,10 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
         }
     };
     gmatvec(h1s, Gh1, true);
+    for (int i = tid; i < jm; i += 256) {      // previous plane rotations, staged for the serial update
+        cs_s[i] = d.gv[i];
+        sn_s[i] = d.gv[m + i];
+    }
     __syncthreads();
     gmatvec(hs, Gh, false);
     __syncthreads();
@@ -255,8 +284,8 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
         double r_prev = hs[0];
         for (int i = 0; i < jm; ++i) {
             const double a = r_prev, bnext = hs[i + 1];
-            Rc[i] = cs[i] * a + sn[i] * bnext;
-            r_prev = -sn[i] * a + cs[i] * bnext;
+            Rc[i] = cs_s[i] * a + sn_s[i] * bnext;
+            r_prev = -sn_s[i] * a + cs_s[i] * bnext;
         }
         const double rr = hypot(r_prev, hn);
         const double cj = rr > 0.0 ? r_prev / rr : 1.0;

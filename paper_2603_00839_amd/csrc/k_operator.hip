@@ -104,15 +104,14 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int tile, float* smem
     auto load_slab = [&](int k) {
 #pragma unroll
         for (int it = 0; it < NLD; ++it) {
+            // unconditional load from a clamped address, masked afterwards
             const int e = tid + 256 * it;
             const int row = e % SR, c = e / SR;
             const int i1 = i10 - R + row, i2 = i20 - R + c;
-            float v = 0.f;
-            if (e < SR * SC && i1 >= 0 && i1 < I1 && i2 >= 0 && i2 < I2) {
-                const size_t off = (size_t)k * plane + (size_t)i2 * I1 + i1;
-                v = BF16IN ? bf2f(srch[off]) : srcf[off];
-            }
-            pre[it] = v;
+            const bool inb = e < SR * SC && i1 >= 0 && i1 < I1 && i2 >= 0 && i2 < I2;
+            const size_t off = (size_t)k * plane + (size_t)min(max(i2, 0), I2 - 1) * I1 + min(max(i1, 0), I1 - 1);
+            const float v = BF16IN ? bf2f(*gptr(srch + off)) : *gptr(srcf + off);
+            pre[it] = inb ? v : 0.f;
         }
     };
     load_slab(klo);
@@ -179,8 +178,8 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int tile, float* smem
                 if (i2 < I2) {
                     size_t off = (size_t)(j0 + jj) * plane + (size_t)i2 * I1 + i1;
                     float v = acc[jj][o];
-                    if (a.C) v = a.C[off] - v;
-                    a.dst[off] = v;
+                    if (a.C) v = *gptr(a.C + off) - v;
+                    *gptr_w(a.dst + off) = v;
                 }
             }
         }

@@ -80,32 +80,40 @@ __global__ void __launch_bounds__(1024) k_solve(const Desc* __restrict__ descs) 
     const double gam = fabs(gvec[k]);
     __syncthreads();
 
-    // ---- one-sided Jacobi, round-robin (circle) ordering of column pairs
+    // ---- one-sided Jacobi, round-robin (circle) ordering of column pairs.
+    // Sixteen lanes handle one pair (k <= 96: at most six rows per lane), so
+    // all pairs of a round (k/2 <= 48 <= 64 groups) rotate concurrently.
     const int nb = k + (k & 1);
+    const int grp = tid >> 4, gl = tid & 15, ngrp = blockDim.x >> 4;
     for (int sweep = 0; sweep < 60; ++sweep) {
         if (tid == 0) s_rot = 0;
         __syncthreads();
         for (int rd = 0; rd < nb - 1; ++rd) {
-            for (int pi = wave; pi < nb / 2; pi += nwave) {
-                const int pos_a = pi, pos_b = nb - 1 - pi;
-                const int pa = pos_a == 0 ? 0 : 1 + (pos_a - 1 + rd) % (nb - 1);
-                const int pb = pos_b == 0 ? 0 : 1 + (pos_b - 1 + rd) % (nb - 1);
-                if (pa >= k || pb >= k) continue;
+            for (int pi = grp; pi < nb / 2; pi += ngrp) {
+                const int pos_b = nb - 1 - pi;
+                const int pa = pi == 0 ? 0 : 1 + (pi - 1 + rd) % (nb - 1);
+                const int pb = 1 + (pos_b - 1 + rd) % (nb - 1);
+                if (pa >= k || pb >= k) continue;      // uniform within the 16-lane group
                 double* ca = As + pa * LD;
                 double* cb = As + pb * LD;
                 double al = 0.0, be = 0.0, ga = 0.0;
-                for (int r = lane; r < k; r += 64) {
+                for (int r = gl; r < k; r += 16) {
                     const double x = ca[r], y = cb[r];
                     al += x * x; be += y * y; ga += x * y;
                 }
-                al = wave_sum(al); be = wave_sum(be); ga = wave_sum(ga);
+#pragma unroll
+                for (int off = 8; off > 0; off >>= 1) {
+                    al += __shfl_xor(al, off, 16);
+                    be += __shfl_xor(be, off, 16);
+                    ga += __shfl_xor(ga, off, 16);
+                }
                 if (ga != 0.0 && fabs(ga) > JACOBI_TOL * sqrt(al * be)) {
                     const double zeta = (be - al) / (2.0 * ga);
                     const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
                     const double cth = 1.0 / sqrt(1.0 + t * t), sth = cth * t;
                     double* wa = Ws + pa * LD;
                     double* wb = Ws + pb * LD;
-                    for (int r = lane; r < k; r += 64) {
+                    for (int r = gl; r < k; r += 16) {
                         const double x = ca[r], y = cb[r];
                         ca[r] = cth * x - sth * y;
                         cb[r] = sth * x + cth * y;
@@ -113,7 +121,7 @@ __global__ void __launch_bounds__(1024) k_solve(const Desc* __restrict__ descs) 
                         wa[r] = cth * u - sth * v;
                         wb[r] = sth * u + cth * v;
                     }
-                    if (lane == 0) s_rot = 1;
+                    if (gl == 0) s_rot = 1;
                 }
             }
             __syncthreads();

@@ -29,12 +29,13 @@ namespace rtg {
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u2 __attribute__((ext_vector_type(2)));
 
 template <int RC>
 __device__ __forceinline__ void load_f32(const float* p, float* x) {
 #pragma unroll
     for (int q = 0; q < RC; q += 4) {
-        f4 v = *(const f4*)(p + q);
+        f4 v = *gptr((const f4*)(p + q));
         x[q] = v[0]; x[q + 1] = v[1]; x[q + 2] = v[2]; x[q + 3] = v[3];
     }
 }
@@ -42,16 +43,16 @@ __device__ __forceinline__ void load_f32(const float* p, float* x) {
 template <int RC>
 __device__ __forceinline__ void load_bf16(const bf16_t* p, float* x) {
     if constexpr (RC == 8) {
-        u4 v = *(const u4*)p;
+        u4 v = *gptr((const u4*)p);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             x[2 * q] = __uint_as_float(v[q] << 16);
             x[2 * q + 1] = __uint_as_float(v[q] & 0xffff0000u);
         }
     } else {
-        uint2 v = *(const uint2*)p;
-        x[0] = __uint_as_float(v.x << 16); x[1] = __uint_as_float(v.x & 0xffff0000u);
-        x[2] = __uint_as_float(v.y << 16); x[3] = __uint_as_float(v.y & 0xffff0000u);
+        u2 v = *gptr((const u2*)p);
+        x[0] = __uint_as_float(v[0] << 16); x[1] = __uint_as_float(v[0] & 0xffff0000u);
+        x[2] = __uint_as_float(v[1] << 16); x[3] = __uint_as_float(v[1] & 0xffff0000u);
     }
 }
 
@@ -134,45 +135,74 @@ __global__ void __launch_bounds__(256) k_tile(const Desc* __restrict__ descs,
 #pragma unroll
         for (int g = 0; g < 2; ++g) acc[rt][g] = f4{0.f, 0.f, 0.f, 0.f};
 
+    // Loads are unconditional from clamped (always in-bounds) addresses and
+    // masked afterwards with a select: a branch per load would make the
+    // compiler wait for each load before the next one is issued.
     const int nsb = (I1 + SBR - 1) / SBR;
     for (int sb = 0; sb < nsb; ++sb) {
         float x[KPW][2][RC];
         bool ok[KPW][2];
+        int offs[KPW][2];             // element offsets from the tile start
         int row0[KPW];
 #pragma unroll
         for (int kb = 0; kb < KPW; ++kb) {
             row0[kb] = sb * SBR + (kb * 4 + wave) * KB + RC * kq;
+            const int rowc = min(row0[kb], I1 - RC);
 #pragma unroll
             for (int g = 0; g < 2; ++g) {
                 const int col = 16 * g + coll;
                 ok[kb][g] = (row0[kb] < I1) && (col < ncol);
-                const size_t off = tile_off + (size_t)col * I1 + row0[kb];
-                if (ok[kb][g] && src != nullptr) {
-                    if (src_is_bf) load_bf16<RC>((const bf16_t*)src + off, x[kb][g]);
-                    else load_f32<RC>((const float*)src + off, x[kb][g]);
-                } else {
-#pragma unroll
-                    for (int q = 0; q < RC; ++q) x[kb][g][q] = 0.f;
-                }
+                offs[kb][g] = min(col, ncol - 1) * I1 + rowc;
             }
         }
-        // multi-AXPY over the basis
-        for (int i = 0; i < nterms; ++i) {
-            const float ci = coef_s[i];
-            const char* vb = (const char*)d.V + (size_t)i * d.n * es;
+        if (src != nullptr) {
 #pragma unroll
             for (int kb = 0; kb < KPW; ++kb)
 #pragma unroll
                 for (int g = 0; g < 2; ++g) {
-                    if (!ok[kb][g]) continue;
-                    const size_t off = tile_off + (size_t)(16 * g + coll) * I1 + row0[kb];
-                    float v[RC];
-                    if (BB) load_bf16<RC>((const bf16_t*)vb + off, v);
-                    else load_f32<RC>((const float*)vb + off, v);
-#pragma unroll
-                    for (int q = 0; q < RC; ++q) x[kb][g][q] = fmaf(-ci, v[q], x[kb][g][q]);
+                    if (src_is_bf) load_bf16<RC>((const bf16_t*)src + tile_off + offs[kb][g], x[kb][g]);
+                    else load_f32<RC>((const float*)src + tile_off + offs[kb][g], x[kb][g]);
                 }
+        } else {
+#pragma unroll
+            for (int kb = 0; kb < KPW; ++kb)
+#pragma unroll
+                for (int g = 0; g < 2; ++g)
+#pragma unroll
+                    for (int q = 0; q < RC; ++q) x[kb][g][q] = 0.f;
         }
+        // multi-AXPY over the basis, each term in two halves of K-blocks
+        for (int i = 0; i < nterms; ++i) {
+            const float ci = coef_s[i];
+            const char* vb = (const char*)d.V + ((size_t)i * d.n + tile_off) * es;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                float v[KPW / 2][2][RC];
+#pragma unroll
+                for (int kk = 0; kk < KPW / 2; ++kk)
+#pragma unroll
+                    for (int g = 0; g < 2; ++g) {
+                        const int kb = h * (KPW / 2) + kk;
+                        if (BB) load_bf16<RC>((const bf16_t*)vb + offs[kb][g], v[kk][g]);
+                        else load_f32<RC>((const float*)vb + offs[kb][g], v[kk][g]);
+                    }
+#pragma unroll
+                for (int kk = 0; kk < KPW / 2; ++kk)
+#pragma unroll
+                    for (int g = 0; g < 2; ++g)
+#pragma unroll
+                        for (int q = 0; q < RC; ++q) {
+                            const int kb = h * (KPW / 2) + kk;
+                            x[kb][g][q] = fmaf(-ci, v[kk][g][q], x[kb][g][q]);
+                        }
+            }
+        }
+#pragma unroll
+        for (int kb = 0; kb < KPW; ++kb)
+#pragma unroll
+            for (int g = 0; g < 2; ++g)
+#pragma unroll
+                for (int q = 0; q < RC; ++q) x[kb][g][q] = ok[kb][g] ? x[kb][g][q] : 0.f;
         // scale, round (bfloat16 basis) and store
         bf16_t h[KPW][2][BB ? RC : 1];
         if (do_store) {
@@ -185,7 +215,7 @@ __global__ void __launch_bounds__(256) k_tile(const Desc* __restrict__ descs,
 #pragma unroll
                     for (int q = 0; q < RC; ++q) x[kb][g][q] *= scale;
                     if (!ok[kb][g]) continue;
-                    const size_t off = tile_off + (size_t)(16 * g + coll) * I1 + row0[kb];
+                    const size_t off = tile_off + offs[kb][g];
                     if (out_bf) {
                         if constexpr (BB) {
                             u4 pk;
@@ -197,13 +227,13 @@ __global__ void __launch_bounds__(256) k_tile(const Desc* __restrict__ descs,
 #pragma unroll
                             for (int q = 0; q < 4; ++q)
                                 pk[q] = (unsigned)h[kb][g][2 * q] | ((unsigned)h[kb][g][2 * q + 1] << 16);
-                            *(u4*)((bf16_t*)dstb + off) = pk;
+                            *gptr_w((u4*)((bf16_t*)dstb + off)) = pk;
                         }
                     } else {
                         float* o = (float*)dstb + off;
 #pragma unroll
                         for (int q = 0; q < RC; q += 4)
-                            *(f4*)(o + q) = f4{x[kb][g][q], x[kb][g][q + 1], x[kb][g][q + 2], x[kb][g][q + 3]};
+                            *gptr_w((f4*)(o + q)) = f4{x[kb][g][q], x[kb][g][q + 1], x[kb][g][q + 2], x[kb][g][q + 3]};
                     }
                 }
         }
@@ -213,15 +243,18 @@ __global__ void __launch_bounds__(256) k_tile(const Desc* __restrict__ descs,
         // one is multiplied.
         auto load_a = [&](int kb, AFrag<BB>* A) {
             const bool rowok = row0[kb] < I1;
+            const int rowc = min(row0[kb], I1 - RC);
 #pragma unroll
             for (int rt = 0; rt < RTMAX; ++rt) {
                 const int a = 16 * rt + coll;
                 const bool okA = a < l1 && rowok;
+                const size_t off = (size_t)min(a, l1 - 1) * I1 + rowc;
                 if constexpr (!BB) {
-                    A[rt].v = okA ? *(const f4*)(d.om1 + (size_t)a * I1 + row0[kb]) : f4{0.f, 0.f, 0.f, 0.f};
+                    const f4 v = *gptr((const f4*)(d.om1 + off));
+                    A[rt].v = okA ? v : f4{0.f, 0.f, 0.f, 0.f};
                 } else {
-                    A[rt].v = __builtin_bit_cast(bf8, okA ? *(const u4*)(d.om1h + (size_t)a * I1 + row0[kb])
-                                                          : u4{0u, 0u, 0u, 0u});
+                    const u4 v = *gptr((const u4*)(d.om1h + off));
+                    A[rt].v = __builtin_bit_cast(bf8, okA ? v : u4{0u, 0u, 0u, 0u});
                 }
             }
         };
@@ -303,17 +336,23 @@ __global__ void __launch_bounds__(256) k_tile(const Desc* __restrict__ descs,
         f4 pacc = f4{0.f, 0.f, 0.f, 0.f};
         const int a = 16 * rt + coll;
         const int bcol = 16 * rt2 + coll;
+        // rows a >= l1 of Ys hold zeros; Om2 loads are clamped and masked
+        float Bv[TC / 4];
 #pragma unroll
         for (int ks = 0; ks < TC / 4; ++ks) {
             const int k = 4 * ks + kq;
-            const float A = (a < l1) ? Ys[a * TCP + k] : 0.f;
-            const float B = (bcol < l2 && k < ncol) ? d.om2[(size_t)bcol * I2 + i20 + k] : 0.f;
-            pacc = __builtin_amdgcn_mfma_f32_16x16x4f32(A, B, pacc, 0, 0, 0);
+            const float v = *gptr(d.om2 + (size_t)min(bcol, l2 - 1) * I2 + i20 + min(k, ncol - 1));
+            Bv[ks] = (bcol < l2 && k < ncol) ? v : 0.f;
+        }
+#pragma unroll
+        for (int ks = 0; ks < TC / 4; ++ks) {
+            const int k = 4 * ks + kq;
+            pacc = __builtin_amdgcn_mfma_f32_16x16x4f32(Ys[a * TCP + k], Bv[ks], pacc, 0, 0, 0);
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int ar = 16 * rt + 4 * kq + i;
-            if (ar < l1 && bcol < l2) P[(size_t)ar * l2 + bcol] = pacc[i];
+            if (ar < l1 && bcol < l2) *gptr_w(P + (size_t)ar * l2 + bcol) = pacc[i];
         }
     }
 }

@@ -116,6 +116,19 @@ __device__ __forceinline__ bf16_t f2bf(float f) {
     return (bf16_t)(x >> 16);
 }
 
+// Pointers read from descriptors are generic; loads through them become flat
+// instructions (which also count against the LDS wait counter).  Tensor data
+// always lives in device global memory, so cast to the global address space.
+#define RTG_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ const RTG_GLOBAL T* gptr(const T* p) {
+    return (const RTG_GLOBAL T*)p;
+}
+template <typename T>
+__device__ __forceinline__ RTG_GLOBAL T* gptr_w(T* p) {
+    return (RTG_GLOBAL T*)p;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
