@@ -163,6 +163,35 @@ size_t rtg_batch_workspace_bytes(int count, const rtg_problem* probs);
 int rtg_solve_batched(int count, const rtg_problem* probs, void* ws,
                       size_t ws_bytes, void* stream);
 
+/* ---- learned warm start ----------------------------------------------------
+ * X0 = C + f(C), f = six 3x3 zero-padded convolutions 3 -> 32 -> 32 -> 32 ->
+ * 32 -> 32 -> 3 with biases and ReLU after the first five (38,755
+ * parameters), computed with bfloat16 MFMA and float32 accumulation; float32
+ * master weights and Adam moments.  The warm start only changes X0: the
+ * RTG-GMRES solve that follows is the method itself and corrects it.
+ * Parameters cross the ABI as one HOST float array, layer after layer, each
+ * layer w[co][t1][t2][ci] (t1, t2 in 0..2: offsets -1..+1 along i1 and i2)
+ * followed by b[co].  Images are device arrays [N][3][I2][I1] (each the
+ * column-major tensor layout above).  state is a caller-owned device buffer
+ * of rtg_cnn_state_bytes(); ws of rtg_cnn_workspace_bytes(N, I1, I2). */
+size_t rtg_cnn_state_bytes(void);
+size_t rtg_cnn_workspace_bytes(int N, int I1, int I2);
+/* copy the parameters in, zero the moments (synchronous on stream) */
+int rtg_cnn_init(void* state, const float* params, void* stream);
+/* copy the float32 master parameters out (synchronous) */
+int rtg_cnn_export(const void* state, float* params, void* stream);
+/* X0 = C + f(C) */
+int rtg_cnn_forward(const void* state, const float* C, int N, int I1, int I2,
+                    float* X0, void* ws, size_t ws_bytes, void* stream);
+/* gradients of sum((X0 - Y)^2) / (3 N I1 I2) w.r.t. every parameter, kept
+ * in state; *loss (device float) receives the sum of squared errors */
+int rtg_cnn_gradients(void* state, const float* C, const float* Y, int N, int I1,
+                      int I2, void* ws, size_t ws_bytes, float* loss, void* stream);
+/* the gradients of the last rtg_cnn_gradients call, parameter layout (synchronous) */
+int rtg_cnn_read_gradients(const void* state, float* grads, void* stream);
+/* one Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias correction for step >= 1) */
+int rtg_cnn_adam(void* state, float lr, int step, void* stream);
+
 /* ---- measurement ----------------------------------------------------------
  * When enabled, every launch of the selected kernel kinds made by the solver
  * calls (bit k of kind_mask: 0 operator Phi, 1 multi-AXPY + sketch tile,

@@ -1,0 +1,613 @@
+// Warm-start network: six 3x3 "same" convolutions (3 -> 32 -> 32 -> 32 -> 32
+// -> 32 -> 3, ReLU after the first five, biases) with the residual output
+// X0 = C + f(C), trained on RTG-GMRES solutions with the mean squared error
+// and Adam.  All kernels are bfloat16 MFMA (v_mfma_f32_16x16x32_bf16) with
+// float32 accumulation; master weights and Adam moments are float32.
+//
+// Activations are NHWC bfloat16 with S in {8, 32} stored channels (the
+// 3-channel tensors are padded with zeros to 8 = 16 bytes per pixel); the
+// pixel index is i1 + I1 * i2 (i1 fastest, as in the solver's tensors).
+// Weights are stored as W[co][k], k = tap * S_in + ci, tap = 3 t1 + t2 with
+// t1, t2 the offsets + 1 along i1 and i2, rows padded to the MFMA tile (16 or
+// 32) and k padded to a multiple of 32 with zeros.
+//
+// Convolution (implicit GEMM): D[co][pixel] = sum_k W[co][k] patch[k][pixel];
+// the MFMA A operand is a weight row (from LDS), the B operand the lane's
+// pixel with 8 consecutive k (one tap, 8 channels: one 16-byte load).
+// Epilogues: bias + ReLU (hidden layers); X0 = C + out (inference);
+// X0, squared error and the loss gradient (training); for the backward data
+// pass the same kernel runs on flipped, transposed weights and masks the
+// result with the ReLU of the layer input.
+// Weight gradient: dW[co][tap, ci] = sum_pixels g[pixel][co] x[pixel + tap][ci]
+// on MFMA with K = pixels (both operands staged transposed in LDS), per-
+// workgroup partials reduced in a fixed order (deterministic).
+#include "rtg_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+namespace rtg {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+
+enum ConvMode { CV_HIDDEN = 0, CV_LAST_INFER = 1, CV_LAST_TRAIN = 2, CV_BWD_DATA = 3 };
+
+constexpr int kpad_of(int s) { return ((9 * s + 31) / 32) * 32; }
+
+struct ConvArgs {
+    int N, I1, I2;
+    const bf16_t* x;      // NHWC input
+    const bf16_t* w;      // [COUT_M][KPAD]
+    const float* bias;    // [COUT_M] (hidden / last layers)
+    bf16_t* out;          // NHWC output (activation or gradient)
+    const bf16_t* mask;   // backward data: layer input whose positivity masks the result
+    const float* C;       // last layer: observation, [N][3][I2][I1]
+    const float* Y;       // training: target, [N][3][I2][I1]
+    float* X0;            // inference: X0 = C + f(C), [N][3][I2][I1]
+    float* loss_part;     // training: per-workgroup sum of squared errors
+    float gscale;         // training: 2 / (number of target elements)
+};
+
+__device__ __forceinline__ bool bf_pos(bf16_t v) { return (v & 0x8000u) == 0 && (v & 0x7fffu) != 0; }
+
+template <int CIN_S, int COUT_M, int COUT_S, int MODE>
+__global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
+    constexpr int KPAD = kpad_of(CIN_S);
+    constexpr int KQ = KPAD / 32;
+    constexpr int KL = KPAD + 8;          // padded LDS row (bank spread), 16-byte multiple
+    constexpr int MT = COUT_M / 16;
+    __shared__ bf16_t Wl[COUT_M * KL];
+    __shared__ float red[4];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n16 = lane & 15, s = lane >> 4;
+    const int I1 = a.I1, I2 = a.I2;
+    for (int e = tid; e < COUT_M * (KPAD / 8); e += 256) {
+        const int row = e / (KPAD / 8), c8 = e % (KPAD / 8);
+        *(u4*)(Wl + row * KL + c8 * 8) = *gptr((const u4*)(a.w + (size_t)row * KPAD + c8 * 8));
+    }
+    const int nt1 = (I1 + 63) / 64, nt2 = (I2 + 3) / 4;
+    int b = blockIdx.x;
+    const int t1 = b % nt1;
+    b /= nt1;
+    const int t2 = b % nt2;
+    const int img = b / nt2;
+    const int i2 = t2 * 4 + wave;
+    const bool row_ok = i2 < I2;
+    const size_t plane = (size_t)I1 * I2;
+    __syncthreads();
+
+    float lsum = 0.f;
+    for (int nt = 0; nt < 4; ++nt) {
+        const int i1 = t1 * 64 + nt * 16 + n16;
+        const bool px_ok = row_ok && i1 < I1;
+        bf8 B[KQ];
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) {
+            const int k = 32 * q + 8 * s;
+            const int tap = k / CIN_S, ci0 = k % CIN_S;
+            const int y1 = i1 + tap / 3 - 1, y2 = i2 + tap % 3 - 1;
+            const bool ok = tap < 9 && y1 >= 0 && y1 < I1 && y2 >= 0 && y2 < I2 && row_ok;
+            const int c1 = min(max(y1, 0), I1 - 1), c2 = min(max(y2, 0), I2 - 1);
+            const u4 v = *gptr((const u4*)(a.x + (((size_t)img * I2 + c2) * I1 + c1) * CIN_S + ci0));
+            B[q] = __builtin_bit_cast(bf8, ok ? v : u4{0u, 0u, 0u, 0u});
+        }
+        f4 acc[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) acc[mt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < KQ; ++q)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const bf8 A = __builtin_bit_cast(bf8, *(const u4*)(Wl + (16 * mt + n16) * KL + 32 * q + 8 * s));
+                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B[q], acc[mt], 0, 0, 0);
+            }
+        if (!px_ok) continue;
+        const size_t pix = ((size_t)img * I2 + i2) * I1 + i1;
+        if constexpr (MODE == CV_HIDDEN || MODE == CV_BWD_DATA) {
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const int co0 = 16 * mt + 4 * s;
+                float v[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    v[i] = acc[mt][i];
+                    if constexpr (MODE == CV_HIDDEN) v[i] = fmaxf(v[i] + a.bias[co0 + i], 0.f);
+                }
+                if constexpr (MODE == CV_BWD_DATA) {
+                    const u2 mk = *gptr((const u2*)(a.mask + pix * COUT_S + co0));
+                    const bf16_t mb[4] = {(bf16_t)(mk[0] & 0xffffu), (bf16_t)(mk[0] >> 16),
+                                          (bf16_t)(mk[1] & 0xffffu), (bf16_t)(mk[1] >> 16)};
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) v[i] = bf_pos(mb[i]) ? v[i] : 0.f;
+                }
+                u2 pk;
+                pk[0] = (unsigned)f2bf(v[0]) | ((unsigned)f2bf(v[1]) << 16);
+                pk[1] = (unsigned)f2bf(v[2]) | ((unsigned)f2bf(v[3]) << 16);
+                *gptr_w((u2*)(a.out + pix * COUT_S + co0)) = pk;
+            }
+        } else {
+            // last layer: rows 0..2 of the first M tile are the three output channels
+            if (s == 0) {
+                float x0[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const size_t po = ((size_t)img * 3 + c) * plane + (size_t)i2 * I1 + i1;
+                    x0[c] = *gptr(a.C + po) + acc[0][c] + a.bias[c];
+                    if constexpr (MODE == CV_LAST_INFER) *gptr_w(a.X0 + po) = x0[c];
+                }
+                if constexpr (MODE == CV_LAST_TRAIN) {
+                    bf16_t gb[8];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const size_t po = ((size_t)img * 3 + c) * plane + (size_t)i2 * I1 + i1;
+                        const float dlt = x0[c] - *gptr(a.Y + po);
+                        lsum += dlt * dlt;
+                        gb[c] = f2bf(a.gscale * dlt);
+                    }
+#pragma unroll
+                    for (int c = 3; c < 8; ++c) gb[c] = 0;
+                    u4 pk;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) pk[q] = (unsigned)gb[2 * q] | ((unsigned)gb[2 * q + 1] << 16);
+                    *gptr_w((u4*)(a.out + pix * 8)) = pk;
+                }
+            }
+        }
+    }
+    if constexpr (MODE == CV_LAST_TRAIN) {
+        lsum = wave_sum(lsum);
+        if (lane == 0) red[wave] = lsum;
+        __syncthreads();
+        if (tid == 0) a.loss_part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+    }
+}
+
+struct WgradArgs {
+    int N, I1, I2, rows;  // rows (i2) per workgroup
+    const bf16_t* g;      // NHWC gradient at the layer output (COUT_S channels)
+    const bf16_t* x;      // NHWC layer input (CIN_S channels)
+    float* part;          // [workgroups][COUT_M * KPAD + COUT_M]
+};
+
+template <int CIN_S, int COUT_S, int COUT_M>
+__global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
+    constexpr int KPAD = kpad_of(CIN_S);
+    constexpr int TAPS = KPAD / CIN_S;    // 9, or 12 with zero padding
+    constexpr int NT = KPAD / 16, MT = COUT_M / 16;
+    constexpr int TILES = NT * MT;
+    constexpr int SLOTS = (TILES + 3) / 4;
+    constexpr int PX = 32, PXL = PX + 8;  // pixels per chunk, padded LDS row
+    __shared__ bf16_t gT[COUT_M * PXL];
+    __shared__ bf16_t xs[TAPS * CIN_S * PXL];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n16 = lane & 15, s = lane >> 4;
+    const int I1 = a.I1, I2 = a.I2;
+    const int ngrp = (I2 + a.rows - 1) / a.rows;
+    const int img = blockIdx.x / ngrp;
+    const int r0 = (blockIdx.x % ngrp) * a.rows;
+
+    for (int e = tid; e < COUT_M * PXL; e += 256) gT[e] = 0;
+    f4 acc[SLOTS];
+#pragma unroll
+    for (int u = 0; u < SLOTS; ++u) acc[u] = f4{0.f, 0.f, 0.f, 0.f};
+    float dbacc = 0.f;
+
+    for (int i2 = r0; i2 < min(r0 + a.rows, I2); ++i2) {
+        for (int c0 = 0; c0 < I1; c0 += PX) {
+            __syncthreads();
+            // stage g^T: rows co < COUT_S (rows beyond stay zero)
+            for (int e = tid; e < PX * (COUT_S / 8); e += 256) {
+                const int px = e % PX, c8 = e / PX;
+                const int i1 = c0 + px;
+                const bool ok = i1 < I1;
+                const u4 v = *gptr((const u4*)(a.g + (((size_t)img * I2 + i2) * I1 + min(i1, I1 - 1)) * COUT_S + c8 * 8));
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    gT[(c8 * 8 + 2 * t) * PXL + px] = ok ? (bf16_t)(v[t] & 0xffffu) : (bf16_t)0;
+                    gT[(c8 * 8 + 2 * t + 1) * PXL + px] = ok ? (bf16_t)(v[t] >> 16) : (bf16_t)0;
+                }
+            }
+            // stage the shifted input for every tap: xs[tap][ci][px] = x[i1 + t1 - 1, i2 + t2 - 1][ci]
+            for (int e = tid; e < TAPS * PX * (CIN_S / 8); e += 256) {
+                const int px = e % PX;
+                const int r = e / PX;
+                const int c8 = r % (CIN_S / 8), tap = r / (CIN_S / 8);
+                const int y1 = c0 + px + tap / 3 - 1, y2 = i2 + tap % 3 - 1;
+                const bool ok = tap < 9 && c0 + px < I1 && y1 >= 0 && y1 < I1 && y2 >= 0 && y2 < I2;
+                const int c1 = min(max(y1, 0), I1 - 1), c2 = min(max(y2, 0), I2 - 1);
+                const u4 v = *gptr((const u4*)(a.x + (((size_t)img * I2 + c2) * I1 + c1) * CIN_S + c8 * 8));
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    xs[(tap * CIN_S + c8 * 8 + 2 * t) * PXL + px] = ok ? (bf16_t)(v[t] & 0xffffu) : (bf16_t)0;
+                    xs[(tap * CIN_S + c8 * 8 + 2 * t + 1) * PXL + px] = ok ? (bf16_t)(v[t] >> 16) : (bf16_t)0;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < SLOTS; ++u) {
+                const int t = wave + 4 * u;
+                if (t < TILES) {
+                    const int mt = t / NT, nt = t % NT;
+                    const bf8 A = __builtin_bit_cast(bf8, *(const u4*)(gT + (16 * mt + n16) * PXL + 8 * s));
+                    const bf8 B = __builtin_bit_cast(bf8, *(const u4*)(xs + (16 * nt + n16) * PXL + 8 * s));
+                    acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B, acc[u], 0, 0, 0);
+                }
+            }
+            if (tid < COUT_M) {
+                for (int px = 0; px < PX; ++px) dbacc += bf2f(gT[tid * PXL + px]);
+            }
+        }
+    }
+    float* part = a.part + (size_t)blockIdx.x * (COUT_M * KPAD + COUT_M);
+#pragma unroll
+    for (int u = 0; u < SLOTS; ++u) {
+        const int t = wave + 4 * u;
+        if (t < TILES) {
+            const int mt = t / NT, nt = t % NT;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                *gptr_w(part + (size_t)(16 * mt + 4 * s + i) * KPAD + 16 * nt + n16) = acc[u][i];
+        }
+    }
+    if (tid < COUT_M) *gptr_w(part + COUT_M * KPAD + tid) = dbacc;
+}
+
+// out[e] = sum over parts in a fixed order (deterministic)
+__global__ void k_reduce_parts(const float* __restrict__ part, int nparts, int len, float* __restrict__ out) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= len) return;
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    int w = 0;
+    for (; w + 8 <= nparts; w += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u] += *gptr(part + (size_t)(w + u) * len + e);
+    }
+    for (; w < nparts; ++w) acc[0] += *gptr(part + (size_t)w * len + e);
+    out[e] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+}
+
+// planar float32 [N][3][I2][I1] -> NHWC bfloat16 with 8 stored channels
+__global__ void k_pack(const float* __restrict__ X, int N, int I1, int I2, bf16_t* __restrict__ out) {
+    const size_t plane = (size_t)I1 * I2;
+    const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= (size_t)N * plane) return;
+    const size_t img = p / plane, r = p % plane;
+    bf16_t v[8];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[c] = f2bf(*gptr(X + (img * 3 + c) * plane + r));
+#pragma unroll
+    for (int c = 3; c < 8; ++c) v[c] = 0;
+    u4 pk;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) pk[q] = (unsigned)v[2 * q] | ((unsigned)v[2 * q + 1] << 16);
+    *gptr_w((u4*)(out + p * 8)) = pk;
+}
+
+// Adam on a float32 array (bias-corrected; c1 = 1 - b1^t, c2 = 1 - b2^t)
+__global__ void k_adam(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
+                       const float* __restrict__ g, int n, float lr, float b1, float b2, float eps,
+                       float c1, float c2) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const float ge = g[e];
+    const float me = b1 * m[e] + (1.f - b1) * ge;
+    const float ve = b2 * v[e] + (1.f - b2) * ge * ge;
+    m[e] = me;
+    v[e] = ve;
+    p[e] -= lr * (me / c1) / (sqrtf(ve / c2) + eps);
+}
+
+// bfloat16 working copies of a layer: W (as stored) and the flipped,
+// transposed weights of the backward data pass,
+// Wt[ci][tap' * S_out + co] = W[co][(8 - tap') * S_in + ci].
+__global__ void k_make_weights(const float* __restrict__ W, int cout_m, int kpad, int s_in,
+                               bf16_t* __restrict__ Wh, bf16_t* __restrict__ Wt, int s_out, int kpad_t) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < cout_m * kpad) Wh[e] = f2bf(W[e]);
+    if (Wt != nullptr && e < 32 * kpad_t) {
+        const int ci = e / kpad_t, k = e % kpad_t;
+        const int tapp = k / s_out, co = k % s_out;
+        float v = 0.f;
+        if (tapp < 9 && co < cout_m && ci < s_in) v = W[(size_t)co * kpad + (8 - tapp) * s_in + ci];
+        Wt[e] = f2bf(v);
+    }
+}
+
+}  // namespace rtg
+
+// ---------------------------------------------------------------------------
+// host side: network state, workspace and the C ABI
+// ---------------------------------------------------------------------------
+namespace {
+using namespace rtg;
+
+struct LayerDef {
+    int cin, cout, s_in, s_out, cout_m;
+};
+constexpr int NL = 6;
+const LayerDef LAYERS[NL] = {
+    {3, 32, 8, 32, 32}, {32, 32, 32, 32, 32}, {32, 32, 32, 32, 32},
+    {32, 32, 32, 32, 32}, {32, 32, 32, 32, 32}, {32, 3, 32, 8, 16}};
+
+size_t al(size_t x) { return (x + 255) / 256 * 256; }
+
+struct LayerOff {
+    size_t W, b, mW, vW, mb, vb, gW, gb, Wh, Wt;
+    int kpad, kpad_t, nw, nb;
+};
+
+struct StateLayout {
+    LayerOff L[NL];
+    size_t total;
+};
+
+StateLayout state_layout() {
+    StateLayout S{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) { off = al(off); size_t at = off; off += bytes; return at; };
+    for (int l = 0; l < NL; ++l) {
+        const LayerDef& d = LAYERS[l];
+        LayerOff& o = S.L[l];
+        o.kpad = kpad_of(d.s_in);
+        o.kpad_t = kpad_of(d.s_out);
+        o.nw = d.cout_m * o.kpad;
+        o.nb = d.cout_m;
+        o.W = take(o.nw * 4);
+        o.b = take(o.nb * 4);
+        o.mW = take(o.nw * 4);
+        o.vW = take(o.nw * 4);
+        o.mb = take(o.nb * 4);
+        o.vb = take(o.nb * 4);
+        o.gW = take((o.nw + o.nb) * 4);        // gradient of W followed by that of b
+        o.gb = o.gW + (size_t)o.nw * 4;
+        o.Wh = take(o.nw * 2);
+        o.Wt = take((size_t)32 * o.kpad_t * 2);
+    }
+    S.total = al(off);
+    return S;
+}
+
+constexpr int WG_ROWS = 8;
+
+struct WsLayout {
+    size_t xin, act[NL - 1], g8, gA, gB, part, loss, total;
+    int nconv, nwg;
+};
+
+WsLayout ws_layout(int N, int I1, int I2) {
+    WsLayout W{};
+    const size_t px = (size_t)N * I1 * I2;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { off = al(off); size_t at = off; off += bytes; return at; };
+    W.xin = take(px * 8 * 2);
+    for (int l = 0; l < NL - 1; ++l) W.act[l] = take(px * 32 * 2);
+    W.g8 = take(px * 8 * 2);
+    W.gA = take(px * 32 * 2);
+    W.gB = take(px * 32 * 2);
+    W.nconv = N * ((I2 + 3) / 4) * ((I1 + 63) / 64);
+    W.nwg = N * ((I2 + WG_ROWS - 1) / WG_ROWS);
+    W.part = take((size_t)W.nwg * (32 * kpad_of(32) + 32) * 4);
+    W.loss = take((size_t)W.nconv * 4 + 4);
+    W.total = al(off);
+    return W;
+}
+
+template <int CIN_S, int COUT_M, int COUT_S, int MODE>
+hipError_t conv(const ConvArgs& a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_conv<CIN_S, COUT_M, COUT_S, MODE>), dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int CIN_S, int COUT_S, int COUT_M>
+hipError_t wgrad(const WgradArgs& a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_wgrad<CIN_S, COUT_S, COUT_M>), dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// forward of layer l (0-based) into out / X0
+hipError_t layer_forward(int l, char* st, const StateLayout& S, const bf16_t* x, bf16_t* out, const float* C,
+                         const float* Y, float* X0, float* loss_part, float gscale, int N, int I1, int I2,
+                         int grid, bool train, hipStream_t s) {
+    const LayerOff& o = S.L[l];
+    ConvArgs a{};
+    a.N = N; a.I1 = I1; a.I2 = I2;
+    a.x = x;
+    a.w = (const bf16_t*)(st + o.Wh);
+    a.bias = (const float*)(st + o.b);
+    a.out = out;
+    a.C = C; a.Y = Y; a.X0 = X0; a.loss_part = loss_part; a.gscale = gscale;
+    if (l == 0) return conv<8, 32, 32, CV_HIDDEN>(a, grid, s);
+    if (l < NL - 1) return conv<32, 32, 32, CV_HIDDEN>(a, grid, s);
+    if (train) return conv<32, 16, 8, CV_LAST_TRAIN>(a, grid, s);
+    return conv<32, 16, 8, CV_LAST_INFER>(a, grid, s);
+}
+
+int check_dims(int N, int I1, int I2) {
+    if (N < 1 || I1 < 1 || I2 < 1) return RTG_E_SHAPE;
+    return RTG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t rtg_cnn_state_bytes(void) { return state_layout().total; }
+
+size_t rtg_cnn_workspace_bytes(int N, int I1, int I2) {
+    if (check_dims(N, I1, I2)) return 0;
+    return ws_layout(N, I1, I2).total;
+}
+
+int rtg_cnn_init(void* state, const float* params, void* stream) {
+    if (!state || !params) return RTG_E_ARG;
+    const StateLayout S = state_layout();
+    std::vector<unsigned char> host(S.total, 0);
+    size_t pi = 0;
+    for (int l = 0; l < NL; ++l) {
+        const LayerDef& d = LAYERS[l];
+        const LayerOff& o = S.L[l];
+        float* W = (float*)(host.data() + o.W);
+        float* b = (float*)(host.data() + o.b);
+        for (int co = 0; co < d.cout; ++co)
+            for (int t1 = 0; t1 < 3; ++t1)
+                for (int t2 = 0; t2 < 3; ++t2)
+                    for (int ci = 0; ci < d.cin; ++ci)
+                        W[(size_t)co * o.kpad + (t1 * 3 + t2) * d.s_in + ci] = params[pi++];
+        for (int co = 0; co < d.cout; ++co) b[co] = params[pi++];
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemcpyAsync(state, host.data(), S.total, hipMemcpyHostToDevice, s) != hipSuccess) return RTG_E_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return RTG_E_HIP;
+    for (int l = 0; l < NL; ++l) {
+        const LayerDef& d = LAYERS[l];
+        const LayerOff& o = S.L[l];
+        char* st = (char*)state;
+        const int n = std::max(o.nw, 32 * o.kpad_t);
+        hipLaunchKernelGGL(k_make_weights, dim3((n + 255) / 256), dim3(256), 0, s, (const float*)(st + o.W),
+                           d.cout_m, o.kpad, d.s_in, (bf16_t*)(st + o.Wh), l > 0 ? (bf16_t*)(st + o.Wt) : nullptr,
+                           d.s_out, o.kpad_t);
+    }
+    return hipGetLastError() == hipSuccess ? RTG_OK : RTG_E_HIP;
+}
+
+static int export_arrays(const void* state, float* out, bool grads) {
+    const StateLayout S = state_layout();
+    std::vector<unsigned char> host(S.total);
+    if (hipMemcpy(host.data(), state, S.total, hipMemcpyDeviceToHost) != hipSuccess) return RTG_E_HIP;
+    size_t pi = 0;
+    for (int l = 0; l < NL; ++l) {
+        const LayerDef& d = LAYERS[l];
+        const LayerOff& o = S.L[l];
+        const float* W = (const float*)(host.data() + (grads ? o.gW : o.W));
+        const float* b = (const float*)(host.data() + (grads ? o.gb : o.b));
+        for (int co = 0; co < d.cout; ++co)
+            for (int t1 = 0; t1 < 3; ++t1)
+                for (int t2 = 0; t2 < 3; ++t2)
+                    for (int ci = 0; ci < d.cin; ++ci)
+                        out[pi++] = W[(size_t)co * o.kpad + (t1 * 3 + t2) * d.s_in + ci];
+        for (int co = 0; co < d.cout; ++co) out[pi++] = b[co];
+    }
+    return RTG_OK;
+}
+
+int rtg_cnn_export(const void* state, float* params, void* stream) {
+    if (!state || !params) return RTG_E_ARG;
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return RTG_E_HIP;
+    return export_arrays(state, params, false);
+}
+
+int rtg_cnn_read_gradients(const void* state, float* grads, void* stream) {
+    if (!state || !grads) return RTG_E_ARG;
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return RTG_E_HIP;
+    return export_arrays(state, grads, true);
+}
+
+int rtg_cnn_forward(const void* state, const float* C, int N, int I1, int I2, float* X0, void* ws,
+                    size_t ws_bytes, void* stream) {
+    if (!state || !C || !X0 || !ws) return RTG_E_ARG;
+    if (check_dims(N, I1, I2)) return RTG_E_SHAPE;
+    const WsLayout W = ws_layout(N, I1, I2);
+    if (ws_bytes < W.total) return RTG_E_WORKSPACE;
+    const StateLayout S = state_layout();
+    hipStream_t s = (hipStream_t)stream;
+    char* w = (char*)ws;
+    char* st = (char*)state;
+    const size_t px = (size_t)N * I1 * I2;
+    hipLaunchKernelGGL(k_pack, dim3((px + 255) / 256), dim3(256), 0, s, C, N, I1, I2, (bf16_t*)(w + W.xin));
+    const bf16_t* x = (const bf16_t*)(w + W.xin);
+    for (int l = 0; l < NL; ++l) {
+        bf16_t* out = l < NL - 1 ? (bf16_t*)(w + W.act[l % 2]) : nullptr;
+        if (layer_forward(l, st, S, x, out, C, nullptr, X0, nullptr, 0.f, N, I1, I2, W.nconv, false, s) !=
+            hipSuccess)
+            return RTG_E_HIP;
+        x = out;
+    }
+    return RTG_OK;
+}
+
+int rtg_cnn_gradients(void* state, const float* C, const float* Y, int N, int I1, int I2, void* ws,
+                      size_t ws_bytes, float* loss, void* stream) {
+    if (!state || !C || !Y || !ws || !loss) return RTG_E_ARG;
+    if (check_dims(N, I1, I2)) return RTG_E_SHAPE;
+    const WsLayout W = ws_layout(N, I1, I2);
+    if (ws_bytes < W.total) return RTG_E_WORKSPACE;
+    const StateLayout S = state_layout();
+    hipStream_t s = (hipStream_t)stream;
+    char* w = (char*)ws;
+    char* st = (char*)state;
+    const size_t px = (size_t)N * I1 * I2;
+    const float gscale = 2.0f / (float)(px * 3);
+    hipLaunchKernelGGL(k_pack, dim3((px + 255) / 256), dim3(256), 0, s, C, N, I1, I2, (bf16_t*)(w + W.xin));
+    // forward, keeping every hidden activation
+    const bf16_t* acts[NL];
+    acts[0] = (const bf16_t*)(w + W.xin);
+    for (int l = 0; l < NL; ++l) {
+        bf16_t* out = l < NL - 1 ? (bf16_t*)(w + W.act[l]) : (bf16_t*)(w + W.g8);
+        if (layer_forward(l, st, S, acts[l], out, C, Y, nullptr, (float*)(w + W.loss), gscale, N, I1, I2,
+                          W.nconv, true, s) != hipSuccess)
+            return RTG_E_HIP;
+        if (l < NL - 1) acts[l + 1] = out;
+    }
+    // loss = mean squared error (sum of per-workgroup partials / elements)
+    hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(64), 0, s, (const float*)(w + W.loss), W.nconv, 1, loss);
+    // backward
+    const bf16_t* g = (const bf16_t*)(w + W.g8);
+    for (int l = NL - 1; l >= 0; --l) {
+        const LayerOff& o = S.L[l];
+        WgradArgs wa{N, I1, I2, WG_ROWS, g, acts[l], (float*)(w + W.part)};
+        hipError_t e;
+        if (l == 0) e = wgrad<8, 32, 32>(wa, W.nwg, s);
+        else if (l < NL - 1) e = wgrad<32, 32, 32>(wa, W.nwg, s);
+        else e = wgrad<32, 8, 16>(wa, W.nwg, s);
+        if (e != hipSuccess) return RTG_E_HIP;
+        const int len = o.nw + o.nb;
+        hipLaunchKernelGGL(k_reduce_parts, dim3((len + 255) / 256), dim3(256), 0, s, (const float*)(w + W.part),
+                           W.nwg, len, (float*)(st + o.gW));
+        if (l > 0) {
+            // gradient w.r.t. the layer input, masked by the ReLU of that input
+            ConvArgs a{};
+            a.N = N; a.I1 = I1; a.I2 = I2;
+            a.x = g;
+            a.w = (const bf16_t*)(st + o.Wt);
+            a.mask = acts[l];
+            bf16_t* gout = (bf16_t*)(w + ((l % 2) ? W.gA : W.gB));
+            a.out = gout;
+            if (l == NL - 1) e = conv<8, 32, 32, CV_BWD_DATA>(a, W.nconv, s);
+            else e = conv<32, 32, 32, CV_BWD_DATA>(a, W.nconv, s);
+            if (e != hipSuccess) return RTG_E_HIP;
+            g = gout;
+        }
+    }
+    return hipGetLastError() == hipSuccess ? RTG_OK : RTG_E_HIP;
+}
+
+int rtg_cnn_adam(void* state, float lr, int step, void* stream) {
+    if (!state || step < 1) return RTG_E_ARG;
+    const StateLayout S = state_layout();
+    hipStream_t s = (hipStream_t)stream;
+    char* st = (char*)state;
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+    for (int l = 0; l < NL; ++l) {
+        const LayerDef& d = LAYERS[l];
+        const LayerOff& o = S.L[l];
+        hipLaunchKernelGGL(k_adam, dim3((o.nw + 255) / 256), dim3(256), 0, s, (float*)(st + o.W), (float*)(st + o.mW),
+                           (float*)(st + o.vW), (const float*)(st + o.gW), o.nw, lr, b1, b2, eps, c1, c2);
+        hipLaunchKernelGGL(k_adam, dim3(1), dim3(64), 0, s, (float*)(st + o.b), (float*)(st + o.mb),
+                           (float*)(st + o.vb), (const float*)(st + o.gb), o.nb, lr, b1, b2, eps, c1, c2);
+        const int n = std::max(o.nw, 32 * o.kpad_t);
+        hipLaunchKernelGGL(k_make_weights, dim3((n + 255) / 256), dim3(256), 0, s, (const float*)(st + o.W),
+                           d.cout_m, o.kpad, d.s_in, (bf16_t*)(st + o.Wh), l > 0 ? (bf16_t*)(st + o.Wt) : nullptr,
+                           d.s_out, o.kpad_t);
+    }
+    return hipGetLastError() == hipSuccess ? RTG_OK : RTG_E_HIP;
+}
+
+}  // extern "C"

@@ -75,6 +75,14 @@ def load_library():
         "rtg_solve": (c_int, [c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(Params), c_vp, c_sz, c_vp, c_vp, c_vp]),
         "rtg_batch_workspace_bytes": (c_sz, [c_int, ctypes.POINTER(Problem)]),
         "rtg_solve_batched": (c_int, [c_int, ctypes.POINTER(Problem), c_vp, c_sz, c_vp]),
+        "rtg_cnn_state_bytes": (c_sz, []),
+        "rtg_cnn_workspace_bytes": (c_sz, [c_int, c_int, c_int]),
+        "rtg_cnn_init": (c_int, [c_vp, fp, c_vp]),
+        "rtg_cnn_export": (c_int, [c_vp, fp, c_vp]),
+        "rtg_cnn_forward": (c_int, [c_vp, c_vp, c_int, c_int, c_int, c_vp, c_vp, c_sz, c_vp]),
+        "rtg_cnn_gradients": (c_int, [c_vp, c_vp, c_vp, c_int, c_int, c_int, c_vp, c_sz, c_vp, c_vp]),
+        "rtg_cnn_read_gradients": (c_int, [c_vp, fp, c_vp]),
+        "rtg_cnn_adam": (c_int, [c_vp, ctypes.c_float, c_int, c_vp]),
         "rtg_event_timing_enable": (c_int, [c_int]),
         "rtg_event_timing_read": (c_int, [ctypes.POINTER(c_d), ctypes.POINTER(ctypes.c_longlong), c_int]),
         "rtg_status_string": (ctypes.c_char_p, [c_int]),
@@ -387,3 +395,76 @@ def event_timing_read():
     n = (ctypes.c_longlong * 4)()
     _check(lib().rtg_event_timing_read(ms, n, 4), "rtg_event_timing_read")
     return {k: (ms[k], n[k]) for k in range(4)}
+
+
+# ---------------------------------------------------------------------------
+# learned warm start (network state lives in one device buffer)
+# ---------------------------------------------------------------------------
+N_CNN_PARAMS = 38755
+
+
+class WarmStartNet:
+    """Handle of the warm-start network state; parameters use the flat layout
+    of the C ABI (per layer w[co][t1][t2][ci] then b[co])."""
+
+    def __init__(self, params: np.ndarray, device="cuda"):
+        torch = _torch()
+        params = np.ascontiguousarray(params, dtype=np.float32)
+        if params.size != N_CNN_PARAMS:
+            raise RTGError(f"expected {N_CNN_PARAMS} parameters, got {params.size}")
+        self.state = torch.zeros(lib().rtg_cnn_state_bytes(), dtype=torch.uint8, device=device)
+        self.step = 0
+        self._ws = None
+        self.loss = torch.zeros(1, dtype=torch.float32, device=device)
+        _check(lib().rtg_cnn_init(_ptr(self.state), _fptr(params), _stream()), "rtg_cnn_init")
+
+    def _workspace(self, N, I1, I2, device):
+        torch = _torch()
+        n = lib().rtg_cnn_workspace_bytes(N, I1, I2)
+        if self._ws is None or self._ws.numel() < n:
+            self._ws = torch.empty(n, dtype=torch.uint8, device=device)
+        return self._ws
+
+    def export(self) -> np.ndarray:
+        out = np.empty(N_CNN_PARAMS, dtype=np.float32)
+        _check(lib().rtg_cnn_export(_ptr(self.state), _fptr(out), _stream()), "rtg_cnn_export")
+        return out
+
+    def forward(self, C, out=None):
+        """C: device float32 (N, 3, I2, I1) or (3, I2, I1); returns X0 = C + f(C)."""
+        torch = _torch()
+        Cb = C if C.dim() == 4 else C.unsqueeze(0)
+        if not Cb.is_contiguous() or Cb.dtype != torch.float32 or Cb.shape[1] != 3:
+            raise RTGError("C must be contiguous float32 (N, 3, I2, I1)")
+        N, _, I2, I1 = Cb.shape
+        if out is None:
+            out = torch.empty_like(Cb)
+        ws = self._workspace(N, I1, I2, Cb.device)
+        _check(lib().rtg_cnn_forward(_ptr(self.state), _ptr(Cb), N, I1, I2, _ptr(out), _ptr(ws), ws.numel(),
+                                     _stream()), "rtg_cnn_forward")
+        return out if C.dim() == 4 else out[0]
+
+    infer = forward
+
+    def gradients(self, C, Y):
+        """Gradients of the mean squared error kept in the state; returns the
+        device tensor holding the sum of squared errors."""
+        N, _, I2, I1 = C.shape
+        ws = self._workspace(N, I1, I2, C.device)
+        _check(lib().rtg_cnn_gradients(_ptr(self.state), _ptr(C), _ptr(Y), N, I1, I2, _ptr(ws), ws.numel(),
+                                       _ptr(self.loss), _stream()), "rtg_cnn_gradients")
+        return self.loss
+
+    def read_gradients(self) -> np.ndarray:
+        out = np.empty(N_CNN_PARAMS, dtype=np.float32)
+        _check(lib().rtg_cnn_read_gradients(_ptr(self.state), _fptr(out), _stream()), "rtg_cnn_read_gradients")
+        return out
+
+    def adam(self, lr: float):
+        self.step += 1
+        _check(lib().rtg_cnn_adam(_ptr(self.state), float(lr), self.step, _stream()), "rtg_cnn_adam")
+
+    def train_step(self, C, Y, lr: float):
+        loss = self.gradients(C, Y)
+        self.adam(lr)
+        return loss
