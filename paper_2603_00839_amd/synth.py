@@ -305,39 +305,47 @@ def _round16(v: float) -> int:
     return int(math.floor(v / 16.0 + 0.5)) * 16
 
 
+def _child_streams(seed: int, p: int):
+    """Streams of problem p of a batched config: child p of the aux stream of
+    SeedSequence(seed) (spawn key (3, p)), re-seeded from its first word."""
+    child = np.random.SeedSequence(seed, spawn_key=(3, p))
+    return streams(int(child.generate_state(1)[0]))
+
+
+def cfg4_problem(seed: int, p: int, m: int = 40) -> Problem:
+    """Problem p of the uneven batch: sides uniform integers in [64, 512]
+    rounded to multiples of 16, sigma ~ U(1,3) (r = round-half-even(3 sigma)),
+    nu ~ U[1e-3, 1e-2], sketch sides I/4 (channel mode identity)."""
+    cr = _child_streams(seed, p)
+    aux = cr["aux"]
+    I1 = _round16(aux.integers(64, 513))
+    I2 = _round16(aux.integers(64, 513))
+    sigma = float(aux.uniform(1.0, 3.0))
+    nu = float(aux.uniform(1e-3, 1e-2))
+    return make_image_problem(f"cfg4_{p}", 0, I1, I2, 200, True, sigma, half_bandwidth(sigma), nu,
+                              I1 // 4, I2 // 4, m, rng_set=cr)
+
+
 def cfg4(seed: int = 0, count: int = 256, m: int = 40):
-    """Batch of ``count`` independent colour images of uneven size: sides
-    uniform integers in [64, 512] rounded to multiples of 16, sigma ~ U(1,3)
-    (r = round-half-even(3 sigma)), nu ~ U[1e-3, 1e-2], sketch sides I/4
-    (channel mode identity), m = 40."""
-    rs = streams(seed, n_children=count)
-    probs = []
-    for p, child in enumerate(rs["children"]):
-        cr = streams(int(child.generate_state(1)[0]))
-        aux = cr["aux"]
-        I1 = _round16(aux.integers(64, 513))
-        I2 = _round16(aux.integers(64, 513))
-        sigma = float(aux.uniform(1.0, 3.0))
-        nu = float(aux.uniform(1e-3, 1e-2))
-        probs.append(make_image_problem(
-            f"cfg4_{p}", 0, I1, I2, 200, True, sigma, half_bandwidth(sigma), nu,
-            I1 // 4, I2 // 4, m, rng_set=cr))
-    return probs
+    """Batch of ``count`` independent colour images of uneven size, m = 40."""
+    return [cfg4_problem(seed, p, m) for p in range(count)]
+
+
+def cfg5_problem(seed: int, p: int, side: int = 128, m: int = 50) -> Problem:
+    """Training problem p for the learned warm start: the cfg2 generator at
+    side x side x 3 (200 rectangles + Gaussian random field), sigma ~ U(1,3),
+    nu ~ U[1e-3, 1e-2]; label solver sketch I/8 per spatial mode, m = 50."""
+    cr = _child_streams(seed, p)
+    aux = cr["aux"]
+    sigma = float(aux.uniform(1.0, 3.0))
+    nu = float(aux.uniform(1e-3, 1e-2))
+    return make_image_problem(f"cfg5_{p}", 0, side, side, 200, True, sigma, half_bandwidth(sigma),
+                              nu, side // 8, side // 8, m, rng_set=cr)
 
 
 def cfg5_train(seed: int = 0, count: int = 20000, side: int = 128, m: int = 50):
-    """Training problems for the learned warm start: the cfg2 generator at
-    ``side`` x ``side`` x 3 with sigma ~ U(1,3), nu ~ U[1e-3, 1e-2]; label
-    solver sketch I/8 per spatial mode, m = 50."""
-    rs = streams(seed, n_children=count)
-    for p, child in enumerate(rs["children"]):
-        cr = streams(int(child.generate_state(1)[0]))
-        aux = cr["aux"]
-        sigma = float(aux.uniform(1.0, 3.0))
-        nu = float(aux.uniform(1e-3, 1e-2))
-        yield make_image_problem(
-            f"cfg5_{p}", 0, side, side, 200, True, sigma, half_bandwidth(sigma),
-            nu, side // 8, side // 8, m, rng_set=cr)
+    for p in range(count):
+        yield cfg5_problem(seed, p, side, m)
 
 
 def small_problem(seed: int, I1: int, I2: int, J: int, r1: int, r2: int,
