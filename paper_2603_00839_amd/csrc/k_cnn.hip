@@ -55,47 +55,91 @@ struct ConvArgs {
 
 __device__ __forceinline__ bool bf_pos(bf16_t v) { return (v & 0x8000u) == 0 && (v & 0x7fffu) != 0; }
 
+constexpr int CONV_TH = 8;               // output rows per workgroup (one wave per row)
+constexpr int CONV_THREADS = 64 * CONV_TH;
+
 template <int CIN_S, int COUT_M, int COUT_S, int MODE>
-__global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
+__global__ void __launch_bounds__(CONV_THREADS) k_conv(ConvArgs a) {
     constexpr int KPAD = kpad_of(CIN_S);
     constexpr int KQ = KPAD / 32;
     constexpr int KL = KPAD + 8;          // padded LDS row (bank spread), 16-byte multiple
     constexpr int MT = COUT_M / 16;
+    constexpr int TW = 64, TH = CONV_TH;  // output tile: 64 pixels along i1 x TH rows
+    constexpr int NTH = CONV_THREADS;
+    constexpr int HW = TW + 2, HH = TH + 2;
+    constexpr int PS = CIN_S + 8;         // padded channels per staged pixel
     __shared__ bf16_t Wl[COUT_M * KL];
-    __shared__ float red[4];
+    __shared__ bf16_t Xs[HH * HW * PS];   // input tile with a one-pixel halo
+    __shared__ float red[CONV_TH];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n16 = lane & 15, s = lane >> 4;
     const int I1 = a.I1, I2 = a.I2;
-    for (int e = tid; e < COUT_M * (KPAD / 8); e += 256) {
+    for (int e = tid; e < COUT_M * (KPAD / 8); e += NTH) {
         const int row = e / (KPAD / 8), c8 = e % (KPAD / 8);
         *(u4*)(Wl + row * KL + c8 * 8) = *gptr((const u4*)(a.w + (size_t)row * KPAD + c8 * 8));
     }
-    const int nt1 = (I1 + 63) / 64, nt2 = (I2 + 3) / 4;
+    // bias of the lane's four output rows per M tile
+    float bias[MT][4];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bias[mt][i] = (MODE == CV_BWD_DATA) ? 0.f : a.bias[16 * mt + 4 * s + i];
+    const int nt1 = (I1 + TW - 1) / TW, nt2 = (I2 + TH - 1) / TH;
     int b = blockIdx.x;
     const int t1 = b % nt1;
     b /= nt1;
     const int t2 = b % nt2;
     const int img = b / nt2;
-    const int i2 = t2 * 4 + wave;
+    const int i10 = t1 * TW, i20 = t2 * TH;
+    const int i2 = i20 + wave;
     const bool row_ok = i2 < I2;
     const size_t plane = (size_t)I1 * I2;
+    // stage the input tile (zero outside the image); loads are unconditional
+    // from clamped addresses so that they all stay in flight
+    constexpr int NCH = CIN_S / 8;
+    constexpr int NST = (HH * HW * NCH + NTH - 1) / NTH;
+    u4 stg[NST];
+#pragma unroll
+    for (int it = 0; it < NST; ++it) {
+        const int e = tid + NTH * it;
+        const int c8 = e % NCH, pxl = e / NCH;
+        const int y1 = i10 - 1 + pxl % HW, y2 = i20 - 1 + pxl / HW;
+        const int c1 = min(max(y1, 0), I1 - 1), c2 = min(max(y2, 0), I2 - 1);
+        const u4 v = *gptr((const u4*)(a.x + (((size_t)img * I2 + c2) * I1 + c1) * CIN_S + c8 * 8));
+        const bool ok = e < HH * HW * NCH && y1 >= 0 && y1 < I1 && y2 >= 0 && y2 < I2;
+        stg[it] = ok ? v : u4{0u, 0u, 0u, 0u};
+    }
+#pragma unroll
+    for (int it = 0; it < NST; ++it) {
+        const int e = tid + NTH * it;
+        if (e < HH * HW * NCH) {
+            const int c8 = e % NCH, pxl = e / NCH;
+            *(u4*)(Xs + pxl * PS + c8 * 8) = stg[it];
+        }
+    }
     __syncthreads();
+    // weight fragments (MFMA A operand) stay in registers for all pixel tiles
+    bf8 Afr[KQ][MT];
+#pragma unroll
+    for (int q = 0; q < KQ; ++q)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+            Afr[q][mt] = __builtin_bit_cast(bf8, *(const u4*)(Wl + (16 * mt + n16) * KL + 32 * q + 8 * s));
 
     float lsum = 0.f;
     for (int nt = 0; nt < 4; ++nt) {
-        const int i1 = t1 * 64 + nt * 16 + n16;
+        const int il = nt * 16 + n16;            // pixel within the tile row
+        const int i1 = i10 + il;
         const bool px_ok = row_ok && i1 < I1;
         bf8 B[KQ];
 #pragma unroll
         for (int q = 0; q < KQ; ++q) {
             const int k = 32 * q + 8 * s;
             const int tap = k / CIN_S, ci0 = k % CIN_S;
-            const int y1 = i1 + tap / 3 - 1, y2 = i2 + tap % 3 - 1;
-            const bool ok = tap < 9 && y1 >= 0 && y1 < I1 && y2 >= 0 && y2 < I2 && row_ok;
-            const int c1 = min(max(y1, 0), I1 - 1), c2 = min(max(y2, 0), I2 - 1);
-            const u4 v = *gptr((const u4*)(a.x + (((size_t)img * I2 + c2) * I1 + c1) * CIN_S + ci0));
-            B[q] = __builtin_bit_cast(bf8, ok ? v : u4{0u, 0u, 0u, 0u});
+            const int tp = tap < 9 ? tap : 0;
+            const u4 v = *(const u4*)(Xs + ((wave + tp % 3) * HW + il + tp / 3) * PS + ci0);
+            B[q] = __builtin_bit_cast(bf8, tap < 9 ? v : u4{0u, 0u, 0u, 0u});
         }
         f4 acc[MT];
 #pragma unroll
@@ -103,10 +147,8 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
 #pragma unroll
         for (int q = 0; q < KQ; ++q)
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-                const bf8 A = __builtin_bit_cast(bf8, *(const u4*)(Wl + (16 * mt + n16) * KL + 32 * q + 8 * s));
-                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B[q], acc[mt], 0, 0, 0);
-            }
+            for (int mt = 0; mt < MT; ++mt)
+                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Afr[q][mt], B[q], acc[mt], 0, 0, 0);
         if (!px_ok) continue;
         const size_t pix = ((size_t)img * I2 + i2) * I1 + i1;
         if constexpr (MODE == CV_HIDDEN || MODE == CV_BWD_DATA) {
@@ -117,7 +159,7 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     v[i] = acc[mt][i];
-                    if constexpr (MODE == CV_HIDDEN) v[i] = fmaxf(v[i] + a.bias[co0 + i], 0.f);
+                    if constexpr (MODE == CV_HIDDEN) v[i] = fmaxf(v[i] + bias[mt][i], 0.f);
                 }
                 if constexpr (MODE == CV_BWD_DATA) {
                     const u2 mk = *gptr((const u2*)(a.mask + pix * COUT_S + co0));
@@ -138,7 +180,7 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const size_t po = ((size_t)img * 3 + c) * plane + (size_t)i2 * I1 + i1;
-                    x0[c] = *gptr(a.C + po) + acc[0][c] + a.bias[c];
+                    x0[c] = *gptr(a.C + po) + acc[0][c] + bias[0][c];
                     if constexpr (MODE == CV_LAST_INFER) *gptr_w(a.X0 + po) = x0[c];
                 }
                 if constexpr (MODE == CV_LAST_TRAIN) {
@@ -164,7 +206,11 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
         lsum = wave_sum(lsum);
         if (lane == 0) red[wave] = lsum;
         __syncthreads();
-        if (tid == 0) a.loss_part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+        if (tid == 0) {
+            float t = 0.f;
+            for (int w = 0; w < CONV_TH; ++w) t += red[w];
+            a.loss_part[blockIdx.x] = t;
+        }
     }
 }
 
@@ -391,7 +437,7 @@ WsLayout ws_layout(int N, int I1, int I2) {
     W.g8 = take(px * 8 * 2);
     W.gA = take(px * 32 * 2);
     W.gB = take(px * 32 * 2);
-    W.nconv = N * ((I2 + 3) / 4) * ((I1 + 63) / 64);
+    W.nconv = N * ((I2 + CONV_TH - 1) / CONV_TH) * ((I1 + 63) / 64);
     W.nwg = N * ((I2 + WG_ROWS - 1) / WG_ROWS);
     W.part = take((size_t)W.nwg * (32 * kpad_of(32) + 32) * 4);
     W.loss = take((size_t)W.nconv * 4 + 4);
@@ -401,7 +447,7 @@ WsLayout ws_layout(int N, int I1, int I2) {
 
 template <int CIN_S, int COUT_M, int COUT_S, int MODE>
 hipError_t conv(const ConvArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_conv<CIN_S, COUT_M, COUT_S, MODE>), dim3(grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_conv<CIN_S, COUT_M, COUT_S, MODE>), dim3(grid), dim3(CONV_THREADS), 0, s, a);
     return hipGetLastError();
 }
 
