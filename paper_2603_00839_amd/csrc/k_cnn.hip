@@ -55,141 +55,191 @@ struct ConvArgs {
 
 __device__ __forceinline__ bool bf_pos(bf16_t v) { return (v & 0x8000u) == 0 && (v & 0x7fffu) != 0; }
 
-constexpr int CONV_TH = 8;               // output rows per workgroup (one wave per row)
+constexpr int CONV_TH = 8;               // output rows per tile (one wave per row)
 constexpr int CONV_THREADS = 64 * CONV_TH;
+constexpr int CONV_MAX_WG = 2 * 256;     // persistent grid: two workgroups per compute unit
 
+// Tiles are 64 pixels along i1 by CONV_TH rows.  The grid is persistent: a
+// workgroup walks the tiles t = blockIdx.x, blockIdx.x + gridDim.x, ... and
+// loads the next tile's input (with its one-pixel halo) into registers while
+// it computes the current tile from LDS.
 template <int CIN_S, int COUT_M, int COUT_S, int MODE>
 __global__ void __launch_bounds__(CONV_THREADS) k_conv(ConvArgs a) {
     constexpr int KPAD = kpad_of(CIN_S);
     constexpr int KQ = KPAD / 32;
     constexpr int KL = KPAD + 8;          // padded LDS row (bank spread), 16-byte multiple
     constexpr int MT = COUT_M / 16;
-    constexpr int TW = 64, TH = CONV_TH;  // output tile: 64 pixels along i1 x TH rows
+    constexpr int TW = 64, TH = CONV_TH;
     constexpr int NTH = CONV_THREADS;
     constexpr int HW = TW + 2, HH = TH + 2;
     constexpr int PS = CIN_S + 8;         // padded channels per staged pixel
+    constexpr int NCH = CIN_S / 8;
+    constexpr int NST = (HH * HW * NCH + NTH - 1) / NTH;
+    constexpr bool LAST = MODE == CV_LAST_INFER || MODE == CV_LAST_TRAIN;
     __shared__ bf16_t Wl[COUT_M * KL];
-    __shared__ bf16_t Xs[HH * HW * PS];   // input tile with a one-pixel halo
+    __shared__ bf16_t Xs[HH * HW * PS];
     __shared__ float red[CONV_TH];
+    __shared__ float Bl[COUT_M];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n16 = lane & 15, s = lane >> 4;
     const int I1 = a.I1, I2 = a.I2;
+    const size_t plane = (size_t)I1 * I2;
+    const int nt1 = (I1 + TW - 1) / TW, nt2 = (I2 + TH - 1) / TH;
+    const int ntiles = a.N * nt1 * nt2;
     for (int e = tid; e < COUT_M * (KPAD / 8); e += NTH) {
         const int row = e / (KPAD / 8), c8 = e % (KPAD / 8);
         *(u4*)(Wl + row * KL + c8 * 8) = *gptr((const u4*)(a.w + (size_t)row * KPAD + c8 * 8));
     }
-    // bias of the lane's four output rows per M tile
+    if (tid < COUT_M) Bl[tid] = (MODE == CV_BWD_DATA) ? 0.f : a.bias[tid];
+    __syncthreads();
+    // bias of the lane's four output rows per M tile (read from LDS, so that no
+    // use inside the tile loop waits on global loads)
     float bias[MT][4];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) bias[mt][i] = (MODE == CV_BWD_DATA) ? 0.f : a.bias[16 * mt + 4 * s + i];
-    const int nt1 = (I1 + TW - 1) / TW, nt2 = (I2 + TH - 1) / TH;
-    int b = blockIdx.x;
-    const int t1 = b % nt1;
-    b /= nt1;
-    const int t2 = b % nt2;
-    const int img = b / nt2;
-    const int i10 = t1 * TW, i20 = t2 * TH;
-    const int i2 = i20 + wave;
-    const bool row_ok = i2 < I2;
-    const size_t plane = (size_t)I1 * I2;
-    // stage the input tile (zero outside the image); loads are unconditional
-    // from clamped addresses so that they all stay in flight
-    constexpr int NCH = CIN_S / 8;
-    constexpr int NST = (HH * HW * NCH + NTH - 1) / NTH;
-    u4 stg[NST];
-#pragma unroll
-    for (int it = 0; it < NST; ++it) {
-        const int e = tid + NTH * it;
-        const int c8 = e % NCH, pxl = e / NCH;
-        const int y1 = i10 - 1 + pxl % HW, y2 = i20 - 1 + pxl / HW;
-        const int c1 = min(max(y1, 0), I1 - 1), c2 = min(max(y2, 0), I2 - 1);
-        const u4 v = *gptr((const u4*)(a.x + (((size_t)img * I2 + c2) * I1 + c1) * CIN_S + c8 * 8));
-        const bool ok = e < HH * HW * NCH && y1 >= 0 && y1 < I1 && y2 >= 0 && y2 < I2;
-        stg[it] = ok ? v : u4{0u, 0u, 0u, 0u};
-    }
-#pragma unroll
-    for (int it = 0; it < NST; ++it) {
-        const int e = tid + NTH * it;
-        if (e < HH * HW * NCH) {
-            const int c8 = e % NCH, pxl = e / NCH;
-            *(u4*)(Xs + pxl * PS + c8 * 8) = stg[it];
-        }
-    }
-    __syncthreads();
-    // weight fragments (MFMA A operand) stay in registers for all pixel tiles
-    bf8 Afr[KQ][MT];
-#pragma unroll
-    for (int q = 0; q < KQ; ++q)
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-            Afr[q][mt] = __builtin_bit_cast(bf8, *(const u4*)(Wl + (16 * mt + n16) * KL + 32 * q + 8 * s));
+        for (int i = 0; i < 4; ++i) bias[mt][i] = Bl[16 * mt + 4 * s + i];
 
+    // input tile of tile t into registers (zero outside the image); loads are
+    // unconditional from clamped addresses so that they all stay in flight
+    u4 stg[NST];
+    unsigned okbits = 0;
+    auto fetch = [&](int t) {
+        okbits = 0;
+        const int t1 = t % nt1, r = t / nt1;
+        const int i10 = t1 * TW, i20 = (r % nt2) * TH, img = r / nt2;
+#pragma unroll
+        for (int it = 0; it < NST; ++it) {
+            const int e = tid + NTH * it;
+            const int c8 = e % NCH, pxl = e / NCH;
+            const int y1 = i10 - 1 + pxl % HW, y2 = i20 - 1 + pxl / HW;
+            const int c1 = min(max(y1, 0), I1 - 1), c2 = min(max(y2, 0), I2 - 1);
+            stg[it] = *gptr((const u4*)(a.x + (((size_t)img * I2 + c2) * I1 + c1) * CIN_S + c8 * 8));
+            // the zero padding is applied when the registers go to LDS, so
+            // that nothing waits for these loads before then
+            okbits |= (unsigned)((e < HH * HW * NCH) & (y1 >= 0) & (y1 < I1) & (y2 >= 0) & (y2 < I2)) << it;
+        }
+    };
     float lsum = 0.f;
-    for (int nt = 0; nt < 4; ++nt) {
-        const int il = nt * 16 + n16;            // pixel within the tile row
-        const int i1 = i10 + il;
-        const bool px_ok = row_ok && i1 < I1;
-        bf8 B[KQ];
+    int t = blockIdx.x;
+    if (t < ntiles) fetch(t);
+    for (; t < ntiles; t += gridDim.x) {
+        const int t1 = t % nt1, r = t / nt1;
+        const int i10 = t1 * TW, i2 = (r % nt2) * TH + wave, img = r / nt2;
+        const bool row_ok = i2 < I2;
+        const int i2c = min(i2, I2 - 1);
+        __syncthreads();                  // the previous tile's reads of Xs are done
+#pragma unroll
+        for (int it = 0; it < NST; ++it) {
+            const int e = tid + NTH * it;
+            if (e < HH * HW * NCH) {
+                const int c8 = e % NCH, pxl = e / NCH;
+                const unsigned m = 0u - ((okbits >> it) & 1u);
+                *(u4*)(Xs + pxl * PS + c8 * 8) = stg[it] & u4{m, m, m, m};
+            }
+        }
+        __syncthreads();
+        // epilogue operands of this tile, loaded before the next tile's input
+        // so that waiting for them does not wait for the prefetch
+        float cin[4][3], yin[4][3];
+        u2 mk[4][MT];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const int i1c = min(i10 + nt * 16 + n16, I1 - 1);
+            if constexpr (LAST) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const size_t po = ((size_t)img * 3 + c) * plane + (size_t)i2c * I1 + i1c;
+                    cin[nt][c] = *gptr(a.C + po);
+                    if constexpr (MODE == CV_LAST_TRAIN) yin[nt][c] = *gptr(a.Y + po);
+                }
+            }
+            if constexpr (MODE == CV_BWD_DATA) {
+                const size_t pix = ((size_t)img * I2 + i2c) * I1 + i1c;
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) mk[nt][mt] = *gptr((const u2*)(a.mask + pix * COUT_S + 16 * mt + 4 * s));
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);   // keep those loads ahead of the prefetch
+        fetch(min(t + (int)gridDim.x, ntiles - 1));   // the last tile loads a valid tile again, unused
+
+        f4 acc[4][MT];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) acc[nt][mt] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int q = 0; q < KQ; ++q) {
+            bf8 A[MT];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+                A[mt] = __builtin_bit_cast(bf8, *(const u4*)(Wl + (16 * mt + n16) * KL + 32 * q + 8 * s));
             const int k = 32 * q + 8 * s;
             const int tap = k / CIN_S, ci0 = k % CIN_S;
             const int tp = tap < 9 ? tap : 0;
-            const u4 v = *(const u4*)(Xs + ((wave + tp % 3) * HW + il + tp / 3) * PS + ci0);
-            B[q] = __builtin_bit_cast(bf8, tap < 9 ? v : u4{0u, 0u, 0u, 0u});
-        }
-        f4 acc[MT];
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) acc[mt] = f4{0.f, 0.f, 0.f, 0.f};
+            for (int nt = 0; nt < 4; ++nt) {
+                const int il = nt * 16 + n16;
+                const u4 v = *(const u4*)(Xs + ((wave + tp % 3) * HW + il + tp / 3) * PS + ci0);
+                const bf8 B = __builtin_bit_cast(bf8, tap < 9 ? v : u4{0u, 0u, 0u, 0u});
 #pragma unroll
-        for (int q = 0; q < KQ; ++q)
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Afr[q][mt], B[q], acc[mt], 0, 0, 0);
-        if (!px_ok) continue;
-        const size_t pix = ((size_t)img * I2 + i2) * I1 + i1;
-        if constexpr (MODE == CV_HIDDEN || MODE == CV_BWD_DATA) {
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-                const int co0 = 16 * mt + 4 * s;
-                float v[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    v[i] = acc[mt][i];
-                    if constexpr (MODE == CV_HIDDEN) v[i] = fmaxf(v[i] + bias[mt][i], 0.f);
-                }
-                if constexpr (MODE == CV_BWD_DATA) {
-                    const u2 mk = *gptr((const u2*)(a.mask + pix * COUT_S + co0));
-                    const bf16_t mb[4] = {(bf16_t)(mk[0] & 0xffffu), (bf16_t)(mk[0] >> 16),
-                                          (bf16_t)(mk[1] & 0xffffu), (bf16_t)(mk[1] >> 16)};
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) v[i] = bf_pos(mb[i]) ? v[i] : 0.f;
-                }
-                u2 pk;
-                pk[0] = (unsigned)f2bf(v[0]) | ((unsigned)f2bf(v[1]) << 16);
-                pk[1] = (unsigned)f2bf(v[2]) | ((unsigned)f2bf(v[3]) << 16);
-                *gptr_w((u2*)(a.out + pix * COUT_S + co0)) = pk;
+                for (int mt = 0; mt < MT; ++mt)
+                    acc[nt][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mt], B, acc[nt][mt], 0, 0, 0);
             }
-        } else {
-            // last layer: rows 0..2 of the first M tile are the three output channels
-            if (s == 0) {
+        }
+        // values for every lane first (so that no load is sunk into the
+        // guarded stores, where waiting for it would also wait for the
+        // prefetch), then the guarded stores
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const int i1 = i10 + nt * 16 + n16;
+            const bool ok = row_ok && i1 < I1;
+            const size_t pix = ((size_t)img * I2 + i2c) * I1 + min(i1, I1 - 1);
+            if constexpr (MODE == CV_HIDDEN || MODE == CV_BWD_DATA) {
+                u2 pk[MT];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    float v[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        v[i] = acc[nt][mt][i];
+                        if constexpr (MODE == CV_HIDDEN) v[i] = fmaxf(v[i] + bias[mt][i], 0.f);
+                    }
+                    if constexpr (MODE == CV_BWD_DATA) {
+                        const u2 m2 = mk[nt][mt];
+                        const bf16_t mb[4] = {(bf16_t)(m2[0] & 0xffffu), (bf16_t)(m2[0] >> 16),
+                                              (bf16_t)(m2[1] & 0xffffu), (bf16_t)(m2[1] >> 16)};
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) v[i] = bf_pos(mb[i]) ? v[i] : 0.f;
+                    }
+                    pk[mt][0] = (unsigned)f2bf(v[0]) | ((unsigned)f2bf(v[1]) << 16);
+                    pk[mt][1] = (unsigned)f2bf(v[2]) | ((unsigned)f2bf(v[3]) << 16);
+                }
+                if (ok) {
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) *gptr_w((u2*)(a.out + pix * COUT_S + 16 * mt + 4 * s)) = pk[mt];
+                }
+            } else {
+                // last layer: rows 0..2 of the first M tile (lanes with s = 0)
+                // are the three output channels
                 float x0[3];
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const size_t po = ((size_t)img * 3 + c) * plane + (size_t)i2 * I1 + i1;
-                    x0[c] = *gptr(a.C + po) + acc[0][c] + bias[0][c];
-                    if constexpr (MODE == CV_LAST_INFER) *gptr_w(a.X0 + po) = x0[c];
-                }
-                if constexpr (MODE == CV_LAST_TRAIN) {
+                for (int c = 0; c < 3; ++c) x0[c] = cin[nt][c] + acc[nt][0][c] + bias[0][c];
+                const bool own = ok && s == 0;
+                if constexpr (MODE == CV_LAST_INFER) {
+                    if (own) {
+#pragma unroll
+                        for (int c = 0; c < 3; ++c)
+                            *gptr_w(a.X0 + ((size_t)img * 3 + c) * plane + (size_t)i2 * I1 + i1) = x0[c];
+                    }
+                } else {
                     bf16_t gb[8];
+                    float l = 0.f;
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        const size_t po = ((size_t)img * 3 + c) * plane + (size_t)i2 * I1 + i1;
-                        const float dlt = x0[c] - *gptr(a.Y + po);
-                        lsum += dlt * dlt;
+                        const float dlt = x0[c] - yin[nt][c];
+                        l += dlt * dlt;
                         gb[c] = f2bf(a.gscale * dlt);
                     }
 #pragma unroll
@@ -197,7 +247,8 @@ __global__ void __launch_bounds__(CONV_THREADS) k_conv(ConvArgs a) {
                     u4 pk;
 #pragma unroll
                     for (int q = 0; q < 4; ++q) pk[q] = (unsigned)gb[2 * q] | ((unsigned)gb[2 * q + 1] << 16);
-                    *gptr_w((u4*)(a.out + pix * 8)) = pk;
+                    lsum += own ? l : 0.f;
+                    if (own) *gptr_w((u4*)(a.out + pix * 8)) = pk;
                 }
             }
         }
@@ -207,9 +258,9 @@ __global__ void __launch_bounds__(CONV_THREADS) k_conv(ConvArgs a) {
         if (lane == 0) red[wave] = lsum;
         __syncthreads();
         if (tid == 0) {
-            float t = 0.f;
-            for (int w = 0; w < CONV_TH; ++w) t += red[w];
-            a.loss_part[blockIdx.x] = t;
+            float tot = 0.f;
+            for (int w = 0; w < CONV_TH; ++w) tot += red[w];
+            a.loss_part[blockIdx.x] = tot;
         }
     }
 }
@@ -437,7 +488,7 @@ WsLayout ws_layout(int N, int I1, int I2) {
     W.g8 = take(px * 8 * 2);
     W.gA = take(px * 32 * 2);
     W.gB = take(px * 32 * 2);
-    W.nconv = N * ((I2 + CONV_TH - 1) / CONV_TH) * ((I1 + 63) / 64);
+    W.nconv = std::min(N * ((I2 + CONV_TH - 1) / CONV_TH) * ((I1 + 63) / 64), CONV_MAX_WG);
     W.nwg = N * ((I2 + WG_ROWS - 1) / WG_ROWS);
     W.part = take((size_t)W.nwg * (32 * kpad_of(32) + 32) * 4);
     W.loss = take((size_t)W.nconv * 4 + 4);

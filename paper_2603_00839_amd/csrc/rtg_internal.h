@@ -109,12 +109,8 @@ __host__ __device__ inline int gram_pairs_per_block(int l3) {
 
 // bfloat16 values are handled as raw 16-bit patterns (round to nearest even)
 __device__ __forceinline__ float bf2f(bf16_t u) { return __uint_as_float((unsigned)u << 16); }
-__device__ __forceinline__ bf16_t f2bf(float f) {
-    unsigned x = __float_as_uint(f);
-    if ((x & 0x7fffffffu) > 0x7f800000u) return (bf16_t)((x >> 16) | 0x40u);   // quiet NaN
-    x += 0x7fffu + ((x >> 16) & 1u);
-    return (bf16_t)(x >> 16);
-}
+// round to nearest even (v_cvt_pk_bf16_f32 on gfx950; NaN stays NaN)
+__device__ __forceinline__ bf16_t f2bf(float f) { return __builtin_bit_cast(bf16_t, (__bf16)f); }
 
 // Pointers read from descriptors are generic; loads through them become flat
 // instructions (which also count against the LDS wait counter).  Tensor data
