@@ -5,7 +5,9 @@
 //     by k_tile over the i2 tiles, and applies mode 3,
 //        s[a,b,c'] = sum_c Om3[c',c] sum_tiles P_(tile,c)[a,b]
 //     (Om3 = identity when absent) -- for s = S(Phi(V_j)) and, in a step,
-//     for S(V_j), the sketch of the newest stored basis tensor;
+//     for S(V_j), the sketch of the newest stored basis tensor.  In a step
+//     the partials of s were taken from V_j with Om1 A1 and Om2 A2, and
+//     mode 3 uses Om3 B^T (mode products compose);
 //  2. computes its share of the inner products <S(V_i), s> and
 //     <S(V_i), S(V_j)> (i <= j) and of ||s||^2 in float64;
 //  3. the last workgroup of a problem to finish sums the shares in a fixed
@@ -28,8 +30,9 @@ __device__ __forceinline__ double load_coherent(const double* p) {
 }
 
 // s_out[e] for the pairs [q0, q0 + qn): e = (q - q0) * l3 + c'
+// m3: mode-3 matrix (l3 x J), nullptr for the identity
 __device__ __forceinline__ void finish_sketch(const Desc& d, const float* __restrict__ Pbuf, int q0,
-                                              int qn, float* s_out) {
+                                              int qn, float* s_out, const float* __restrict__ m3) {
     const int tid = threadIdx.x;
     const int L12 = d.l1 * d.l2;
     const int J = d.J, nt2 = d.n_i2t, l3 = d.l3;
@@ -51,15 +54,15 @@ __device__ __forceinline__ void finish_sketch(const Desc& d, const float* __rest
             }
             for (; t2 < nt2; ++t2) Qp[0] += pc[(size_t)t2 * L12];
             const float Q = ((Qp[0] + Qp[1]) + (Qp[2] + Qp[3])) + ((Qp[4] + Qp[5]) + (Qp[6] + Qp[7]));
-            if (d.has_om3) {
+            if (m3) {
 #pragma unroll
                 for (int c3 = 0; c3 < LMAX_3; ++c3)
-                    if (c3 < l3) acc3[c3] = fmaf(d.om3[(size_t)c3 * J + c], Q, acc3[c3]);
+                    if (c3 < l3) acc3[c3] = fmaf(m3[(size_t)c3 * J + c], Q, acc3[c3]);
             } else {
                 s_out[t * l3 + c] = Q;
             }
         }
-        if (d.has_om3) {
+        if (m3) {
 #pragma unroll
             for (int c3 = 0; c3 < LMAX_3; ++c3)
                 if (c3 < l3) s_out[t * l3 + c3] = acc3[c3];
@@ -90,8 +93,11 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
     const int qn = min(CH, L12 - q0);
     const int E = qn * l3;
 
-    finish_sketch(d, d.PW, q0, qn, s_s);
-    if (mode == GM_STEP) finish_sketch(d, d.PV, q0, qn, s_v);
+    // in a step the W partials are those of S(Phi(V_j)) taken with the
+    // composed first two matrices, so mode 3 is Om3 B^T
+    const float* om3 = d.has_om3 ? d.om3 : nullptr;
+    finish_sketch(d, d.PW, q0, qn, s_s, mode == GM_STEP ? d.om3t : om3);
+    if (mode == GM_STEP) finish_sketch(d, d.PV, q0, qn, s_v, om3);
     __syncthreads();
 
     if (mode == GM_SKETCH_OUT) {

@@ -230,6 +230,63 @@ __global__ void k_init(const Desc* __restrict__ descs) {
     for (int e = tid; e < 3 * m + 1; e += blockDim.x) d.gv[e] = 0.0;
 }
 
+// Composed sketch matrices: S(Phi(X)) = X x_1 (Om1 A1) x_2 (Om2 A2) x_3 (Om3 B^T)
+// (mode products compose; Phi of eq. (2)).  Om1 is the matrix the basis
+// sketches use: the bfloat16-rounded one for a bfloat16 basis.  A1 has band
+// rows, A1[i', i] = a1[i' (2 r1 + 1) + r1 + i - i'] (read here from the
+// transposed copy, so that neighbouring entries read neighbouring words);
+// B[k, j] = bb[k (2 rB + 1) + rB + j - k]
+// is the weight of input channel k in output channel j.
+__global__ void k_compose(const Desc* __restrict__ descs, int nbc) {
+    const int p = blockIdx.x / nbc, part = blockIdx.x % nbc;
+    const Desc& d = descs[p];
+    const int I1 = d.I1, I2 = d.I2, J = d.J, l1 = d.l1, l2 = d.l2, l3 = d.l3;
+    const int r1 = d.r1, r2 = d.r2, rB = d.rB;
+    const int wB = 2 * rB + 1;
+    const int E1 = l1 * I1, E2 = l2 * I2, E3 = l3 * J;
+    // one entry per thread; taps read from clamped indices and masked, so
+    // that the loads of a thread are independent of each other
+    const int e = part * blockDim.x + threadIdx.x;
+    if (e < E1) {
+        const int a = e / I1, i = e % I1;
+        float acc = 0.f;
+#pragma unroll 5
+        for (int dd = -r1; dd <= r1; ++dd) {
+            const int ip = i - dd;
+            const int ipc = min(max(ip, 0), I1 - 1);
+            const float om = d.bf16 ? bf2f(d.om1h[(size_t)a * I1 + ipc]) : d.om1[(size_t)a * I1 + ipc];
+            const float w = d.a1t[(size_t)(r1 + dd) * I1 + ipc];
+            acc = fmaf((ip >= 0 && ip < I1) ? om : 0.f, w, acc);
+        }
+        ((float*)d.om1t)[e] = acc;
+        const bf16_t hi = f2bf(acc);
+        ((bf16_t*)d.om1th)[e] = hi;
+        ((bf16_t*)d.om1th)[E1 + e] = f2bf(acc - bf2f(hi));
+    } else if (e < E1 + E2) {
+        const int e2 = e - E1;
+        const int b = e2 / I2, i = e2 % I2;
+        float acc = 0.f;
+#pragma unroll 5
+        for (int dd = -r2; dd <= r2; ++dd) {
+            const int ip = i - dd;
+            const int ipc = min(max(ip, 0), I2 - 1);
+            const float om = d.om2[(size_t)b * I2 + ipc];
+            const float w = d.a2t[(size_t)(r2 + dd) * I2 + ipc];
+            acc = fmaf((ip >= 0 && ip < I2) ? om : 0.f, w, acc);
+        }
+        ((float*)d.om2t)[e2] = acc;
+    } else if (e < E1 + E2 + E3) {
+        const int e3 = e - E1 - E2;
+        const int c3 = e3 / J, k = e3 % J;
+        float acc = 0.f;
+        for (int j = max(0, k - rB); j <= min(J - 1, k + rB); ++j) {
+            const float o3 = d.has_om3 ? d.om3[(size_t)c3 * J + j] : (c3 == j ? 1.f : 0.f);
+            acc = fmaf(o3, d.bb[(size_t)k * wB + rB + (j - k)], acc);
+        }
+        ((float*)d.om3t)[e3] = acc;
+    }
+}
+
 __global__ void k_finish_arnoldi(const Desc* __restrict__ descs, double* H, double* beta,
                                  int* m_done, int m) {
     const Desc& d = descs[0];
@@ -247,6 +304,12 @@ hipError_t launch_solve(const Desc* d, int count, hipStream_t s) {
 
 hipError_t launch_init(const Desc* d, int count, hipStream_t s) {
     hipLaunchKernelGGL(k_init, dim3(count), dim3(256), 0, s, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_compose(const Desc* d, int count, int max_entries, hipStream_t s) {
+    const int nbc = (max_entries + 255) / 256;
+    hipLaunchKernelGGL(k_compose, dim3(count * nbc), dim3(256), 0, s, d, nbc);
     return hipGetLastError();
 }
 

@@ -1,4 +1,4 @@
-// Fused multi-AXPY, store and mode-wise sketch over one column tile.
+// Fused multi-AXPY, store and mode-wise sketches over one column tile.
 //
 // A tile is I1 rows x 32 columns (i2) of one channel c, a contiguous block of
 // memory in the i1-fastest layout.  Depending on the mode the workgroup
@@ -12,16 +12,23 @@
 //   P[a, b] = sum_{i2 in tile} Om2[b, i2] sum_{i1} Om1[a, i1] out[i1, i2]
 //
 // (the first two mode products of S(X) = X x_1 Om1 x_2 Om2 x_3 Om3,
-// Sec. 3.1).  The mode-1 contraction runs on MFMA directly from the
-// registers that hold the tile: with the float32 basis v_mfma_f32_16x16x4f32,
-// with the bfloat16 basis v_mfma_f32_16x16x32_bf16 on the stored (rounded)
-// values, float32 sources being split into two bfloat16 terms.  Each lane
-// owns, for 16 columns, a chunk of RC consecutive rows; since a contraction
-// may visit its index in any order, the same chunk serves as the MFMA
-// K-slice of both operands.  The four waves split the rows, their partial
-// results are summed in LDS, and the mode-2 contraction is a second small
-// MFMA product.  The partial P of every tile goes to a buffer that the
-// sketched-Gram kernel reduces (and where mode 3 is applied).
+// Sec. 3.1).  A new basis tensor is sketched twice in the same pass: with
+// (Om1, Om2) for S(V_{j+1}) and with the composed matrices (Om1 A1, Om2 A2)
+// for S(Phi(V_{j+1})), because mode products compose and Phi is the mode-wise
+// product with (A1, A2, B^T) (eq. (2)).  The next step's sketched inner
+// products then need no separate pass over W = Phi(V_{j+1}).
+//
+// Phase 1 (per super-block of 256 rows): every lane owns 32 elements of the
+// tile, accumulates the multi-AXPY in float32 registers, stores the result
+// (rounded to bfloat16 for a bfloat16 basis) and writes it to LDS, column-
+// major.  Phase 2: the four waves split the (stacked) sketch rows and run the
+// mode-1 contraction on MFMA with the tile from LDS as the B operand
+// (v_mfma_f32_16x16x4f32 for a float32 basis, v_mfma_f32_16x16x32_bf16 for a
+// bfloat16 one; a float32 tile in bfloat16 mode is split into high and low
+// bfloat16 planes, and so is the composed matrix Om1 A1).  After the last
+// super-block the mode-2 contraction is a second small MFMA product, and the
+// partial P of every tile goes to a buffer that the sketched-Gram kernel
+// reduces (applying mode 3).
 #include "rtg_internal.h"
 
 namespace rtg {
@@ -29,79 +36,61 @@ namespace rtg {
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
-typedef unsigned int u2 __attribute__((ext_vector_type(2)));
 
-template <int RC>
-__device__ __forceinline__ void load_f32(const float* p, float* x) {
-#pragma unroll
-    for (int q = 0; q < RC; q += 4) {
-        f4 v = *gptr((const f4*)(p + q));
-        x[q] = v[0]; x[q + 1] = v[1]; x[q + 2] = v[2]; x[q + 3] = v[3];
-    }
+constexpr int TILE_SBR = 256;   // rows per super-block: 256 lanes x 32 elements / 32 columns
+// element offset of a chunk outside the tile: its byte offset lies past every
+// buffer extent used here (a tile spans 32 x I1 elements of at most 4 bytes)
+constexpr unsigned OOB_ELEM = 0x20000000u;
+
+// raw buffer resource over [base, base + bytes): loads past the end return
+// zero and stores past it are dropped
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, 0x00020000);
 }
 
-template <int RC>
-__device__ __forceinline__ void load_bf16(const bf16_t* p, float* x) {
-    if constexpr (RC == 8) {
-        u4 v = *gptr((const u4*)p);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            x[2 * q] = __uint_as_float(v[q] << 16);
-            x[2 * q + 1] = __uint_as_float(v[q] & 0xffff0000u);
-        }
-    } else {
-        u2 v = *gptr((const u2*)p);
-        x[0] = __uint_as_float(v[0] << 16); x[1] = __uint_as_float(v[0] & 0xffff0000u);
-        x[2] = __uint_as_float(v[1] << 16); x[3] = __uint_as_float(v[1] & 0xffff0000u);
-    }
-}
-
-__device__ __forceinline__ bf8 pack_bf8(const bf16_t* h) {
-    u4 v;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) v[q] = (unsigned)h[2 * q] | ((unsigned)h[2 * q + 1] << 16);
-    return __builtin_bit_cast(bf8, v);
-}
-
-// Om1 fragment (MFMA A operand) of row tile rt for the lane's K-chunk
-template <bool BB>
-struct AFrag;
-template <>
-struct AFrag<false> {
-    f4 v;
-};
-template <>
-struct AFrag<true> {
-    bf8 v;
+template <bool BB, bool SPLIT, int RPW>
+struct TileSmem {
+    static constexpr int TC = TILE_TC;
+    static constexpr int CSB = TILE_SBR + 8;    // bfloat16 plane column stride (elements)
+    static constexpr int CSF = TILE_SBR + 4;    // float32 column stride (elements)
+    static constexpr int XBYTES = BB ? (SPLIT ? 2 : 1) * TC * CSB * 2 : TC * CSF * 4;
+    static constexpr int YP = TC + 1;
+    static constexpr int YBYTES = 64 * RPW * YP * 4;   // stacked sketch rows x columns
+    static constexpr int BYTES = XBYTES > YBYTES ? XBYTES : YBYTES;
 };
 
-// BB: basis stored as bfloat16 (bf16 MFMA); SRCBF: R0src holds bfloat16;
-// RTMAX: row tiles of 16 covering l1 (4 for l1 <= 64, 8 for l1 <= 128).
-template <bool BB, bool SRCBF, int RTMAX>
+// BB: basis stored as bfloat16 (bfloat16 MFMA); SPLIT: the sketched tile is
+// float32 in bfloat16 mode (two planes); RPW: sketch row tiles of 16 per wave.
+template <bool BB, bool SPLIT, int RPW>
 __global__ void __launch_bounds__(256) k_tile(const Desc* __restrict__ descs,
                                               const int* __restrict__ starts, int count,
                                               int mode, int nterms_arg, int dst_index) {
-    constexpr int RC = BB ? 8 : 4;          // rows per lane chunk (MFMA K per lane)
-    constexpr int KB = 4 * RC;              // rows per K-block (one lane group span)
-    constexpr int KPW = BB ? 4 : 8;         // K-blocks per wave in a super-block
-    constexpr int SBR = 4 * KPW * KB;       // rows per super-block (4 waves) = 512
+    using SM = TileSmem<BB, SPLIT, RPW>;
     constexpr int TC = TILE_TC;
-    constexpr int TCP = TC + 1;
+    constexpr int SBR = TILE_SBR;
+    constexpr int CK = BB ? 8 : 4;             // elements per lane chunk (16 bytes of basis)
+    constexpr int NCK = SBR * TC / 256 / CK;   // chunks per lane
+    constexpr int KBR = BB ? 32 : 16;          // rows per MFMA K-block
+    constexpr int CSB = SM::CSB, CSF = SM::CSF, YP = SM::YP;
 
     __shared__ float coef_s[MMAX + 2];
-    __shared__ float Ys[LMAX_SPATIAL * TCP];
+    __shared__ __attribute__((aligned(16))) unsigned char smem[SM::BYTES];
+    bf16_t* Xh = (bf16_t*)smem;                 // high (or only) bfloat16 plane
+    bf16_t* Xl = Xh + TC * CSB;                 // low plane (SPLIT)
+    float* Xf = (float*)smem;                   // float32 tile
+    float* Ys = (float*)smem;                   // mode-1 results (after the last super-block)
 
     const int b = blockIdx.x;
     const int p = find_problem(starts, count, b);
     const Desc& d = descs[p];
     const int tile = b - starts[p];
-    if ((mode == TM_SKETCH || mode == TM_NEWV) && d.state[ST_ACTIVE] == 0) return;
+    if (mode == TM_NEWV && d.state[ST_ACTIVE] == 0) return;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int coll = lane & 15;       // MFMA column (n) / row (m) index
-    const int kq = lane >> 4;         // MFMA K-slot group
+    const int m16 = lane & 15;        // MFMA row (A) / column (B) index
+    const int kq = lane >> 4;         // MFMA K group
 
     const int I1 = d.I1, I2 = d.I2;
     const int l1 = d.l1, l2 = d.l2;
@@ -116,11 +105,11 @@ __global__ void __launch_bounds__(256) k_tile(const Desc* __restrict__ descs,
     else if (mode == TM_ASSEMBLE) nterms = d.state[ST_MEFF];
     const bool do_store = (mode == TM_NEWV || mode == TM_ASSEMBLE);
     const bool do_sketch = (mode != TM_ASSEMBLE);
-    const bool src_is_bf = SRCBF && (mode == TM_SKETCH_SRC);
+    const bool dual = (mode == TM_NEWV);
+    const bool src_is_bf = BB && !SPLIT && (mode == TM_SKETCH_SRC);
 
     const void* src;
-    if (mode == TM_SKETCH) src = d.W;
-    else if (mode == TM_SKETCH_SRC) src = d.R0src;
+    if (mode == TM_SKETCH_SRC) src = d.R0src;
     else if (mode == TM_NEWV) src = (nterms == 0) ? d.R0src : (const void*)d.W;
     else src = d.X0;     // may be null: zero
 
@@ -129,229 +118,268 @@ __global__ void __launch_bounds__(256) k_tile(const Desc* __restrict__ descs,
     __syncthreads();
 
     const int RT = (l1 + 15) >> 4;
-    f4 acc[RTMAX][2];
+    const int NRT = dual ? 2 * RT : RT;       // stacked row tiles: [Om1 ; Om1 A1]
+    f4 acc[RPW][2];
 #pragma unroll
-    for (int rt = 0; rt < RTMAX; ++rt)
+    for (int u = 0; u < RPW; ++u)
 #pragma unroll
-        for (int g = 0; g < 2; ++g) acc[rt][g] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int g = 0; g < 2; ++g) acc[u][g] = f4{0.f, 0.f, 0.f, 0.f};
 
-    // Loads are unconditional from clamped (always in-bounds) addresses and
-    // masked afterwards with a select: a branch per load would make the
-    // compiler wait for each load before the next one is issued.
+    // chunk u of this lane: column col[u], rows row[u] .. row[u] + CK - 1 of the super-block
+    int colu[NCK], rowu[NCK];
+#pragma unroll
+    for (int u = 0; u < NCK; ++u) {
+        const int e = (u * 256 + tid) * CK;
+        colu[u] = e / SBR;
+        rowu[u] = e % SBR;
+    }
+
     const int nsb = (I1 + SBR - 1) / SBR;
     for (int sb = 0; sb < nsb; ++sb) {
-        float x[KPW][2][RC];
-        bool ok[KPW][2];
-        int offs[KPW][2];             // element offsets from the tile start
-        int row0[KPW];
+        // ---- phase 1: multi-AXPY, store, LDS.  Loads are unconditional from
+        // clamped (always in-bounds) addresses and masked afterwards, so that
+        // they stay in flight together.
+        // Buffer loads and stores with per-lane byte offsets from a uniform
+        // base: a chunk outside the tile gets an offset past the buffer's
+        // extent, so the hardware returns zeros for its loads and drops its
+        // stores -- no branches, no clamping, all loads in flight together.
+        unsigned offs[NCK];
 #pragma unroll
-        for (int kb = 0; kb < KPW; ++kb) {
-            row0[kb] = sb * SBR + (kb * 4 + wave) * KB + RC * kq;
-            const int rowc = min(row0[kb], I1 - RC);
-#pragma unroll
-            for (int g = 0; g < 2; ++g) {
-                const int col = 16 * g + coll;
-                ok[kb][g] = (row0[kb] < I1) && (col < ncol);
-                offs[kb][g] = min(col, ncol - 1) * I1 + rowc;
-            }
+        for (int u = 0; u < NCK; ++u) {
+            const int rg = sb * SBR + rowu[u];
+            offs[u] = ((rg < I1) & (colu[u] < ncol)) ? (unsigned)(colu[u] * I1 + rg) : OOB_ELEM;
         }
-        if (src != nullptr) {
+        const int tile_elems = ncol * I1;
+        float x[NCK][CK];
+        if (src == nullptr) {
 #pragma unroll
-            for (int kb = 0; kb < KPW; ++kb)
+            for (int u = 0; u < NCK; ++u)
 #pragma unroll
-                for (int g = 0; g < 2; ++g) {
-                    if (src_is_bf) load_bf16<RC>((const bf16_t*)src + tile_off + offs[kb][g], x[kb][g]);
-                    else load_f32<RC>((const float*)src + tile_off + offs[kb][g], x[kb][g]);
+                for (int q = 0; q < CK; ++q) x[u][q] = 0.f;
+        } else if (src_is_bf) {
+            const auto rs = make_rsrc((const char*)src + tile_off * 2, tile_elems * 2);
+#pragma unroll
+            for (int u = 0; u < NCK; ++u) {
+                const u4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, offs[u] * 2u, 0, 0);
+#pragma unroll
+                for (int q = 0; q < CK / 2; ++q) {
+                    x[u][2 * q] = __uint_as_float(v[q] << 16);
+                    x[u][2 * q + 1] = __uint_as_float(v[q] & 0xffff0000u);
                 }
+            }
         } else {
+            const auto rs = make_rsrc((const char*)src + tile_off * 4, tile_elems * 4);
 #pragma unroll
-            for (int kb = 0; kb < KPW; ++kb)
+            for (int u = 0; u < NCK; ++u)
 #pragma unroll
-                for (int g = 0; g < 2; ++g)
-#pragma unroll
-                    for (int q = 0; q < RC; ++q) x[kb][g][q] = 0.f;
+                for (int q = 0; q < CK; q += 4) {
+                    const u4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, offs[u] * 4u + q * 4u, 0, 0);
+                    x[u][q] = __uint_as_float(v[0]); x[u][q + 1] = __uint_as_float(v[1]);
+                    x[u][q + 2] = __uint_as_float(v[2]); x[u][q + 3] = __uint_as_float(v[3]);
+                }
         }
-        // multi-AXPY over the basis, each term in two halves of K-blocks
         for (int i = 0; i < nterms; ++i) {
             const float ci = coef_s[i];
-            const char* vb = (const char*)d.V + ((size_t)i * d.n + tile_off) * es;
+            const auto rv = make_rsrc((const char*)d.V + ((size_t)i * d.n + tile_off) * es, tile_elems * (int)es);
+            if constexpr (BB) {
+                // two halves of the lane's chunks (packed, unpacked just before use)
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                float v[KPW / 2][2][RC];
+                for (int h = 0; h < 2; ++h) {
+                    u4 v[NCK / 2];
 #pragma unroll
-                for (int kk = 0; kk < KPW / 2; ++kk)
+                    for (int uu = 0; uu < NCK / 2; ++uu)
+                        v[uu] = __builtin_amdgcn_raw_buffer_load_b128(rv, offs[h * (NCK / 2) + uu] * 2u, 0, 0);
 #pragma unroll
-                    for (int g = 0; g < 2; ++g) {
-                        const int kb = h * (KPW / 2) + kk;
-                        if (BB) load_bf16<RC>((const bf16_t*)vb + offs[kb][g], v[kk][g]);
-                        else load_f32<RC>((const float*)vb + offs[kb][g], v[kk][g]);
-                    }
+                    for (int uu = 0; uu < NCK / 2; ++uu)
 #pragma unroll
-                for (int kk = 0; kk < KPW / 2; ++kk)
-#pragma unroll
-                    for (int g = 0; g < 2; ++g)
-#pragma unroll
-                        for (int q = 0; q < RC; ++q) {
-                            const int kb = h * (KPW / 2) + kk;
-                            x[kb][g][q] = fmaf(-ci, v[kk][g][q], x[kb][g][q]);
+                        for (int q = 0; q < 4; ++q) {
+                            const int u = h * (NCK / 2) + uu;
+                            x[u][2 * q] = fmaf(-ci, __uint_as_float(v[uu][q] << 16), x[u][2 * q]);
+                            x[u][2 * q + 1] = fmaf(-ci, __uint_as_float(v[uu][q] & 0xffff0000u), x[u][2 * q + 1]);
                         }
+                }
+            } else {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    u4 v[NCK / 2];
+#pragma unroll
+                    for (int uu = 0; uu < NCK / 2; ++uu)
+                        v[uu] = __builtin_amdgcn_raw_buffer_load_b128(rv, offs[h * (NCK / 2) + uu] * 4u, 0, 0);
+#pragma unroll
+                    for (int uu = 0; uu < NCK / 2; ++uu)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            x[h * (NCK / 2) + uu][q] = fmaf(-ci, __uint_as_float(v[uu][q]), x[h * (NCK / 2) + uu][q]);
+                }
             }
         }
+        // scale (chunks outside the tile are zero already), round (bfloat16 basis), store
 #pragma unroll
-        for (int kb = 0; kb < KPW; ++kb)
+        for (int u = 0; u < NCK; ++u)
 #pragma unroll
-            for (int g = 0; g < 2; ++g)
+            for (int q = 0; q < CK; ++q) x[u][q] *= scale;
+        if (mode == TM_NEWV && BB) {
+            const auto rd = make_rsrc((const char*)d.V + ((size_t)dst_index * d.n + tile_off) * 2, tile_elems * 2);
 #pragma unroll
-                for (int q = 0; q < RC; ++q) x[kb][g][q] = ok[kb][g] ? x[kb][g][q] : 0.f;
-        // scale, round (bfloat16 basis) and store
-        bf16_t h[KPW][2][BB ? RC : 1];
-        if (do_store) {
-            const bool out_bf = BB && (mode == TM_NEWV);
-            char* dstb = (mode == TM_NEWV) ? (char*)d.V + (size_t)dst_index * d.n * es : (char*)d.X;
+            for (int u = 0; u < NCK; ++u) {
+                u4 pk;
 #pragma unroll
-            for (int kb = 0; kb < KPW; ++kb)
+                for (int q = 0; q < 4; ++q)
+                    pk[q] = (unsigned)f2bf(x[u][2 * q]) | ((unsigned)f2bf(x[u][2 * q + 1]) << 16);
+                __builtin_amdgcn_raw_buffer_store_b128(pk, rd, offs[u] * 2u, 0, 0);
+            }
+        } else if (do_store) {
+            const char* db = (mode == TM_NEWV) ? (const char*)d.V + ((size_t)dst_index * d.n + tile_off) * 4
+                                               : (const char*)d.X + tile_off * 4;
+            const auto rd = make_rsrc(db, tile_elems * 4);
 #pragma unroll
-                for (int g = 0; g < 2; ++g) {
+            for (int u = 0; u < NCK; ++u)
 #pragma unroll
-                    for (int q = 0; q < RC; ++q) x[kb][g][q] *= scale;
-                    if (!ok[kb][g]) continue;
-                    const size_t off = tile_off + offs[kb][g];
-                    if (out_bf) {
-                        if constexpr (BB) {
-                            u4 pk;
-#pragma unroll
-                            for (int q = 0; q < RC; ++q) {
-                                h[kb][g][q] = f2bf(x[kb][g][q]);
-                                x[kb][g][q] = bf2f(h[kb][g][q]);
-                            }
-#pragma unroll
-                            for (int q = 0; q < 4; ++q)
-                                pk[q] = (unsigned)h[kb][g][2 * q] | ((unsigned)h[kb][g][2 * q + 1] << 16);
-                            *gptr_w((u4*)((bf16_t*)dstb + off)) = pk;
-                        }
-                    } else {
-                        float* o = (float*)dstb + off;
-#pragma unroll
-                        for (int q = 0; q < RC; q += 4)
-                            *gptr_w((f4*)(o + q)) = f4{x[kb][g][q], x[kb][g][q + 1], x[kb][g][q + 2], x[kb][g][q + 3]};
-                    }
+                for (int q = 0; q < CK; q += 4) {
+                    const u4 pk = u4{__float_as_uint(x[u][q]), __float_as_uint(x[u][q + 1]),
+                                     __float_as_uint(x[u][q + 2]), __float_as_uint(x[u][q + 3])};
+                    __builtin_amdgcn_raw_buffer_store_b128(pk, rd, offs[u] * 4u + q * 4u, 0, 0);
                 }
         }
         if (!do_sketch) continue;
-        // mode-1 contraction on MFMA: acc[rt][g] += Om1[16 rt + m, rows] * tile[rows, 16 g + n].
-        // The Om1 fragments of the next K-block are loaded while the current
-        // one is multiplied.
-        auto load_a = [&](int kb, AFrag<BB>* A) {
-            const bool rowok = row0[kb] < I1;
-            const int rowc = min(row0[kb], I1 - RC);
+        if (sb > 0) __syncthreads();          // the previous super-block's MFMA reads are done
 #pragma unroll
-            for (int rt = 0; rt < RTMAX; ++rt) {
-                const int a = 16 * rt + coll;
-                const bool okA = a < l1 && rowok;
-                const size_t off = (size_t)min(a, l1 - 1) * I1 + rowc;
-                if constexpr (!BB) {
-                    const f4 v = *gptr((const f4*)(d.om1 + off));
-                    A[rt].v = okA ? v : f4{0.f, 0.f, 0.f, 0.f};
+        for (int u = 0; u < NCK; ++u) {
+            if constexpr (BB) {
+                u4 hi, lo;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const bf16_t h0 = f2bf(x[u][2 * q]), h1 = f2bf(x[u][2 * q + 1]);
+                    hi[q] = (unsigned)h0 | ((unsigned)h1 << 16);
+                    if constexpr (SPLIT) {
+                        const bf16_t g0 = f2bf(x[u][2 * q] - bf2f(h0)), g1 = f2bf(x[u][2 * q + 1] - bf2f(h1));
+                        lo[q] = (unsigned)g0 | ((unsigned)g1 << 16);
+                    }
+                }
+                *(u4*)(Xh + colu[u] * CSB + rowu[u]) = hi;
+                if constexpr (SPLIT) *(u4*)(Xl + colu[u] * CSB + rowu[u]) = lo;
+            } else {
+                *(f4*)(Xf + colu[u] * CSF + rowu[u]) = f4{x[u][0], x[u][1], x[u][2], x[u][3]};
+            }
+        }
+        __syncthreads();
+
+        // ---- phase 2: mode-1 contraction of this super-block on MFMA.
+        // Wave w owns stacked row tiles w, w + 4, ...; rows of tile t are
+        // rows of Om1 (t < RT) or of Om1 A1 (RT <= t < 2 RT).
+        const int rows_sb = min(SBR, I1 - sb * SBR);
+        const int nkb = (rows_sb + KBR - 1) / KBR;
+        struct AF {
+            u4 h, l;     // bfloat16: Om1 (h), or Om1 A1 high / low; float32: h as f4 bits
+        };
+        auto load_a = [&](int kb, AF* A) {
+            const int row = sb * SBR + kb * KBR + (BB ? 8 : 4) * kq;
+            const int rowc = min(row, I1 - CK);
+#pragma unroll
+            for (int u = 0; u < RPW; ++u) {
+                // t >= NRT: unused tile, read (masked) from Om1 so that no
+                // pointer of a matrix the mode does not have is touched
+                const int t = wave + 4 * u;
+                const int half = (t >= RT && t < NRT) ? 1 : 0;
+                const int a = 16 * (t - half * RT) + m16;
+                const unsigned msk = 0u - (unsigned)((a < l1) & (row < I1) & (t < NRT));
+                const unsigned off = (unsigned)(min(a, l1 - 1) * I1 + rowc);
+                if constexpr (BB) {
+                    const char* base = (const char*)(half ? d.om1th : d.om1h);
+                    const char* lob = base + (half ? (size_t)l1 * I1 * 2 : 0);
+                    A[u].h = *gptr((const u4*)(base + off * 2u)) & msk;
+                    A[u].l = *gptr((const u4*)(lob + off * 2u)) & (half ? msk : 0u);
                 } else {
-                    const u4 v = *gptr((const u4*)(d.om1h + off));
-                    A[rt].v = __builtin_bit_cast(bf8, okA ? v : u4{0u, 0u, 0u, 0u});
+                    const char* base = (const char*)(half ? d.om1t : d.om1);
+                    A[u].h = *gptr((const u4*)(base + off * 4u)) & msk;
                 }
             }
         };
-        AFrag<BB> Abuf[2][RTMAX];
-        load_a(0, Abuf[0]);
+        auto mfma_block = [&](int kb, const AF* A) {
 #pragma unroll
-        for (int kb = 0; kb < KPW; ++kb) {
-            AFrag<BB>* A = Abuf[kb & 1];
-            if (kb + 1 < KPW) load_a(kb + 1, Abuf[(kb + 1) & 1]);
-            if constexpr (!BB) {
-                f4 B[2];
+            for (int g = 0; g < 2; ++g) {
+                const int col = 16 * g + m16;
+                if constexpr (BB) {
+                    const u4 bh = *(const u4*)(Xh + col * CSB + kb * KBR + 8 * kq);
+                    u4 bl = u4{0u, 0u, 0u, 0u};
+                    if constexpr (SPLIT) bl = *(const u4*)(Xl + col * CSB + kb * KBR + 8 * kq);
 #pragma unroll
-                for (int g = 0; g < 2; ++g)
-                    B[g] = f4{x[kb][g][0], x[kb][g][1], x[kb][g][2], x[kb][g][3]};
+                    for (int u = 0; u < RPW; ++u) {
+                        const int t = wave + 4 * u;
+                        if (t >= NRT) break;
+                        acc[u][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            __builtin_bit_cast(bf8, A[u].h), __builtin_bit_cast(bf8, bh), acc[u][g], 0, 0, 0);
+                        if (t >= RT)
+                            acc[u][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                __builtin_bit_cast(bf8, A[u].l), __builtin_bit_cast(bf8, bh), acc[u][g], 0, 0, 0);
+                        if constexpr (SPLIT)
+                            acc[u][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                __builtin_bit_cast(bf8, A[u].h), __builtin_bit_cast(bf8, bl), acc[u][g], 0, 0, 0);
+                    }
+                } else {
+                    const f4 bv = *(const f4*)(Xf + col * CSF + kb * KBR + 4 * kq);
 #pragma unroll
-                for (int rt = 0; rt < RTMAX; ++rt) {
-                    if (rt >= RT) break;
-#pragma unroll
-                    for (int g = 0; g < 2; ++g)
+                    for (int u = 0; u < RPW; ++u) {
+                        const int t = wave + 4 * u;
+                        if (t >= NRT) break;
+                        const f4 av = __builtin_bit_cast(f4, A[u].h);
 #pragma unroll
                         for (int q = 0; q < 4; ++q)
-                            acc[rt][g] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[rt].v[q], B[g][q], acc[rt][g], 0, 0, 0);
-                }
-            } else {
-                // bfloat16 operands: exact for a bfloat16 tile, hi + lo split for float32
-                const bool split = !(mode == TM_NEWV || src_is_bf);
-                bf8 Bh[2], Bl[2];
-#pragma unroll
-                for (int g = 0; g < 2; ++g) {
-                    bf16_t hi[8], lo[8];
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        hi[q] = f2bf(x[kb][g][q]);
-                        lo[q] = split ? f2bf(x[kb][g][q] - bf2f(hi[q])) : (bf16_t)0;
-                    }
-                    Bh[g] = pack_bf8(hi);
-                    Bl[g] = pack_bf8(lo);
-                }
-#pragma unroll
-                for (int rt = 0; rt < RTMAX; ++rt) {
-                    if (rt >= RT) break;
-#pragma unroll
-                    for (int g = 0; g < 2; ++g) {
-                        acc[rt][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[rt].v, Bh[g], acc[rt][g], 0, 0, 0);
-                        if (split)
-                            acc[rt][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[rt].v, Bl[g], acc[rt][g], 0, 0, 0);
+                            acc[u][g] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[q], bv[q], acc[u][g], 0, 0, 0);
                     }
                 }
+            }
+        };
+        // the fragments of the next K-block are loaded while the current one
+        // is multiplied (two named buffers: no dynamically indexed arrays)
+        AF A0[RPW], A1[RPW];
+        load_a(0, A0);
+        for (int kb = 0; kb < nkb; kb += 2) {
+            if (kb + 1 < nkb) load_a(kb + 1, A1);
+            mfma_block(kb, A0);
+            if (kb + 1 < nkb) {
+                if (kb + 2 < nkb) load_a(kb + 2, A0);
+                mfma_block(kb + 1, A1);
             }
         }
     }
     if (!do_sketch) return;
 
-    // ---- sum the four waves' mode-1 partials: Ys[a][col] (deterministic order)
-    for (int w = 0; w < 4; ++w) {
-        if (wave == w) {
+    // ---- mode-1 results to LDS: Ys[16 t + r][col]
+    __syncthreads();
 #pragma unroll
-            for (int rt = 0; rt < RTMAX; ++rt) {
-                if (rt >= RT) break;
+    for (int u = 0; u < RPW; ++u) {
+        const int t = wave + 4 * u;
+        if (t >= NRT) break;
 #pragma unroll
-                for (int g = 0; g < 2; ++g)
+        for (int g = 0; g < 2; ++g)
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int a = 16 * rt + 4 * kq + i;
-                        const int col = 16 * g + coll;
-                        float v = acc[rt][g][i];
-                        if (w > 0) v += Ys[a * TCP + col];
-                        Ys[a * TCP + col] = v;
-                    }
-            }
-        }
-        __syncthreads();
+            for (int i = 0; i < 4; ++i) Ys[(16 * t + 4 * kq + i) * YP + 16 * g + m16] = acc[u][g][i];
     }
-    // ---- mode-2 contraction: P[a][b] = sum_k Ys[a][k] Om2[b][i20 + k]
+    __syncthreads();
+
+    // ---- mode-2 contraction: P[a][b] = sum_k Ys[a][k] Om2x[b][i20 + k]
     const int RT2 = (l2 + 15) >> 4;
-    float* P = ((mode == TM_NEWV) ? d.PV : d.PW) + (size_t)tile * l1 * l2;
-    for (int t = wave; t < RT * RT2; t += 4) {
-        const int rt = t / RT2, rt2 = t % RT2;
-        f4 pacc = f4{0.f, 0.f, 0.f, 0.f};
-        const int a = 16 * rt + coll;
-        const int bcol = 16 * rt2 + coll;
-        // rows a >= l1 of Ys hold zeros; Om2 loads are clamped and masked
+    for (int tt = wave; tt < NRT * RT2; tt += 4) {
+        const int t = tt / RT2, rt2 = tt % RT2;
+        const int half = t >= RT ? 1 : 0;
+        const float* om2x = half ? d.om2t : d.om2;
+        float* P = (half ? d.PW : (mode == TM_NEWV ? d.PV : d.PW)) + (size_t)tile * l1 * l2;
+        const int bcol = 16 * rt2 + m16;
         float Bv[TC / 4];
 #pragma unroll
         for (int ks = 0; ks < TC / 4; ++ks) {
             const int k = 4 * ks + kq;
-            const float v = *gptr(d.om2 + (size_t)min(bcol, l2 - 1) * I2 + i20 + min(k, ncol - 1));
+            const float v = *gptr(om2x + (size_t)min(bcol, l2 - 1) * I2 + i20 + min(k, ncol - 1));
             Bv[ks] = (bcol < l2 && k < ncol) ? v : 0.f;
         }
+        f4 pacc = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int ks = 0; ks < TC / 4; ++ks) {
-            const int k = 4 * ks + kq;
-            pacc = __builtin_amdgcn_mfma_f32_16x16x4f32(Ys[a * TCP + k], Bv[ks], pacc, 0, 0, 0);
-        }
+        for (int ks = 0; ks < TC / 4; ++ks)
+            pacc = __builtin_amdgcn_mfma_f32_16x16x4f32(Ys[(16 * t + m16) * YP + 4 * ks + kq], Bv[ks], pacc, 0, 0, 0);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int ar = 16 * rt + 4 * kq + i;
+            const int ar = 16 * (t - half * RT) + 4 * kq + i;
             if (ar < l1 && bcol < l2) *gptr_w(P + (size_t)ar * l2 + bcol) = pacc[i];
         }
     }
@@ -359,15 +387,17 @@ __global__ void __launch_bounds__(256) k_tile(const Desc* __restrict__ descs,
 
 hipError_t launch_tile(const Desc* d, const int* starts, int count, int total_tiles, int mode,
                        int nterms, int dst_index, int basis_bf16, int src_bf16, int l1max, hipStream_t s) {
-#define RTG_TILE(BBV, SBV, RTV)                                                                  \
-    hipLaunchKernelGGL((k_tile<BBV, SBV, RTV>), dim3(total_tiles), dim3(256), 0, s, d, starts, count, \
+#define RTG_TILE(BBV, SPV, RPV)                                                                   \
+    hipLaunchKernelGGL((k_tile<BBV, SPV, RPV>), dim3(total_tiles), dim3(256), 0, s, d, starts, count, \
                        mode, nterms, dst_index)
-    const bool small = l1max <= 64;
+    const int rtiles = ((l1max + 15) / 16) * (mode == TM_NEWV ? 2 : 1);
+    const bool small = rtiles <= 8;
     if (basis_bf16) {
-        if (src_bf16) { if (small) RTG_TILE(true, true, 4); else RTG_TILE(true, true, 8); }
-        else { if (small) RTG_TILE(true, false, 4); else RTG_TILE(true, false, 8); }
+        const bool split = mode == TM_SKETCH_SRC && !src_bf16;
+        if (split) { if (small) RTG_TILE(true, true, 2); else RTG_TILE(true, true, 4); }
+        else { if (small) RTG_TILE(true, false, 2); else RTG_TILE(true, false, 4); }
     } else {
-        if (small) RTG_TILE(false, false, 4); else RTG_TILE(false, false, 8);
+        if (small) RTG_TILE(false, false, 2); else RTG_TILE(false, false, 4);
     }
 #undef RTG_TILE
     return hipGetLastError();

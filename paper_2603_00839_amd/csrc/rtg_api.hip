@@ -4,15 +4,15 @@
 // sketched global Arnoldi process of Sec. 4.3).
 //
 // Per problem the sequence is
+//   Om1 A1, Om2 A2, Om3 B^T                k_compose (sketch of Phi(X) as a sketch of X)
 //   R0 = C - Phi(X0)                       k_phi   (skipped when X0 = 0)
 //   partial sketches of R0                 k_tile  (sketch)
 //   beta = ||S(R0)||                       k_gram  (start)
-//   V1 = R0 / beta, partial S(V1)          k_tile  (new basis tensor)
+//   V1 = R0 / beta, partial S(V1), S(Phi(V1))                       k_tile
 //   for j = 1..m:
 //     W = Phi(V_j)                         k_phi
-//     partial S(W)                         k_tile  (sketch)
-//     S(V_j), h_{:,j}, h_{j+1,j}, Givens   k_gram  (step)
-//     V_{j+1} = (W - sum h_ij V_i) / h_{j+1,j}, partial S(V_{j+1})   k_tile
+//     S(V_j), S(W), h_{:,j}, h_{j+1,j}, Givens                      k_gram  (step)
+//     V_{j+1} = (W - sum h_ij V_i) / h_{j+1,j}, partial S(V_{j+1}), S(Phi(V_{j+1}))   k_tile
 //   projected Tikhonov problem, mu         k_solve
 //   X = X0 + sum y_j V_j                   k_tile  (assemble)
 // Every launch covers all problems of a batch; the host never waits.
@@ -29,6 +29,8 @@ struct rtg_op_s {
     float* a1;
     float* a2;
     float* bb;
+    float* a1t;   // transposed bands: a1t[(r1 + dd) I1 + i] = a1[i (2 r1 + 1) + r1 + dd]
+    float* a2t;
 };
 
 struct rtg_sk_s {
@@ -48,7 +50,7 @@ size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
 struct Layout {
-    size_t V, W, PW, PV, SV, dots, G, H, R, gv, coef, y, state, scal, total;
+    size_t V, W, PW, PV, SV, dots, G, H, R, gv, coef, y, state, scal, ot1, ot1h, ot2, ot3, total;
     int n_i2t, ntile_tile, ntile_gram, ntile_phi;
 };
 
@@ -79,6 +81,10 @@ Layout problem_layout(const rtg_op_s* op, const rtg_sk_s* sk, int m, int bf16) {
     L.y = take((size_t)m * sizeof(double));
     L.state = take(NSTATE * sizeof(int));
     L.scal = take(NSCAL * sizeof(double));
+    L.ot1 = take((size_t)sk->l1 * op->I1 * sizeof(float));
+    L.ot1h = take((size_t)2 * sk->l1 * op->I1 * sizeof(bf16_t));
+    L.ot2 = take((size_t)sk->l2 * op->I2 * sizeof(float));
+    L.ot3 = take((size_t)sk->l3 * op->J * sizeof(float));
     L.total = align_up(off);
     return L;
 }
@@ -115,6 +121,7 @@ void fill_desc(Desc& d, const rtg_op_s* op, const rtg_sk_s* sk, int m, int bf16,
     d.n = (long long)op->I1 * op->I2 * op->J;
     d.L = (long long)sk->l1 * sk->l2 * sk->l3;
     d.a1 = op->a1; d.a2 = op->a2; d.bb = op->bb;
+    d.a1t = op->a1t; d.a2t = op->a2t;
     d.om1 = sk->om1; d.om1h = sk->om1h; d.om2 = sk->om2; d.om3 = sk->om3;
     if (base) {
         d.V = base + L.V;
@@ -131,6 +138,10 @@ void fill_desc(Desc& d, const rtg_op_s* op, const rtg_sk_s* sk, int m, int bf16,
         d.y = (double*)(base + L.y);
         d.state = (int*)(base + L.state);
         d.scal = (double*)(base + L.scal);
+        d.om1t = (const float*)(base + L.ot1);
+        d.om1th = (const bf16_t*)(base + L.ot1h);
+        d.om2t = (const float*)(base + L.ot2);
+        d.om3t = (const float*)(base + L.ot3);
     }
 }
 
@@ -162,6 +173,7 @@ struct Plan {
     int total[NKIND];
     int rmax;
     int l1max;
+    int compose_max;   // largest l1 I1 + l2 I2 + l3 J of the batch
 };
 
 int build_plan(std::vector<Desc>& descs, void* ws, hipStream_t s, Plan& plan) {
@@ -178,9 +190,11 @@ int build_plan(std::vector<Desc>& descs, void* ws, hipStream_t s, Plan& plan) {
         plan.total[k] = acc;
     }
     plan.l1max = 1;
+    plan.compose_max = 1;
     for (auto& d : descs) {
         plan.rmax = std::max(plan.rmax, std::max(d.r1, d.r2));
         plan.l1max = std::max(plan.l1max, d.l1);
+        plan.compose_max = std::max(plan.compose_max, d.l1 * d.I1 + d.l2 * d.I2 + d.l3 * d.J);
     }
     char* base = (char*)ws;
     plan.d_desc = (Desc*)base;
@@ -236,11 +250,38 @@ struct TimedLaunch {
         }
     }
 };
-#define RTG_TIMED(kind, call)                            \
+#define RTG_TIMED_ON(kind, strm, call)                   \
     do {                                                 \
-        TimedLaunch _tl((kind), s);                      \
+        TimedLaunch _tl((kind), (strm));                 \
         if ((call) != hipSuccess) return RTG_E_HIP;      \
     } while (0)
+#define RTG_TIMED(kind, call) RTG_TIMED_ON(kind, s, call)
+
+// Second stream for work of a step that does not depend on the operator
+// application (the sketched Gram step), forked from and joined back into the
+// caller's stream with events.  One per host thread and device, so that
+// concurrent callers never share the fork/join events.  Default priority.
+struct AuxStream {
+    int device = -1;
+    hipStream_t aux = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+thread_local AuxStream t_aux[16];
+
+int aux_stream(AuxStream** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) return RTG_E_HIP;
+    AuxStream& a = t_aux[dev];
+    if (a.aux == nullptr) {
+        if (hipStreamCreateWithFlags(&a.aux, hipStreamNonBlocking) != hipSuccess) return RTG_E_HIP;
+        if (hipEventCreateWithFlags(&a.fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&a.join, hipEventDisableTiming) != hipSuccess)
+            return RTG_E_HIP;
+        a.device = dev;
+    }
+    *out = &a;
+    return RTG_OK;
+}
 
 // Arnoldi loop + (optionally) solve and assembly for a prepared plan.
 int run_solver(const Plan& plan, int count, int mmax, int bf16, bool any_x0, bool solve,
@@ -249,14 +290,24 @@ int run_solver(const Plan& plan, int count, int mmax, int bf16, bool any_x0, boo
     const int* st = starts_of(plan, KIND_TILE, count);
     const int* sg = starts_of(plan, KIND_GRAM, count);
     RTG_HIP(launch_init(plan.d_desc, count, s));
+    RTG_HIP(launch_compose(plan.d_desc, count, plan.compose_max, s));
     if (any_x0) RTG_TIMED(0, launch_phi(plan.d_desc, sp, count, plan.total[KIND_PHI], PS_X0, 0, plan.rmax, 0, s));
     RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_SKETCH_SRC, 0, 0, bf16, 0, plan.l1max, s));
     RTG_TIMED(2, launch_gram(plan.d_desc, sg, count, plan.total[KIND_GRAM], GM_START, 0, nullptr, s));
     RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_NEWV, 0, 0, bf16, 0, plan.l1max, s));
+    AuxStream* ax = nullptr;
+    int rc = aux_stream(&ax);
+    if (rc) return rc;
     for (int j = 1; j <= mmax; ++j) {
+        // S(V_j) and S(Phi(V_j)) come from the step that formed V_j, so the
+        // sketched Gram step runs on the second stream while W = Phi(V_j) is
+        // formed; the multi-AXPY waits for both
+        RTG_HIP(hipEventRecord(ax->fork, s));
+        RTG_HIP(hipStreamWaitEvent(ax->aux, ax->fork, 0));
+        RTG_TIMED_ON(2, ax->aux, launch_gram(plan.d_desc, sg, count, plan.total[KIND_GRAM], GM_STEP, j, nullptr, ax->aux));
+        RTG_HIP(hipEventRecord(ax->join, ax->aux));
         RTG_TIMED(0, launch_phi(plan.d_desc, sp, count, plan.total[KIND_PHI], PS_BASIS, j - 1, plan.rmax, bf16, s));
-        RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_SKETCH, 0, 0, bf16, 0, plan.l1max, s));
-        RTG_TIMED(2, launch_gram(plan.d_desc, sg, count, plan.total[KIND_GRAM], GM_STEP, j, nullptr, s));
+        RTG_HIP(hipStreamWaitEvent(s, ax->join, 0));
         if (j < mmax || last_newv)
             RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_NEWV, j, j, bf16, 0, plan.l1max, s));
     }
@@ -307,16 +358,27 @@ int rtg_setup_operator(int I1, int I2, int J, const float* a1_band, int r1, cons
     if (I1 < 8 || I2 < 1 || J < 1 || (I1 % 8) != 0) return RTG_E_SHAPE;
     if (r1 < 0 || r2 < 0 || rB < 0 || r1 > RMAX_SPATIAL || r2 > RMAX_SPATIAL || rB > RMAX_B) return RTG_E_SHAPE;
     if (r1 >= I1 || (r2 >= I2 && I2 > 1) || (rB >= J && J > 1)) return RTG_E_SHAPE;
-    rtg_op_s* op = new rtg_op_s{I1, I2, J, r1, r2, rB, nullptr, nullptr, nullptr};
+    rtg_op_s* op = new rtg_op_s{I1, I2, J, r1, r2, rB, nullptr, nullptr, nullptr, nullptr, nullptr};
     const size_t n1 = (size_t)I1 * (2 * r1 + 1), n2 = (size_t)I2 * (2 * r2 + 1), nb = (size_t)J * (2 * rB + 1);
     if (hipMalloc(&op->a1, n1 * 4) != hipSuccess || hipMalloc(&op->a2, n2 * 4) != hipSuccess ||
-        hipMalloc(&op->bb, nb * 4) != hipSuccess) {
+        hipMalloc(&op->bb, nb * 4) != hipSuccess || hipMalloc(&op->a1t, n1 * 4) != hipSuccess ||
+        hipMalloc(&op->a2t, n2 * 4) != hipSuccess) {
         rtg_destroy_operator(op);
         return RTG_E_NOMEM;
     }
+    auto transpose_band = [](const float* band, int I, int r) {
+        const int w = 2 * r + 1;
+        std::vector<float> t((size_t)I * w);
+        for (int i = 0; i < I; ++i)
+            for (int k = 0; k < w; ++k) t[(size_t)k * I + i] = band[(size_t)i * w + k];
+        return t;
+    };
+    const std::vector<float> a1t = transpose_band(a1_band, I1, r1), a2t = transpose_band(a2_band, I2, r2);
     if (hipMemcpy(op->a1, a1_band, n1 * 4, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(op->a2, a2_band, n2 * 4, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(op->bb, b_band, nb * 4, hipMemcpyHostToDevice) != hipSuccess) {
+        hipMemcpy(op->bb, b_band, nb * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(op->a1t, a1t.data(), n1 * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(op->a2t, a2t.data(), n2 * 4, hipMemcpyHostToDevice) != hipSuccess) {
         rtg_destroy_operator(op);
         return RTG_E_HIP;
     }
@@ -329,6 +391,8 @@ int rtg_destroy_operator(rtg_op op) {
     if (op->a1) (void)hipFree(op->a1);
     if (op->a2) (void)hipFree(op->a2);
     if (op->bb) (void)hipFree(op->bb);
+    if (op->a1t) (void)hipFree(op->a1t);
+    if (op->a2t) (void)hipFree(op->a2t);
     delete op;
     return RTG_OK;
 }
@@ -410,7 +474,7 @@ int rtg_sketch(rtg_sk sk, int x_dtype, const void* X, float* SX, void* ws, size_
     if (!aligned16(X) || !aligned16(ws)) return RTG_E_ARG;
     if (ws_bytes < rtg_sketch_workspace_bytes(sk)) return RTG_E_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
-    rtg_op_s dummy{sk->I1, sk->I2, sk->J, 0, 0, 0, nullptr, nullptr, nullptr};
+    rtg_op_s dummy{sk->I1, sk->I2, sk->J, 0, 0, 0, nullptr, nullptr, nullptr, nullptr, nullptr};
     Layout L = problem_layout(&dummy, sk, 1, x_dtype == RTG_BF16);
     std::vector<Desc> descs(1);
     fill_desc(descs[0], &dummy, sk, 1, x_dtype == RTG_BF16, nullptr, L);

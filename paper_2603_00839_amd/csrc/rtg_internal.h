@@ -56,10 +56,18 @@ struct Desc {
     const float* a1;
     const float* a2;
     const float* bb;
+    const float* a1t;             // bands transposed: a1t[(r1 + dd) I1 + i] = a1[i (2 r1 + 1) + r1 + dd]
+    const float* a2t;
     const float* om1;
     const bf16_t* om1h;           // bfloat16 copy of Om1
     const float* om2;
     const float* om3;             // nullptr => identity
+    // sketch of Phi(X) as a sketch of X (mode products compose, eq. (2)):
+    // Om1 A1 (float32, and bfloat16 high/low planes), Om2 A2, Om3 B^T (l3 x J)
+    const float* om1t;
+    const bf16_t* om1th;
+    const float* om2t;
+    const float* om3t;
     // data (device)
     const float* C;
     const float* X0;    // nullptr => 0
@@ -151,11 +159,12 @@ hipError_t launch_gram(const Desc* d, const int* starts, int count, int total_ti
                        int mode, int j, float* sketch_out, hipStream_t s);
 hipError_t launch_solve(const Desc* d, int count, hipStream_t s);
 hipError_t launch_init(const Desc* d, int count, hipStream_t s);
+hipError_t launch_compose(const Desc* d, int count, int max_entries, hipStream_t s);
 hipError_t launch_finish_arnoldi(const Desc* d, double* H, double* beta, int* m_done,
                                  int m, hipStream_t s);
 
 // k_tile modes
-enum TileMode { TM_SKETCH = 0, TM_NEWV = 1, TM_ASSEMBLE = 2, TM_SKETCH_SRC = 3 };
+enum TileMode { TM_NEWV = 1, TM_ASSEMBLE = 2, TM_SKETCH_SRC = 3 };
 // k_phi source selection
 enum PhiSrc { PS_BASIS = 0, PS_X0 = 1 };
 // k_gram modes
