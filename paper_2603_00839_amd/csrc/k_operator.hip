@@ -8,7 +8,7 @@
 // channel k is blurred spatially once and scattered into the (at most
 // 2 rB + 1) output channels it feeds.
 //
-// Tile: 64 rows (i1) x 32 columns (i2) x up to 8 output channels.  For every
+// Tile: 64 rows (i1) x 32 columns (i2) x up to JT (4 or 8) output channels.  For every
 // input channel the workgroup stages a (64 + 2R) x (32 + 2R) slab in LDS
 // (zeros outside the image), runs the i1 pass with lanes across columns
 // (band coefficients are wave-uniform), then the i2 pass with lanes across
@@ -39,15 +39,15 @@ __device__ __forceinline__ int xcd_remap(int b, int G) {
     return x * q + min(x, rem) + slot;
 }
 
-template <int R, bool BF16IN>
+template <int R, bool BF16IN, int JT>
 __device__ __forceinline__ void phi_tile(const PhiArgs& a, int tile, float* smem) {
-    constexpr int T1 = PHI_T1, T2 = PHI_T2, JT = PHI_JT;
+    constexpr int T1 = PHI_T1, T2 = PHI_T2;
     constexpr int SR = T1 + 2 * R;       // slab rows
     constexpr int SRP = SR + 1;          // padded (odd) row stride
     constexpr int SC = T2 + 2 * R;       // slab columns (<= 64)
     constexpr int ZRP = T1 + 1;
     constexpr int WP = ((2 * R + 1) + 3) / 4 * 4;   // padded taps per band row
-    constexpr int NKB = PHI_JT + 2 * RMAX_B;        // input channels per tile (max)
+    constexpr int NKB = JT + 2 * RMAX_B;            // input channels per tile (max)
     float* S = smem;                     // [SC][SRP]
     float* Z = S + SC * SRP;             // [SC][ZRP]
     float* A1c = Z + SC * ZRP;           // [T1][WP]: A1[i1, i1 + d], d = t - R (0 outside the band)
@@ -166,8 +166,24 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int tile, float* smem
             for (int o = 0; o < 8; ++o) acc[jj][o] = fmaf(bkj, u[o], acc[jj][o]);
         }
     }
-    // ---- store (lanes along i1: coalesced)
+    // ---- store (lanes along i1: coalesced).  In residual mode the values
+    // of C are loaded first, all together, from clamped addresses.
     const int i1 = i10 + lane;
+    const int i1c = min(i1, I1 - 1);
+    float cv[JT][8];
+    if (a.C) {
+#pragma unroll
+        for (int jj = 0; jj < JT; ++jj)
+#pragma unroll
+            for (int o = 0; o < 8; ++o) {
+                const int jc = min(j0 + jj, J - 1), i2c = min(i20 + wave * 8 + o, I2 - 1);
+                cv[jj][o] = *gptr(a.C + (size_t)jc * plane + (size_t)i2c * I1 + i1c);
+            }
+#pragma unroll
+        for (int jj = 0; jj < JT; ++jj)
+#pragma unroll
+            for (int o = 0; o < 8; ++o) acc[jj][o] = cv[jj][o] - acc[jj][o];
+    }
     if (i1 < I1) {
 #pragma unroll
         for (int jj = 0; jj < JT; ++jj) {
@@ -175,34 +191,29 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int tile, float* smem
 #pragma unroll
             for (int o = 0; o < 8; ++o) {
                 const int i2 = i20 + wave * 8 + o;
-                if (i2 < I2) {
-                    size_t off = (size_t)(j0 + jj) * plane + (size_t)i2 * I1 + i1;
-                    float v = acc[jj][o];
-                    if (a.C) v = *gptr(a.C + off) - v;
-                    *gptr_w(a.dst + off) = v;
-                }
+                if (i2 < I2) *gptr_w(a.dst + (size_t)(j0 + jj) * plane + (size_t)i2 * I1 + i1) = acc[jj][o];
             }
         }
     }
 }
 
-template <int R>
+template <int R, int JT>
 constexpr int phi_smem_floats() {
     return (PHI_T2 + 2 * R) * (PHI_T1 + 2 * R + 1) + (PHI_T2 + 2 * R) * (PHI_T1 + 1) +
-           (PHI_T1 + PHI_T2) * (((2 * R + 1) + 3) / 4 * 4) + (PHI_JT + 2 * RMAX_B) * PHI_JT;
+           (PHI_T1 + PHI_T2) * (((2 * R + 1) + 3) / 4 * 4) + (JT + 2 * RMAX_B) * JT;
 }
 
-template <int R, bool BF16IN>
+template <int R, bool BF16IN, int JT>
 __global__ void __launch_bounds__(256) k_phi_single(PhiArgs a) {
-    __shared__ float smem[phi_smem_floats<R>()];
-    phi_tile<R, BF16IN>(a, xcd_remap(blockIdx.x, gridDim.x), smem);
+    __shared__ float smem[phi_smem_floats<R, JT>()];
+    phi_tile<R, BF16IN, JT>(a, xcd_remap(blockIdx.x, gridDim.x), smem);
 }
 
-template <int R, bool BF16IN>
+template <int R, bool BF16IN, int JT>
 __global__ void __launch_bounds__(256) k_phi_batched(const Desc* __restrict__ descs,
                                                      const int* __restrict__ starts, int count,
                                                      int src_sel, int src_index) {
-    __shared__ float smem[phi_smem_floats<R>()];
+    __shared__ float smem[phi_smem_floats<R, JT>()];
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int p = find_problem(starts, count, b);
     const Desc& d = descs[p];
@@ -220,38 +231,45 @@ __global__ void __launch_bounds__(256) k_phi_batched(const Desc* __restrict__ de
         a.C = d.C;
     }
     a.dst = d.W;
-    phi_tile<R, BF16IN>(a, b - starts[p], smem);
+    phi_tile<R, BF16IN, JT>(a, b - starts[p], smem);
 }
 
 static int phi_tier(int r) { return r <= 4 ? 4 : (r <= 8 ? 8 : 12); }
 
-int phi_tiles(int I1, int I2, int J) {
-    return ((I1 + PHI_T1 - 1) / PHI_T1) * ((I2 + PHI_T2 - 1) / PHI_T2) * ((J + PHI_JT - 1) / PHI_JT);
+int phi_jt(int max_j) { return max_j <= 4 ? 4 : 8; }
+
+int phi_tiles(int I1, int I2, int J, int jt) {
+    return ((I1 + PHI_T1 - 1) / PHI_T1) * ((I2 + PHI_T2 - 1) / PHI_T2) * ((J + jt - 1) / jt);
 }
 
 hipError_t launch_phi_single(int I1, int I2, int J, int r1, int r2, int rB, const float* a1,
                              const float* a2, const float* bb, const void* src, int bf16_in,
                              const float* C, float* dst, hipStream_t s) {
     PhiArgs a{I1, I2, J, r1, r2, rB, a1, a2, bb, src, C, dst};
-    const int tiles = phi_tiles(I1, I2, J);
+    const int jt = phi_jt(J);
+    const int tiles = phi_tiles(I1, I2, J, jt);
     const int tier = phi_tier(r1 > r2 ? r1 : r2);
-#define RTG_PHI_SINGLE(RR)                                                          \
-    if (bf16_in) hipLaunchKernelGGL((k_phi_single<RR, true>), dim3(tiles), dim3(256), 0, s, a); \
-    else hipLaunchKernelGGL((k_phi_single<RR, false>), dim3(tiles), dim3(256), 0, s, a);
-    if (tier == 4) { RTG_PHI_SINGLE(4) } else if (tier == 8) { RTG_PHI_SINGLE(8) } else { RTG_PHI_SINGLE(12) }
+#define RTG_PHI_SINGLE(RR, JJ)                                                                      \
+    if (bf16_in) hipLaunchKernelGGL((k_phi_single<RR, true, JJ>), dim3(tiles), dim3(256), 0, s, a); \
+    else hipLaunchKernelGGL((k_phi_single<RR, false, JJ>), dim3(tiles), dim3(256), 0, s, a);
+#define RTG_PHI_SINGLE_J(RR) if (jt == 4) { RTG_PHI_SINGLE(RR, 4) } else { RTG_PHI_SINGLE(RR, 8) }
+    if (tier == 4) { RTG_PHI_SINGLE_J(4) } else if (tier == 8) { RTG_PHI_SINGLE_J(8) } else { RTG_PHI_SINGLE_J(12) }
+#undef RTG_PHI_SINGLE_J
 #undef RTG_PHI_SINGLE
     return hipGetLastError();
 }
 
 hipError_t launch_phi(const Desc* d, const int* starts, int count, int total_tiles, int src_sel,
-                      int src_index, int rmax, int bf16_in, hipStream_t s) {
+                      int src_index, int rmax, int jt, int bf16_in, hipStream_t s) {
     const int tier = phi_tier(rmax);
-#define RTG_PHI_BATCH(RR)                                                                   \
-    if (bf16_in) hipLaunchKernelGGL((k_phi_batched<RR, true>), dim3(total_tiles), dim3(256), 0, s, \
-                                    d, starts, count, src_sel, src_index);                 \
-    else hipLaunchKernelGGL((k_phi_batched<RR, false>), dim3(total_tiles), dim3(256), 0, s, \
+#define RTG_PHI_BATCH(RR, JJ)                                                                   \
+    if (bf16_in) hipLaunchKernelGGL((k_phi_batched<RR, true, JJ>), dim3(total_tiles), dim3(256), 0, s, \
+                                    d, starts, count, src_sel, src_index);                     \
+    else hipLaunchKernelGGL((k_phi_batched<RR, false, JJ>), dim3(total_tiles), dim3(256), 0, s, \
                             d, starts, count, src_sel, src_index);
-    if (tier == 4) { RTG_PHI_BATCH(4) } else if (tier == 8) { RTG_PHI_BATCH(8) } else { RTG_PHI_BATCH(12) }
+#define RTG_PHI_BATCH_J(RR) if (jt == 4) { RTG_PHI_BATCH(RR, 4) } else { RTG_PHI_BATCH(RR, 8) }
+    if (tier == 4) { RTG_PHI_BATCH_J(4) } else if (tier == 8) { RTG_PHI_BATCH_J(8) } else { RTG_PHI_BATCH_J(12) }
+#undef RTG_PHI_BATCH_J
 #undef RTG_PHI_BATCH
     return hipGetLastError();
 }

@@ -178,39 +178,44 @@ __global__ void __launch_bounds__(256) k_tile(const Desc* __restrict__ descs,
                     x[u][q + 2] = __uint_as_float(v[2]); x[u][q + 3] = __uint_as_float(v[3]);
                 }
         }
-        for (int i = 0; i < nterms; ++i) {
-            const float ci = coef_s[i];
+        // multi-AXPY, software-pipelined: the next stage's loads are in
+        // flight while the current stage is applied.  A stage is one term
+        // (bfloat16 basis: 4 chunks) or half a term (float32: 4 of 8 chunks).
+        constexpr int SPT = BB ? 1 : 2;          // stages per term
+        constexpr int CPS = NCK / SPT;           // chunks per stage
+        const int nst = nterms * SPT;
+        auto load_stage = [&](int st, u4* v) {
+            const int i = st / SPT, c0 = (st % SPT) * CPS;
             const auto rv = make_rsrc((const char*)d.V + ((size_t)i * d.n + tile_off) * es, tile_elems * (int)es);
-            if constexpr (BB) {
-                // two halves of the lane's chunks (packed, unpacked just before use)
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    u4 v[NCK / 2];
+            for (int u = 0; u < CPS; ++u)
+                v[u] = __builtin_amdgcn_raw_buffer_load_b128(rv, offs[c0 + u] * (unsigned)es, 0, 0);
+        };
+        auto apply_stage = [&](int st, const u4* v) {
+            const float ci = coef_s[st / SPT];
+            const int c0 = (st % SPT) * CPS;
 #pragma unroll
-                    for (int uu = 0; uu < NCK / 2; ++uu)
-                        v[uu] = __builtin_amdgcn_raw_buffer_load_b128(rv, offs[h * (NCK / 2) + uu] * 2u, 0, 0);
+            for (int uu = 0; uu < CPS; ++uu)
 #pragma unroll
-                    for (int uu = 0; uu < NCK / 2; ++uu)
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const int u = h * (NCK / 2) + uu;
-                            x[u][2 * q] = fmaf(-ci, __uint_as_float(v[uu][q] << 16), x[u][2 * q]);
-                            x[u][2 * q + 1] = fmaf(-ci, __uint_as_float(v[uu][q] & 0xffff0000u), x[u][2 * q + 1]);
-                        }
+                for (int q = 0; q < 4; ++q) {
+                    if constexpr (BB) {
+                        x[uu][2 * q] = fmaf(-ci, __uint_as_float(v[uu][q] << 16), x[uu][2 * q]);
+                        x[uu][2 * q + 1] = fmaf(-ci, __uint_as_float(v[uu][q] & 0xffff0000u), x[uu][2 * q + 1]);
+                    } else {
+                        // c0 is 0 or CPS: select the half with a uniform branch-free index
+                        float& xr = (c0 == 0) ? x[uu][q] : x[CPS + uu][q];
+                        xr = fmaf(-ci, __uint_as_float(v[uu][q]), xr);
+                    }
                 }
-            } else {
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    u4 v[NCK / 2];
-#pragma unroll
-                    for (int uu = 0; uu < NCK / 2; ++uu)
-                        v[uu] = __builtin_amdgcn_raw_buffer_load_b128(rv, offs[h * (NCK / 2) + uu] * 4u, 0, 0);
-#pragma unroll
-                    for (int uu = 0; uu < NCK / 2; ++uu)
-#pragma unroll
-                        for (int q = 0; q < 4; ++q)
-                            x[h * (NCK / 2) + uu][q] = fmaf(-ci, __uint_as_float(v[uu][q]), x[h * (NCK / 2) + uu][q]);
-                }
+        };
+        u4 va[CPS], vb[CPS];
+        if (nst > 0) load_stage(0, va);
+        for (int st = 0; st < nst; st += 2) {
+            if (st + 1 < nst) load_stage(st + 1, vb);
+            apply_stage(st, va);
+            if (st + 1 < nst) {
+                if (st + 2 < nst) load_stage(st + 2, va);
+                apply_stage(st + 1, vb);
             }
         }
         // scale (chunks outside the tile are zero already), round (bfloat16 basis), store

@@ -63,7 +63,7 @@ Layout problem_layout(const rtg_op_s* op, const rtg_sk_s* sk, int m, int bf16) {
     L.ntile_tile = op->J * L.n_i2t;
     const int ch = gram_pairs_per_block(sk->l3);
     L.ntile_gram = (sk->l1 * sk->l2 + ch - 1) / ch;
-    L.ntile_phi = phi_tiles(op->I1, op->I2, op->J);
+    L.ntile_phi = phi_tiles(op->I1, op->I2, op->J, phi_jt(op->J));
     const size_t part = (size_t)L.ntile_tile * sk->l1 * sk->l2 * sizeof(float);
     size_t off = 0;
     auto take = [&](size_t bytes) { off = align_up(off); size_t at = off; off += bytes; return at; };
@@ -174,11 +174,17 @@ struct Plan {
     int rmax;
     int l1max;
     int compose_max;   // largest l1 I1 + l2 I2 + l3 J of the batch
+    int phi_jt;        // output channels per operator tile (one choice per batch)
 };
 
 int build_plan(std::vector<Desc>& descs, void* ws, hipStream_t s, Plan& plan) {
     const int count = (int)descs.size();
     std::vector<int> starts((size_t)NKIND * (count + 1), 0);
+    int maxJ = 1;
+    for (auto& d : descs) maxJ = std::max(maxJ, d.J);
+    plan.phi_jt = phi_jt(maxJ);
+    for (auto& d : descs)
+        if (d.ntile[KIND_PHI] > 0) d.ntile[KIND_PHI] = phi_tiles(d.I1, d.I2, d.J, plan.phi_jt);
     plan.rmax = 1;
     for (int k = 0; k < NKIND; ++k) {
         int acc = 0;
@@ -291,7 +297,7 @@ int run_solver(const Plan& plan, int count, int mmax, int bf16, bool any_x0, boo
     const int* sg = starts_of(plan, KIND_GRAM, count);
     RTG_HIP(launch_init(plan.d_desc, count, s));
     RTG_HIP(launch_compose(plan.d_desc, count, plan.compose_max, s));
-    if (any_x0) RTG_TIMED(0, launch_phi(plan.d_desc, sp, count, plan.total[KIND_PHI], PS_X0, 0, plan.rmax, 0, s));
+    if (any_x0) RTG_TIMED(0, launch_phi(plan.d_desc, sp, count, plan.total[KIND_PHI], PS_X0, 0, plan.rmax, plan.phi_jt, 0, s));
     RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_SKETCH_SRC, 0, 0, bf16, 0, plan.l1max, s));
     RTG_TIMED(2, launch_gram(plan.d_desc, sg, count, plan.total[KIND_GRAM], GM_START, 0, nullptr, s));
     RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_NEWV, 0, 0, bf16, 0, plan.l1max, s));
@@ -306,7 +312,7 @@ int run_solver(const Plan& plan, int count, int mmax, int bf16, bool any_x0, boo
         RTG_HIP(hipStreamWaitEvent(ax->aux, ax->fork, 0));
         RTG_TIMED_ON(2, ax->aux, launch_gram(plan.d_desc, sg, count, plan.total[KIND_GRAM], GM_STEP, j, nullptr, ax->aux));
         RTG_HIP(hipEventRecord(ax->join, ax->aux));
-        RTG_TIMED(0, launch_phi(plan.d_desc, sp, count, plan.total[KIND_PHI], PS_BASIS, j - 1, plan.rmax, bf16, s));
+        RTG_TIMED(0, launch_phi(plan.d_desc, sp, count, plan.total[KIND_PHI], PS_BASIS, j - 1, plan.rmax, plan.phi_jt, bf16, s));
         RTG_HIP(hipStreamWaitEvent(s, ax->join, 0));
         if (j < mmax || last_newv)
             RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_NEWV, j, j, bf16, 0, plan.l1max, s));

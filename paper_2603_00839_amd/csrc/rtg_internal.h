@@ -22,10 +22,9 @@ constexpr int LMAX_SPATIAL = 128;  // max l1, l2
 constexpr int LMAX_3 = 16;         // max l3 when Om3 is given
 constexpr int MMAX = 96;           // max Arnoldi steps (FP64 SVD fits in LDS)
 
-// operator tile (k_phi): T1 rows (i1) x T2 columns (i2) x JT channels
+// operator tile (k_phi): T1 rows (i1) x T2 columns (i2) x JT (4 or 8) channels
 constexpr int PHI_T1 = 64;
 constexpr int PHI_T2 = 32;
-constexpr int PHI_JT = 8;
 // AXPY/sketch tile (k_tile): I1 rows x TC columns of one channel
 constexpr int TILE_TC = 32;
 // sketched-Gram chunk (k_gram): CH (a,b) pairs per workgroup
@@ -146,9 +145,10 @@ __device__ __forceinline__ T wave_sum(T v) {
 // host-side launchers (one per translation unit)
 // ---------------------------------------------------------------------------
 namespace rtg {
-int phi_tiles(int I1, int I2, int J);
+int phi_jt(int max_j);
+int phi_tiles(int I1, int I2, int J, int jt);
 hipError_t launch_phi(const Desc* d, const int* starts, int count, int total_tiles,
-                      int src_sel, int src_index, int rmax, int bf16_in, hipStream_t s);
+                      int src_sel, int src_index, int rmax, int jt, int bf16_in, hipStream_t s);
 hipError_t launch_phi_single(int I1, int I2, int J, int r1, int r2, int rB, const float* a1,
                              const float* a2, const float* bb, const void* src, int bf16_in,
                              const float* C, float* dst, hipStream_t s);
