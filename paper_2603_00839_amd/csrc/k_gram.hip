@@ -29,43 +29,69 @@ __device__ __forceinline__ double load_coherent(const double* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// s_out[e] for the pairs [q0, q0 + qn): e = (q - q0) * l3 + c'
-// m3: mode-3 matrix (l3 x J), nullptr for the identity
-__device__ __forceinline__ void finish_sketch(const Desc& d, const float* __restrict__ Pbuf, int q0,
-                                              int qn, float* s_out, const float* __restrict__ m3) {
+// Finished sketch for the pairs [q0, q0 + qn):
+//   out[(q - q0) l3 + c'] = sum_c M[c', c] sum_{i2 tiles t of channel c} P[(c, t)][q]
+// with M = m3 (l3 x J) or the identity (m3 == nullptr); band >= 0 says that
+// M[c', c] = 0 for |c' - c| > band.  NB buffers are finished together.
+// Output channels are taken 16 at a time; for each input channel the
+// partials (16 tiles at a time) and the weights are loaded together, all in
+// flight (clamped indices, masked), and summed in a fixed order.
+template <int NB>
+__device__ __forceinline__ void finish_sketches(const Desc& d, int q0, int qn,
+                                                const float* __restrict__ P0, const float* __restrict__ m30,
+                                                int band0, float* out0, const float* __restrict__ P1,
+                                                const float* __restrict__ m31, int band1, float* out1) {
+    constexpr int U = 16, G3 = 16;
     const int tid = threadIdx.x;
     const int L12 = d.l1 * d.l2;
     const int J = d.J, nt2 = d.n_i2t, l3 = d.l3;
+    // channels that feed output channels [g, g + G3)
+    auto reach = [&](const float* m3, int band) { return m3 == nullptr ? 0 : (band >= 0 ? band : J); };
+    const int rch = max(reach(m30, band0), NB > 1 ? reach(m31, band1) : 0);
     for (int t = tid; t < qn; t += blockDim.x) {
         const int q = q0 + t;
-        float acc3[LMAX_3];
+        for (int g = 0; g < l3; g += G3) {
+            float a0[G3], a1[G3];
 #pragma unroll
-        for (int c3 = 0; c3 < LMAX_3; ++c3) acc3[c3] = 0.f;
-        for (int c = 0; c < J; ++c) {
-            // partials of the i2 tiles of channel c (independent loads in flight)
-            const float* pc = Pbuf + (size_t)c * nt2 * L12 + q;
-            float Qp[8];
+            for (int c3 = 0; c3 < G3; ++c3) { a0[c3] = 0.f; a1[c3] = 0.f; }
+            const int clo = max(0, g - rch), chi = min(J, g + G3 + rch);
+            for (int c = clo; c < chi; ++c) {
+                float w0[G3], w1[G3];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) Qp[u] = 0.f;
-            int t2 = 0;
-            for (; t2 + 8 <= nt2; t2 += 8) {
+                for (int c3 = 0; c3 < G3; ++c3) {
+                    const int r = min(g + c3, l3 - 1);
+                    w0[c3] = m30 ? *gptr(m30 + (size_t)r * J + c) : (g + c3 == c ? 1.f : 0.f);
+                    if constexpr (NB > 1) w1[c3] = m31 ? *gptr(m31 + (size_t)r * J + c) : (g + c3 == c ? 1.f : 0.f);
+                }
+                const size_t cb = (size_t)c * nt2 * L12 + q;
+                float Q0 = 0.f, Q1 = 0.f;
+                for (int t20 = 0; t20 < nt2; t20 += U) {
+                    float v0[U], v1[U];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) Qp[u] += *gptr(pc + (size_t)(t2 + u) * L12);
+                    for (int u = 0; u < U; ++u) {
+                        const size_t off = cb + (size_t)min(t20 + u, nt2 - 1) * L12;
+                        v0[u] = *gptr(P0 + off);
+                        if constexpr (NB > 1) v1[u] = *gptr(P1 + off);
+                    }
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const bool ok = t20 + u < nt2;
+                        Q0 += ok ? v0[u] : 0.f;
+                        if constexpr (NB > 1) Q1 += ok ? v1[u] : 0.f;
+                    }
+                }
+#pragma unroll
+                for (int c3 = 0; c3 < G3; ++c3) {
+                    a0[c3] = fmaf(w0[c3], Q0, a0[c3]);
+                    if constexpr (NB > 1) a1[c3] = fmaf(w1[c3], Q1, a1[c3]);
+                }
             }
-            for (; t2 < nt2; ++t2) Qp[0] += pc[(size_t)t2 * L12];
-            const float Q = ((Qp[0] + Qp[1]) + (Qp[2] + Qp[3])) + ((Qp[4] + Qp[5]) + (Qp[6] + Qp[7]));
-            if (m3) {
 #pragma unroll
-                for (int c3 = 0; c3 < LMAX_3; ++c3)
-                    if (c3 < l3) acc3[c3] = fmaf(m3[(size_t)c3 * J + c], Q, acc3[c3]);
-            } else {
-                s_out[t * l3 + c] = Q;
+            for (int c3 = 0; c3 < G3; ++c3) {
+                if (g + c3 >= l3) break;
+                out0[t * l3 + g + c3] = a0[c3];
+                if constexpr (NB > 1) out1[t * l3 + g + c3] = a1[c3];
             }
-        }
-        if (m3) {
-#pragma unroll
-            for (int c3 = 0; c3 < LMAX_3; ++c3)
-                if (c3 < l3) s_out[t * l3 + c3] = acc3[c3];
         }
     }
 }
@@ -95,9 +121,10 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
 
     // in a step the W partials are those of S(Phi(V_j)) taken with the
     // composed first two matrices, so mode 3 is Om3 B^T
+    // (Om3 B^T is banded when Om3 is the identity)
     const float* om3 = d.has_om3 ? d.om3 : nullptr;
-    finish_sketch(d, d.PW, q0, qn, s_s, mode == GM_STEP ? d.om3t : om3);
-    if (mode == GM_STEP) finish_sketch(d, d.PV, q0, qn, s_v, om3);
+    if (mode == GM_STEP) finish_sketches<2>(d, q0, qn, d.PW, d.om3t, d.has_om3 ? -1 : d.rB, s_s, d.PV, om3, -1, s_v);
+    else finish_sketches<1>(d, q0, qn, d.PW, om3, -1, s_s, nullptr, nullptr, -1, nullptr);
     __syncthreads();
 
     if (mode == GM_SKETCH_OUT) {
@@ -127,6 +154,7 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
         double as[IG], av[IG];
 #pragma unroll
         for (int u = 0; u < IG; ++u) { as[u] = 0.0; av[u] = 0.0; }
+#pragma unroll 3
         for (int e = lane; e < E; e += 64) {
             const double se = s_s[e], ve = s_v[e];
             float xv[IG];
@@ -234,15 +262,21 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
     auto gmatvec = [&](const double* v, double* out, bool make_h) {
         for (int i0 = wave * 4; i0 < j; i0 += 16) {
             double acc4[4] = {0.0, 0.0, 0.0, 0.0};
+            double gi[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) gi[u] = gnew[min(i0 + u, j - 1)];
             for (int k = lane; k < j; k += 64) {
                 const double vk = v[k];
+                const double gk = gnew[k];
                 double gl[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) gl[u] = *gptr(d.G + (size_t)min(i0 + u, j - 1) * ldg + k);
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
+                    // row / column jm of G are the new entries (held in LDS)
                     const int i = min(i0 + u, j - 1);
-                    const double gik = (i == jm) ? gnew[k] : (k == jm ? gnew[i] : gl[u]);
+                    double gik = (k == jm) ? gi[u] : gl[u];
+                    gik = (i == jm) ? gk : gik;
                     acc4[u] += gik * vk;
                 }
             }

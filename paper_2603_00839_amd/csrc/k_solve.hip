@@ -10,7 +10,7 @@
 //   phi(mu) = sum_i (mu / (s_i^2 + mu))^2 ghat_i^2 + gamma^2
 // is the projected residual; it increases from gamma^2 to beta^2 and the
 // discrepancy principle takes the root of phi(mu) = (eta delta)^2, found by
-// bisection in log(mu).  Then y = W diag(s / (s^2 + mu)) ghat, the filter
+// multisection (64 points per pass) in log(mu).  Then y = W diag(s / (s^2 + mu)) ghat, the filter
 // form of the stacked least-squares problem (13).  The kernel writes the
 // coefficients -y_j of the solution update and the result summary.
 #include "rtg_internal.h"
@@ -169,9 +169,26 @@ __global__ void __launch_bounds__(1024) k_solve(const Desc* __restrict__ descs) 
                 double lo = log(smax2) - 80.0, hi = log(smax2) + 80.0;
                 for (int it = 0; it < 40 && proj_res2(sig, gh, k, exp(lo), gp2, lane) > t2; ++it) lo -= 40.0;
                 for (int it = 0; it < 40 && proj_res2(sig, gh, k, exp(hi), gp2, lane) < t2; ++it) hi += 40.0;
-                for (int it = 0; it < 200; ++it) {
-                    const double mid = 0.5 * (lo + hi);
-                    if (proj_res2(sig, gh, k, exp(mid), gp2, lane) < t2) lo = mid; else hi = mid;
+                // Multisection in log(mu): each lane evaluates phi at one of 64
+                // interior points of [lo, hi]; phi increases with mu, so the
+                // lanes below the target form a prefix and the bracket shrinks
+                // 65-fold per pass (the bracket bisection would reach, six
+                // halvings at a time), until it stops shrinking.
+                for (int it = 0; it < 16; ++it) {
+                    const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
+                    double ph = gp2;
+                    const double mu_l = exp(x);
+                    for (int i = 0; i < k; ++i) {
+                        const double f = mu_l / (sig[i] * sig[i] + mu_l);
+                        ph += f * f * gh[i] * gh[i];
+                    }
+                    const unsigned long long below = __ballot(ph < t2);
+                    const int pfx = (below == ~0ull) ? 64 : __builtin_ctzll(~below);
+                    const double nlo = pfx > 0 ? __shfl(x, pfx - 1, 64) : lo;
+                    const double nhi = pfx < 64 ? __shfl(x, pfx, 64) : hi;
+                    if (!(nhi - nlo < hi - lo)) break;
+                    lo = nlo;
+                    hi = nhi;
                 }
                 mu = exp(0.5 * (lo + hi));
             }
@@ -297,8 +314,14 @@ __global__ void k_finish_arnoldi(const Desc* __restrict__ descs, double* H, doub
     }
 }
 
-hipError_t launch_solve(const Desc* d, int count, hipStream_t s) {
-    hipLaunchKernelGGL(k_solve, dim3(count), dim3(1024), 0, s, d);
+hipError_t launch_solve(const Desc* d, int count, int mmax, hipStream_t s) {
+    // sixteen lanes per Jacobi column pair; at least 128 threads (one per
+    // column for the final products), so that small problems synchronise
+    // few waves
+    int threads = 16 * ((mmax + 1) / 2);
+    threads = (threads + 63) / 64 * 64;
+    threads = threads < 128 ? 128 : (threads > 1024 ? 1024 : threads);
+    hipLaunchKernelGGL(k_solve, dim3(count), dim3(threads), 0, s, d);
     return hipGetLastError();
 }
 

@@ -263,32 +263,6 @@ struct TimedLaunch {
     } while (0)
 #define RTG_TIMED(kind, call) RTG_TIMED_ON(kind, s, call)
 
-// Second stream for work of a step that does not depend on the operator
-// application (the sketched Gram step), forked from and joined back into the
-// caller's stream with events.  One per host thread and device, so that
-// concurrent callers never share the fork/join events.  Default priority.
-struct AuxStream {
-    int device = -1;
-    hipStream_t aux = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
-};
-thread_local AuxStream t_aux[16];
-
-int aux_stream(AuxStream** out) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) return RTG_E_HIP;
-    AuxStream& a = t_aux[dev];
-    if (a.aux == nullptr) {
-        if (hipStreamCreateWithFlags(&a.aux, hipStreamNonBlocking) != hipSuccess) return RTG_E_HIP;
-        if (hipEventCreateWithFlags(&a.fork, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&a.join, hipEventDisableTiming) != hipSuccess)
-            return RTG_E_HIP;
-        a.device = dev;
-    }
-    *out = &a;
-    return RTG_OK;
-}
-
 // Arnoldi loop + (optionally) solve and assembly for a prepared plan.
 int run_solver(const Plan& plan, int count, int mmax, int bf16, bool any_x0, bool solve,
                bool last_newv, hipStream_t s) {
@@ -301,24 +275,18 @@ int run_solver(const Plan& plan, int count, int mmax, int bf16, bool any_x0, boo
     RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_SKETCH_SRC, 0, 0, bf16, 0, plan.l1max, s));
     RTG_TIMED(2, launch_gram(plan.d_desc, sg, count, plan.total[KIND_GRAM], GM_START, 0, nullptr, s));
     RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_NEWV, 0, 0, bf16, 0, plan.l1max, s));
-    AuxStream* ax = nullptr;
-    int rc = aux_stream(&ax);
-    if (rc) return rc;
     for (int j = 1; j <= mmax; ++j) {
         // S(V_j) and S(Phi(V_j)) come from the step that formed V_j, so the
-        // sketched Gram step runs on the second stream while W = Phi(V_j) is
-        // formed; the multi-AXPY waits for both
-        RTG_HIP(hipEventRecord(ax->fork, s));
-        RTG_HIP(hipStreamWaitEvent(ax->aux, ax->fork, 0));
-        RTG_TIMED_ON(2, ax->aux, launch_gram(plan.d_desc, sg, count, plan.total[KIND_GRAM], GM_STEP, j, nullptr, ax->aux));
-        RTG_HIP(hipEventRecord(ax->join, ax->aux));
+        // sketched Gram step does not wait for W = Phi(V_j).  (Running the two
+        // on separate streams was measured slower than in sequence: both
+        // launches fill the chip.)
+        RTG_TIMED(2, launch_gram(plan.d_desc, sg, count, plan.total[KIND_GRAM], GM_STEP, j, nullptr, s));
         RTG_TIMED(0, launch_phi(plan.d_desc, sp, count, plan.total[KIND_PHI], PS_BASIS, j - 1, plan.rmax, plan.phi_jt, bf16, s));
-        RTG_HIP(hipStreamWaitEvent(s, ax->join, 0));
         if (j < mmax || last_newv)
             RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_NEWV, j, j, bf16, 0, plan.l1max, s));
     }
     if (solve) {
-        RTG_TIMED(3, launch_solve(plan.d_desc, count, s));
+        RTG_TIMED(3, launch_solve(plan.d_desc, count, mmax, s));
         RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_ASSEMBLE, 0, 0, bf16, 0, plan.l1max, s));
     }
     return RTG_OK;

@@ -157,7 +157,7 @@ hipError_t launch_tile(const Desc* d, const int* starts, int count, int total_ti
                        int l1max, hipStream_t s);
 hipError_t launch_gram(const Desc* d, const int* starts, int count, int total_tiles,
                        int mode, int j, float* sketch_out, hipStream_t s);
-hipError_t launch_solve(const Desc* d, int count, hipStream_t s);
+hipError_t launch_solve(const Desc* d, int count, int mmax, hipStream_t s);
 hipError_t launch_init(const Desc* d, int count, hipStream_t s);
 hipError_t launch_compose(const Desc* d, int count, int max_entries, hipStream_t s);
 hipError_t launch_finish_arnoldi(const Desc* d, double* H, double* beta, int* m_done,
