@@ -195,7 +195,8 @@ int rtg_cnn_adam(void* state, float lr, int step, void* stream);
 /* ---- measurement ----------------------------------------------------------
  * When enabled, every launch of the selected kernel kinds made by the solver
  * calls (bit k of kind_mask: 0 operator Phi, 1 multi-AXPY + sketch tile,
- * 2 sketched Gram / Hessenberg update, 3 projected Tikhonov solve) is
+ * 2 sketched Gram / Hessenberg update, 3 projected Tikhonov solve, 4 Arnoldi
+ * step with the operator applied on the fly) is
  * bracketed by two hipEvents recorded on the launch stream.
  * rtg_event_timing_read waits for those events and returns, per kind, the
  * summed duration in milliseconds and the number of launches, then clears

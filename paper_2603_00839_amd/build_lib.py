@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librtg.so")
-SOURCES = ["rtg_api.hip", "k_operator.hip", "k_tile.hip", "k_gram.hip", "k_solve.hip", "k_cnn.hip"]
+SOURCES = ["rtg_api.hip", "k_operator.hip", "k_tile.hip", "k_step.hip", "k_gram.hip", "k_solve.hip", "k_cnn.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -10,9 +10,11 @@
 //   beta = ||S(R0)||                       k_gram  (start)
 //   V1 = R0 / beta, partial S(V1), S(Phi(V1))                       k_tile
 //   for j = 1..m:
-//     W = Phi(V_j)                         k_phi
-//     S(V_j), S(W), h_{:,j}, h_{j+1,j}, Givens                      k_gram  (step)
-//     V_{j+1} = (W - sum h_ij V_i) / h_{j+1,j}, partial S(V_{j+1}), S(Phi(V_{j+1}))   k_tile
+//     S(V_j), S(Phi(V_j)), h_{:,j}, h_{j+1,j}, Givens               k_gram  (step)
+//     V_{j+1} = (Phi(V_j) - sum h_ij V_i) / h_{j+1,j},
+//     partial S(V_{j+1}), S(Phi(V_{j+1})):
+//       bfloat16 basis: Phi(V_j) formed tile by tile       k_step
+//       float32 basis:  W = Phi(V_j)                      k_phi, then k_tile
 //   projected Tikhonov problem, mu         k_solve
 //   X = X0 + sum y_j V_j                   k_tile  (assemble)
 // Every launch covers all problems of a batch; the host never waits.
@@ -220,7 +222,7 @@ const int* starts_of(const Plan& plan, int kind, int count) {
     } while (0)
 
 // ---- optional event timing of launches (measurement facility)
-constexpr int NTIMED = 4;   // 0 phi, 1 tile, 2 gram, 3 solve
+constexpr int NTIMED = 5;   // 0 operator, 1 tile, 2 gram, 3 solve, 4 step
 struct EventTiming {
     int mask = 0;
     std::vector<hipEvent_t> pool;
@@ -276,14 +278,22 @@ int run_solver(const Plan& plan, int count, int mmax, int bf16, bool any_x0, boo
     RTG_TIMED(2, launch_gram(plan.d_desc, sg, count, plan.total[KIND_GRAM], GM_START, 0, nullptr, s));
     RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_NEWV, 0, 0, bf16, 0, plan.l1max, s));
     for (int j = 1; j <= mmax; ++j) {
-        // S(V_j) and S(Phi(V_j)) come from the step that formed V_j, so the
-        // sketched Gram step does not wait for W = Phi(V_j).  (Running the two
-        // on separate streams was measured slower than in sequence: both
-        // launches fill the chip.)
+        // S(V_j) and S(Phi(V_j)) come from the pass that formed V_j.  With a
+        // bfloat16 basis the step kernel recomputes Phi(V_j) tile by tile (W
+        // is never stored); with a float32 basis W is formed by the operator
+        // kernel and read by the multi-AXPY tile kernel, which measured faster
+        // there (the fused kernel's float32 variant runs at lower occupancy).
         RTG_TIMED(2, launch_gram(plan.d_desc, sg, count, plan.total[KIND_GRAM], GM_STEP, j, nullptr, s));
-        RTG_TIMED(0, launch_phi(plan.d_desc, sp, count, plan.total[KIND_PHI], PS_BASIS, j - 1, plan.rmax, plan.phi_jt, bf16, s));
-        if (j < mmax || last_newv)
-            RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_NEWV, j, j, bf16, 0, plan.l1max, s));
+        if (j < mmax || last_newv) {
+            if (bf16) {
+                RTG_TIMED(4, launch_step(plan.d_desc, st, count, plan.total[KIND_TILE], j, plan.rmax, bf16, plan.l1max, s));
+            } else {
+                RTG_TIMED(0, launch_phi(plan.d_desc, sp, count, plan.total[KIND_PHI], PS_BASIS, j - 1, plan.rmax,
+                                        plan.phi_jt, bf16, s));
+                RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_NEWV, j, j, bf16, 0,
+                                         plan.l1max, s));
+            }
+        }
     }
     if (solve) {
         RTG_TIMED(3, launch_solve(plan.d_desc, count, mmax, s));

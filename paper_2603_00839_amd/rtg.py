@@ -381,7 +381,8 @@ def solve_batched(ops, sks, Cs, X0s, params, outs=None) -> BatchPlan:
 # ---------------------------------------------------------------------------
 # measurement
 # ---------------------------------------------------------------------------
-KIND_PHI, KIND_TILE, KIND_GRAM, KIND_SOLVE = 0, 1, 2, 3
+KIND_PHI, KIND_TILE, KIND_GRAM, KIND_SOLVE, KIND_STEP = 0, 1, 2, 3, 4
+N_KINDS = 5
 
 
 def event_timing_enable(kind_mask: int):
@@ -391,10 +392,10 @@ def event_timing_enable(kind_mask: int):
 def event_timing_read():
     """{kind: (total_ms, launches)} for the kernel kinds recorded since the
     last read (waits for the recorded events)."""
-    ms = (ctypes.c_double * 4)()
-    n = (ctypes.c_longlong * 4)()
-    _check(lib().rtg_event_timing_read(ms, n, 4), "rtg_event_timing_read")
-    return {k: (ms[k], n[k]) for k in range(4)}
+    ms = (ctypes.c_double * N_KINDS)()
+    n = (ctypes.c_longlong * N_KINDS)()
+    _check(lib().rtg_event_timing_read(ms, n, N_KINDS), "rtg_event_timing_read")
+    return {k: (ms[k], n[k]) for k in range(N_KINDS)}
 
 
 # ---------------------------------------------------------------------------
