@@ -15,11 +15,19 @@ Variants (each timed over the same number of steps):
 The JSON line reports the headline variant in "value" and both variants
 under "variants", with restoration errors against the ground truth.
 
-Live measurement: the multi-AXPY + sketch tile kernel (the dominant byte
-mover) is bracketed by HIP events on its launch stream inside the library;
-its algorithmic bytes (tensor reads and writes the method needs) over its
-measured time give the roofline entry.  The CPU baseline times the float64
-oracle on one problem of the same workload on the host cores.
+Live measurement: the dominant byte mover of the headline variant (the
+fused Arnoldi step kernel for the bfloat16 basis, the multi-AXPY tile kernel
+for the float32 one) is bracketed by HIP events on its launch stream inside
+the library; its algorithmic bytes (the tensor reads and writes the method
+needs) over its measured time give the roofline entry.  "traffic" is the
+rocprofv3-measured HBM traffic per launch recorded under profiles/ for the
+same kernel source (null once the source has changed).  The CPU baseline
+times the float64 oracle on one problem of the same workload on the host
+cores.
+
+--copy-calibration MB runs only a device-to-device copy of MB megabytes
+(three times), the plain copy kernel that calibrates the rocprofv3
+FETCH_SIZE / WRITE_SIZE counters.
 """
 import argparse
 import json
@@ -46,6 +54,8 @@ def parse():
     ap.add_argument("--x0", choices=["learned", "observation"], default="learned")
     ap.add_argument("--headline", choices=["auto", "fp32_plain", "bf16_warm"], default="auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
+                    help="only run a device-to-device copy of MB megabytes (counter calibration)")
     ap.add_argument("--only", choices=["fp32_plain", "bf16_warm"], default=None,
                     help="time one variant only (profiling runs)")
     return ap.parse_args()
@@ -78,24 +88,33 @@ def rel_err(x, xt):
     return float(torch.linalg.vector_norm((x - xt).double()) / torch.linalg.vector_norm(xt.double()))
 
 
-def tile_bytes(n, es, m_eff, has_x0, m_run):
+def step_bytes(n, es, m_eff):
+    """Algorithmic HBM bytes of the fused step launches of one bfloat16-basis
+    solve: step j reads V_1..V_j and writes V_{j+1}, (j + 1) tensors (the
+    operator's re-read of the V_j tile and its halo is not counted again; W is
+    never stored).  Steps j = 1 .. m_eff - 1 form a new tensor."""
+    return sum((j + 1) * es * n for j in range(1, m_eff))
+
+
+def tile_bytes(n, es, m_eff, has_x0):
     """Algorithmic HBM bytes of the multi-AXPY + sketch tile launches of one
-    solve (tensor traffic only): sketch of R0, V1 = R0/beta, per step the
-    sketch of W and the orthogonalisation/normalisation that reads W and
-    V_1..V_j and writes V_{j+1}, and the final assembly."""
-    b = 4 * n                                   # sketch of R0
-    b += 4 * n + es * n                         # V1
-    for j in range(1, m_eff + 1):
-        b += 4 * n                              # sketch of W = Phi(V_j)
-        if j < m_run and j < m_eff:
-            b += 4 * n + j * es * n + es * n    # V_{j+1}
-    b += (4 * n if has_x0 else 0) + m_eff * es * n + 4 * n   # X = X0 + V y
+    float32-basis solve: sketch of R0 (reads it), V1 = R0/beta (reads R0,
+    writes V1), steps j = 1 .. m_eff - 1 (read V_1..V_j, write V_{j+1}; the
+    read of the stored W is not counted: the method does not need W in
+    memory), and the assembly X = X0 + V y (reads X0, V_1..V_m, writes X)."""
+    b = 2 * 4 * n + es * n
+    for j in range(1, m_eff):
+        b += (j + 1) * es * n
+    b += (4 * n if has_x0 else 0) + m_eff * es * n + 4 * n
     return b
 
 
-def time_variant(plan, steps, warmup, rtg, torch, n, es, m_run, has_x0, pre=None):
+def time_variant(plan, steps, warmup, rtg, torch, kind, bytes_of, pre=None):
     """Time `steps` batch solves; `pre` (the warm-start network forward that
-    produces the X0 of the batch) runs inside every timed step."""
+    produces the X0 of the batch) runs inside every timed step.  Launches of
+    kernel kind `kind` are bracketed by HIP events on their stream inside the
+    library; `bytes_of(info)` gives the algorithmic bytes of those launches for
+    one problem."""
     def one():
         if pre is not None:
             pre()
@@ -104,7 +123,7 @@ def time_variant(plan, steps, warmup, rtg, torch, n, es, m_run, has_x0, pre=None
         one()
     torch.cuda.synchronize()
     rtg.event_timing_read()                     # clear
-    rtg.event_timing_enable(1 << rtg.KIND_TILE)
+    rtg.event_timing_enable(1 << kind)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -114,15 +133,35 @@ def time_variant(plan, steps, warmup, rtg, torch, n, es, m_run, has_x0, pre=None
     rtg.event_timing_enable(0)
     ev = rtg.event_timing_read()
     infos = plan.infos()
-    tb = sum(tile_bytes(n, es, inf.iters, has_x0, m_run) for inf in infos) * steps
-    tile_ms, tile_launches = ev[rtg.KIND_TILE]
+    kb = sum(bytes_of(inf) for inf in infos) * steps
+    k_ms, k_launches = ev[kind]
     return {
         "seconds": t1 - t0,
-        "tile_ms": tile_ms,
-        "tile_launches": tile_launches,
-        "tile_bytes": tb,
+        "k_ms": k_ms,
+        "k_launches": k_launches,
+        "k_bytes": kb,
         "infos": infos,
     }
+
+
+def recorded_traffic(kernel_src):
+    """HBM traffic per launch measured with rocprofv3 counters (FETCH_SIZE and
+    WRITE_SIZE, scaled by a copy-kernel calibration) and recorded with the
+    SHA-256 of the kernel source it was measured on; None when the kernel
+    source has changed since (or nothing was recorded)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    src = os.path.join(ROOT, "paper_2603_00839_amd", "csrc", kernel_src)
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    ent = rec.get(kernel_src)
+    if not ent or ent.get("source_sha256") != sha:
+        return None
+    return ent["bytes_per_launch"]
 
 
 def cpu_baseline(problem0):
@@ -164,6 +203,15 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+    if args.copy_calibration > 0:
+        nbytes = args.copy_calibration << 20
+        x = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": nbytes, "copies": 3}), flush=True)
+        return
     from paper_2603_00839_amd import rtg
     if not os.path.exists(rtg.LIB_PATH):
         from paper_2603_00839_amd import build_lib
@@ -198,11 +246,16 @@ def main():
         if v == "fp32_plain":
             prm = [rtg.make_params(args.m, rtg.F32, delta=q["delta"], eta=1.01) for q in probs]
             plan = rtg.BatchPlan([op] * B, [q["sk"] for q in probs], [q["C"] for q in probs], [None] * B, prm)
-            r = time_variant(plan, args.steps, args.warmup, rtg, torch, n, 4, args.m, False)
+            r = time_variant(plan, args.steps, args.warmup, rtg, torch, rtg.KIND_TILE,
+                             lambda inf: tile_bytes(n, 4, inf.iters, False))
+            r["kernel"] = ("k_tile", "k_tile.hip", "multi-AXPY + store + MFMA mode-1/2 sketch (float32 basis)")
         else:
             prm = [rtg.make_params(args.m_warm, rtg.BF16, delta=q["delta"], eta=1.01) for q in probs]
             plan = rtg.BatchPlan([op] * B, [q["sk"] for q in probs], [q["C"] for q in probs], X0s, prm)
-            r = time_variant(plan, args.steps, args.warmup, rtg, torch, n, 2, args.m_warm, True, pre=pre)
+            r = time_variant(plan, args.steps, args.warmup, rtg, torch, rtg.KIND_STEP,
+                             lambda inf: step_bytes(n, 2, inf.iters), pre=pre)
+            r["kernel"] = ("k_step", "k_step.hip", "Arnoldi step: operator per tile + multi-AXPY + store + "
+                                                   "dual MFMA sketch (bfloat16 basis)")
         res = [rel_err(plan.outs[b], probs[b]["xt"]) for b in range(B)]
         r["re_mean"] = float(np.mean(res))
         r["re_p0"] = res[0]
@@ -221,7 +274,9 @@ def main():
     if head not in results:
         head = variants[0]
     H = results[head]
-    gbs = H["tile_bytes"] / (H["tile_ms"] * 1e-3) / 1e9 if H["tile_ms"] > 0 else 0.0
+    gbs = H["k_bytes"] / (H["k_ms"] * 1e-3) / 1e9 if H["k_ms"] > 0 else 0.0
+    bpl = H["k_bytes"] / max(H["k_launches"], 1)
+    traffic = recorded_traffic(H["kernel"][1])
     out = {
         "metric": METRIC,
         "value": H["solves_per_s"],
@@ -244,15 +299,17 @@ def main():
         },
         "roofline": {
             "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": gbs / HBM_PEAK_GBS, "traffic": None,
-            "kernel": "k_tile (multi-AXPY + store + MFMA mode-1/2 sketch)",
-            "launches": H["tile_launches"],
-            "avg_launch_us": 1e3 * H["tile_ms"] / max(H["tile_launches"], 1),
-            "bytes_per_launch": H["tile_bytes"] / max(H["tile_launches"], 1),
+            "frac": gbs / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": f"{H['kernel'][0]} ({H['kernel'][2]})",
+            "launches": H["k_launches"],
+            "avg_launch_us": 1e3 * H["k_ms"] / max(H["k_launches"], 1),
+            "bytes_per_launch": bpl,
         },
         "variants": {k: {"solves_per_s": v["solves_per_s"], "ms_per_step": v["ms_per_step"],
                          "re_mean": v["re_mean"], "re_problem0": v["re_p0"], "iters_mean": v["iters_mean"],
-                         "flags": v["flags"]} for k, v in results.items()},
+                         "flags": v["flags"], "kernel": v["kernel"][0],
+                         "kernel_gbs": (v["k_bytes"] / (v["k_ms"] * 1e-3) / 1e9 if v["k_ms"] > 0 else 0.0)}
+                     for k, v in results.items()},
     }
     if not args.no_cpu_baseline:
         cb = cpu_baseline(p0)
