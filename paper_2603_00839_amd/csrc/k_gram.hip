@@ -55,35 +55,44 @@ __device__ __forceinline__ void finish_sketches(const Desc& d, int q0, int qn,
 #pragma unroll
             for (int c3 = 0; c3 < G3; ++c3) { a0[c3] = 0.f; a1[c3] = 0.f; }
             const int clo = max(0, g - rch), chi = min(J, g + G3 + rch);
-            for (int c = clo; c < chi; ++c) {
-                float w0[G3], w1[G3];
-#pragma unroll
-                for (int c3 = 0; c3 < G3; ++c3) {
-                    const int r = min(g + c3, l3 - 1);
-                    w0[c3] = m30 ? *gptr(m30 + (size_t)r * J + c) : (g + c3 == c ? 1.f : 0.f);
-                    if constexpr (NB > 1) w1[c3] = m31 ? *gptr(m31 + (size_t)r * J + c) : (g + c3 == c ? 1.f : 0.f);
-                }
-                const size_t cb = (size_t)c * nt2 * L12 + q;
-                float Q0 = 0.f, Q1 = 0.f;
+            // two input channels per pass: their partials (16 tiles each, both
+            // buffers) are all in flight together
+            for (int c0 = clo; c0 < chi; c0 += 2) {
+                float Q0[2] = {0.f, 0.f}, Q1[2] = {0.f, 0.f};
                 for (int t20 = 0; t20 < nt2; t20 += U) {
-                    float v0[U], v1[U];
+                    float v0[2][U], v1[2][U];
 #pragma unroll
-                    for (int u = 0; u < U; ++u) {
-                        const size_t off = cb + (size_t)min(t20 + u, nt2 - 1) * L12;
-                        v0[u] = *gptr(P0 + off);
-                        if constexpr (NB > 1) v1[u] = *gptr(P1 + off);
-                    }
+                    for (int cc = 0; cc < 2; ++cc)
 #pragma unroll
-                    for (int u = 0; u < U; ++u) {
-                        const bool ok = t20 + u < nt2;
-                        Q0 += ok ? v0[u] : 0.f;
-                        if constexpr (NB > 1) Q1 += ok ? v1[u] : 0.f;
-                    }
+                        for (int u = 0; u < U; ++u) {
+                            const int c = min(c0 + cc, chi - 1);
+                            const size_t off = ((size_t)c * nt2 + min(t20 + u, nt2 - 1)) * L12 + q;
+                            v0[cc][u] = *gptr(P0 + off);
+                            if constexpr (NB > 1) v1[cc][u] = *gptr(P1 + off);
+                        }
+#pragma unroll
+                    for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+                        for (int u = 0; u < U; ++u) {
+                            const bool ok = t20 + u < nt2;
+                            Q0[cc] += ok ? v0[cc][u] : 0.f;
+                            if constexpr (NB > 1) Q1[cc] += ok ? v1[cc][u] : 0.f;
+                        }
                 }
 #pragma unroll
-                for (int c3 = 0; c3 < G3; ++c3) {
-                    a0[c3] = fmaf(w0[c3], Q0, a0[c3]);
-                    if constexpr (NB > 1) a1[c3] = fmaf(w1[c3], Q1, a1[c3]);
+                for (int cc = 0; cc < 2; ++cc) {
+                    const int c = c0 + cc;
+                    if (c >= chi) break;
+#pragma unroll
+                    for (int c3 = 0; c3 < G3; ++c3) {
+                        const int r = min(g + c3, l3 - 1);
+                        const float w0 = m30 ? *gptr(m30 + (size_t)r * J + c) : (g + c3 == c ? 1.f : 0.f);
+                        a0[c3] = fmaf(w0, Q0[cc], a0[c3]);
+                        if constexpr (NB > 1) {
+                            const float w1 = m31 ? *gptr(m31 + (size_t)r * J + c) : (g + c3 == c ? 1.f : 0.f);
+                            a1[c3] = fmaf(w1, Q1[cc], a1[c3]);
+                        }
+                    }
                 }
             }
 #pragma unroll
@@ -148,22 +157,31 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
     // newest tensor S(V_j) and ||s||^2 from LDS.
     const int nitems = (mode == GM_STEP) ? j + 1 : 1;
     const int nglob = (mode == GM_STEP) ? j - 1 : 0;
-    constexpr int IG = 8;
+    // four items per wave; sixteen elements per lane of each item in flight
+    constexpr int IG = 4, EU = 16;
     for (int it0 = wave * IG; it0 < nglob; it0 += 4 * IG) {
         const float* svb = d.SV + (size_t)q0 * l3;
         double as[IG], av[IG];
 #pragma unroll
         for (int u = 0; u < IG; ++u) { as[u] = 0.0; av[u] = 0.0; }
-#pragma unroll 3
-        for (int e = lane; e < E; e += 64) {
-            const double se = s_s[e], ve = s_v[e];
-            float xv[IG];
+        for (int e0 = lane; e0 < E; e0 += 64 * EU) {
+            float xv[EU][IG];
 #pragma unroll
-            for (int u = 0; u < IG; ++u) xv[u] = *gptr(svb + (size_t)min(it0 + u, nglob - 1) * Lsz + e);
+            for (int eu = 0; eu < EU; ++eu)
 #pragma unroll
-            for (int u = 0; u < IG; ++u) {
-                as[u] += (double)xv[u] * se;
-                av[u] += (double)xv[u] * ve;
+                for (int u = 0; u < IG; ++u)
+                    xv[eu][u] = *gptr(svb + (size_t)min(it0 + u, nglob - 1) * Lsz + min(e0 + 64 * eu, E - 1));
+#pragma unroll
+            for (int eu = 0; eu < EU; ++eu) {
+                const int e = e0 + 64 * eu;
+                const bool ok = e < E;
+                const double se = ok ? (double)s_s[min(e, E - 1)] : 0.0;
+                const double ve = ok ? (double)s_v[min(e, E - 1)] : 0.0;
+#pragma unroll
+                for (int u = 0; u < IG; ++u) {
+                    as[u] += (double)xv[eu][u] * se;
+                    av[u] += (double)xv[eu][u] * ve;
+                }
             }
         }
 #pragma unroll
