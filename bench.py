@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--m", type=int, default=50)
     ap.add_argument("--m-warm", type=int, default=10, help="Arnoldi steps of the warm-started BF16 solve")
+    ap.add_argument("--warm-stop", choices=["fixed", "discrepancy"], default="discrepancy",
+                    help="warm-started solve: run --m-warm steps, or stop at the first step whose projected "
+                         "least-squares residual is within the discrepancy level eta*delta (at most --m-warm)")
     ap.add_argument("--x0", choices=["learned", "observation"], default="learned")
     ap.add_argument("--headline", choices=["auto", "fp32_plain", "bf16_warm"], default="auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -250,7 +253,9 @@ def main():
                              lambda inf: tile_bytes(n, 4, inf.iters, False))
             r["kernel"] = ("k_tile", "k_tile.hip", "multi-AXPY + store + MFMA mode-1/2 sketch (float32 basis)")
         else:
-            prm = [rtg.make_params(args.m_warm, rtg.BF16, delta=q["delta"], eta=1.01) for q in probs]
+            prm = [rtg.make_params(args.m_warm, rtg.BF16, delta=q["delta"], eta=1.01,
+                                   stop_res=(1.01 * q["delta"] if args.warm_stop == "discrepancy" else 0.0))
+                   for q in probs]
             plan = rtg.BatchPlan([op] * B, [q["sk"] for q in probs], [q["C"] for q in probs], X0s, prm)
             r = time_variant(plan, args.steps, args.warmup, rtg, torch, rtg.KIND_STEP,
                              lambda inf: step_bytes(n, 2, inf.iters), pre=pre)
@@ -295,6 +300,8 @@ def main():
                         "sigma 2.5, r 8, nu 1e-3), sketch 64x64x3, discrepancy mu",
             "problems_per_step": B, "m": args.m if head == "fp32_plain" else args.m_warm,
             "variant": head, "x0": "zero" if head == "fp32_plain" else x0_kind,
+            "stop": "m steps" if head == "fp32_plain" else
+                    ("m steps" if args.warm_stop == "fixed" else "LS residual <= eta*delta, at most m steps"),
             "x0_in_timed_region": head != "fp32_plain",
         },
         "roofline": {
