@@ -272,6 +272,217 @@ struct WgradArgs {
     float* part;          // [workgroups][COUT_M * KPAD + COUT_M]
 };
 
+// ---------------------------------------------------------------------------
+// Two consecutive 3x3 layers in one pass (inference).  Layer A (CIN -> 32,
+// bias, ReLU) is evaluated on the output tile grown by one pixel on every
+// side and kept in LDS as bfloat16 -- zero outside the image, which is the
+// zero padding layer B sees -- and layer B (32 -> COUT) reads it from LDS, so
+// the activation between the two layers never goes to memory.  Layer A's
+// weights stay in registers for the whole kernel, layer B's in LDS.
+// Persistent grid: a workgroup loads the next tile's input (with its
+// two-pixel halo) into registers while it computes the current tile.
+// ---------------------------------------------------------------------------
+struct Conv2Args {
+    int N, I1, I2;
+    const bf16_t* x;       // NHWC input, CIN_S channels
+    const bf16_t* wA;      // [32][KPAD(CIN_S)]
+    const float* bA;       // [32]
+    const bf16_t* wB;      // [COUTB_M][KPAD(32)]
+    const float* bB;       // [COUTB_M]
+    bf16_t* out;           // NHWC output, COUTB_S channels (hidden pair)
+    const float* C;        // last pair: observation, [N][3][I2][I1]
+    float* X0;             // last pair: X0 = C + f(C)
+};
+
+constexpr int C2_TH = 8, C2_TW = 64;
+constexpr int C2_THREADS = 64 * C2_TH;
+constexpr int C2_MAX_WG = 256;           // one workgroup per compute unit (LDS)
+
+template <int CIN_S, int COUTB_M, int COUTB_S, bool LASTB>
+__global__ void __launch_bounds__(C2_THREADS) k_conv2(Conv2Args a) {
+    constexpr int TH = C2_TH, TW = C2_TW, NTH = C2_THREADS;
+    constexpr int IH = TH + 4, IW = TW + 4;            // input tile (two-pixel halo)
+    constexpr int MH = TH + 2, MW = TW + 2;            // layer-A tile (one-pixel halo)
+    constexpr int MP = MH * MW;                         // layer-A pixels
+    constexpr int MNT = (MP + 15) / 16;                 // layer-A N-tiles of 16 pixels
+    constexpr int PSA = CIN_S + 8, PSB = 32 + 8;        // padded channels per pixel in LDS
+    constexpr int KPA = kpad_of(CIN_S), KQA = KPA / 32;
+    constexpr int KPB = kpad_of(32), KQB = KPB / 32;
+    constexpr int MTB = COUTB_M / 16;
+    constexpr int NCH = CIN_S / 8;
+    constexpr int NST = (IH * IW * NCH + NTH - 1) / NTH;
+    constexpr int KLB = KPB + 8;                        // padded LDS row of layer-B weights
+    __shared__ __attribute__((aligned(16))) bf16_t Xs[IH * IW * PSA];
+    __shared__ __attribute__((aligned(16))) bf16_t Ms[MP * PSB];
+    __shared__ __attribute__((aligned(16))) bf16_t WlB[COUTB_M * KLB];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n16 = lane & 15, s = lane >> 4;
+    const int I1 = a.I1, I2 = a.I2;
+    const size_t plane = (size_t)I1 * I2;
+    const int nt1 = (I1 + TW - 1) / TW, nt2 = (I2 + TH - 1) / TH;
+    const int ntiles = a.N * nt1 * nt2;
+
+    // layer-A weights (MFMA A operands, reused by every N-tile) in registers;
+    // layer-B weights in LDS (each fragment serves four N-tiles); biases in registers
+    bf8 AfA[KQA][2];
+#pragma unroll
+    for (int q = 0; q < KQA; ++q)
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+            AfA[q][mt] = __builtin_bit_cast(bf8, *gptr((const u4*)(a.wA + (size_t)(16 * mt + n16) * KPA + 32 * q + 8 * s)));
+    for (int e = tid; e < COUTB_M * (KPB / 8); e += NTH) {
+        const int row = e / (KPB / 8), c8 = e % (KPB / 8);
+        *(u4*)(WlB + row * KLB + c8 * 8) = *gptr((const u4*)(a.wB + (size_t)row * KPB + c8 * 8));
+    }
+    float biasA[2][4], biasB[MTB][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) biasA[mt][i] = *gptr(a.bA + 16 * mt + 4 * s + i);
+#pragma unroll
+        for (int mt = 0; mt < MTB; ++mt) biasB[mt][i] = *gptr(a.bB + 16 * mt + 4 * s + i);
+    }
+
+    u4 stg[NST];
+    unsigned okbits = 0;
+    auto fetch = [&](int t) {
+        okbits = 0;
+        const int t1 = t % nt1, r = t / nt1;
+        const int i10 = t1 * TW, i20 = (r % nt2) * TH, img = r / nt2;
+#pragma unroll
+        for (int it = 0; it < NST; ++it) {
+            const int e = tid + NTH * it;
+            const int c8 = e % NCH, pxl = e / NCH;
+            const int y1 = i10 - 2 + pxl % IW, y2 = i20 - 2 + pxl / IW;
+            const int c1 = min(max(y1, 0), I1 - 1), c2 = min(max(y2, 0), I2 - 1);
+            stg[it] = *gptr((const u4*)(a.x + (((size_t)img * I2 + c2) * I1 + c1) * CIN_S + c8 * 8));
+            okbits |= (unsigned)((e < IH * IW * NCH) & (y1 >= 0) & (y1 < I1) & (y2 >= 0) & (y2 < I2)) << it;
+        }
+    };
+    int t = blockIdx.x;
+    if (t < ntiles) fetch(t);
+    for (; t < ntiles; t += gridDim.x) {
+        const int t1 = t % nt1, rr = t / nt1;
+        const int i10 = t1 * TW, i20 = (rr % nt2) * TH, img = rr / nt2;
+        __syncthreads();                  // the previous tile's reads of Xs and Ms are done
+#pragma unroll
+        for (int it = 0; it < NST; ++it) {
+            const int e = tid + NTH * it;
+            if (e < IH * IW * NCH) {
+                const int c8 = e % NCH, pxl = e / NCH;
+                const unsigned m = 0u - ((okbits >> it) & 1u);
+                *(u4*)(Xs + pxl * PSA + c8 * 8) = stg[it] & u4{m, m, m, m};
+            }
+        }
+        __syncthreads();
+        // epilogue operands of layer B (last pair), before the prefetch
+        float cin[4][3];
+        const int i2 = i20 + wave;
+        const int i2c = min(i2, I2 - 1);
+        if constexpr (LASTB) {
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const int i1c = min(i10 + nt * 16 + n16, I1 - 1);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) cin[nt][c] = *gptr(a.C + ((size_t)img * 3 + c) * plane + (size_t)i2c * I1 + i1c);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        fetch(min(t + (int)gridDim.x, ntiles - 1));   // the last tile loads a valid tile again, unused
+
+        // ---- layer A on the grown tile: N-tiles of 16 pixels, wave w takes w, w + 8, ...
+        for (int nt = wave; nt < MNT; nt += TH) {
+            const int p = nt * 16 + n16;
+            const int pc = min(p, MP - 1);
+            const int mr = pc / MW, mc = pc % MW;
+            f4 acc[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+            for (int q = 0; q < KQA; ++q) {
+                const int k = 32 * q + 8 * s;
+                const int tap = k / CIN_S, ci0 = k % CIN_S;
+                const int tp = tap < 9 ? tap : 0;
+                const u4 v = *(const u4*)(Xs + ((mr + tp % 3) * IW + mc + tp / 3) * PSA + ci0);
+                const bf8 B = __builtin_bit_cast(bf8, tap < 9 ? v : u4{0u, 0u, 0u, 0u});
+#pragma unroll
+                for (int mt = 0; mt < 2; ++mt)
+                    acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AfA[q][mt], B, acc[mt], 0, 0, 0);
+            }
+            const int y2 = i20 - 1 + mr, y1 = i10 - 1 + mc;
+            const bool inimg = (y1 >= 0) & (y1 < I1) & (y2 >= 0) & (y2 < I2);
+            if (p < MP) {
+#pragma unroll
+                for (int mt = 0; mt < 2; ++mt) {
+                    float v[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) v[i] = inimg ? fmaxf(acc[mt][i] + biasA[mt][i], 0.f) : 0.f;
+                    u2 pk;
+                    pk[0] = (unsigned)f2bf(v[0]) | ((unsigned)f2bf(v[1]) << 16);
+                    pk[1] = (unsigned)f2bf(v[2]) | ((unsigned)f2bf(v[3]) << 16);
+                    *(u2*)(Ms + p * PSB + 16 * mt + 4 * s) = pk;
+                }
+            }
+        }
+        __syncthreads();
+        // ---- layer B: wave w takes output row w, four N-tiles of 16 pixels
+        f4 acc[4][MTB];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int mt = 0; mt < MTB; ++mt) acc[nt][mt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < KQB; ++q) {
+            const int k = 32 * q + 8 * s;
+            const int tap = k / 32, ci0 = k % 32;
+            const int tp = tap < 9 ? tap : 0;
+            bf8 Af[MTB];
+#pragma unroll
+            for (int mt = 0; mt < MTB; ++mt)
+                Af[mt] = __builtin_bit_cast(bf8, *(const u4*)(WlB + (16 * mt + n16) * KLB + 32 * q + 8 * s));
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const int il = nt * 16 + n16;
+                const u4 v = *(const u4*)(Ms + ((wave + tp % 3) * MW + il + tp / 3) * PSB + ci0);
+                const bf8 B = __builtin_bit_cast(bf8, tap < 9 ? v : u4{0u, 0u, 0u, 0u});
+#pragma unroll
+                for (int mt = 0; mt < MTB; ++mt)
+                    acc[nt][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Af[mt], B, acc[nt][mt], 0, 0, 0);
+            }
+        }
+        const bool row_ok = i2 < I2;
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const int i1 = i10 + nt * 16 + n16;
+            const bool ok = row_ok && i1 < I1;
+            if constexpr (!LASTB) {
+                const size_t pix = ((size_t)img * I2 + i2c) * I1 + min(i1, I1 - 1);
+                u2 pk[MTB];
+#pragma unroll
+                for (int mt = 0; mt < MTB; ++mt) {
+                    float v[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) v[i] = fmaxf(acc[nt][mt][i] + biasB[mt][i], 0.f);
+                    pk[mt][0] = (unsigned)f2bf(v[0]) | ((unsigned)f2bf(v[1]) << 16);
+                    pk[mt][1] = (unsigned)f2bf(v[2]) | ((unsigned)f2bf(v[3]) << 16);
+                }
+                if (ok) {
+#pragma unroll
+                    for (int mt = 0; mt < MTB; ++mt) *gptr_w((u2*)(a.out + pix * COUTB_S + 16 * mt + 4 * s)) = pk[mt];
+                }
+            } else {
+                // rows 0..2 of the first M tile (lanes with s = 0) are the three output channels
+                float x0[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) x0[c] = cin[nt][c] + acc[nt][0][c] + biasB[0][c];
+                if (ok && s == 0) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) *gptr_w(a.X0 + ((size_t)img * 3 + c) * plane + (size_t)i2 * I1 + i1) = x0[c];
+                }
+            }
+        }
+    }
+}
+
 template <int CIN_S, int COUT_S, int COUT_M>
 __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
     constexpr int KPAD = kpad_of(CIN_S);
@@ -502,6 +713,12 @@ hipError_t conv(const ConvArgs& a, int grid, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <int CIN_S, int COUTB_M, int COUTB_S, bool LASTB>
+hipError_t conv2(const Conv2Args& a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_conv2<CIN_S, COUTB_M, COUTB_S, LASTB>), dim3(grid), dim3(C2_THREADS), 0, s, a);
+    return hipGetLastError();
+}
+
 template <int CIN_S, int COUT_S, int COUT_M>
 hipError_t wgrad(const WgradArgs& a, int grid, hipStream_t s) {
     hipLaunchKernelGGL((k_wgrad<CIN_S, COUT_S, COUT_M>), dim3(grid), dim3(256), 0, s, a);
@@ -618,14 +835,28 @@ int rtg_cnn_forward(const void* state, const float* C, int N, int I1, int I2, fl
     char* st = (char*)state;
     const size_t px = (size_t)N * I1 * I2;
     hipLaunchKernelGGL(k_pack, dim3((px + 255) / 256), dim3(256), 0, s, C, N, I1, I2, (bf16_t*)(w + W.xin));
-    const bf16_t* x = (const bf16_t*)(w + W.xin);
-    for (int l = 0; l < NL; ++l) {
-        bf16_t* out = l < NL - 1 ? (bf16_t*)(w + W.act[l % 2]) : nullptr;
-        if (layer_forward(l, st, S, x, out, C, nullptr, X0, nullptr, 0.f, N, I1, I2, W.nconv, false, s) !=
-            hipSuccess)
-            return RTG_E_HIP;
-        x = out;
-    }
+    // three fused pairs of layers: (0, 1), (2, 3), (4, 5)
+    const int ntiles = N * ((I2 + C2_TH - 1) / C2_TH) * ((I1 + C2_TW - 1) / C2_TW);
+    const int grid = std::min(ntiles, C2_MAX_WG);
+    auto pair = [&](int l, const bf16_t* x, bf16_t* out) {
+        Conv2Args a{};
+        a.N = N; a.I1 = I1; a.I2 = I2;
+        a.x = x;
+        a.wA = (const bf16_t*)(st + S.L[l].Wh);
+        a.bA = (const float*)(st + S.L[l].b);
+        a.wB = (const bf16_t*)(st + S.L[l + 1].Wh);
+        a.bB = (const float*)(st + S.L[l + 1].b);
+        a.out = out;
+        a.C = C;
+        a.X0 = X0;
+        return a;
+    };
+    bf16_t* h0 = (bf16_t*)(w + W.act[0]);
+    bf16_t* h1 = (bf16_t*)(w + W.act[1]);
+    if (conv2<8, 32, 32, false>(pair(0, (const bf16_t*)(w + W.xin), h0), grid, s) != hipSuccess ||
+        conv2<32, 32, 32, false>(pair(2, h0, h1), grid, s) != hipSuccess ||
+        conv2<32, 16, 8, true>(pair(4, h1, nullptr), grid, s) != hipSuccess)
+        return RTG_E_HIP;
     return RTG_OK;
 }
 
