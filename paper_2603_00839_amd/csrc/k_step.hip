@@ -1,5 +1,5 @@
-// One Arnoldi step over a column tile with the operator applied on the fly
-// (Sec. 4.3; Phi of eq. (2)):
+// One Arnoldi step over a column tile with the operator applied on the fly,
+// for a bfloat16 basis (Sec. 4.3; Phi of eq. (2)):
 //
 //   V_{j+1} = scale * (Phi(V_j) - sum_{i<=j} h_ij V_i),   scale = 1 / h_{j+1,j}
 //
@@ -9,17 +9,25 @@
 // stored: each workgroup recomputes it for its own tile from V_j.
 //
 // A workgroup owns output channel c and a strip of 32 columns (i2) over all
-// I1 rows, walked in blocks of 64 rows.  Mode products commute, so per block
-// it first mixes the input channels of c's band, U = sum_k B[k, c] V_j[k]
-// (on a slab with an R-wide halo, zeros outside the tensor), then blurs U
-// along i1 and along i2 with the band rows staged in LDS (wave-uniform
-// coefficients), which gives the W tile in registers.  The tile goes through
-// LDS to a layout where each lane owns eight consecutive rows of one column
-// for the multi-AXPY (16-byte loads of the basis, software-pipelined over
-// the terms, the first two terms in flight during the blur), the result is
-// scaled, rounded (bfloat16 basis) and stored, and it is contracted on MFMA
-// against the stacked [Om1 ; Om1 A1] rows of the block (as in the tile
-// kernel).  After the last block the mode-2 contraction writes the partials.
+// I1 rows, walked in blocks of 64 rows.  Per block:
+//  * the raw bfloat16 slab of V_j (the input channels of c's band; the
+//    block's rows with a halo of whole 8-row chunks; the strip's columns
+//    with an R-wide halo) and the block's rows of A1 reach LDS through
+//    asynchronous global-to-LDS loads issued while the previous block is
+//    processed.  Chunks outside the tensor are fetched from past the end of
+//    the buffer range, which reads zeros (the zero boundary condition);
+//  * i1 pass: a lane per slab column mixes the input channels,
+//    U = sum_k B[k, c] V_j[k] (mode products commute), and blurs along i1
+//    with wave-uniform band coefficients, into Z (LDS, float);
+//  * i2 pass: a lane per row blurs eight columns of Z, which leaves the W
+//    tile in registers in the basis' own layout (lane = row);
+//  * multi-AXPY with V_1..V_j (two terms in flight), scale, round to
+//    bfloat16, store V_{j+1}; the tile also goes to LDS column-major;
+//  * mode-1 contraction of the block on MFMA (16x16x32 bf16) against the
+//    stacked rows [Om1 ; Om1 A1] (the composed matrix split into high and
+//    low bfloat16 parts).
+// After the last block the mode-2 contraction with Om2 / Om2 A2 writes two
+// l1 x l2 partials per tile, which the sketched-Gram kernel reduces.
 #include "rtg_internal.h"
 
 namespace rtg {
@@ -28,51 +36,55 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
-constexpr int STEP_T1 = 64;          // rows per block
-constexpr unsigned STEP_OOB = 0x20000000u;
+constexpr int STEP_T1 = 64;                 // rows per block
+constexpr int STEP_NKR = 3;                 // input channels per raw slab
+// Byte offset that lies past every buffer range used here: the host only
+// launches this kernel when a basis vector is under 2^31 bytes.
+constexpr unsigned STEP_OOB = 0x80000000u;
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t step_rsrc(const void* base, int bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, 0x00020000);
 }
 
-template <int R, bool BB, int RPW>
+#define RTG_LDS __attribute__((address_space(3)))
+
+template <int R, int RPW>
 struct StepSmem {
     static constexpr int T1 = STEP_T1, TC = TILE_TC;
-    static constexpr int SR = T1 + 2 * R, SRP = SR + 1, SC = TC + 2 * R, ZRP = T1 + 1;
+    static constexpr int R8 = (R + 7) / 8 * 8;          // row halo in whole 16-byte chunks
+    static constexpr int CHR = (T1 + 2 * R8) / 8;       // chunks per raw column
+    static constexpr int CHP = CHR | 1;                 // column stride in chunks (odd: no bank conflicts)
+    static constexpr int SC = TC + 2 * R;               // slab columns
+    static constexpr int NSLOT = STEP_NKR * SC * CHP;   // 16-byte slots of the raw slab
+    static constexpr int RAWB = NSLOT * 16;
+    static constexpr int ZRP = T1 + 1;
     static constexpr int WP = ((2 * R + 1) + 3) / 4 * 4;
-    static constexpr int WTP = T1 + 4;                  // W tile, column-major
-    static constexpr int XP = BB ? T1 + 8 : T1 + 4;     // MFMA B tile, column-major
+    static constexpr int XP = T1 + 8;
     static constexpr int YP = TC + 1;
-    static constexpr int U1 = SC * SRP + SC * ZRP;      // slab + Z (floats)
-    static constexpr int UY = 64 * RPW * YP;            // mode-1 results (floats)
-    static constexpr int UN = U1 > UY ? U1 : UY;
-    static constexpr int XB = BB ? TC * XP * 2 : TC * XP * 4;
+    static constexpr int YB = 64 * RPW * YP * 4;
+    static constexpr int UB = RAWB > YB ? RAWB : YB;
 };
 
-template <int R, bool BB, int RPW>
+template <int R, int RPW>
 __global__ void __launch_bounds__(256) k_step(const Desc* __restrict__ descs, const int* __restrict__ starts,
                                               int count, int j) {
-    using SM = StepSmem<R, BB, RPW>;
-    constexpr int T1 = SM::T1, TC = SM::TC;
-    constexpr int SR = SM::SR, SRP = SM::SRP, SC = SM::SC, ZRP = SM::ZRP, WP = SM::WP;
-    constexpr int WTP = SM::WTP, XP = SM::XP, YP = SM::YP;
-    constexpr int SRH = SR / 2;                         // row pairs of the slab
-    constexpr int NLP = (SRH * SC + 255) / 256;         // slab row pairs per lane
-    constexpr int KG = 3;                               // input channels loaded together
-    constexpr int KBR = BB ? 32 : 16;                   // rows per MFMA K-block
-    constexpr int NST = BB ? 1 : 2;                     // 16-byte loads per lane per term
+    using SM = StepSmem<R, RPW>;
+    constexpr int T1 = SM::T1, TC = SM::TC, R8 = SM::R8, CHR = SM::CHR, CHP = SM::CHP, SC = SM::SC;
+    constexpr int NSLOT = SM::NSLOT, ZRP = SM::ZRP, WP = SM::WP, XP = SM::XP, YP = SM::YP;
+    constexpr int NKR = STEP_NKR;
+    constexpr int NIN = 8 + 2 * R;                      // i1-pass window (rows) per eight outputs
+    constexpr int NRD = (R8 - R + NIN + 7) / 8;         // 16-byte reads covering it from an aligned row
 
+    // Separate LDS arrays: reads of one are not held back by the compiler
+    // for asynchronous loads still in flight into another.
     __shared__ float coef_s[MMAX + 2];
-    __shared__ __attribute__((aligned(16))) float su[SM::UN];
-    __shared__ float A1c[T1 * WP];
+    __shared__ __attribute__((aligned(16))) unsigned char su[SM::UB];
+    __shared__ float Z[SC * ZRP];                       // [col][row] after the i1 pass
+    __shared__ __attribute__((aligned(16))) float A1c[T1 * WP];
     __shared__ float A2c[TC * WP];
-    __shared__ __attribute__((aligned(16))) unsigned char sx[SM::XB];
-    float* S = su;                      // [SC][SRP] mixed slab
-    float* Z = su + SC * SRP;           // [SC][ZRP] after the i1 pass
-    float* Wt = su;                     // [TC][WTP] W tile (reuses the slab)
-    float* Ys = su;                     // [16 NRT][YP] (after the last block)
-    bf16_t* Xh = (bf16_t*)sx;
-    float* Xf = (float*)sx;
+    __shared__ __attribute__((aligned(16))) bf16_t Xh[TC * XP];
+    bf16_t* raw = (bf16_t*)su;                          // slot s = (kk SC + col) CHP + rc: rows 8 rc .. 8 rc + 7
+    float* Ys = (float*)su;                             // mode-1 results (after the last block)
 
     const int b = blockIdx.x;
     const int p = find_problem(starts, count, b);
@@ -88,14 +100,14 @@ __global__ void __launch_bounds__(256) k_step(const Desc* __restrict__ descs, co
     const int t2 = tile % d.n_i2t, c = tile / d.n_i2t;
     const int i20 = t2 * TC;
     const int ncol = min(TC, I2 - i20);
-    const int r1 = d.r1, r2 = d.r2, rB = d.rB;
-    const int w1 = 2 * r1 + 1, w2 = 2 * r2 + 1, wB = 2 * rB + 1;
+    const int r2 = d.r2, rB = d.rB;
+    const int w2 = 2 * r2 + 1, wB = 2 * rB + 1;
     const int klo = max(0, c - rB), khi = min(J, c + rB + 1);
-    const size_t plane = (size_t)I1 * I2;
-    const size_t es = BB ? 2 : 4;
+    const unsigned plane = (unsigned)I1 * (unsigned)I2;
     const size_t tile_off = (size_t)c * plane + (size_t)i20 * I1;
     const int tile_elems = ncol * I1;
-    const char* vj = (const char*)d.V + (size_t)(j - 1) * d.n * es;   // V_j, source of Phi
+    const auto rvj = step_rsrc((const bf16_t*)d.V + (size_t)(j - 1) * d.n, (int)(d.n * 2));   // V_j
+    const float* a1p = d.a1p[R == 4 ? 0 : (R == 8 ? 1 : 2)];
 
     const int nterms = j;
     for (int i = tid; i < nterms; i += 256) coef_s[i] = d.coef[i];
@@ -114,38 +126,41 @@ __global__ void __launch_bounds__(256) k_step(const Desc* __restrict__ descs, co
 #pragma unroll
         for (int g = 0; g < 2; ++g) acc[u][g] = f4{0.f, 0.f, 0.f, 0.f};
 
-    // slab element e = tid + 256 it: row e % SR, column e / SR (rows fastest:
-    // coalesced), 32-bit offsets within a channel plane, in-tensor bits
-    const int ac = tid >> 3, ar = 8 * (tid & 7);     // AXPY lane: column ac, rows ar .. ar + 7
-
-    const int nrb = (I1 + T1 - 1) / T1;
-    unsigned soff[NLP];
-    // (buffer loads: a uniform channel base and 32-bit per-lane offsets,
-    // always inside the channel plane)
-    auto load_slab = [&](int k, unsigned (*dst)[BB ? 1 : 2]) {
-        const auto rs = step_rsrc(vj + (size_t)k * plane * es, (int)(plane * es));
+    // Asynchronous loads into LDS: a wave's instruction fills a 1 KB window,
+    // lane i writing bytes 16 i .. 16 i + 15 of it, so slot s is fetched by
+    // thread s % 256 of pass s / 256.
+    auto dma_slab = [&](int rb, int k0) {
+        const int i10 = rb * T1;
+        auto one = [&](int it) {
+            const int s = it * 256 + tid;
+            const int kk = s / (SC * CHP), rem = s % (SC * CHP);
+            const int col = rem / CHP, rc = rem % CHP;
+            const int k = k0 + kk, i1 = i10 - R8 + 8 * rc, i2 = i20 - R + col;
+            // I1 is a multiple of 8: a chunk is wholly inside the tensor or wholly outside
+            const bool ok = (rc < CHR) & (k < khi) & (i1 >= 0) & (i1 < I1) & (i2 >= 0) & (i2 < I2);
+            const unsigned off = ok ? ((unsigned)k * plane + (unsigned)i2 * (unsigned)I1 + (unsigned)i1) * 2u
+                                    : STEP_OOB;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rvj, (RTG_LDS void*)(raw + (it * 256 + wave * 64) * 8), 16, off,
+                                                     0, 0, 0);
+        };
 #pragma unroll
-        for (int it = 0; it < NLP; ++it) {
-            if constexpr (BB) {
-                dst[it][0] = __builtin_amdgcn_raw_buffer_load_b32(rs, soff[it], 0, 0);
-            } else {
-                const auto w2v = __builtin_amdgcn_raw_buffer_load_b64(rs, soff[it], 0, 0);
-                dst[it][0] = w2v[0];
-                dst[it][1] = w2v[1];
-            }
-        }
+        for (int it = 0; it < NSLOT / 256; ++it) one(it);
+        if constexpr (NSLOT % 256 != 0)
+            if (tid < NSLOT % 256) one(NSLOT / 256);
     };
-    auto mix = [&](float (*u)[2], const unsigned (*src)[BB ? 1 : 2], float w) {
+    auto dma_bands = [&](int rb) {
+        const int i10 = rb * T1;
+        // rows i10 .. i10 + 63 of the padded band copy; rows past I1 read zeros
+        const auto ra = step_rsrc(a1p + (size_t)i10 * WP, (I1 - i10) * WP * 4);
+        constexpr int NA = T1 * WP / 4;
+        auto one = [&](int it) {
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (RTG_LDS void*)(A1c + (it * 256 + wave * 64) * 4), 16,
+                                                     (unsigned)(it * 256 + tid) * 16u, 0, 0, 0);
+        };
 #pragma unroll
-        for (int it = 0; it < NLP; ++it) {
-            if constexpr (BB) {
-                u[it][0] = fmaf(w, __uint_as_float(src[it][0] << 16), u[it][0]);
-                u[it][1] = fmaf(w, __uint_as_float(src[it][0] & 0xffff0000u), u[it][1]);
-            } else {
-                u[it][0] = fmaf(w, __uint_as_float(src[it][0]), u[it][0]);
-                u[it][1] = fmaf(w, __uint_as_float(src[it][1]), u[it][1]);
-            }
-        }
+        for (int it = 0; it < NA / 256; ++it) one(it);
+        if constexpr (NA % 256 != 0)
+            if (tid < NA % 256) one(NA / 256);
     };
     auto bweight = [&](int k) {
         const int kc = min(k, khi - 1);
@@ -153,136 +168,96 @@ __global__ void __launch_bounds__(256) k_step(const Desc* __restrict__ descs, co
         return k < khi ? bkc : 0.f;
     };
 
+    const int nrb = (I1 + T1 - 1) / T1;
+    dma_slab(0, klo);
+    dma_bands(0);
     for (int rb = 0; rb < nrb; ++rb) {
         const int i10 = rb * T1;
-        __syncthreads();                  // previous block: LDS reads done (A1c, S, Z, Wt, X)
-        // ---- slab offsets: a lane loads two consecutive rows (the slab starts
-        // on an even row and I1 is even, so a pair is inside the tensor or outside)
-        unsigned sok = 0;
+        // ---- i1 pass, over groups of NKR input channels:
+        //      Z[col][row] = sum_d A1[i1, i1 + d] U[col][row + d]
+        for (int k0 = klo; k0 < khi; k0 += NKR) {
+            if (k0 > klo) {
+                __syncthreads();                           // previous group's slab reads done
+                dma_slab(rb, k0);
+            }
+            __builtin_amdgcn_s_waitcnt(0x0F70);            // vmcnt(0): this wave's loads into LDS landed
+            __syncthreads();
+            float wk[NKR];
 #pragma unroll
-        for (int it = 0; it < NLP; ++it) {
-            const int e = tid + 256 * it;
-            const int rp = e % SRH, col = e / SRH;
-            const int i1 = i10 - R + 2 * rp, i2 = i20 - R + col;
-            sok |= (unsigned)((e < SRH * SC) & (i1 >= 0) & (i1 < I1) & (i2 >= 0) & (i2 < I2)) << it;
-            soff[it] = (unsigned)(min(max(i2, 0), I2 - 1) * I1 + min(max(i1, 0), I1 - 2)) * (unsigned)es;
+            for (int kk = 0; kk < NKR; ++kk) wk[kk] = bweight(k0 + kk);
+            if (lane < SC) {
+#pragma unroll
+                for (int blk = 0; blk < 2; ++blk) {
+                    const int rbase = wave * 16 + blk * 8;
+                    // in[e] = U at slab row rbase + (R8 - R) + e of this column
+                    float in[NIN];
+#pragma unroll
+                    for (int e = 0; e < NIN; ++e) in[e] = 0.f;
+#pragma unroll
+                    for (int kk = 0; kk < NKR; ++kk) {
+                        const bf16_t* colp = raw + ((kk * SC + lane) * CHP) * 8 + rbase;
+                        u4 rv[NRD];
+#pragma unroll
+                        for (int q = 0; q < NRD; ++q) rv[q] = *(const u4*)(colp + 8 * q);
+#pragma unroll
+                        for (int e = 0; e < NIN; ++e) {
+                            const int qq = R8 - R + e;
+                            const unsigned w = rv[qq / 8][(qq % 8) / 2];
+                            const float v = __uint_as_float((qq & 1) ? (w & 0xffff0000u) : (w << 16));
+                            in[e] = fmaf(wk[kk], v, in[e]);
+                        }
+                    }
+#pragma unroll
+                    for (int o = 0; o < 8; ++o) {
+                        const float* cr = A1c + (rbase + o) * WP;
+                        float s2 = (k0 > klo) ? Z[lane * ZRP + rbase + o] : 0.f;
+#pragma unroll
+                        for (int t = 0; t <= 2 * R; ++t) s2 = fmaf(cr[t], in[o + t], s2);
+                        Z[lane * ZRP + rbase + o] = s2;
+                    }
+                }
+            }
         }
-        // the first two multi-AXPY terms of this block go in flight now
-        const unsigned aoff = (ac < ncol && i10 + ar < I1) ? (unsigned)(ac * I1 + i10 + ar) * (unsigned)es : STEP_OOB;
-        auto load_term = [&](int i, u4* v) {
-            const auto rv = step_rsrc((const char*)d.V + ((size_t)i * d.n + tile_off) * es, tile_elems * (int)es);
+        __syncthreads();                                   // Z complete; slab and band rows free
+        if (rb + 1 < nrb) {
+            dma_slab(rb + 1, klo);
+            dma_bands(rb + 1);
+        }
+        // ---- the first two multi-AXPY terms (lane = row, eight columns per wave)
+        const int row = i10 + lane;
+        unsigned aoff[8];
 #pragma unroll
-            for (int s2 = 0; s2 < NST; ++s2) v[s2] = __builtin_amdgcn_raw_buffer_load_b128(rv, aoff + 16u * s2, 0, 0);
+        for (int o = 0; o < 8; ++o) {
+            const int col = wave * 8 + o;
+            aoff[o] = (row < I1 && col < ncol) ? (unsigned)(col * I1 + row) * 2u : STEP_OOB;
+        }
+        auto load_term = [&](int i, unsigned* v) {
+            const auto rv = step_rsrc((const bf16_t*)d.V + (size_t)i * d.n + tile_off, tile_elems * 2);
+#pragma unroll
+            for (int o = 0; o < 8; ++o) v[o] = __builtin_amdgcn_raw_buffer_load_b16(rv, aoff[o], 0, 0);
         };
-        u4 va[NST], vb[NST];
+        unsigned va[8], vb[8];
         if (nterms > 0) load_term(0, va);
         if (nterms > 1) load_term(1, vb);
-        // ---- band rows of the block, and the mixed slab
-        //      U = sum_k B[k, c] V_j[k] (zero outside the tensor)
-        for (int e = tid; e < T1 * WP; e += 256) {
-            const int row = e / WP, t = e % WP, dd = t - R;
-            const int i1 = i10 + row;
-            A1c[e] = (t <= 2 * R && dd >= -r1 && dd <= r1 && i1 < I1) ? *gptr(d.a1 + (size_t)i1 * w1 + r1 + dd) : 0.f;
-        }
-        float u[NLP][2];
-#pragma unroll
-        for (int it = 0; it < NLP; ++it) { u[it][0] = 0.f; u[it][1] = 0.f; }
-        for (int k0 = klo; k0 < khi; k0 += KG) {
-            unsigned v[KG][NLP][BB ? 1 : 2];
-#pragma unroll
-            for (int kk = 0; kk < KG; ++kk) load_slab(min(k0 + kk, khi - 1), v[kk]);
-#pragma unroll
-            for (int kk = 0; kk < KG; ++kk) mix(u, v[kk], bweight(k0 + kk));
-        }
-#pragma unroll
-        for (int it = 0; it < NLP; ++it) {
-            const int e = tid + 256 * it;
-            if (e < SRH * SC) {
-                const bool ok = (sok >> it) & 1u;
-                float* sp = S + (e / SRH) * SRP + 2 * (e % SRH);
-                sp[0] = ok ? u[it][0] : 0.f;
-                sp[1] = ok ? u[it][1] : 0.f;
-            }
-        }
-        const int nkb = (min(T1, I1 - i10) + KBR - 1) / KBR;
-        struct AF {
-            u4 h, l;
-        };
-        auto load_a = [&](int kb, AF* A) {
-            const int row = i10 + kb * KBR + (BB ? 8 : 4) * kq;
-            const int rowc = min(row, I1 - (BB ? 8 : 4));
-#pragma unroll
-            for (int u2 = 0; u2 < RPW; ++u2) {
-                const int t = wave + 4 * u2;
-                const int half = (t >= RT && t < NRT) ? 1 : 0;
-                const int a = 16 * (t - half * RT) + m16;
-                const unsigned msk = 0u - (unsigned)((a < l1) & (row < I1) & (t < NRT));
-                const unsigned off = (unsigned)(min(a, l1 - 1) * I1 + rowc);
-                if constexpr (BB) {
-                    const char* base = (const char*)(half ? d.om1th : d.om1h);
-                    const char* lob = base + (half ? (size_t)l1 * I1 * 2 : 0);
-                    A[u2].h = *gptr((const u4*)(base + off * 2u)) & msk;
-                    A[u2].l = *gptr((const u4*)(lob + off * 2u)) & (half ? msk : 0u);
-                } else {
-                    const char* base = (const char*)(half ? d.om1t : d.om1);
-                    A[u2].h = *gptr((const u4*)(base + off * 4u)) & msk;
-                }
-            }
-        };
-        __syncthreads();
-        // ---- i1 pass: Z[col][row] = sum_d A1[i1, i1 + d] U[col][row + R + d]
-        if (lane < SC) {
-#pragma unroll
-            for (int blk = 0; blk < 2; ++blk) {
-                const int rbase = wave * 16 + blk * 8;
-                float in[8 + 2 * R];
-#pragma unroll
-                for (int e = 0; e < 8 + 2 * R; ++e) in[e] = S[lane * SRP + rbase + e];
-#pragma unroll
-                for (int o = 0; o < 8; ++o) {
-                    const float* cr = A1c + (rbase + o) * WP;
-                    float s2 = 0.f;
-#pragma unroll
-                    for (int t = 0; t <= 2 * R; ++t) s2 = fmaf(cr[t], in[o + t], s2);
-                    Z[lane * ZRP + rbase + o] = s2;
-                }
-            }
-        }
-        __syncthreads();
-        // ---- i2 pass (lane = row, wave = eight columns), W tile to LDS
+        // ---- i2 pass: the W tile in registers
+        float x[8];
         {
-            float in2[8 + 2 * R];
+            float in2[NIN];
 #pragma unroll
-            for (int e = 0; e < 8 + 2 * R; ++e) in2[e] = Z[(wave * 8 + e) * ZRP + lane];
+            for (int e = 0; e < NIN; ++e) in2[e] = Z[(wave * 8 + e) * ZRP + lane];
 #pragma unroll
             for (int o = 0; o < 8; ++o) {
                 const float* cr = A2c + (wave * 8 + o) * WP;
                 float s2 = 0.f;
 #pragma unroll
                 for (int t = 0; t <= 2 * R; ++t) s2 = fmaf(cr[t], in2[o + t], s2);
-                Wt[(wave * 8 + o) * WTP + lane] = s2;
+                x[o] = s2;
             }
         }
-        __syncthreads();
-        // ---- multi-AXPY on eight rows of one column per lane
-        float x[8];
-        {
-            const f4 w0 = *(const f4*)(Wt + ac * WTP + ar);
-            const f4 w1v = *(const f4*)(Wt + ac * WTP + ar + 4);
-            x[0] = w0[0]; x[1] = w0[1]; x[2] = w0[2]; x[3] = w0[3];
-            x[4] = w1v[0]; x[5] = w1v[1]; x[6] = w1v[2]; x[7] = w1v[3];
-        }
-        auto apply_term = [&](float ci, const u4* v) {
+        // ---- multi-AXPY, two terms in flight
+        auto apply_term = [&](float ci, const unsigned* v) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if constexpr (BB) {
-                    x[2 * q] = fmaf(-ci, __uint_as_float(v[0][q] << 16), x[2 * q]);
-                    x[2 * q + 1] = fmaf(-ci, __uint_as_float(v[0][q] & 0xffff0000u), x[2 * q + 1]);
-                } else {
-                    x[q] = fmaf(-ci, __uint_as_float(v[0][q]), x[q]);
-                    x[4 + q] = fmaf(-ci, __uint_as_float(v[1][q]), x[4 + q]);
-                }
-            }
+            for (int o = 0; o < 8; ++o) x[o] = fmaf(-ci, __uint_as_float(v[o] << 16), x[o]);
         };
         for (int i = 0; i < nterms; i += 2) {
             apply_term(coef_s[i], va);
@@ -292,53 +267,50 @@ __global__ void __launch_bounds__(256) k_step(const Desc* __restrict__ descs, co
                 if (i + 3 < nterms) load_term(i + 3, vb);
             }
         }
-        const bool aok = aoff != STEP_OOB;
+        // ---- scale, round, store V_{j+1}; the tile to LDS for the sketch
+        const auto rd = step_rsrc((const bf16_t*)d.V + (size_t)j * d.n + tile_off, tile_elems * 2);
 #pragma unroll
-        for (int q = 0; q < 8; ++q) x[q] = aok ? x[q] * scale : 0.f;
-        const auto rd = step_rsrc((const char*)d.V + ((size_t)j * d.n + tile_off) * es, tile_elems * (int)es);
-        if constexpr (BB) {
-            u4 pk;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) pk[q] = (unsigned)f2bf(x[2 * q]) | ((unsigned)f2bf(x[2 * q + 1]) << 16);
-            __builtin_amdgcn_raw_buffer_store_b128(pk, rd, aoff, 0, 0);
-            *(u4*)(Xh + ac * XP + ar) = pk;
-        } else {
-            const u4 p0 = u4{__float_as_uint(x[0]), __float_as_uint(x[1]), __float_as_uint(x[2]), __float_as_uint(x[3])};
-            const u4 p1 = u4{__float_as_uint(x[4]), __float_as_uint(x[5]), __float_as_uint(x[6]), __float_as_uint(x[7])};
-            __builtin_amdgcn_raw_buffer_store_b128(p0, rd, aoff, 0, 0);
-            __builtin_amdgcn_raw_buffer_store_b128(p1, rd, aoff + 16u, 0, 0);
-            *(f4*)(Xf + ac * XP + ar) = f4{x[0], x[1], x[2], x[3]};
-            *(f4*)(Xf + ac * XP + ar + 4) = f4{x[4], x[5], x[6], x[7]};
+        for (int o = 0; o < 8; ++o) {
+            const bf16_t h = f2bf(aoff[o] != STEP_OOB ? x[o] * scale : 0.f);
+            __builtin_amdgcn_raw_buffer_store_b16(h, rd, aoff[o], 0, 0);
+            Xh[(wave * 8 + o) * XP + lane] = h;
         }
         __syncthreads();
         // ---- mode-1 contraction of this block on MFMA (stacked rows [Om1 ; Om1 A1])
+        const int nkb = (min(T1, I1 - i10) + 31) / 32;
+        struct AF {
+            u4 h, l;
+        };
+        auto load_a = [&](int kb, AF* A) {
+            const int arow = i10 + kb * 32 + 8 * kq;
+            const int rowc = min(arow, I1 - 8);
+#pragma unroll
+            for (int u2 = 0; u2 < RPW; ++u2) {
+                const int t = wave + 4 * u2;
+                const int half = (t >= RT && t < NRT) ? 1 : 0;
+                const int a = 16 * (t - half * RT) + m16;
+                const unsigned msk = 0u - (unsigned)((a < l1) & (arow < I1) & (t < NRT));
+                const unsigned off = (unsigned)(min(a, l1 - 1) * I1 + rowc);
+                const char* base = (const char*)(half ? d.om1th : d.om1h);
+                const char* lob = base + (half ? (size_t)l1 * I1 * 2 : 0);
+                A[u2].h = *gptr((const u4*)(base + off * 2u)) & msk;
+                A[u2].l = *gptr((const u4*)(lob + off * 2u)) & (half ? msk : 0u);
+            }
+        };
         auto mfma_block = [&](int kb, const AF* A) {
 #pragma unroll
             for (int g = 0; g < 2; ++g) {
                 const int col = 16 * g + m16;
-                if constexpr (BB) {
-                    const u4 bh = *(const u4*)(Xh + col * XP + kb * KBR + 8 * kq);
+                const u4 bh = *(const u4*)(Xh + col * XP + kb * 32 + 8 * kq);
 #pragma unroll
-                    for (int u2 = 0; u2 < RPW; ++u2) {
-                        const int t = wave + 4 * u2;
-                        if (t >= NRT) break;
+                for (int u2 = 0; u2 < RPW; ++u2) {
+                    const int t = wave + 4 * u2;
+                    if (t >= NRT) break;
+                    acc[u2][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        __builtin_bit_cast(bf8, A[u2].h), __builtin_bit_cast(bf8, bh), acc[u2][g], 0, 0, 0);
+                    if (t >= RT)
                         acc[u2][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                            __builtin_bit_cast(bf8, A[u2].h), __builtin_bit_cast(bf8, bh), acc[u2][g], 0, 0, 0);
-                        if (t >= RT)
-                            acc[u2][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                                __builtin_bit_cast(bf8, A[u2].l), __builtin_bit_cast(bf8, bh), acc[u2][g], 0, 0, 0);
-                    }
-                } else {
-                    const f4 bv = *(const f4*)(Xf + col * XP + kb * KBR + 4 * kq);
-#pragma unroll
-                    for (int u2 = 0; u2 < RPW; ++u2) {
-                        const int t = wave + 4 * u2;
-                        if (t >= NRT) break;
-                        const f4 av = __builtin_bit_cast(f4, A[u2].h);
-#pragma unroll
-                        for (int q = 0; q < 4; ++q)
-                            acc[u2][g] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[q], bv[q], acc[u2][g], 0, 0, 0);
-                    }
+                            __builtin_bit_cast(bf8, A[u2].l), __builtin_bit_cast(bf8, bh), acc[u2][g], 0, 0, 0);
                 }
             }
         };
@@ -392,16 +364,15 @@ __global__ void __launch_bounds__(256) k_step(const Desc* __restrict__ descs, co
     }
 }
 
-// Only the bfloat16-basis variants are built: with a float32 basis the
-// solver forms W with the operator kernel and uses the tile kernel (faster
-// there, see the launch sequence).
+// Only bfloat16-basis variants exist: with a float32 basis the solver forms
+// W with the operator kernel and uses the tile kernel (faster there).
 hipError_t launch_step(const Desc* d, const int* starts, int count, int total_tiles, int j, int rmax,
                        int basis_bf16, int l1max, hipStream_t s) {
     if (!basis_bf16) return hipErrorInvalidValue;
     const int tier = rmax <= 4 ? 4 : (rmax <= 8 ? 8 : 12);
     const bool small = 2 * ((l1max + 15) / 16) <= 8;
 #define RTG_STEP(RR, RPV) \
-    hipLaunchKernelGGL((k_step<RR, true, RPV>), dim3(total_tiles), dim3(256), 0, s, d, starts, count, j)
+    hipLaunchKernelGGL((k_step<RR, RPV>), dim3(total_tiles), dim3(256), 0, s, d, starts, count, j)
 #define RTG_STEP_R(RR) if (small) RTG_STEP(RR, 2); else RTG_STEP(RR, 4);
     if (tier == 4) { RTG_STEP_R(4) } else if (tier == 8) { RTG_STEP_R(8) } else { RTG_STEP_R(12) }
 #undef RTG_STEP_R

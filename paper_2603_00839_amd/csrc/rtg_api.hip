@@ -33,6 +33,8 @@ struct rtg_op_s {
     float* bb;
     float* a1t;   // transposed bands: a1t[(r1 + dd) I1 + i] = a1[i (2 r1 + 1) + r1 + dd]
     float* a2t;
+    float* a1p[3];  // A1 band rows zero-padded to the operator tiers R = 4, 8, 12:
+                    // a1p[k][i * WP + R + dd] = A1[i, i + dd], WP = 2R + 1 rounded up to 4
 };
 
 struct rtg_sk_s {
@@ -124,6 +126,7 @@ void fill_desc(Desc& d, const rtg_op_s* op, const rtg_sk_s* sk, int m, int bf16,
     d.L = (long long)sk->l1 * sk->l2 * sk->l3;
     d.a1 = op->a1; d.a2 = op->a2; d.bb = op->bb;
     d.a1t = op->a1t; d.a2t = op->a2t;
+    for (int k = 0; k < 3; ++k) d.a1p[k] = op->a1p[k];
     d.om1 = sk->om1; d.om1h = sk->om1h; d.om2 = sk->om2; d.om3 = sk->om3;
     if (base) {
         d.V = base + L.V;
@@ -177,6 +180,7 @@ struct Plan {
     int l1max;
     int compose_max;   // largest l1 I1 + l2 I2 + l3 J of the batch
     int phi_jt;        // output channels per operator tile (one choice per batch)
+    bool step_ok;      // the fused step kernel applies (32-bit byte offsets into a basis vector)
 };
 
 int build_plan(std::vector<Desc>& descs, void* ws, hipStream_t s, Plan& plan) {
@@ -199,7 +203,9 @@ int build_plan(std::vector<Desc>& descs, void* ws, hipStream_t s, Plan& plan) {
     }
     plan.l1max = 1;
     plan.compose_max = 1;
+    plan.step_ok = true;
     for (auto& d : descs) {
+        plan.step_ok = plan.step_ok && d.n * 2 <= 0x7FFFFFFFll && d.a1p[0] != nullptr;
         plan.rmax = std::max(plan.rmax, std::max(d.r1, d.r2));
         plan.l1max = std::max(plan.l1max, d.l1);
         plan.compose_max = std::max(plan.compose_max, d.l1 * d.I1 + d.l2 * d.I2 + d.l3 * d.J);
@@ -283,9 +289,11 @@ int run_solver(const Plan& plan, int count, int mmax, int bf16, bool any_x0, boo
         // is never stored); with a float32 basis W is formed by the operator
         // kernel and read by the multi-AXPY tile kernel, which measured faster
         // there (the fused kernel's float32 variant runs at lower occupancy).
+        // The same two kernels serve a bfloat16 basis whose vectors reach
+        // 2^31 bytes (the fused kernel addresses them with 32-bit offsets).
         RTG_TIMED(2, launch_gram(plan.d_desc, sg, count, plan.total[KIND_GRAM], GM_STEP, j, nullptr, s));
         if (j < mmax || last_newv) {
-            if (bf16) {
+            if (bf16 && plan.step_ok) {
                 RTG_TIMED(4, launch_step(plan.d_desc, st, count, plan.total[KIND_TILE], j, plan.rmax, bf16, plan.l1max, s));
             } else {
                 RTG_TIMED(0, launch_phi(plan.d_desc, sp, count, plan.total[KIND_PHI], PS_BASIS, j - 1, plan.rmax,
@@ -342,7 +350,8 @@ int rtg_setup_operator(int I1, int I2, int J, const float* a1_band, int r1, cons
     if (I1 < 8 || I2 < 1 || J < 1 || (I1 % 8) != 0) return RTG_E_SHAPE;
     if (r1 < 0 || r2 < 0 || rB < 0 || r1 > RMAX_SPATIAL || r2 > RMAX_SPATIAL || rB > RMAX_B) return RTG_E_SHAPE;
     if (r1 >= I1 || (r2 >= I2 && I2 > 1) || (rB >= J && J > 1)) return RTG_E_SHAPE;
-    rtg_op_s* op = new rtg_op_s{I1, I2, J, r1, r2, rB, nullptr, nullptr, nullptr, nullptr, nullptr};
+    rtg_op_s* op = new rtg_op_s{I1, I2, J, r1, r2, rB, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                {nullptr, nullptr, nullptr}};
     const size_t n1 = (size_t)I1 * (2 * r1 + 1), n2 = (size_t)I2 * (2 * r2 + 1), nb = (size_t)J * (2 * rB + 1);
     if (hipMalloc(&op->a1, n1 * 4) != hipSuccess || hipMalloc(&op->a2, n2 * 4) != hipSuccess ||
         hipMalloc(&op->bb, nb * 4) != hipSuccess || hipMalloc(&op->a1t, n1 * 4) != hipSuccess ||
@@ -358,6 +367,21 @@ int rtg_setup_operator(int I1, int I2, int J, const float* a1_band, int r1, cons
         return t;
     };
     const std::vector<float> a1t = transpose_band(a1_band, I1, r1), a2t = transpose_band(a2_band, I2, r2);
+    for (int k = 0; k < 3; ++k) {
+        const int R = 4 * (k + 1), WP = ((2 * R + 1) + 3) / 4 * 4;
+        std::vector<float> pad((size_t)I1 * WP, 0.f);
+        if (r1 <= R)
+            for (int i = 0; i < I1; ++i)
+                for (int dd = -r1; dd <= r1; ++dd) pad[(size_t)i * WP + R + dd] = a1_band[(size_t)i * (2 * r1 + 1) + r1 + dd];
+        if (hipMalloc(&op->a1p[k], pad.size() * 4) != hipSuccess) {
+            rtg_destroy_operator(op);
+            return RTG_E_NOMEM;
+        }
+        if (hipMemcpy(op->a1p[k], pad.data(), pad.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+            rtg_destroy_operator(op);
+            return RTG_E_HIP;
+        }
+    }
     if (hipMemcpy(op->a1, a1_band, n1 * 4, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(op->a2, a2_band, n2 * 4, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(op->bb, b_band, nb * 4, hipMemcpyHostToDevice) != hipSuccess ||
@@ -377,6 +401,8 @@ int rtg_destroy_operator(rtg_op op) {
     if (op->bb) (void)hipFree(op->bb);
     if (op->a1t) (void)hipFree(op->a1t);
     if (op->a2t) (void)hipFree(op->a2t);
+    for (int k = 0; k < 3; ++k)
+        if (op->a1p[k]) (void)hipFree(op->a1p[k]);
     delete op;
     return RTG_OK;
 }
@@ -458,7 +484,8 @@ int rtg_sketch(rtg_sk sk, int x_dtype, const void* X, float* SX, void* ws, size_
     if (!aligned16(X) || !aligned16(ws)) return RTG_E_ARG;
     if (ws_bytes < rtg_sketch_workspace_bytes(sk)) return RTG_E_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
-    rtg_op_s dummy{sk->I1, sk->I2, sk->J, 0, 0, 0, nullptr, nullptr, nullptr, nullptr, nullptr};
+    rtg_op_s dummy{sk->I1, sk->I2, sk->J, 0, 0, 0, nullptr, nullptr, nullptr, nullptr, nullptr,
+                   {nullptr, nullptr, nullptr}};
     Layout L = problem_layout(&dummy, sk, 1, x_dtype == RTG_BF16);
     std::vector<Desc> descs(1);
     fill_desc(descs[0], &dummy, sk, 1, x_dtype == RTG_BF16, nullptr, L);

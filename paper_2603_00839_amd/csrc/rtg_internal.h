@@ -57,6 +57,7 @@ struct Desc {
     const float* bb;
     const float* a1t;             // bands transposed: a1t[(r1 + dd) I1 + i] = a1[i (2 r1 + 1) + r1 + dd]
     const float* a2t;
+    const float* a1p[3];          // A1 band rows zero-padded to the tiers R = 4, 8, 12 (row stride 2R+1 rounded up to 4)
     const float* om1;
     const bf16_t* om1h;           // bfloat16 copy of Om1
     const float* om2;
