@@ -119,8 +119,9 @@ int rtg_destroy_operator(rtg_op op);
 /* ---- sketch (Sec. 3.1, global tensor sketching operator) ------------------
  * S(X) = X x_1 Om1 x_2 Om2 x_3 Om3 with Om_k in R^{l_k x I_k}.  Requires
  * 1 <= l1 <= min(I1, 128), 1 <= l2 <= min(I2, 128), 1 <= l3 <= min(J, 16)
- * when Om3 is given.  The device keeps float32 copies and a bfloat16 copy of
- * Om1 (used by the BF16 path). */
+ * when Om3 is given, and I1, I2 below 2^20.  The device keeps float32 copies and a
+ * bfloat16 copy of Om1 (used by the BF16 path), plus copies of Om1 in the
+ * tile order of the matrix-core contractions. */
 int rtg_setup_sketch(int I1, int I2, int J, int l1, int l2, int l3,
                      const float* om1, const float* om2, const float* om3,
                      rtg_sk* out);

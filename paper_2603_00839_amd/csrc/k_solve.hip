@@ -260,25 +260,34 @@ __global__ void k_compose(const Desc* __restrict__ descs, int nbc) {
     const int I1 = d.I1, I2 = d.I2, J = d.J, l1 = d.l1, l2 = d.l2, l3 = d.l3;
     const int r1 = d.r1, r2 = d.r2, rB = d.rB;
     const int wB = 2 * rB + 1;
-    const int E1 = l1 * I1, E2 = l2 * I2, E3 = l3 * J;
+    // mode 1 over the operand-padded index space: padding entries are
+    // written as zeros (the MFMA contractions read whole tiles)
+    const int I1p = frag_nkb(I1, FRAG_K_BF16) * FRAG_K_BF16;
+    const int E1 = (int)compose_mode1_entries(l1, I1), E2 = l2 * I2, E3 = l3 * J;
+    const int nkf = frag_nkb(I1, FRAG_K_F32), nkh = frag_nkb(I1, FRAG_K_BF16);
+    const size_t lo_plane = frag_elems(l1, I1, FRAG_K_BF16);
     // one entry per thread; taps read from clamped indices and masked, so
     // that the loads of a thread are independent of each other
     const int e = part * blockDim.x + threadIdx.x;
     if (e < E1) {
-        const int a = e / I1, i = e % I1;
+        const int a = e / I1p, i = e % I1p;
+        const bool real = a < l1 && i < I1;
+        const int ac = min(a, l1 - 1);
         float acc = 0.f;
 #pragma unroll 5
         for (int dd = -r1; dd <= r1; ++dd) {
             const int ip = i - dd;
             const int ipc = min(max(ip, 0), I1 - 1);
-            const float om = d.bf16 ? bf2f(d.om1h[(size_t)a * I1 + ipc]) : d.om1[(size_t)a * I1 + ipc];
+            const float om = d.bf16 ? bf2f(d.om1h[(size_t)ac * I1 + ipc]) : d.om1[(size_t)ac * I1 + ipc];
             const float w = d.a1t[(size_t)(r1 + dd) * I1 + ipc];
             acc = fmaf((ip >= 0 && ip < I1) ? om : 0.f, w, acc);
         }
-        ((float*)d.om1t)[e] = acc;
+        acc = real ? acc : 0.f;
+        if (i < nkf * FRAG_K_F32) ((float*)d.om1t)[frag_index(a, i, nkf, FRAG_K_F32)] = acc;
         const bf16_t hi = f2bf(acc);
-        ((bf16_t*)d.om1th)[e] = hi;
-        ((bf16_t*)d.om1th)[E1 + e] = f2bf(acc - bf2f(hi));
+        const size_t fh = frag_index(a, i, nkh, FRAG_K_BF16);
+        ((bf16_t*)d.om1th)[fh] = hi;
+        ((bf16_t*)d.om1th)[lo_plane + fh] = f2bf(acc - bf2f(hi));
     } else if (e < E1 + E2) {
         const int e2 = e - E1;
         const int b = e2 / I2, i = e2 % I2;

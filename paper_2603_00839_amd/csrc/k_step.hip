@@ -86,7 +86,7 @@ __global__ void __launch_bounds__(256) k_step(const Desc* __restrict__ descs, co
     bf16_t* raw = (bf16_t*)su;                          // slot s = (kk SC + col) CHP + rc: rows 8 rc .. 8 rc + 7
     float* Ys = (float*)su;                             // mode-1 results (after the last block)
 
-    const int b = blockIdx.x;
+    const int b = xcd_tile(blockIdx.x, gridDim.x);
     const int p = find_problem(starts, count, b);
     const Desc& d = descs[p];
     const int tile = b - starts[p];
@@ -108,6 +108,11 @@ __global__ void __launch_bounds__(256) k_step(const Desc* __restrict__ descs, co
     const int tile_elems = ncol * I1;
     const auto rvj = step_rsrc((const bf16_t*)d.V + (size_t)(j - 1) * d.n, (int)(d.n * 2));   // V_j
     const float* a1p = d.a1p[R == 4 ? 0 : (R == 8 ? 1 : 2)];
+    // Om1 and the composed Om1 A1 (high plane, then low plane) in operand order
+    const int nkbf = frag_nkb(I1, FRAG_K_BF16);
+    const unsigned om1_lo = (unsigned)frag_elems(l1, I1, FRAG_K_BF16) * 2u;
+    const auto rom1 = step_rsrc(d.om1hf, (int)om1_lo);
+    const auto rom1c = step_rsrc(d.om1th, 2 * (int)om1_lo);
 
     const int nterms = j;
     for (int i = tid; i < nterms; i += 256) coef_s[i] = d.coef[i];
@@ -281,20 +286,20 @@ __global__ void __launch_bounds__(256) k_step(const Desc* __restrict__ descs, co
         struct AF {
             u4 h, l;
         };
+        // A fragments in operand order: one contiguous 1 KB read per wave and
+        // tile (padding is stored zeros); the low part is fetched for the
+        // composed rows only
         auto load_a = [&](int kb, AF* A) {
-            const int arow = i10 + kb * 32 + 8 * kq;
-            const int rowc = min(arow, I1 - 8);
+            const int kbg = rb * (T1 / FRAG_K_BF16) + kb;
 #pragma unroll
             for (int u2 = 0; u2 < RPW; ++u2) {
                 const int t = wave + 4 * u2;
-                const int half = (t >= RT && t < NRT) ? 1 : 0;
-                const int a = 16 * (t - half * RT) + m16;
-                const unsigned msk = 0u - (unsigned)((a < l1) & (arow < I1) & (t < NRT));
-                const unsigned off = (unsigned)(min(a, l1 - 1) * I1 + rowc);
-                const char* base = (const char*)(half ? d.om1th : d.om1h);
-                const char* lob = base + (half ? (size_t)l1 * I1 * 2 : 0);
-                A[u2].h = *gptr((const u4*)(base + off * 2u)) & msk;
-                A[u2].l = *gptr((const u4*)(lob + off * 2u)) & (half ? msk : 0u);
+                const bool half = t >= RT;
+                const int tl = t - (half ? RT : 0);
+                const unsigned off = (t < NRT) ? (unsigned)((tl * nkbf + kbg) * 64 + lane) * 16u : STEP_OOB;
+                const auto& rs = half ? rom1c : rom1;
+                A[u2].h = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+                A[u2].l = half ? __builtin_amdgcn_raw_buffer_load_b128(rs, off + om1_lo, 0, 0) : u4{0u, 0u, 0u, 0u};
             }
         };
         auto mfma_block = [&](int kb, const AF* A) {
@@ -338,30 +343,8 @@ __global__ void __launch_bounds__(256) k_step(const Desc* __restrict__ descs, co
             for (int i = 0; i < 4; ++i) Ys[(16 * t + 4 * kq + i) * YP + 16 * g + m16] = acc[u2][g][i];
     }
     __syncthreads();
-    const int RT2 = (l2 + 15) >> 4;
-    for (int tt = wave; tt < NRT * RT2; tt += 4) {
-        const int t = tt / RT2, rt2 = tt % RT2;
-        const int half = t >= RT ? 1 : 0;
-        const float* om2x = half ? d.om2t : d.om2;
-        float* P = (half ? d.PW : d.PV) + (size_t)tile * l1 * l2;
-        const int bcol = 16 * rt2 + m16;
-        float Bv[TC / 4];
-#pragma unroll
-        for (int ks = 0; ks < TC / 4; ++ks) {
-            const int k = 4 * ks + kq;
-            const float v = *gptr(om2x + (size_t)min(bcol, l2 - 1) * I2 + i20 + min(k, ncol - 1));
-            Bv[ks] = (bcol < l2 && k < ncol) ? v : 0.f;
-        }
-        f4 pacc = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int ks = 0; ks < TC / 4; ++ks)
-            pacc = __builtin_amdgcn_mfma_f32_16x16x4f32(Ys[(16 * t + m16) * YP + 4 * ks + kq], Bv[ks], pacc, 0, 0, 0);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int ar2 = 16 * (t - half * RT) + 4 * kq + i;
-            if (ar2 < l1 && bcol < l2) *gptr_w(P + (size_t)ar2 * l2 + bcol) = pacc[i];
-        }
-    }
+    mode2_partials<TC, YP>(Ys, wave, lane, NRT, RT, l1, l2, I2, i20, ncol, d.om2, d.om2t,
+                           d.PV + (size_t)tile * l1 * l2, d.PW + (size_t)tile * l1 * l2);
 }
 
 // Only bfloat16-basis variants exist: with a float32 basis the solver forms

@@ -41,6 +41,8 @@ constexpr int TILE_SBR = 256;   // rows per super-block: 256 lanes x 32 elements
 // element offset of a chunk outside the tile: its byte offset lies past every
 // buffer extent used here (a tile spans 32 x I1 elements of at most 4 bytes)
 constexpr unsigned OOB_ELEM = 0x20000000u;
+// byte offset past the operand-order sketch matrices (under 1 GiB a plane)
+constexpr unsigned OOB_A = 0x80000000u;
 
 // raw buffer resource over [base, base + bytes): loads past the end return
 // zero and stores past it are dropped
@@ -119,6 +121,12 @@ __global__ void __launch_bounds__(256) k_tile(const Desc* __restrict__ descs,
 
     const int RT = (l1 + 15) >> 4;
     const int NRT = dual ? 2 * RT : RT;       // stacked row tiles: [Om1 ; Om1 A1]
+    // sketch matrices in operand order: Om1, and Om1 A1 (bfloat16: high
+    // plane then low plane)
+    const int nkbf = frag_nkb(I1, KBR);
+    const unsigned fbytes = (unsigned)frag_elems(l1, I1, KBR) * (unsigned)es;
+    const auto rom1 = make_rsrc(BB ? (const void*)d.om1hf : (const void*)d.om1f, (int)fbytes);
+    const auto rom1c = make_rsrc(BB ? (const void*)d.om1th : (const void*)d.om1t, (int)(BB ? 2 * fbytes : fbytes));
     f4 acc[RPW][2];
 #pragma unroll
     for (int u = 0; u < RPW; ++u)
@@ -277,27 +285,21 @@ __global__ void __launch_bounds__(256) k_tile(const Desc* __restrict__ descs,
         struct AF {
             u4 h, l;     // bfloat16: Om1 (h), or Om1 A1 high / low; float32: h as f4 bits
         };
+        // A fragments in operand order: one contiguous 1 KB read per wave and
+        // tile; padding rows and columns are stored zeros, and unused tiles
+        // (t >= NRT) read nothing (offset past the buffer range)
         auto load_a = [&](int kb, AF* A) {
-            const int row = sb * SBR + kb * KBR + (BB ? 8 : 4) * kq;
-            const int rowc = min(row, I1 - CK);
+            const int kbg = sb * (SBR / KBR) + kb;
 #pragma unroll
             for (int u = 0; u < RPW; ++u) {
-                // t >= NRT: unused tile, read (masked) from Om1 so that no
-                // pointer of a matrix the mode does not have is touched
                 const int t = wave + 4 * u;
-                const int half = (t >= RT && t < NRT) ? 1 : 0;
-                const int a = 16 * (t - half * RT) + m16;
-                const unsigned msk = 0u - (unsigned)((a < l1) & (row < I1) & (t < NRT));
-                const unsigned off = (unsigned)(min(a, l1 - 1) * I1 + rowc);
-                if constexpr (BB) {
-                    const char* base = (const char*)(half ? d.om1th : d.om1h);
-                    const char* lob = base + (half ? (size_t)l1 * I1 * 2 : 0);
-                    A[u].h = *gptr((const u4*)(base + off * 2u)) & msk;
-                    A[u].l = *gptr((const u4*)(lob + off * 2u)) & (half ? msk : 0u);
-                } else {
-                    const char* base = (const char*)(half ? d.om1t : d.om1);
-                    A[u].h = *gptr((const u4*)(base + off * 4u)) & msk;
-                }
+                const bool half = t >= RT;
+                const int tl = t - (half ? RT : 0);
+                const unsigned off = (t < NRT) ? (unsigned)((tl * nkbf + kbg) * 64 + lane) * 16u : OOB_A;
+                const auto& rs = half ? rom1c : rom1;
+                A[u].h = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+                if constexpr (BB)
+                    A[u].l = half ? __builtin_amdgcn_raw_buffer_load_b128(rs, off + fbytes, 0, 0) : u4{0u, 0u, 0u, 0u};
             }
         };
         auto mfma_block = [&](int kb, const AF* A) {
@@ -364,30 +366,9 @@ __global__ void __launch_bounds__(256) k_tile(const Desc* __restrict__ descs,
     __syncthreads();
 
     // ---- mode-2 contraction: P[a][b] = sum_k Ys[a][k] Om2x[b][i20 + k]
-    const int RT2 = (l2 + 15) >> 4;
-    for (int tt = wave; tt < NRT * RT2; tt += 4) {
-        const int t = tt / RT2, rt2 = tt % RT2;
-        const int half = t >= RT ? 1 : 0;
-        const float* om2x = half ? d.om2t : d.om2;
-        float* P = (half ? d.PW : (mode == TM_NEWV ? d.PV : d.PW)) + (size_t)tile * l1 * l2;
-        const int bcol = 16 * rt2 + m16;
-        float Bv[TC / 4];
-#pragma unroll
-        for (int ks = 0; ks < TC / 4; ++ks) {
-            const int k = 4 * ks + kq;
-            const float v = *gptr(om2x + (size_t)min(bcol, l2 - 1) * I2 + i20 + min(k, ncol - 1));
-            Bv[ks] = (bcol < l2 && k < ncol) ? v : 0.f;
-        }
-        f4 pacc = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int ks = 0; ks < TC / 4; ++ks)
-            pacc = __builtin_amdgcn_mfma_f32_16x16x4f32(Ys[(16 * t + m16) * YP + 4 * ks + kq], Bv[ks], pacc, 0, 0, 0);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int ar = 16 * (t - half * RT) + 4 * kq + i;
-            if (ar < l1 && bcol < l2) *gptr_w(P + (size_t)ar * l2 + bcol) = pacc[i];
-        }
-    }
+    float* Pt0 = (mode == TM_NEWV ? d.PV : d.PW) + (size_t)tile * l1 * l2;
+    float* Pt1 = d.PW + (size_t)tile * l1 * l2;
+    mode2_partials<TC, YP>(Ys, wave, lane, NRT, RT, l1, l2, I2, i20, ncol, d.om2, d.om2t, Pt0, Pt1);
 }
 
 hipError_t launch_tile(const Desc* d, const int* starts, int count, int total_tiles, int mode,

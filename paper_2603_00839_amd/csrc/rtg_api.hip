@@ -43,6 +43,8 @@ struct rtg_sk_s {
     float* om2;
     float* om3;
     rtg::bf16_t* om1h;
+    float* om1f;          // Om1 in MFMA operand order (float32 tiles)
+    rtg::bf16_t* om1hf;   // bfloat16 Om1 in MFMA operand order
 };
 
 namespace {
@@ -85,8 +87,8 @@ Layout problem_layout(const rtg_op_s* op, const rtg_sk_s* sk, int m, int bf16) {
     L.y = take((size_t)m * sizeof(double));
     L.state = take(NSTATE * sizeof(int));
     L.scal = take(NSCAL * sizeof(double));
-    L.ot1 = take((size_t)sk->l1 * op->I1 * sizeof(float));
-    L.ot1h = take((size_t)2 * sk->l1 * op->I1 * sizeof(bf16_t));
+    L.ot1 = take(frag_elems(sk->l1, op->I1, FRAG_K_F32) * sizeof(float));
+    L.ot1h = take(2 * frag_elems(sk->l1, op->I1, FRAG_K_BF16) * sizeof(bf16_t));
     L.ot2 = take((size_t)sk->l2 * op->I2 * sizeof(float));
     L.ot3 = take((size_t)sk->l3 * op->J * sizeof(float));
     L.total = align_up(off);
@@ -128,6 +130,7 @@ void fill_desc(Desc& d, const rtg_op_s* op, const rtg_sk_s* sk, int m, int bf16,
     d.a1t = op->a1t; d.a2t = op->a2t;
     for (int k = 0; k < 3; ++k) d.a1p[k] = op->a1p[k];
     d.om1 = sk->om1; d.om1h = sk->om1h; d.om2 = sk->om2; d.om3 = sk->om3;
+    d.om1f = sk->om1f; d.om1hf = sk->om1hf;
     if (base) {
         d.V = base + L.V;
         d.W = (float*)(base + L.W);
@@ -178,7 +181,7 @@ struct Plan {
     int total[NKIND];
     int rmax;
     int l1max;
-    int compose_max;   // largest l1 I1 + l2 I2 + l3 J of the batch
+    int compose_max;   // largest entry count of the composed matrices (mode 1 padded to operand tiles)
     int phi_jt;        // output channels per operator tile (one choice per batch)
     bool step_ok;      // the fused step kernel applies (32-bit byte offsets into a basis vector)
 };
@@ -205,10 +208,11 @@ int build_plan(std::vector<Desc>& descs, void* ws, hipStream_t s, Plan& plan) {
     plan.compose_max = 1;
     plan.step_ok = true;
     for (auto& d : descs) {
-        plan.step_ok = plan.step_ok && d.n * 2 <= 0x7FFFFFFFll && d.a1p[0] != nullptr;
+        plan.step_ok = plan.step_ok && d.n * 2 <= 0x7FFFFFFFll &&
+                       frag_elems(d.l1, d.I1, FRAG_K_BF16) * 4 <= 0x7FFFFFFFull && d.a1p[0] != nullptr;
         plan.rmax = std::max(plan.rmax, std::max(d.r1, d.r2));
         plan.l1max = std::max(plan.l1max, d.l1);
-        plan.compose_max = std::max(plan.compose_max, d.l1 * d.I1 + d.l2 * d.I2 + d.l3 * d.J);
+        plan.compose_max = std::max(plan.compose_max, (int)compose_mode1_entries(d.l1, d.I1) + d.l2 * d.I2 + d.l3 * d.J);
     }
     char* base = (char*)ws;
     plan.d_desc = (Desc*)base;
@@ -433,7 +437,8 @@ int rtg_setup_sketch(int I1, int I2, int J, int l1, int l2, int l3, const float*
     if ((!om1 && l1 != I1) || (!om2 && l2 != I2) || (!om3 && l3 != J)) return RTG_E_SHAPE;
     if (om3 && (l3 < 1 || l3 > J || l3 > LMAX_3)) return RTG_E_SHAPE;
     if (!om3 && J > 4096) return RTG_E_SHAPE;
-    rtg_sk_s* sk = new rtg_sk_s{I1, I2, J, l1, l2, l3, om3 ? 1 : 0, nullptr, nullptr, nullptr, nullptr};
+    if (I1 >= (1 << 20) || I2 >= (1 << 20)) return RTG_E_SHAPE;   // 32-bit byte offsets into the sketch matrices
+    rtg_sk_s* sk = new rtg_sk_s{I1, I2, J, l1, l2, l3, om3 ? 1 : 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     // identity factors are stored explicitly for modes 1 and 2
     std::vector<float> h1((size_t)l1 * I1, 0.f), h2((size_t)l2 * I2, 0.f);
     if (om1) std::memcpy(h1.data(), om1, h1.size() * 4);
@@ -442,9 +447,20 @@ int rtg_setup_sketch(int I1, int I2, int J, int l1, int l2, int l3, const float*
     else for (int i = 0; i < I2; ++i) h2[(size_t)i * I2 + i] = 1.f;
     std::vector<bf16_t> h1h(h1.size());
     for (size_t i = 0; i < h1.size(); ++i) h1h[i] = host_f2bf(h1[i]);
+    // operand-order copies for the MFMA contractions (zero padding)
+    std::vector<float> h1f(frag_elems(l1, I1, FRAG_K_F32), 0.f);
+    std::vector<bf16_t> h1hf(frag_elems(l1, I1, FRAG_K_BF16), 0);
+    const int nkf = frag_nkb(I1, FRAG_K_F32), nkh = frag_nkb(I1, FRAG_K_BF16);
+    for (int a = 0; a < l1; ++a)
+        for (int i = 0; i < I1; ++i) {
+            h1f[frag_index(a, i, nkf, FRAG_K_F32)] = h1[(size_t)a * I1 + i];
+            h1hf[frag_index(a, i, nkh, FRAG_K_BF16)] = h1h[(size_t)a * I1 + i];
+        }
     bool ok = hipMalloc(&sk->om1, h1.size() * 4) == hipSuccess &&
               hipMalloc(&sk->om2, h2.size() * 4) == hipSuccess &&
               hipMalloc(&sk->om1h, h1h.size() * 2) == hipSuccess &&
+              hipMalloc(&sk->om1f, h1f.size() * 4) == hipSuccess &&
+              hipMalloc(&sk->om1hf, h1hf.size() * 2) == hipSuccess &&
               (!om3 || hipMalloc(&sk->om3, (size_t)l3 * J * 4) == hipSuccess);
     if (!ok) {
         rtg_destroy_sketch(sk);
@@ -453,6 +469,8 @@ int rtg_setup_sketch(int I1, int I2, int J, int l1, int l2, int l3, const float*
     ok = hipMemcpy(sk->om1, h1.data(), h1.size() * 4, hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(sk->om2, h2.data(), h2.size() * 4, hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(sk->om1h, h1h.data(), h1h.size() * 2, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(sk->om1f, h1f.data(), h1f.size() * 4, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(sk->om1hf, h1hf.data(), h1hf.size() * 2, hipMemcpyHostToDevice) == hipSuccess &&
          (!om3 || hipMemcpy(sk->om3, om3, (size_t)l3 * J * 4, hipMemcpyHostToDevice) == hipSuccess);
     if (!ok) {
         rtg_destroy_sketch(sk);
@@ -468,6 +486,8 @@ int rtg_destroy_sketch(rtg_sk sk) {
     if (sk->om2) (void)hipFree(sk->om2);
     if (sk->om3) (void)hipFree(sk->om3);
     if (sk->om1h) (void)hipFree(sk->om1h);
+    if (sk->om1f) (void)hipFree(sk->om1f);
+    if (sk->om1hf) (void)hipFree(sk->om1hf);
     delete sk;
     return RTG_OK;
 }

@@ -60,10 +60,13 @@ struct Desc {
     const float* a1p[3];          // A1 band rows zero-padded to the tiers R = 4, 8, 12 (row stride 2R+1 rounded up to 4)
     const float* om1;
     const bf16_t* om1h;           // bfloat16 copy of Om1
+    const float* om1f;            // Om1 in operand order, FRAG_K_F32
+    const bf16_t* om1hf;          // bfloat16 Om1 in operand order, FRAG_K_BF16
     const float* om2;
     const float* om3;             // nullptr => identity
     // sketch of Phi(X) as a sketch of X (mode products compose, eq. (2)):
-    // Om1 A1 (float32, and bfloat16 high/low planes), Om2 A2, Om3 B^T (l3 x J)
+    // Om1 A1 (float32, and bfloat16 high then low planes, both in operand
+    // order), Om2 A2, Om3 B^T (l3 x J)
     const float* om1t;
     const bf16_t* om1th;
     const float* om2t;
@@ -107,6 +110,40 @@ __device__ __forceinline__ int find_problem(const int* __restrict__ starts, int 
     return lo;
 }
 
+// Operand order of the mode-1 sketch matrices for the MFMA contractions.
+// The l1 x I1 matrix is cut into tiles of 16 rows (a) by K columns (i),
+// K = 32 for bfloat16 (16x16x32 products) and 16 for float32 (16x16x4);
+// tile (t, kb) is stored as 64 lanes x 16 bytes, lane m + 16 q holding row
+// 16 t + m, columns kb K + q K/4 .. kb K + (q + 1) K/4 - 1, and tiles run
+// kb fastest.  A wave then loads a whole tile with one contiguous 1 KB read.
+// Rows past l1 and columns past I1 are zero.
+constexpr int FRAG_K_BF16 = 32;
+constexpr int FRAG_K_F32 = 16;
+__host__ __device__ inline int frag_nkb(int I1, int k) { return (I1 + k - 1) / k; }
+__host__ __device__ inline size_t frag_elems(int l1, int I1, int k) {
+    return (size_t)((l1 + 15) / 16) * 16 * frag_nkb(I1, k) * k;
+}
+__host__ __device__ inline size_t frag_index(int a, int i, int nkb, int k) {
+    const int per = k / 4, t = a >> 4, m = a & 15, kb = i / k, r = i % k;
+    return (((size_t)t * nkb + kb) * 64 + m + 16 * (r / per)) * per + r % per;
+}
+
+// entries of the mode-1 part of the composition kernel's index space
+// (rows padded to 16, columns to FRAG_K_BF16, so that padding is written)
+__host__ __device__ inline size_t compose_mode1_entries(int l1, int I1) {
+    return (size_t)((l1 + 15) / 16) * 16 * frag_nkb(I1, FRAG_K_BF16) * FRAG_K_BF16;
+}
+
+// Workgroups go to the chip's 8 XCDs round-robin by index, and each XCD has
+// its own L2.  Renumbering so that XCD x takes the contiguous range of
+// logical tiles [x q + min(x, r), ...) (q = total / 8, r = total % 8) keeps
+// tiles of one problem, which read the same sketch matrices and overlapping
+// halos, on one L2.  A bijection of [0, total).
+__device__ __forceinline__ int xcd_tile(int b, int total) {
+    const int q = total >> 3, r = total & 7, x = b & 7;
+    return x * q + min(x, r) + (b >> 3);
+}
+
 // (a, b) pairs of the sketch owned by one sketched-Gram workgroup
 __host__ __device__ inline int gram_pairs_per_block(int l3) {
     int ch = 4096 / (l3 > 0 ? l3 : 1);
@@ -131,6 +168,58 @@ __device__ __forceinline__ const RTG_GLOBAL T* gptr(const T* p) {
 template <typename T>
 __device__ __forceinline__ RTG_GLOBAL T* gptr_w(T* p) {
     return (RTG_GLOBAL T*)p;
+}
+
+// Mode-2 contraction of a column tile's mode-1 results (the second factor
+// of the sketch, Sec. 3.1): for the stacked row tiles t < NRT,
+//   P[a][b] = sum_k Ys[16 t + .][k] Om2x[b][i20 + k],
+// with Om2 into P0 for t < RT and the composed Om2 A2 into P1 for t >= RT
+// (P0, P1: l1 x l2 partials of this tile).  Ys holds 16 NRT rows of TC
+// columns, row stride YP.  Wave w takes the pairs (t, column tile) with
+// index w, w + 4, ...; the TC values of Om2x a lane needs for one column tile
+// are loaded once per (column tile, matrix), all in flight together, by
+// buffer loads that read zeros past l2 and past the tile's ncol columns.
+// I2 l2 stays below 2^29 (sketch set-up limits), so 0x80000000 is past the
+// buffer range.
+template <int TC, int YP>
+__device__ __forceinline__ void mode2_partials(const float* Ys, int wave, int lane, int NRT, int RT, int l1,
+                                               int l2, int I2, int i20, int ncol, const float* om2,
+                                               const float* om2t, float* P0, float* P1) {
+    typedef float f4v __attribute__((ext_vector_type(4)));
+    const int m16 = lane & 15, kq = lane >> 4;
+    const int RT2 = (l2 + 15) >> 4;
+    const int obytes = l2 * I2 * 4;
+    int key = -1;
+    float Bv[TC / 4];
+#pragma unroll
+    for (int ks = 0; ks < TC / 4; ++ks) Bv[ks] = 0.f;
+    for (int tt = wave; tt < NRT * RT2; tt += 4) {
+        const int t = tt / RT2, rt2 = tt % RT2;
+        const int half = t >= RT ? 1 : 0;
+        const int bcol = 16 * rt2 + m16;
+        if (2 * rt2 + half != key) {
+            key = 2 * rt2 + half;
+            const auto rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(half ? om2t : om2), (short)0, obytes,
+                                                              0x00020000);
+#pragma unroll
+            for (int ks = 0; ks < TC / 4; ++ks) {
+                const int k = 4 * ks + kq;
+                const unsigned off =
+                    (bcol < l2 && k < ncol) ? (unsigned)(bcol * I2 + i20 + k) * 4u : 0x80000000u;
+                Bv[ks] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+            }
+        }
+        f4v pacc = f4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < TC / 4; ++ks)
+            pacc = __builtin_amdgcn_mfma_f32_16x16x4f32(Ys[(16 * t + m16) * YP + 4 * ks + kq], Bv[ks], pacc, 0, 0, 0);
+        float* P = half ? P1 : P0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int ar = 16 * (t - half * RT) + 4 * kq + i;
+            if (ar < l1 && bcol < l2) *gptr_w(P + (size_t)ar * l2 + bcol) = pacc[i];
+        }
+    }
 }
 
 template <typename T>

@@ -61,6 +61,8 @@ def test_setup_rejects_bad_shapes_before_touching_the_device(lib):
     assert lib.rtg_setup_sketch(16, 16, 3, 32, 8, 3, fp, fp, None, ctypes.byref(h)) == -2
     assert lib.rtg_setup_sketch(16, 16, 3, 8, 8, 3, None, fp, None, ctypes.byref(h)) == -2
     assert lib.rtg_setup_sketch(16, 16, 3, 8, 8, 2, fp, fp, None, ctypes.byref(h)) == -2
+    # mode 1 beyond the 32-bit offsets of the operand-order copies
+    assert lib.rtg_setup_sketch(1 << 20, 16, 3, 8, 8, 3, fp, fp, None, ctypes.byref(h)) == -2
     # null handles
     assert lib.rtg_workspace_bytes(None, None, 10, 0) == 0
     assert lib.rtg_solve(None, None, None, None, None, None, 0, None, None, None) == -1
