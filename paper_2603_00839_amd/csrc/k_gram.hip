@@ -25,6 +25,9 @@
 
 namespace rtg {
 
+// largest step whose stored block of G the finishing workgroup stages in LDS
+constexpr int GLDS = 64;
+
 __device__ __forceinline__ double load_coherent(const double* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -33,15 +36,15 @@ __device__ __forceinline__ double load_coherent(const double* p) {
 //   out[(q - q0) l3 + c'] = sum_c M[c', c] sum_{i2 tiles t of channel c} P[(c, t)][q]
 // with M = m3 (l3 x J) or the identity (m3 == nullptr); band >= 0 says that
 // M[c', c] = 0 for |c' - c| > band.  NB buffers are finished together.
-// Output channels are taken 16 at a time; for each input channel the
-// partials (16 tiles at a time) and the weights are loaded together, all in
-// flight (clamped indices, masked), and summed in a fixed order.
+// Output channels are taken 16 at a time; three input channels at a time,
+// their partials (16 tiles each, of every buffer) are loaded together, all
+// in flight (clamped indices, masked), and summed in a fixed order.
 template <int NB>
 __device__ __forceinline__ void finish_sketches(const Desc& d, int q0, int qn,
                                                 const float* __restrict__ P0, const float* __restrict__ m30,
                                                 int band0, float* out0, const float* __restrict__ P1,
                                                 const float* __restrict__ m31, int band1, float* out1) {
-    constexpr int U = 16, G3 = 16;
+    constexpr int U = 16, G3 = 16, CP = 3;
     const int tid = threadIdx.x;
     const int L12 = d.l1 * d.l2;
     const int J = d.J, nt2 = d.n_i2t, l3 = d.l3;
@@ -55,14 +58,14 @@ __device__ __forceinline__ void finish_sketches(const Desc& d, int q0, int qn,
 #pragma unroll
             for (int c3 = 0; c3 < G3; ++c3) { a0[c3] = 0.f; a1[c3] = 0.f; }
             const int clo = max(0, g - rch), chi = min(J, g + G3 + rch);
-            // two input channels per pass: their partials (16 tiles each, both
-            // buffers) are all in flight together
-            for (int c0 = clo; c0 < chi; c0 += 2) {
-                float Q0[2] = {0.f, 0.f}, Q1[2] = {0.f, 0.f};
-                for (int t20 = 0; t20 < nt2; t20 += U) {
-                    float v0[2][U], v1[2][U];
+            for (int c0 = clo; c0 < chi; c0 += CP) {
+                float Q0[CP], Q1[CP];
 #pragma unroll
-                    for (int cc = 0; cc < 2; ++cc)
+                for (int cc = 0; cc < CP; ++cc) { Q0[cc] = 0.f; Q1[cc] = 0.f; }
+                for (int t20 = 0; t20 < nt2; t20 += U) {
+                    float v0[CP][U], v1[CP][U];
+#pragma unroll
+                    for (int cc = 0; cc < CP; ++cc)
 #pragma unroll
                         for (int u = 0; u < U; ++u) {
                             const int c = min(c0 + cc, chi - 1);
@@ -71,7 +74,7 @@ __device__ __forceinline__ void finish_sketches(const Desc& d, int q0, int qn,
                             if constexpr (NB > 1) v1[cc][u] = *gptr(P1 + off);
                         }
 #pragma unroll
-                    for (int cc = 0; cc < 2; ++cc)
+                    for (int cc = 0; cc < CP; ++cc)
 #pragma unroll
                         for (int u = 0; u < U; ++u) {
                             const bool ok = t20 + u < nt2;
@@ -80,7 +83,7 @@ __device__ __forceinline__ void finish_sketches(const Desc& d, int q0, int qn,
                         }
                 }
 #pragma unroll
-                for (int cc = 0; cc < 2; ++cc) {
+                for (int cc = 0; cc < CP; ++cc) {
                     const int c = c0 + cc;
                     if (c >= chi) break;
 #pragma unroll
@@ -112,6 +115,8 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
     __shared__ float s_v[4096];
     __shared__ double ds[2 * (MMAX + 2)];
     __shared__ double h1s[MMAX], hs[MMAX], gnew[MMAX], Gh1[MMAX], Gh[MMAX], cs_s[MMAX], sn_s[MMAX];
+    __shared__ double sG[GLDS * GLDS];   // stored block of G (symmetric), j <= GLDS
+    __shared__ double g_s;
     __shared__ int s_last;
 
     const int b = blockIdx.x;
@@ -152,25 +157,26 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
     }
 
     // ---- shares of the inner products (float64): <S(V_i), s> and
-    // <S(V_i), S(V_j)> for the stored S(V_i), i < j - 1 (from global memory,
-    // eight items per wave pass, branch-free so the loads overlap), then the
-    // newest tensor S(V_j) and ||s||^2 from LDS.
+    // <S(V_i), S(V_j)> for the stored S(V_i), i < j - 1 (from global memory),
+    // then the newest tensor S(V_j) and ||s||^2 from LDS.  Stored item i goes
+    // to wave i % 4; a wave takes IG of its items per pass with EU elements
+    // of each per lane, all loads in flight together (clamped indices,
+    // masked: branch-free).
     const int nitems = (mode == GM_STEP) ? j + 1 : 1;
     const int nglob = (mode == GM_STEP) ? j - 1 : 0;
-    // four items per wave; sixteen elements per lane of each item in flight
-    constexpr int IG = 4, EU = 16;
-    for (int it0 = wave * IG; it0 < nglob; it0 += 4 * IG) {
+    constexpr int IG = 4, EU = 12;
+    for (int it0 = wave; it0 < nglob; it0 += 4 * IG) {
         const float* svb = d.SV + (size_t)q0 * l3;
         double as[IG], av[IG];
 #pragma unroll
         for (int u = 0; u < IG; ++u) { as[u] = 0.0; av[u] = 0.0; }
         for (int e0 = lane; e0 < E; e0 += 64 * EU) {
-            float xv[EU][IG];
+            float xv[IG][EU];
 #pragma unroll
-            for (int eu = 0; eu < EU; ++eu)
+            for (int u = 0; u < IG; ++u)
 #pragma unroll
-                for (int u = 0; u < IG; ++u)
-                    xv[eu][u] = *gptr(svb + (size_t)min(it0 + u, nglob - 1) * Lsz + min(e0 + 64 * eu, E - 1));
+                for (int eu = 0; eu < EU; ++eu)
+                    xv[u][eu] = *gptr(svb + (size_t)min(it0 + 4 * u, nglob - 1) * Lsz + min(e0 + 64 * eu, E - 1));
 #pragma unroll
             for (int eu = 0; eu < EU; ++eu) {
                 const int e = e0 + 64 * eu;
@@ -179,8 +185,8 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
                 const double ve = ok ? (double)s_v[min(e, E - 1)] : 0.0;
 #pragma unroll
                 for (int u = 0; u < IG; ++u) {
-                    as[u] += (double)xv[eu][u] * se;
-                    av[u] += (double)xv[eu][u] * ve;
+                    as[u] += (double)xv[u][eu] * se;
+                    av[u] += (double)xv[u][eu] * ve;
                 }
             }
         }
@@ -188,9 +194,9 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
         for (int u = 0; u < IG; ++u) {
             const double ra = wave_sum(as[u]);
             const double rv = wave_sum(av[u]);
-            if (lane == 0 && it0 + u < nglob) {
-                d.dots[((size_t)wgi * (MMAX + 2) + it0 + u) * 2 + 0] = ra;
-                d.dots[((size_t)wgi * (MMAX + 2) + it0 + u) * 2 + 1] = rv;
+            if (lane == 0 && it0 + 4 * u < nglob) {
+                d.dots[((size_t)wgi * (MMAX + 2) + it0 + 4 * u) * 2 + 0] = ra;
+                d.dots[((size_t)wgi * (MMAX + 2) + it0 + 4 * u) * 2 + 1] = rv;
             }
         }
     }
@@ -226,24 +232,65 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
     __syncthreads();
     if (!s_last) return;
     __threadfence();
-    for (int x = tid; x < 2 * nitems; x += 256) {
-        // fixed order over workgroups (deterministic); 8 loads in flight
-        double part[8];
+    // Everything the rest reads from global memory is requested together:
+    // the inner-product shares of all workgroups and, in a step with
+    // j <= GLDS, the stored block G[0..j-2][0..j-2] (to LDS), the previous
+    // plane rotations and g[j-1].
+    const int m = d.m;
+    const int ldg = m + 1;
+    const int jm = j - 1;              // step: column index, also index of the newest basis tensor
+    const bool g_lds = (mode == GM_STEP) && j <= GLDS && jm > 0;
+    constexpr int GR = GLDS * GLDS / 256;
+    double gblk[GR];
+    if (g_lds) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) part[u] = 0.0;
-        const double* base = d.dots + (size_t)(x / 2) * 2 + (x & 1);
-        int w = 0;
-        for (; w + 8 <= nwg; w += 8) {
-#pragma unroll
-            for (int u = 0; u < 8; ++u) part[u] += load_coherent(base + (size_t)(w + u) * (MMAX + 2) * 2);
+        for (int r = 0; r < GR; ++r) {
+            const int e = tid + 256 * r, i = e / GLDS, k = e % GLDS;
+            gblk[r] = *gptr(d.G + (size_t)min(i, jm - 1) * ldg + min(k, jm - 1));
         }
-        for (; w < nwg; ++w) part[0] += load_coherent(base + (size_t)w * (MMAX + 2) * 2);
-        ds[x] = ((part[0] + part[1]) + (part[2] + part[3])) + ((part[4] + part[5]) + (part[6] + part[7]));
+    }
+    double cs_r = 0.0, sn_r = 0.0, g_r = 0.0;
+    if (mode == GM_STEP) {
+        cs_r = *gptr(d.gv + min(tid, max(jm - 1, 0)));
+        sn_r = *gptr(d.gv + m + min(tid, max(jm - 1, 0)));
+        g_r = *gptr(d.gv + 2 * m + jm);
+    }
+    for (int x = tid; x < 2 * nitems; x += 256) {
+        // fixed order over workgroups (deterministic); 16 loads in flight
+        double part[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) part[u] = 0.0;
+        const double* base = d.dots + (size_t)(x / 2) * 2 + (x & 1);
+        for (int w0 = 0; w0 < nwg; w0 += 16) {
+            double v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) v[u] = load_coherent(base + (size_t)min(w0 + u, nwg - 1) * (MMAX + 2) * 2);
+#pragma unroll
+            for (int u = 0; u < 16; ++u) part[u] += (w0 + u < nwg) ? v[u] : 0.0;
+        }
+#pragma unroll
+        for (int h = 8; h > 0; h >>= 1)
+#pragma unroll
+            for (int u = 0; u < h; ++u) part[u] += part[u + h];
+        ds[x] = part[0];
+    }
+    if (g_lds) {
+#pragma unroll
+        for (int r = 0; r < GR; ++r) {
+            const int e = tid + 256 * r, i = e / GLDS, k = e % GLDS;
+            if (i < jm && k < jm) sG[e] = gblk[r];
+        }
+    }
+    if (mode == GM_STEP) {
+        if (tid < jm) {                  // previous plane rotations, staged for the serial update
+            cs_s[tid] = cs_r;
+            sn_s[tid] = sn_r;
+        }
+        if (tid == 0) g_s = g_r;
     }
     __syncthreads();
     int* st = d.state;
     double* sc = d.scal;
-    const int m = d.m;
     double* gvec = d.gv + 2 * m;       // rotated right-hand side g[0..m]
     if (mode == GM_START) {
         if (tid == 0) {
@@ -264,8 +311,6 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
     }
 
     // ---- step j: classical Gram-Schmidt + reorthogonalisation in sketch space
-    const int jm = j - 1;              // column index, also index of the newest basis tensor
-    const int ldg = m + 1;
     if (tid < j) {
         h1s[tid] = ds[2 * tid];
         gnew[tid] = ds[2 * tid + 1];
@@ -275,9 +320,28 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
         d.G[(size_t)tid * ldg + jm] = gnew[tid];
         d.G[(size_t)jm * ldg + tid] = gnew[tid];
     }
-    // Gh1 = G h1 and then Gh = G h with h = 2 h1 - G h1: each wave takes four
-    // rows at a time, lanes run along the row (coalesced), wave reductions.
+    // Gh1 = G h1 and then Gh = G h with h = 2 h1 - G h1.  With the block of
+    // G in LDS: a thread per row, k ascending (G is symmetric, so row i is
+    // read as column i: neighbouring threads read neighbouring words).
+    // Otherwise: each wave takes four rows at a time, lanes run along the row
+    // (coalesced), wave reductions.
+    auto gmatvec_lds = [&](const double* v, double* out, bool make_h) {
+        for (int i = tid; i < j; i += 256) {
+            double acc = 0.0;
+            for (int k = 0; k < j; ++k) {
+                double g = (k == jm) ? gnew[i] : sG[min(k, GLDS - 1) * GLDS + min(i, GLDS - 1)];
+                g = (i == jm) ? gnew[k] : g;
+                acc += g * v[k];
+            }
+            out[i] = acc;
+            if (make_h) hs[i] = 2.0 * h1s[i] - acc;
+        }
+    };
     auto gmatvec = [&](const double* v, double* out, bool make_h) {
+        if (g_lds || jm == 0) {
+            gmatvec_lds(v, out, make_h);
+            return;
+        }
         for (int i0 = wave * 4; i0 < j; i0 += 16) {
             double acc4[4] = {0.0, 0.0, 0.0, 0.0};
             double gi[4];
@@ -310,10 +374,6 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
         }
     };
     gmatvec(h1s, Gh1, true);
-    for (int i = tid; i < jm; i += 256) {      // previous plane rotations, staged for the serial update
-        cs_s[i] = d.gv[i];
-        sn_s[i] = d.gv[m + i];
-    }
     __syncthreads();
     gmatvec(hs, Gh, false);
     __syncthreads();
@@ -351,7 +411,7 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
         cs[jm] = cj;
         sn[jm] = sj;
         Rc[jm] = rr;
-        const double gj = gvec[jm];
+        const double gj = g_s;
         gvec[jm] = cj * gj;
         gvec[j] = -sj * gj;
         const double res_ls = fabs(gvec[j]);

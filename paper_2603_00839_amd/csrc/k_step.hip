@@ -259,29 +259,9 @@ __global__ void __launch_bounds__(256) k_step(const Desc* __restrict__ descs, co
                 x[o] = s2;
             }
         }
-        // ---- multi-AXPY, two terms in flight
-        auto apply_term = [&](float ci, const unsigned* v) {
-#pragma unroll
-            for (int o = 0; o < 8; ++o) x[o] = fmaf(-ci, __uint_as_float(v[o] << 16), x[o]);
-        };
-        for (int i = 0; i < nterms; i += 2) {
-            apply_term(coef_s[i], va);
-            if (i + 2 < nterms) load_term(i + 2, va);
-            if (i + 1 < nterms) {
-                apply_term(coef_s[i + 1], vb);
-                if (i + 3 < nterms) load_term(i + 3, vb);
-            }
-        }
-        // ---- scale, round, store V_{j+1}; the tile to LDS for the sketch
-        const auto rd = step_rsrc((const bf16_t*)d.V + (size_t)j * d.n + tile_off, tile_elems * 2);
-#pragma unroll
-        for (int o = 0; o < 8; ++o) {
-            const bf16_t h = f2bf(aoff[o] != STEP_OOB ? x[o] * scale : 0.f);
-            __builtin_amdgcn_raw_buffer_store_b16(h, rd, aoff[o], 0, 0);
-            Xh[(wave * 8 + o) * XP + lane] = h;
-        }
-        __syncthreads();
-        // ---- mode-1 contraction of this block on MFMA (stacked rows [Om1 ; Om1 A1])
+        // ---- operands of this block's mode-1 contraction (stacked rows
+        // [Om1 ; Om1 A1]), requested before the stores so that they arrive
+        // while the tile is stored
         const int nkb = (min(T1, I1 - i10) + 31) / 32;
         struct AF {
             u4 h, l;
@@ -302,6 +282,32 @@ __global__ void __launch_bounds__(256) k_step(const Desc* __restrict__ descs, co
                 A[u2].l = half ? __builtin_amdgcn_raw_buffer_load_b128(rs, off + om1_lo, 0, 0) : u4{0u, 0u, 0u, 0u};
             }
         };
+        // ---- multi-AXPY, two terms in flight
+        auto apply_term = [&](float ci, const unsigned* v) {
+#pragma unroll
+            for (int o = 0; o < 8; ++o) x[o] = fmaf(-ci, __uint_as_float(v[o] << 16), x[o]);
+        };
+        for (int i = 0; i < nterms; i += 2) {
+            apply_term(coef_s[i], va);
+            if (i + 2 < nterms) load_term(i + 2, va);
+            if (i + 1 < nterms) {
+                apply_term(coef_s[i + 1], vb);
+                if (i + 3 < nterms) load_term(i + 3, vb);
+            }
+        }
+        AF A0[RPW], A1[RPW];
+        load_a(0, A0);
+        if (nkb > 1) load_a(1, A1);
+        // ---- scale, round, store V_{j+1}; the tile to LDS for the sketch
+        const auto rd = step_rsrc((const bf16_t*)d.V + (size_t)j * d.n + tile_off, tile_elems * 2);
+#pragma unroll
+        for (int o = 0; o < 8; ++o) {
+            const bf16_t h = f2bf(aoff[o] != STEP_OOB ? x[o] * scale : 0.f);
+            __builtin_amdgcn_raw_buffer_store_b16(h, rd, aoff[o], 0, 0);
+            Xh[(wave * 8 + o) * XP + lane] = h;
+        }
+        __syncthreads();
+        // ---- mode-1 contraction of this block on MFMA (a block is at most two K-blocks)
         auto mfma_block = [&](int kb, const AF* A) {
 #pragma unroll
             for (int g = 0; g < 2; ++g) {
@@ -319,16 +325,8 @@ __global__ void __launch_bounds__(256) k_step(const Desc* __restrict__ descs, co
                 }
             }
         };
-        AF A0[RPW], A1[RPW];
-        load_a(0, A0);
-        for (int kb = 0; kb < nkb; kb += 2) {
-            if (kb + 1 < nkb) load_a(kb + 1, A1);
-            mfma_block(kb, A0);
-            if (kb + 1 < nkb) {
-                if (kb + 2 < nkb) load_a(kb + 2, A0);
-                mfma_block(kb + 1, A1);
-            }
-        }
+        mfma_block(0, A0);
+        if (nkb > 1) mfma_block(1, A1);
     }
 
     // ---- mode-1 results to LDS, then the mode-2 contraction

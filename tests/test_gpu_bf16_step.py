@@ -19,7 +19,8 @@ the checks are properties of the stored basis that hold at any size:
 The shapes cover ragged tiles (I1 not a multiple of 64, I2 not of 32), one
 and several row blocks, channel bands of one, three and five input
 channels, J = 1, Om3 given and absent, l1 above 64 (four row tiles per
-wave), and band half-widths in each operator tier (4, 8, 12)."""
+wave), band half-widths in each operator tier (4, 8, 12), and a run of 70
+steps (beyond the 64 whose block of G is staged in LDS)."""
 import dataclasses
 import sys
 
@@ -41,6 +42,8 @@ CASES = [
     (520, 40, 3, 8, 8, 1, 64, 16, 3, False, False, 5),
     (48, 32, 1, 4, 4, 0, 16, 16, 1, False, True, 6),
     (96, 64, 8, 6, 6, 2, 24, 24, 4, True, True, 6),
+    # more steps than the Gram kernel stages in LDS (G read from global memory)
+    (48, 32, 2, 3, 3, 1, 16, 8, 2, False, True, 70),
 ]
 
 
