@@ -114,6 +114,7 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
     __shared__ float s_s[4096];
     __shared__ float s_v[4096];
     __shared__ double ds[2 * (MMAX + 2)];
+    __shared__ double wds[2 * (MMAX + 2)];   // this workgroup's shares
     __shared__ double h1s[MMAX], hs[MMAX], gnew[MMAX], Gh1[MMAX], Gh[MMAX], cs_s[MMAX], sn_s[MMAX];
     __shared__ double sG[GLDS * GLDS];   // stored block of G (symmetric), j <= GLDS
     __shared__ double g_s;
@@ -195,8 +196,8 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
             const double ra = wave_sum(as[u]);
             const double rv = wave_sum(av[u]);
             if (lane == 0 && it0 + 4 * u < nglob) {
-                d.dots[((size_t)wgi * (MMAX + 2) + it0 + 4 * u) * 2 + 0] = ra;
-                d.dots[((size_t)wgi * (MMAX + 2) + it0 + 4 * u) * 2 + 1] = rv;
+                wds[(it0 + 4 * u) * 2 + 0] = ra;
+                wds[(it0 + 4 * u) * 2 + 1] = rv;
             }
         }
     }
@@ -212,26 +213,32 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
         a1 = wave_sum(a1);
         a2 = wave_sum(a2);
         if (lane == 0) {
-            d.dots[((size_t)wgi * (MMAX + 2) + nitems - 1) * 2 + 0] = a0;
-            d.dots[((size_t)wgi * (MMAX + 2) + nitems - 1) * 2 + 1] = 0.0;
+            wds[(nitems - 1) * 2 + 0] = a0;
+            wds[(nitems - 1) * 2 + 1] = 0.0;
             if (mode == GM_STEP) {
-                d.dots[((size_t)wgi * (MMAX + 2) + j - 1) * 2 + 0] = a1;
-                d.dots[((size_t)wgi * (MMAX + 2) + j - 1) * 2 + 1] = a2;
+                wds[(j - 1) * 2 + 0] = a1;
+                wds[(j - 1) * 2 + 1] = a2;
             }
         }
     }
 
-    // ---- the last workgroup of this problem finishes the step
-    __threadfence();
+    // ---- the last workgroup of this problem finishes the step.  Wave 0
+    // publishes the workgroup's shares with one release at agent scope (an
+    // L2 write-back on this chip), then counts the workgroup in; the last one
+    // to arrive acquires.  The stored S(V_j) is read only by later launches.
     __syncthreads();
-    if (tid == 0) {
-        const int old = __hip_atomic_fetch_add(d.state + ST_COUNTER, 1, __ATOMIC_ACQ_REL,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-        s_last = (old == nwg - 1);
+    if (wave == 0) {
+        double* dst = d.dots + (size_t)wgi * (MMAX + 2) * 2;
+        for (int x = lane; x < 2 * nitems; x += 64) dst[x] = wds[x];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (lane == 0) {
+            const int old = __hip_atomic_fetch_add(d.state + ST_COUNTER, 1, __ATOMIC_ACQUIRE,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+            s_last = (old == nwg - 1);
+        }
     }
     __syncthreads();
     if (!s_last) return;
-    __threadfence();
     // Everything the rest reads from global memory is requested together:
     // the inner-product shares of all workgroups and, in a step with
     // j <= GLDS, the stored block G[0..j-2][0..j-2] (to LDS), the previous
