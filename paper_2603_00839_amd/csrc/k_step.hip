@@ -65,7 +65,13 @@ struct StepSmem {
     static constexpr int UB = RAWB > YB ? RAWB : YB;
 };
 
-template <int R, int RPW>
+// TOEP: both spatial bands are Toeplitz on their in-range entries (a
+// convolution with zero boundary conditions, as for the blurs of Sec. 5).
+// The i1 and i2 passes then read each group of four taps once for all eight
+// outputs of a lane, instead of per output row or column, and the band rows
+// are not streamed into LDS.  Outputs of rows past I1 come out nonzero in
+// this form; they are never stored.
+template <int R, int RPW, bool TOEP>
 __global__ void __launch_bounds__(256) k_step(const Desc* __restrict__ descs, const int* __restrict__ starts,
                                               int count, int j) {
     using SM = StepSmem<R, RPW>;
@@ -80,8 +86,8 @@ __global__ void __launch_bounds__(256) k_step(const Desc* __restrict__ descs, co
     __shared__ float coef_s[MMAX + 2];
     __shared__ __attribute__((aligned(16))) unsigned char su[SM::UB];
     __shared__ float Z[SC * ZRP];                       // [col][row] after the i1 pass
-    __shared__ __attribute__((aligned(16))) float A1c[T1 * WP];
-    __shared__ float A2c[TC * WP];
+    __shared__ __attribute__((aligned(16))) float A1c[TOEP ? WP : T1 * WP];   // TOEP: the taps of A1
+    __shared__ __attribute__((aligned(16))) float A2c[TOEP ? WP : TC * WP];   // TOEP: the taps of A2
     __shared__ __attribute__((aligned(16))) bf16_t Xh[TC * XP];
     bf16_t* raw = (bf16_t*)su;                          // slot s = (kk SC + col) CHP + rc: rows 8 rc .. 8 rc + 7
     float* Ys = (float*)su;                             // mode-1 results (after the last block)
@@ -117,10 +123,19 @@ __global__ void __launch_bounds__(256) k_step(const Desc* __restrict__ descs, co
     const int nterms = j;
     for (int i = tid; i < nterms; i += 256) coef_s[i] = d.coef[i];
     const float scale = d.coef[MMAX + 1];
-    for (int e = tid; e < TC * WP; e += 256) {
-        const int col = e / WP, t = e % WP, dd = t - R;
-        const int i2 = i20 + col;
-        A2c[e] = (t <= 2 * R && dd >= -r2 && dd <= r2 && i2 < I2) ? *gptr(d.a2 + (size_t)i2 * w2 + r2 + dd) : 0.f;
+    if constexpr (TOEP) {
+        if (tid < WP) {
+            const int dd = tid - R, r1 = d.r1;
+            A1c[tid] = (tid <= 2 * R && dd >= -r1 && dd <= r1) ? *gptr(d.taps + r1 + dd) : 0.f;
+            A2c[tid] = (tid <= 2 * R && dd >= -r2 && dd <= r2) ? *gptr(d.taps + 2 * RMAX_SPATIAL + 1 + r2 + dd) : 0.f;
+        }
+    } else {
+        for (int e = tid; e < TC * WP; e += 256) {
+            const int col = e / WP, t = e % WP, dd = t - R;
+            const int i2 = i20 + col;
+            A2c[e] = (t <= 2 * R && dd >= -r2 && dd <= r2 && i2 < I2) ? *gptr(d.a2 + (size_t)i2 * w2 + r2 + dd)
+                                                                        : 0.f;
+        }
     }
 
     const int RT = (l1 + 15) >> 4;
@@ -175,7 +190,7 @@ __global__ void __launch_bounds__(256) k_step(const Desc* __restrict__ descs, co
 
     const int nrb = (I1 + T1 - 1) / T1;
     dma_slab(0, klo);
-    dma_bands(0);
+    if constexpr (!TOEP) dma_bands(0);
     for (int rb = 0; rb < nrb; ++rb) {
         const int i10 = rb * T1;
         // ---- i1 pass, over groups of NKR input channels:
@@ -212,13 +227,31 @@ __global__ void __launch_bounds__(256) k_step(const Desc* __restrict__ descs, co
                             in[e] = fmaf(wk[kk], v, in[e]);
                         }
                     }
+                    if constexpr (TOEP) {
+                        float s2[8];
 #pragma unroll
-                    for (int o = 0; o < 8; ++o) {
-                        const float* cr = A1c + (rbase + o) * WP;
-                        float s2 = (k0 > klo) ? Z[lane * ZRP + rbase + o] : 0.f;
+                        for (int o = 0; o < 8; ++o) s2[o] = (k0 > klo) ? Z[lane * ZRP + rbase + o] : 0.f;
 #pragma unroll
-                        for (int t = 0; t <= 2 * R; ++t) s2 = fmaf(cr[t], in[o + t], s2);
-                        Z[lane * ZRP + rbase + o] = s2;
+                        for (int t4 = 0; t4 < WP; t4 += 4) {
+                            const f4 cv = *(const f4*)(A1c + t4);
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) {
+                                if (t4 + q > 2 * R) break;
+#pragma unroll
+                                for (int o = 0; o < 8; ++o) s2[o] = fmaf(cv[q], in[o + t4 + q], s2[o]);
+                            }
+                        }
+#pragma unroll
+                        for (int o = 0; o < 8; ++o) Z[lane * ZRP + rbase + o] = s2[o];
+                    } else {
+#pragma unroll
+                        for (int o = 0; o < 8; ++o) {
+                            const float* cr = A1c + (rbase + o) * WP;
+                            float s2 = (k0 > klo) ? Z[lane * ZRP + rbase + o] : 0.f;
+#pragma unroll
+                            for (int t = 0; t <= 2 * R; ++t) s2 = fmaf(cr[t], in[o + t], s2);
+                            Z[lane * ZRP + rbase + o] = s2;
+                        }
                     }
                 }
             }
@@ -226,7 +259,7 @@ __global__ void __launch_bounds__(256) k_step(const Desc* __restrict__ descs, co
         __syncthreads();                                   // Z complete; slab and band rows free
         if (rb + 1 < nrb) {
             dma_slab(rb + 1, klo);
-            dma_bands(rb + 1);
+            if constexpr (!TOEP) dma_bands(rb + 1);
         }
         // ---- the first two multi-AXPY terms (lane = row, eight columns per wave)
         const int row = i10 + lane;
@@ -250,13 +283,28 @@ __global__ void __launch_bounds__(256) k_step(const Desc* __restrict__ descs, co
             float in2[NIN];
 #pragma unroll
             for (int e = 0; e < NIN; ++e) in2[e] = Z[(wave * 8 + e) * ZRP + lane];
+            if constexpr (TOEP) {
 #pragma unroll
-            for (int o = 0; o < 8; ++o) {
-                const float* cr = A2c + (wave * 8 + o) * WP;
-                float s2 = 0.f;
+                for (int o = 0; o < 8; ++o) x[o] = 0.f;
 #pragma unroll
-                for (int t = 0; t <= 2 * R; ++t) s2 = fmaf(cr[t], in2[o + t], s2);
-                x[o] = s2;
+                for (int t4 = 0; t4 < WP; t4 += 4) {
+                    const f4 cv = *(const f4*)(A2c + t4);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        if (t4 + q > 2 * R) break;
+#pragma unroll
+                        for (int o = 0; o < 8; ++o) x[o] = fmaf(cv[q], in2[o + t4 + q], x[o]);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int o = 0; o < 8; ++o) {
+                    const float* cr = A2c + (wave * 8 + o) * WP;
+                    float s2 = 0.f;
+#pragma unroll
+                    for (int t = 0; t <= 2 * R; ++t) s2 = fmaf(cr[t], in2[o + t], s2);
+                    x[o] = s2;
+                }
             }
         }
         // ---- operands of this block's mode-1 contraction (stacked rows
@@ -348,13 +396,16 @@ __global__ void __launch_bounds__(256) k_step(const Desc* __restrict__ descs, co
 // Only bfloat16-basis variants exist: with a float32 basis the solver forms
 // W with the operator kernel and uses the tile kernel (faster there).
 hipError_t launch_step(const Desc* d, const int* starts, int count, int total_tiles, int j, int rmax,
-                       int basis_bf16, int l1max, hipStream_t s) {
+                       int basis_bf16, int l1max, int toeplitz, hipStream_t s) {
     if (!basis_bf16) return hipErrorInvalidValue;
     const int tier = rmax <= 4 ? 4 : (rmax <= 8 ? 8 : 12);
     const bool small = 2 * ((l1max + 15) / 16) <= 8;
-#define RTG_STEP(RR, RPV) \
-    hipLaunchKernelGGL((k_step<RR, RPV>), dim3(total_tiles), dim3(256), 0, s, d, starts, count, j)
-#define RTG_STEP_R(RR) if (small) RTG_STEP(RR, 2); else RTG_STEP(RR, 4);
+#define RTG_STEP(RR, RPV)                                                                               \
+    if (toeplitz)                                                                                       \
+        hipLaunchKernelGGL((k_step<RR, RPV, true>), dim3(total_tiles), dim3(256), 0, s, d, starts, count, j); \
+    else                                                                                                \
+        hipLaunchKernelGGL((k_step<RR, RPV, false>), dim3(total_tiles), dim3(256), 0, s, d, starts, count, j);
+#define RTG_STEP_R(RR) if (small) { RTG_STEP(RR, 2) } else { RTG_STEP(RR, 4) }
     if (tier == 4) { RTG_STEP_R(4) } else if (tier == 8) { RTG_STEP_R(8) } else { RTG_STEP_R(12) }
 #undef RTG_STEP_R
 #undef RTG_STEP

@@ -35,6 +35,8 @@ struct rtg_op_s {
     float* a2t;
     float* a1p[3];  // A1 band rows zero-padded to the operator tiers R = 4, 8, 12:
                     // a1p[k][i * WP + R + dd] = A1[i, i + dd], WP = 2R + 1 rounded up to 4
+    int toeplitz;   // A1 and A2 are Toeplitz on their in-range entries (convolutions with zero BC)
+    float* taps;    // their taps: taps[r1 + dd] = A1[i, i + dd], then RMAX_SPATIAL * 2 + 1 on, A2's
 };
 
 struct rtg_sk_s {
@@ -129,6 +131,8 @@ void fill_desc(Desc& d, const rtg_op_s* op, const rtg_sk_s* sk, int m, int bf16,
     d.a1 = op->a1; d.a2 = op->a2; d.bb = op->bb;
     d.a1t = op->a1t; d.a2t = op->a2t;
     for (int k = 0; k < 3; ++k) d.a1p[k] = op->a1p[k];
+    d.toeplitz = op->toeplitz;
+    d.taps = op->taps;
     d.om1 = sk->om1; d.om1h = sk->om1h; d.om2 = sk->om2; d.om3 = sk->om3;
     d.om1f = sk->om1f; d.om1hf = sk->om1hf;
     if (base) {
@@ -184,6 +188,7 @@ struct Plan {
     int compose_max;   // largest entry count of the composed matrices (mode 1 padded to operand tiles)
     int phi_jt;        // output channels per operator tile (one choice per batch)
     bool step_ok;      // the fused step kernel applies (32-bit byte offsets into a basis vector)
+    int toeplitz;      // every problem's bands are Toeplitz
 };
 
 int build_plan(std::vector<Desc>& descs, void* ws, hipStream_t s, Plan& plan) {
@@ -207,7 +212,9 @@ int build_plan(std::vector<Desc>& descs, void* ws, hipStream_t s, Plan& plan) {
     plan.l1max = 1;
     plan.compose_max = 1;
     plan.step_ok = true;
+    plan.toeplitz = 1;
     for (auto& d : descs) {
+        plan.toeplitz = plan.toeplitz && d.toeplitz;
         plan.step_ok = plan.step_ok && d.n * 2 <= 0x7FFFFFFFll &&
                        frag_elems(d.l1, d.I1, FRAG_K_BF16) * 4 <= 0x7FFFFFFFull && d.a1p[0] != nullptr;
         plan.rmax = std::max(plan.rmax, std::max(d.r1, d.r2));
@@ -298,7 +305,8 @@ int run_solver(const Plan& plan, int count, int mmax, int bf16, bool any_x0, boo
         RTG_TIMED(2, launch_gram(plan.d_desc, sg, count, plan.total[KIND_GRAM], GM_STEP, j, nullptr, s));
         if (j < mmax || last_newv) {
             if (bf16 && plan.step_ok) {
-                RTG_TIMED(4, launch_step(plan.d_desc, st, count, plan.total[KIND_TILE], j, plan.rmax, bf16, plan.l1max, s));
+                RTG_TIMED(4, launch_step(plan.d_desc, st, count, plan.total[KIND_TILE], j, plan.rmax, bf16, plan.l1max,
+                                         plan.toeplitz, s));
             } else {
                 RTG_TIMED(0, launch_phi(plan.d_desc, sp, count, plan.total[KIND_PHI], PS_BASIS, j - 1, plan.rmax,
                                         plan.phi_jt, bf16, s));
@@ -355,7 +363,26 @@ int rtg_setup_operator(int I1, int I2, int J, const float* a1_band, int r1, cons
     if (r1 < 0 || r2 < 0 || rB < 0 || r1 > RMAX_SPATIAL || r2 > RMAX_SPATIAL || rB > RMAX_B) return RTG_E_SHAPE;
     if (r1 >= I1 || (r2 >= I2 && I2 > 1) || (rB >= J && J > 1)) return RTG_E_SHAPE;
     rtg_op_s* op = new rtg_op_s{I1, I2, J, r1, r2, rB, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                {nullptr, nullptr, nullptr}};
+                                {nullptr, nullptr, nullptr}, 0, nullptr};
+    // Toeplitz bands (a convolution with zero boundary conditions, such as the
+    // blurs of Sec. 5): A[i, i + dd] the same for every row i with i + dd in
+    // range, compared bit for bit.  Entries pointing outside the matrix are
+    // never used (they meet the zero boundary) and are not compared.
+    std::vector<float> taps(2 * (2 * RMAX_SPATIAL + 1), 0.f);
+    auto toeplitz_taps = [](const float* band, int I, int r, float* t) {
+        const int w = 2 * r + 1;
+        for (int dd = -r; dd <= r; ++dd) {
+            const int i0 = dd >= 0 ? 0 : -dd;            // first row where column i0 + dd exists
+            if (i0 + dd >= I) { t[r + dd] = 0.f; continue; }
+            const float v = band[(size_t)i0 * w + r + dd];
+            for (int i = i0; i < I && i + dd < I; ++i)
+                if (std::memcmp(band + (size_t)i * w + r + dd, &v, sizeof(float)) != 0) return false;
+            t[r + dd] = v;
+        }
+        return true;
+    };
+    op->toeplitz = (toeplitz_taps(a1_band, I1, r1, taps.data()) &&
+                    toeplitz_taps(a2_band, I2, r2, taps.data() + 2 * RMAX_SPATIAL + 1)) ? 1 : 0;
     const size_t n1 = (size_t)I1 * (2 * r1 + 1), n2 = (size_t)I2 * (2 * r2 + 1), nb = (size_t)J * (2 * rB + 1);
     if (hipMalloc(&op->a1, n1 * 4) != hipSuccess || hipMalloc(&op->a2, n2 * 4) != hipSuccess ||
         hipMalloc(&op->bb, nb * 4) != hipSuccess || hipMalloc(&op->a1t, n1 * 4) != hipSuccess ||
@@ -386,6 +413,14 @@ int rtg_setup_operator(int I1, int I2, int J, const float* a1_band, int r1, cons
             return RTG_E_HIP;
         }
     }
+    if (hipMalloc(&op->taps, taps.size() * 4) != hipSuccess) {
+        rtg_destroy_operator(op);
+        return RTG_E_NOMEM;
+    }
+    if (hipMemcpy(op->taps, taps.data(), taps.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+        rtg_destroy_operator(op);
+        return RTG_E_HIP;
+    }
     if (hipMemcpy(op->a1, a1_band, n1 * 4, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(op->a2, a2_band, n2 * 4, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(op->bb, b_band, nb * 4, hipMemcpyHostToDevice) != hipSuccess ||
@@ -407,6 +442,7 @@ int rtg_destroy_operator(rtg_op op) {
     if (op->a2t) (void)hipFree(op->a2t);
     for (int k = 0; k < 3; ++k)
         if (op->a1p[k]) (void)hipFree(op->a1p[k]);
+    if (op->taps) (void)hipFree(op->taps);
     delete op;
     return RTG_OK;
 }
@@ -505,7 +541,7 @@ int rtg_sketch(rtg_sk sk, int x_dtype, const void* X, float* SX, void* ws, size_
     if (ws_bytes < rtg_sketch_workspace_bytes(sk)) return RTG_E_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     rtg_op_s dummy{sk->I1, sk->I2, sk->J, 0, 0, 0, nullptr, nullptr, nullptr, nullptr, nullptr,
-                   {nullptr, nullptr, nullptr}};
+                   {nullptr, nullptr, nullptr}, 0, nullptr};
     Layout L = problem_layout(&dummy, sk, 1, x_dtype == RTG_BF16);
     std::vector<Desc> descs(1);
     fill_desc(descs[0], &dummy, sk, 1, x_dtype == RTG_BF16, nullptr, L);

@@ -49,6 +49,7 @@ struct Desc {
     int ntile[NKIND];   // tiles of this problem per kernel kind
     int mu_fixed;       // 1: mu given, 0: discrepancy principle
     int keep_last;      // form V_{m+1} after the last step (Arnoldi-only calls)
+    int toeplitz;       // A1 and A2 are Toeplitz on their in-range entries (convolutions, zero BC)
     long long n;        // I1*I2*J
     long long L;        // l1*l2*l3
     // operator / sketch (device)
@@ -58,6 +59,7 @@ struct Desc {
     const float* a1t;             // bands transposed: a1t[(r1 + dd) I1 + i] = a1[i (2 r1 + 1) + r1 + dd]
     const float* a2t;
     const float* a1p[3];          // A1 band rows zero-padded to the tiers R = 4, 8, 12 (row stride 2R+1 rounded up to 4)
+    const float* taps;            // toeplitz: A1 taps at [r1 + dd], A2 taps at [2 RMAX_SPATIAL + 1 + r2 + dd]
     const float* om1;
     const bf16_t* om1h;           // bfloat16 copy of Om1
     const float* om1f;            // Om1 in operand order, FRAG_K_F32
@@ -246,7 +248,7 @@ hipError_t launch_tile(const Desc* d, const int* starts, int count, int total_ti
                        int mode, int nterms, int dst_index, int basis_bf16, int src_bf16,
                        int l1max, hipStream_t s);
 hipError_t launch_step(const Desc* d, const int* starts, int count, int total_tiles, int j, int rmax,
-                       int basis_bf16, int l1max, hipStream_t s);
+                       int basis_bf16, int l1max, int toeplitz, hipStream_t s);
 hipError_t launch_gram(const Desc* d, const int* starts, int count, int total_tiles,
                        int mode, int j, float* sketch_out, hipStream_t s);
 hipError_t launch_solve(const Desc* d, int count, int mmax, hipStream_t s);

@@ -49,12 +49,33 @@ CASES = [
 
 @pytest.mark.parametrize("case", CASES)
 def test_bf16_step_properties(case):
+    _check_step(case, toeplitz=True)
+
+
+# Bands whose rows differ (not a convolution): the step kernel's general form,
+# with the band rows streamed per block
+NON_TOEPLITZ = [CASES[0], CASES[3], CASES[5]]
+
+
+@pytest.mark.parametrize("case", NON_TOEPLITZ)
+def test_bf16_step_properties_general_bands(case):
+    _check_step(case, toeplitz=False)
+
+
+def _check_step(case, toeplitz):
     from paper_2603_00839_amd import rtg
     I1, I2, J, r1, r2, rB, l1, l2, l3, with_om3, rnd, m = case
-    print("[case] bf16 step", case, file=sys.stderr, flush=True)
+    print("[case] bf16 step", case, "toeplitz" if toeplitz else "general bands", file=sys.stderr, flush=True)
     p = synth.small_problem(40 + I1 + J, I1, I2, J, r1, r2, rB, l1, l2, l3, m, nu=1e-2, random_bands=rnd)
     if not with_om3:
         p = dataclasses.replace(p, om3=None)
+    if not toeplitz:
+        # scale the in-range entries of a few rows of each band
+        a1 = p.a1_band.copy()
+        a2 = p.a2_band.copy()
+        a1[[1, I1 // 2, I1 - 2]] *= np.float32(1.07)
+        a2[[0, I2 // 3]] *= np.float32(0.93)
+        p = dataclasses.replace(p, a1_band=a1, a2_band=a2)
     op_o = Operator(p.a1_band, p.a2_band, p.b_band)
     sk_b = Sketch(U.bf16_round(p.om1), p.om2, p.om3)        # the sketch the bfloat16 path uses
     og, sg = U.gpu_pair(p)
