@@ -313,7 +313,7 @@ __global__ void __launch_bounds__(C2_THREADS) k_conv2(Conv2Args a) {
     constexpr int NST = (IH * IW * NCH + NTH - 1) / NTH;
     constexpr int KLB = KPB + 8;                        // padded LDS row of layer-B weights
     __shared__ __attribute__((aligned(16))) bf16_t Xs[IH * IW * PSA];
-    __shared__ __attribute__((aligned(16))) bf16_t Ms[MP * PSB];
+    __shared__ __attribute__((aligned(16))) bf16_t Ms[MNT * 16 * PSB];   // whole N-tiles: unconditional stores
     __shared__ __attribute__((aligned(16))) bf16_t WlB[COUTB_M * KLB];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -392,30 +392,50 @@ __global__ void __launch_bounds__(C2_THREADS) k_conv2(Conv2Args a) {
         fetch(min(t + (int)gridDim.x, ntiles - 1));   // the last tile loads a valid tile again, unused
 
         // ---- layer A on the grown tile: N-tiles of 16 pixels, wave w takes w, w + 8, ...
-        for (int nt = wave; nt < MNT; nt += TH) {
-            const int p = nt * 16 + n16;
-            const int pc = min(p, MP - 1);
+        // Operand reads run three taps ahead of the matrix cores, across the
+        // end of an N-tile into the wave's next one (KQA is a multiple of 3,
+        // so tap q always sits in slot q % 3).
+        constexpr int DA = 3;
+        static_assert(KQA % DA == 0, "tap window");
+        auto readA = [&](int nt, int q) {
+            const int pc = min(nt * 16 + n16, MP - 1);
             const int mr = pc / MW, mc = pc % MW;
-            f4 acc[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
+            const int k = 32 * q + 8 * s;
+            const int tap = k / CIN_S, ci0 = k % CIN_S;
+            const int tp = tap < 9 ? tap : 0;
+            const u4 v = *(const u4*)(Xs + ((mr + tp % 3) * IW + mc + tp / 3) * PSA + ci0);
+            return tap < 9 ? v : u4{0u, 0u, 0u, 0u};
+        };
+        {
+            u4 Bw[DA];
 #pragma unroll
-            for (int q = 0; q < KQA; ++q) {
-                const int k = 32 * q + 8 * s;
-                const int tap = k / CIN_S, ci0 = k % CIN_S;
-                const int tp = tap < 9 ? tap : 0;
-                const u4 v = *(const u4*)(Xs + ((mr + tp % 3) * IW + mc + tp / 3) * PSA + ci0);
-                const bf8 B = __builtin_bit_cast(bf8, tap < 9 ? v : u4{0u, 0u, 0u, 0u});
+            for (int q = 0; q < DA; ++q) Bw[q] = readA(min(wave, MNT - 1), q);
+            for (int nt = wave; nt < MNT; nt += TH) {
+                const int ntn = min(nt + TH, MNT - 1);          // past the last tile: a valid tile again, unused
+                f4 acc[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
-                for (int mt = 0; mt < 2; ++mt)
-                    acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AfA[q][mt], B, acc[mt], 0, 0, 0);
-            }
-            const int y2 = i20 - 1 + mr, y1 = i10 - 1 + mc;
-            const bool inimg = (y1 >= 0) & (y1 < I1) & (y2 >= 0) & (y2 < I2);
-            if (p < MP) {
+                for (int q = 0; q < KQA; ++q) {
+                    const u4 cur = Bw[q % DA];
+                    Bw[q % DA] = (q + DA < KQA) ? readA(nt, q + DA) : readA(ntn, q + DA - KQA);
+                    __builtin_amdgcn_sched_barrier(0);       // keep the read ahead of these products
+#pragma unroll
+                    for (int mt = 0; mt < 2; ++mt)
+                        acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AfA[q][mt], __builtin_bit_cast(bf8, cur), acc[mt],
+                                                                          0, 0, 0);
+                }
+                // epilogue without branches: pixels outside the image (the
+                // zero padding of layer B's input) get a factor 0, and the
+                // pixels past MP of the last N-tile land in Ms's tail
+                const int p = nt * 16 + n16;
+                const int pc = min(p, MP - 1);
+                const int mr = pc / MW, mc = pc % MW;
+                const int y2 = i20 - 1 + mr, y1 = i10 - 1 + mc;
+                const float inimg = ((y1 >= 0) & (y1 < I1) & (y2 >= 0) & (y2 < I2)) ? 1.f : 0.f;
 #pragma unroll
                 for (int mt = 0; mt < 2; ++mt) {
                     float v[4];
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) v[i] = inimg ? fmaxf(acc[mt][i] + biasA[mt][i], 0.f) : 0.f;
+                    for (int i = 0; i < 4; ++i) v[i] = fmaxf(acc[mt][i] + biasA[mt][i], 0.f) * inimg;
                     u2 pk;
                     pk[0] = (unsigned)f2bf(v[0]) | ((unsigned)f2bf(v[1]) << 16);
                     pk[1] = (unsigned)f2bf(v[2]) | ((unsigned)f2bf(v[3]) << 16);
@@ -424,29 +444,40 @@ __global__ void __launch_bounds__(C2_THREADS) k_conv2(Conv2Args a) {
             }
         }
         __syncthreads();
-        // ---- layer B: wave w takes output row w, four N-tiles of 16 pixels
+        // ---- layer B: wave w takes output row w, four N-tiles of 16 pixels;
+        // the operands (weights and activations) of tap q + 1 are read while
+        // tap q is on the matrix cores
         f4 acc[4][MTB];
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
             for (int mt = 0; mt < MTB; ++mt) acc[nt][mt] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int q = 0; q < KQB; ++q) {
+        auto loadB = [&](int q, u4* Bq, u4* Wq) {
             const int k = 32 * q + 8 * s;
             const int tap = k / 32, ci0 = k % 32;
             const int tp = tap < 9 ? tap : 0;
-            bf8 Af[MTB];
 #pragma unroll
-            for (int mt = 0; mt < MTB; ++mt)
-                Af[mt] = __builtin_bit_cast(bf8, *(const u4*)(WlB + (16 * mt + n16) * KLB + 32 * q + 8 * s));
+            for (int mt = 0; mt < MTB; ++mt) Wq[mt] = *(const u4*)(WlB + (16 * mt + n16) * KLB + 32 * q + 8 * s);
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt) {
                 const int il = nt * 16 + n16;
                 const u4 v = *(const u4*)(Ms + ((wave + tp % 3) * MW + il + tp / 3) * PSB + ci0);
-                const bf8 B = __builtin_bit_cast(bf8, tap < 9 ? v : u4{0u, 0u, 0u, 0u});
+                Bq[nt] = tap < 9 ? v : u4{0u, 0u, 0u, 0u};
+            }
+        };
+        {
+            u4 Bb[2][4], Wb[2][MTB];
+            loadB(0, Bb[0], Wb[0]);
 #pragma unroll
-                for (int mt = 0; mt < MTB; ++mt)
-                    acc[nt][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Af[mt], B, acc[nt][mt], 0, 0, 0);
+            for (int q = 0; q < KQB; ++q) {
+                if (q + 1 < KQB) loadB(q + 1, Bb[(q + 1) & 1], Wb[(q + 1) & 1]);
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+                    for (int mt = 0; mt < MTB; ++mt)
+                        acc[nt][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            __builtin_bit_cast(bf8, Wb[q & 1][mt]), __builtin_bit_cast(bf8, Bb[q & 1][nt]), acc[nt][mt],
+                            0, 0, 0);
             }
         }
         const bool row_ok = i2 < I2;
