@@ -181,7 +181,9 @@ size_t rtg_cnn_workspace_bytes(int N, int I1, int I2);
 int rtg_cnn_init(void* state, const float* params, void* stream);
 /* copy the float32 master parameters out (synchronous) */
 int rtg_cnn_export(const void* state, float* params, void* stream);
-/* X0 = C + f(C) */
+/* X0 = C + f(C).  N * I1 * I2 below 2^25 pixels per call (32-bit byte
+ * offsets into the 32-channel activations); larger batches are split by the
+ * caller. */
 int rtg_cnn_forward(const void* state, const float* C, int N, int I1, int I2,
                     float* X0, void* ws, size_t ws_bytes, void* stream);
 /* gradients of sum((X0 - Y)^2) / (3 N I1 I2) w.r.t. every parameter, kept

@@ -279,8 +279,9 @@ struct WgradArgs {
 // zero padding layer B sees -- and layer B (32 -> COUT) reads it from LDS, so
 // the activation between the two layers never goes to memory.  Layer A's
 // weights stay in registers for the whole kernel, layer B's in LDS.
-// Persistent grid: a workgroup loads the next tile's input (with its
-// two-pixel halo) into registers while it computes the current tile.
+// Persistent grid: a workgroup streams the next tile's input (with its
+// two-pixel halo) into LDS by asynchronous loads while it computes layer B of
+// the current tile.
 // ---------------------------------------------------------------------------
 struct Conv2Args {
     int N, I1, I2;
@@ -310,7 +311,6 @@ __global__ void __launch_bounds__(C2_THREADS) k_conv2(Conv2Args a) {
     constexpr int KPB = kpad_of(32), KQB = KPB / 32;
     constexpr int MTB = COUTB_M / 16;
     constexpr int NCH = CIN_S / 8;
-    constexpr int NST = (IH * IW * NCH + NTH - 1) / NTH;
     constexpr int KLB = KPB + 8;                        // padded LDS row of layer-B weights
     __shared__ __attribute__((aligned(16))) bf16_t Xs[IH * IW * PSA];
     __shared__ __attribute__((aligned(16))) bf16_t Ms[MNT * 16 * PSB];   // whole N-tiles: unconditional stores
@@ -344,39 +344,42 @@ __global__ void __launch_bounds__(C2_THREADS) k_conv2(Conv2Args a) {
         for (int mt = 0; mt < MTB; ++mt) biasB[mt][i] = *gptr(a.bB + 16 * mt + 4 * s + i);
     }
 
-    u4 stg[NST];
-    unsigned okbits = 0;
-    auto fetch = [&](int t) {
-        okbits = 0;
-        const int t1 = t % nt1, r = t / nt1;
+    // The input tile (two-pixel halo) reaches Xs by asynchronous global-to-
+    // LDS loads: 16-byte slots, PSA / 8 per pixel, slot s fetched by thread
+    // s % NTH of pass s / NTH (a wave's instruction fills 1 KB, lane i at
+    // bytes 16 i).  Padding slots and pixels outside the image are fetched
+    // from past the buffer range and read as zeros.  The next tile's loads
+    // are issued once layer A no longer reads Xs, so they overlap layer B.
+    constexpr int SPP = PSA / 8;                        // slots per pixel
+    constexpr int NSL = IH * IW * SPP;
+    const auto rx = __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16_t*>(a.x), (short)0,
+                                                      (int)((size_t)a.N * plane * CIN_S * 2), 0x00020000);
+    auto dma_tile = [&](int tt) {
+        const int t1 = tt % nt1, r = tt / nt1;
         const int i10 = t1 * TW, i20 = (r % nt2) * TH, img = r / nt2;
-#pragma unroll
-        for (int it = 0; it < NST; ++it) {
-            const int e = tid + NTH * it;
-            const int c8 = e % NCH, pxl = e / NCH;
+        auto one = [&](int it) {
+            const int sl = it * NTH + tid;
+            const int pxl = sl / SPP, c = sl % SPP;
             const int y1 = i10 - 2 + pxl % IW, y2 = i20 - 2 + pxl / IW;
-            const int c1 = min(max(y1, 0), I1 - 1), c2 = min(max(y2, 0), I2 - 1);
-            stg[it] = *gptr((const u4*)(a.x + (((size_t)img * I2 + c2) * I1 + c1) * CIN_S + c8 * 8));
-            okbits |= (unsigned)((e < IH * IW * NCH) & (y1 >= 0) & (y1 < I1) & (y2 >= 0) & (y2 < I2)) << it;
-        }
+            const bool ok = (c < NCH) & (y1 >= 0) & (y1 < I1) & (y2 >= 0) & (y2 < I2);
+            const unsigned off =
+                ok ? (unsigned)(((((size_t)img * I2 + y2) * I1 + y1) * CIN_S + c * 8) * 2) : 0x80000000u;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                rx, (__attribute__((address_space(3))) void*)(Xs + (size_t)(it * NTH + wave * 64) * 8), 16, off, 0, 0, 0);
+        };
+#pragma unroll
+        for (int it = 0; it < NSL / NTH; ++it) one(it);
+        if constexpr (NSL % NTH != 0)
+            if (tid < NSL % NTH) one(NSL / NTH);
     };
     int t = blockIdx.x;
-    if (t < ntiles) fetch(t);
+    if (t < ntiles) dma_tile(t);
     for (; t < ntiles; t += gridDim.x) {
         const int t1 = t % nt1, rr = t / nt1;
         const int i10 = t1 * TW, i20 = (rr % nt2) * TH, img = rr / nt2;
-        __syncthreads();                  // the previous tile's reads of Xs and Ms are done
-#pragma unroll
-        for (int it = 0; it < NST; ++it) {
-            const int e = tid + NTH * it;
-            if (e < IH * IW * NCH) {
-                const int c8 = e % NCH, pxl = e / NCH;
-                const unsigned m = 0u - ((okbits >> it) & 1u);
-                *(u4*)(Xs + pxl * PSA + c8 * 8) = stg[it] & u4{m, m, m, m};
-            }
-        }
-        __syncthreads();
-        // epilogue operands of layer B (last pair), before the prefetch
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's loads of the tile have landed
+        __syncthreads();                     // all of them; the previous tile's reads of Ms are done
+        // epilogue operands of layer B (last pair)
         float cin[4][3];
         const int i2 = i20 + wave;
         const int i2c = min(i2, I2 - 1);
@@ -388,8 +391,7 @@ __global__ void __launch_bounds__(C2_THREADS) k_conv2(Conv2Args a) {
                 for (int c = 0; c < 3; ++c) cin[nt][c] = *gptr(a.C + ((size_t)img * 3 + c) * plane + (size_t)i2c * I1 + i1c);
             }
         }
-        __builtin_amdgcn_sched_barrier(0);
-        fetch(min(t + (int)gridDim.x, ntiles - 1));   // the last tile loads a valid tile again, unused
+
 
         // ---- layer A on the grown tile: N-tiles of 16 pixels, wave w takes w, w + 8, ...
         // Operand reads run three taps ahead of the matrix cores, across the
@@ -443,7 +445,8 @@ __global__ void __launch_bounds__(C2_THREADS) k_conv2(Conv2Args a) {
                 }
             }
         }
-        __syncthreads();
+        __syncthreads();                     // layer A done: Ms complete, Xs free
+        if (t + (int)gridDim.x < ntiles) dma_tile(t + (int)gridDim.x);
         // ---- layer B: wave w takes output row w, four N-tiles of 16 pixels;
         // the operands (weights and activations) of tap q + 1 are read while
         // tap q is on the matrix cores
@@ -776,6 +779,8 @@ hipError_t layer_forward(int l, char* st, const StateLayout& S, const bf16_t* x,
 
 int check_dims(int N, int I1, int I2) {
     if (N < 1 || I1 < 1 || I2 < 1) return RTG_E_SHAPE;
+    // the fused pairs address a 32-channel activation with 32-bit byte offsets
+    if ((size_t)N * I1 * I2 * 32 * 2 > 0x7FFFFFFFull) return RTG_E_SHAPE;
     return RTG_OK;
 }
 
