@@ -59,7 +59,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a device-to-device copy of MB megabytes (counter calibration)")
-    ap.add_argument("--only", choices=["fp32_plain", "bf16_warm"], default=None,
+    ap.add_argument("--only", choices=["fp32_plain", "bf16_warm", "fp32_unsketched"], default=None,
                     help="time one variant only (profiling runs)")
     return ap.parse_args()
 
@@ -97,6 +97,12 @@ def step_bytes(n, es, m_eff):
     operator's re-read of the V_j tile and its halo is not counted again; W is
     never stored).  Steps j = 1 .. m_eff - 1 form a new tensor."""
     return sum((j + 1) * es * n for j in range(1, m_eff))
+
+
+def frob_bytes(n, es, m_eff):
+    """Algorithmic bytes of the Frobenius Gram launches of one unsketched
+    solve: step j reads W (float32) and V_1..V_j."""
+    return sum(4 * n + j * es * n for j in range(1, m_eff + 1)) + 4 * n
 
 
 def tile_bytes(n, es, m_eff, has_x0):
@@ -244,9 +250,19 @@ def main():
     torch.cuda.synchronize()
 
     results = {}
-    variants = [args.only] if args.only else ["fp32_plain", "bf16_warm"]
+    variants = [args.only] if args.only else ["fp32_plain", "bf16_warm", "fp32_unsketched"]
     for v in variants:
-        if v == "fp32_plain":
+        if v == "fp32_unsketched":
+            # the same solve with the identity sketch: Frobenius inner products of
+            # the full tensors (the unsketched global GMRES the method improves on)
+            sk_id = rtg.setup_sketch(I1, I2, J)
+            prm = [rtg.make_params(args.m, rtg.F32, delta=q["delta"], eta=1.01) for q in probs]
+            plan = rtg.BatchPlan([op] * B, [sk_id] * B, [q["C"] for q in probs], [None] * B, prm)
+            r = time_variant(plan, args.steps, args.warmup, rtg, torch, rtg.KIND_GRAM,
+                             lambda inf: frob_bytes(n, 4, inf.iters))
+            r["kernel"] = ("k_gram", "k_gram.hip", "Frobenius inner products of the full tensors "
+                                                   "(float32 basis, identity sketch)")
+        elif v == "fp32_plain":
             prm = [rtg.make_params(args.m, rtg.F32, delta=q["delta"], eta=1.01) for q in probs]
             plan = rtg.BatchPlan([op] * B, [q["sk"] for q in probs], [q["C"] for q in probs], [None] * B, prm)
             r = time_variant(plan, args.steps, args.warmup, rtg, torch, rtg.KIND_TILE,

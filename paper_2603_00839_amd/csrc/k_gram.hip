@@ -108,6 +108,59 @@ __device__ __forceinline__ void finish_sketches(const Desc& d, int q0, int qn,
     }
 }
 
+// Sum of 16 values over a wave in 17 shuffles: each of the first four levels
+// halves the set a lane keeps (the lane bit of the level's offset picks the
+// half), the last two add across neighbours, so that afterwards lanes
+// 4k .. 4k + 3 hold the total of value k.
+__device__ __forceinline__ void wave_sum16(float (&v)[16], int lane) {
+#define RTG_HALVE(H, OFF)                                          \
+    {                                                              \
+        const bool up = (lane & (OFF)) != 0;                       \
+        _Pragma("unroll") for (int k = 0; k < (H); ++k) {          \
+            const float send = up ? v[k] : v[k + (H)];             \
+            const float keep = up ? v[k + (H)] : v[k];             \
+            v[k] = keep + __shfl_xor(send, (OFF), 64);             \
+        }                                                          \
+    }
+    RTG_HALVE(8, 32) RTG_HALVE(4, 16) RTG_HALVE(2, 8) RTG_HALVE(1, 4)
+#undef RTG_HALVE
+    v[0] += __shfl_xor(v[0], 2, 64);
+    v[0] += __shfl_xor(v[0], 1, 64);
+}
+
+// FROB_CHUNK elements of a tensor, FROB_PT consecutive ones per thread,
+// from a buffer that reads zeros past its end.
+constexpr int FROB_PT = FROB_CHUNK / 256;
+static_assert(FROB_PT == 16, "two 8-element halves per thread");
+__device__ __forceinline__ void frob_load(__amdgpu_buffer_rsrc_t r, bool bf, unsigned e, float (&x)[FROB_PT]) {
+    if (bf) {
+        typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const u4v w = __builtin_amdgcn_raw_buffer_load_b128(r, (e + 8u * h) * 2u, 0, 0);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                x[8 * h + 2 * q] = __uint_as_float(w[q] << 16);
+                x[8 * h + 2 * q + 1] = __uint_as_float(w[q] & 0xffff0000u);
+            }
+        }
+    } else {
+        typedef float f4v __attribute__((ext_vector_type(4)));
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const f4v w = __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(r, (e + 4u * h) * 4u, 0, 0));
+#pragma unroll
+            for (int q = 0; q < 4; ++q) x[4 * h + q] = w[q];
+        }
+    }
+}
+
+// FROB: the sketch is the identity (unsketched global GMRES): the inner
+// products are Frobenius products of the full tensors.  Each workgroup takes
+// FROB_CHUNK elements of the problem's tensors and forms its shares of
+// <V_i, W> and <V_i, V_j> (i <= j) and ||W||^2, reading every stored basis
+// tensor once: the orthogonalisation traffic that a sketch avoids.
+template <bool FROB>
 __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
                                               const int* __restrict__ starts, int count, int mode,
                                               int j, float* sketch_out) {
@@ -128,6 +181,62 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
     if (mode == GM_STEP && d.state[ST_ACTIVE] == 0) return;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nitems = (mode == GM_STEP) ? j + 1 : 1;
+    if constexpr (FROB) {
+        // ---- Frobenius shares over elements [wgi FROB_CHUNK, (wgi + 1) FROB_CHUNK)
+        __shared__ float red[4][16];
+        const int es = d.bf16 ? 2 : 4;
+        const int nb = (int)(d.n * 4);       // float32 tensors (W, R0); the host keeps n 4 < 2^31
+        const unsigned e = (unsigned)wgi * FROB_CHUNK + (unsigned)tid * FROB_PT;
+        const float* wsrc = (mode == GM_START) ? (const float*)d.R0src : d.W;
+        const auto rw = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(wsrc), (short)0, nb, 0x00020000);
+        float wv[FROB_PT];
+        frob_load(rw, false, e, wv);
+        float nw = 0.f;
+#pragma unroll
+        for (int u = 0; u < FROB_PT; ++u) nw = fmaf(wv[u], wv[u], nw);
+        if (mode == GM_STEP) {
+            auto basis = [&](int i) {
+                return __builtin_amdgcn_make_buffer_rsrc((char*)d.V + (size_t)i * d.n * es, (short)0, (int)(d.n * es),
+                                                         0x00020000);
+            };
+            float vj[FROB_PT];
+            frob_load(basis(j - 1), d.bf16, e, vj);
+            for (int i0 = 0; i0 < j; i0 += 8) {
+                float acc[16];
+#pragma unroll
+                for (int k = 0; k < 16; ++k) acc[k] = 0.f;
+                float vb[2][FROB_PT];
+                frob_load(basis(min(i0, j - 1)), d.bf16, e, vb[0]);
+#pragma unroll
+                for (int ii = 0; ii < 8; ++ii) {
+                    if (ii + 1 < 8) frob_load(basis(min(i0 + ii + 1, j - 1)), d.bf16, e, vb[(ii + 1) & 1]);
+                    __builtin_amdgcn_sched_barrier(0);   // one item ahead, no further
+                    const bool live = i0 + ii < j;
+#pragma unroll
+                    for (int u = 0; u < FROB_PT; ++u) {
+                        const float x = live ? vb[ii & 1][u] : 0.f;
+                        acc[2 * ii] = fmaf(x, wv[u], acc[2 * ii]);
+                        acc[2 * ii + 1] = fmaf(x, vj[u], acc[2 * ii + 1]);
+                    }
+                }
+                wave_sum16(acc, lane);
+                if ((lane & 3) == 0) red[wave][(lane >> 2) & 15] = acc[0];
+                __syncthreads();
+                if (tid < 16 && i0 + tid / 2 < j)
+                    wds[2 * (i0 + tid / 2) + (tid & 1)] =
+                        ((double)red[0][tid] + (double)red[1][tid]) + ((double)red[2][tid] + (double)red[3][tid]);
+                __syncthreads();
+            }
+        }
+        const double nws = wave_sum((double)nw);
+        if (lane == 0) ds[wave] = nws;
+        __syncthreads();
+        if (tid == 0) {
+            wds[2 * (nitems - 1)] = (ds[0] + ds[1]) + (ds[2] + ds[3]);
+            wds[2 * (nitems - 1) + 1] = 0.0;
+        }
+    } else {
     const int L12 = d.l1 * d.l2, l3 = d.l3;
     const int CH = gram_pairs_per_block(l3);
     const int q0 = wgi * CH;
@@ -163,7 +272,6 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
     // to wave i % 4; a wave takes IG of its items per pass with EU elements
     // of each per lane, all loads in flight together (clamped indices,
     // masked: branch-free).
-    const int nitems = (mode == GM_STEP) ? j + 1 : 1;
     const int nglob = (mode == GM_STEP) ? j - 1 : 0;
     constexpr int IG = 4, EU = 12;
     for (int it0 = wave; it0 < nglob; it0 += 4 * IG) {
@@ -221,6 +329,8 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
             }
         }
     }
+
+    }   // sketched shares
 
     // ---- the last workgroup of this problem finishes the step.  Wave 0
     // publishes the workgroup's shares with one release at agent scope (an
@@ -449,8 +559,11 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
 }
 
 hipError_t launch_gram(const Desc* d, const int* starts, int count, int total_tiles, int mode, int j,
-                       float* sketch_out, hipStream_t s) {
-    hipLaunchKernelGGL(k_gram, dim3(total_tiles), dim3(256), 0, s, d, starts, count, mode, j, sketch_out);
+                       float* sketch_out, hipStream_t s, int unsketched) {
+    if (unsketched)
+        hipLaunchKernelGGL(k_gram<true>, dim3(total_tiles), dim3(256), 0, s, d, starts, count, mode, j, sketch_out);
+    else
+        hipLaunchKernelGGL(k_gram<false>, dim3(total_tiles), dim3(256), 0, s, d, starts, count, mode, j, sketch_out);
     return hipGetLastError();
 }
 

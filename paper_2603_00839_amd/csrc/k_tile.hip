@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(256) k_tile(const Desc* __restrict__ descs,
     if (mode == TM_NEWV) nterms = nterms_arg;
     else if (mode == TM_ASSEMBLE) nterms = d.state[ST_MEFF];
     const bool do_store = (mode == TM_NEWV || mode == TM_ASSEMBLE);
-    const bool do_sketch = (mode != TM_ASSEMBLE);
+    const bool do_sketch = (mode != TM_ASSEMBLE) && !d.unsketched;   // an identity sketch keeps no partials
     const bool dual = (mode == TM_NEWV);
     const bool src_is_bf = BB && !SPLIT && (mode == TM_SKETCH_SRC);
 

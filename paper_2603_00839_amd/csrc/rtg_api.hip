@@ -47,6 +47,7 @@ struct rtg_sk_s {
     rtg::bf16_t* om1h;
     float* om1f;          // Om1 in MFMA operand order (float32 tiles)
     rtg::bf16_t* om1hf;   // bfloat16 Om1 in MFMA operand order
+    int identity;         // all three factors the identity: unsketched inner products
 };
 
 namespace {
@@ -70,16 +71,18 @@ Layout problem_layout(const rtg_op_s* op, const rtg_sk_s* sk, int m, int bf16) {
     L.n_i2t = (op->I2 + TILE_TC - 1) / TILE_TC;
     L.ntile_tile = op->J * L.n_i2t;
     const int ch = gram_pairs_per_block(sk->l3);
-    L.ntile_gram = (sk->l1 * sk->l2 + ch - 1) / ch;
+    L.ntile_gram = sk->identity ? frob_wgs((long long)n) : (sk->l1 * sk->l2 + ch - 1) / ch;
     L.ntile_phi = phi_tiles(op->I1, op->I2, op->J, phi_jt(op->J));
-    const size_t part = (size_t)L.ntile_tile * sk->l1 * sk->l2 * sizeof(float);
+    // an identity sketch keeps no partials, stored sketches or composed matrices
+    const bool sk_bufs = !sk->identity;
+    const size_t part = sk_bufs ? (size_t)L.ntile_tile * sk->l1 * sk->l2 * sizeof(float) : 0;
     size_t off = 0;
     auto take = [&](size_t bytes) { off = align_up(off); size_t at = off; off += bytes; return at; };
     L.V = take((size_t)(m + 1) * n * es);
     L.W = take(n * sizeof(float));
     L.PW = take(part);
     L.PV = take(part);
-    L.SV = take((size_t)(m + 1) * Ls * sizeof(float));
+    L.SV = take(sk_bufs ? (size_t)(m + 1) * Ls * sizeof(float) : 0);
     L.dots = take((size_t)L.ntile_gram * (MMAX + 2) * 2 * sizeof(double));
     L.G = take((size_t)(m + 1) * (m + 1) * sizeof(double));
     L.H = take((size_t)(m + 1) * m * sizeof(double));
@@ -89,10 +92,10 @@ Layout problem_layout(const rtg_op_s* op, const rtg_sk_s* sk, int m, int bf16) {
     L.y = take((size_t)m * sizeof(double));
     L.state = take(NSTATE * sizeof(int));
     L.scal = take(NSCAL * sizeof(double));
-    L.ot1 = take(frag_elems(sk->l1, op->I1, FRAG_K_F32) * sizeof(float));
-    L.ot1h = take(2 * frag_elems(sk->l1, op->I1, FRAG_K_BF16) * sizeof(bf16_t));
-    L.ot2 = take((size_t)sk->l2 * op->I2 * sizeof(float));
-    L.ot3 = take((size_t)sk->l3 * op->J * sizeof(float));
+    L.ot1 = take(sk_bufs ? frag_elems(sk->l1, op->I1, FRAG_K_F32) * sizeof(float) : 0);
+    L.ot1h = take(sk_bufs ? 2 * frag_elems(sk->l1, op->I1, FRAG_K_BF16) * sizeof(bf16_t) : 0);
+    L.ot2 = take(sk_bufs ? (size_t)sk->l2 * op->I2 * sizeof(float) : 0);
+    L.ot3 = take(sk_bufs ? (size_t)sk->l3 * op->J * sizeof(float) : 0);
     L.total = align_up(off);
     return L;
 }
@@ -133,6 +136,7 @@ void fill_desc(Desc& d, const rtg_op_s* op, const rtg_sk_s* sk, int m, int bf16,
     for (int k = 0; k < 3; ++k) d.a1p[k] = op->a1p[k];
     d.toeplitz = op->toeplitz;
     d.taps = op->taps;
+    d.unsketched = sk->identity;
     d.om1 = sk->om1; d.om1h = sk->om1h; d.om2 = sk->om2; d.om3 = sk->om3;
     d.om1f = sk->om1f; d.om1hf = sk->om1hf;
     if (base) {
@@ -189,6 +193,7 @@ struct Plan {
     int phi_jt;        // output channels per operator tile (one choice per batch)
     bool step_ok;      // the fused step kernel applies (32-bit byte offsets into a basis vector)
     int toeplitz;      // every problem's bands are Toeplitz
+    int unsketched;    // every problem's sketch is the identity (a batch is all one or all the other)
 };
 
 int build_plan(std::vector<Desc>& descs, void* ws, hipStream_t s, Plan& plan) {
@@ -213,12 +218,15 @@ int build_plan(std::vector<Desc>& descs, void* ws, hipStream_t s, Plan& plan) {
     plan.compose_max = 1;
     plan.step_ok = true;
     plan.toeplitz = 1;
+    plan.unsketched = descs.empty() ? 0 : descs[0].unsketched;
     for (auto& d : descs) {
+        if (d.unsketched != plan.unsketched) return RTG_E_ARG;
+        if (d.unsketched && d.n * 4 > 0x7FFFFFFFll) return RTG_E_SHAPE;
         plan.toeplitz = plan.toeplitz && d.toeplitz;
         plan.step_ok = plan.step_ok && d.n * 2 <= 0x7FFFFFFFll &&
                        frag_elems(d.l1, d.I1, FRAG_K_BF16) * 4 <= 0x7FFFFFFFull && d.a1p[0] != nullptr;
         plan.rmax = std::max(plan.rmax, std::max(d.r1, d.r2));
-        plan.l1max = std::max(plan.l1max, d.l1);
+        if (!d.unsketched) plan.l1max = std::max(plan.l1max, d.l1);
         plan.compose_max = std::max(plan.compose_max, (int)compose_mode1_entries(d.l1, d.I1) + d.l2 * d.I2 + d.l3 * d.J);
     }
     char* base = (char*)ws;
@@ -289,6 +297,30 @@ int run_solver(const Plan& plan, int count, int mmax, int bf16, bool any_x0, boo
     const int* st = starts_of(plan, KIND_TILE, count);
     const int* sg = starts_of(plan, KIND_GRAM, count);
     RTG_HIP(launch_init(plan.d_desc, count, s));
+    if (plan.unsketched) {
+        // Identity sketch (unsketched global GMRES, the Omega = I form of the
+        // method): W = Phi(V_j) is formed first, the Gram kernel takes the
+        // Frobenius products of the full tensors, and the tile kernel forms
+        // V_{j+1} without sketching.
+        const int us = 1;
+        if (any_x0) RTG_TIMED(0, launch_phi(plan.d_desc, sp, count, plan.total[KIND_PHI], PS_X0, 0, plan.rmax, plan.phi_jt, 0, s));
+        RTG_TIMED(2, launch_gram(plan.d_desc, sg, count, plan.total[KIND_GRAM], GM_START, 0, nullptr, s, us));
+        RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_NEWV, 0, 0, bf16, 0, plan.l1max, s));
+        for (int j = 1; j <= mmax; ++j) {
+            RTG_TIMED(0, launch_phi(plan.d_desc, sp, count, plan.total[KIND_PHI], PS_BASIS, j - 1, plan.rmax,
+                                    plan.phi_jt, bf16, s));
+            RTG_TIMED(2, launch_gram(plan.d_desc, sg, count, plan.total[KIND_GRAM], GM_STEP, j, nullptr, s, us));
+            if (j < mmax || last_newv)
+                RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_NEWV, j, j, bf16, 0,
+                                         plan.l1max, s));
+        }
+        if (solve) {
+            RTG_TIMED(3, launch_solve(plan.d_desc, count, mmax, s));
+            RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_ASSEMBLE, 0, 0, bf16, 0,
+                                     plan.l1max, s));
+        }
+        return RTG_OK;
+    }
     RTG_HIP(launch_compose(plan.d_desc, count, plan.compose_max, s));
     if (any_x0) RTG_TIMED(0, launch_phi(plan.d_desc, sp, count, plan.total[KIND_PHI], PS_X0, 0, plan.rmax, plan.phi_jt, 0, s));
     RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_SKETCH_SRC, 0, 0, bf16, 0, plan.l1max, s));
@@ -469,12 +501,19 @@ int rtg_setup_sketch(int I1, int I2, int J, int l1, int l2, int l3, const float*
     if (!out) return RTG_E_ARG;
     *out = nullptr;
     if (I1 < 8 || I2 < 1 || J < 1 || (I1 % 8) != 0) return RTG_E_SHAPE;
+    if (!om1 && !om2 && !om3) {
+        // identity on every mode: the unsketched method, any size (no matrices kept)
+        if (l1 != I1 || l2 != I2 || l3 != J) return RTG_E_SHAPE;
+        if (I1 >= (1 << 20) || I2 >= (1 << 20)) return RTG_E_SHAPE;
+        *out = new rtg_sk_s{I1, I2, J, l1, l2, l3, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 1};
+        return RTG_OK;
+    }
     if (l1 < 1 || l1 > I1 || l1 > LMAX_SPATIAL || l2 < 1 || l2 > I2 || l2 > LMAX_SPATIAL) return RTG_E_SHAPE;
     if ((!om1 && l1 != I1) || (!om2 && l2 != I2) || (!om3 && l3 != J)) return RTG_E_SHAPE;
     if (om3 && (l3 < 1 || l3 > J || l3 > LMAX_3)) return RTG_E_SHAPE;
     if (!om3 && J > 4096) return RTG_E_SHAPE;
     if (I1 >= (1 << 20) || I2 >= (1 << 20)) return RTG_E_SHAPE;   // 32-bit byte offsets into the sketch matrices
-    rtg_sk_s* sk = new rtg_sk_s{I1, I2, J, l1, l2, l3, om3 ? 1 : 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    rtg_sk_s* sk = new rtg_sk_s{I1, I2, J, l1, l2, l3, om3 ? 1 : 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0};
     // identity factors are stored explicitly for modes 1 and 2
     std::vector<float> h1((size_t)l1 * I1, 0.f), h2((size_t)l2 * I2, 0.f);
     if (om1) std::memcpy(h1.data(), om1, h1.size() * 4);
@@ -531,6 +570,7 @@ int rtg_destroy_sketch(rtg_sk sk) {
 size_t rtg_sketch_workspace_bytes(rtg_sk sk) {
     if (!sk) return 0;
     const int n_i2t = (sk->I2 + TILE_TC - 1) / TILE_TC;
+    if (sk->identity) return plan_bytes(1);
     return plan_bytes(1) + align_up((size_t)sk->J * n_i2t * sk->l1 * sk->l2 * sizeof(float));
 }
 
@@ -540,6 +580,11 @@ int rtg_sketch(rtg_sk sk, int x_dtype, const void* X, float* SX, void* ws, size_
     if (!aligned16(X) || !aligned16(ws)) return RTG_E_ARG;
     if (ws_bytes < rtg_sketch_workspace_bytes(sk)) return RTG_E_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
+    if (sk->identity) {      // S(X) = X, same column-major order
+        if (x_dtype != RTG_F32) return RTG_E_ARG;
+        RTG_HIP(hipMemcpyAsync(SX, X, (size_t)sk->I1 * sk->I2 * sk->J * sizeof(float), hipMemcpyDeviceToDevice, s));
+        return RTG_OK;
+    }
     rtg_op_s dummy{sk->I1, sk->I2, sk->J, 0, 0, 0, nullptr, nullptr, nullptr, nullptr, nullptr,
                    {nullptr, nullptr, nullptr}, 0, nullptr};
     Layout L = problem_layout(&dummy, sk, 1, x_dtype == RTG_BF16);

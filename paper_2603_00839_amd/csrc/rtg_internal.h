@@ -50,6 +50,7 @@ struct Desc {
     int mu_fixed;       // 1: mu given, 0: discrepancy principle
     int keep_last;      // form V_{m+1} after the last step (Arnoldi-only calls)
     int toeplitz;       // A1 and A2 are Toeplitz on their in-range entries (convolutions, zero BC)
+    int unsketched;     // identity sketch: Frobenius inner products of the full tensors
     long long n;        // I1*I2*J
     long long L;        // l1*l2*l3
     // operator / sketch (device)
@@ -145,6 +146,11 @@ __device__ __forceinline__ int xcd_tile(int b, int total) {
     const int q = total >> 3, r = total & 7, x = b & 7;
     return x * q + min(x, r) + (b >> 3);
 }
+
+// Identity sketch (unsketched global GMRES): tensor elements per Gram
+// workgroup, and the workgroups of one problem
+constexpr int FROB_CHUNK = 4096;
+__host__ __device__ inline int frob_wgs(long long n) { return (int)((n + FROB_CHUNK - 1) / FROB_CHUNK); }
 
 // (a, b) pairs of the sketch owned by one sketched-Gram workgroup
 __host__ __device__ inline int gram_pairs_per_block(int l3) {
@@ -250,7 +256,7 @@ hipError_t launch_tile(const Desc* d, const int* starts, int count, int total_ti
 hipError_t launch_step(const Desc* d, const int* starts, int count, int total_tiles, int j, int rmax,
                        int basis_bf16, int l1max, int toeplitz, hipStream_t s);
 hipError_t launch_gram(const Desc* d, const int* starts, int count, int total_tiles,
-                       int mode, int j, float* sketch_out, hipStream_t s);
+                       int mode, int j, float* sketch_out, hipStream_t s, int unsketched = 0);
 hipError_t launch_solve(const Desc* d, int count, int mmax, hipStream_t s);
 hipError_t launch_init(const Desc* d, int count, hipStream_t s);
 hipError_t launch_compose(const Desc* d, int count, int max_entries, hipStream_t s);

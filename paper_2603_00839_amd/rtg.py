@@ -204,13 +204,16 @@ def apply_operator(op: Operator, X, C=None, out=None):
 # sketch
 # ---------------------------------------------------------------------------
 class Sketch:
-    """Handle of rtg_setup_sketch; Om_k are (l_k, I_k) float32 arrays or None."""
+    """Handle of rtg_setup_sketch; Om_k are (l_k, I_k) float32 arrays or None.
+    With all three None the sketch is the identity: the solver then runs the
+    unsketched method (Frobenius inner products of the full tensors)."""
 
     def __init__(self, I1, I2, J, om1=None, om2=None, om3=None):
         self.shape = (int(I1), int(I2), int(J))
         o = [None if x is None else np.ascontiguousarray(x, dtype=np.float32) for x in (om1, om2, om3)]
         self.l = tuple(d if x is None else x.shape[0] for x, d in zip(o, self.shape))
         self._keep = o
+        self.identity = all(x is None for x in o)
         h = ctypes.c_void_p()
         _check(lib().rtg_setup_sketch(I1, I2, J, self.l[0], self.l[1], self.l[2], _fptr(o[0]), _fptr(o[1]),
                                       _fptr(o[2]), ctypes.byref(h)), "rtg_setup_sketch")
@@ -276,7 +279,8 @@ def workspace_layout(op: Operator, sk: Sketch, m: int, basis_dtype: int = F32):
 def arnoldi(op: Operator, sk: Sketch, R0, m: int, basis_dtype: int = F32, bd_tol: float = 1e-6, ws=None):
     """m steps of the sketched global Arnoldi process.  Returns a dict with H
     ((m+1) x m float64), beta, m_done, and views V ((m+1, J, I2, I1)) and SV
-    ((m+1, L)) into the workspace."""
+    ((m+1, L)) into the workspace; SV is None for the identity sketch (no
+    sketches are kept: S(V) is V itself)."""
     torch = _torch()
     _check_tensor(R0, op.device_shape, "R0")
     nbytes = workspace_bytes(op, sk, m, basis_dtype)
@@ -292,7 +296,7 @@ def arnoldi(op: Operator, sk: Sketch, R0, m: int, basis_dtype: int = F32, bd_tol
     n = int(np.prod(op.shape))
     vdt = torch.bfloat16 if basis_dtype == BF16 else torch.float32
     V = ws[voff:voff + (m + 1) * n * esz].view(vdt).view((m + 1,) + op.device_shape)
-    SV = ws[soff:soff + (m + 1) * sk.L * 4].view(torch.float32).view(m + 1, sk.L)
+    SV = None if sk.identity else ws[soff:soff + (m + 1) * sk.L * 4].view(torch.float32).view(m + 1, sk.L)
     return {"H": H.t(), "beta": beta, "m_done": m_done, "V": V, "SV": SV, "ws": ws}
 
 
