@@ -37,7 +37,7 @@ class SolveResult:
 def rtg_gmres(phi, sketch, C, m, X0=None, mu: Optional[float] = None,
               delta: Optional[float] = None, eta: float = 1.01,
               reorth: bool = True, bd_tol: float = 1e-12,
-              stop_res: Optional[float] = None) -> SolveResult:
+              stop_res: Optional[float] = None, mu_rule: str = "discrepancy") -> SolveResult:
     C = np.asarray(C, dtype=np.float64)
     X0 = np.zeros_like(C) if X0 is None else np.asarray(X0, dtype=np.float64)
     R0 = C - phi(X0)
@@ -46,9 +46,9 @@ def rtg_gmres(phi, sketch, C, m, X0=None, mu: Optional[float] = None,
     if ar.m_eff == 0:
         return SolveResult(X0.copy(), np.zeros(0), 0.0, ar.flags, 0, ar.beta,
                            0.0, 0.0, ar)
-    if mu is None and delta is None:
+    if mu is None and delta is None and mu_rule != "gcv":
         mu = 0.0
-    pt = projected_tikhonov(ar.H, ar.beta, mu=mu, delta=delta, eta=eta)
+    pt = projected_tikhonov(ar.H, ar.beta, mu=mu, delta=delta, eta=eta, rule=mu_rule)
     X = X0.copy()
     for j in range(ar.m_eff):
         X = X + pt["y"][j] * ar.V[j]

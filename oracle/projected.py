@@ -132,16 +132,61 @@ def discrepancy_mu(P: SVDProblem, target: float, iters: int = 200):
     return math.exp(0.5 * (lo + hi)), 0
 
 
-def projected_tikhonov(H, beta, mu=None, delta=None, eta=1.01):
+def gcv(P: SVDProblem, mu: float) -> float:
+    """Generalized cross-validation function of the projected problem (Sec. 3,
+    parameter selection via GCV):
+        GCV(mu) = ||H y_mu - beta e1||^2 / tr(I - H (H^T H + mu I)^{-1} H^T)^2,
+    I the (k+1) x (k+1) identity.  With H = U diag(s) W^T the influence matrix
+    is U diag(s^2 / (s^2 + mu)) U^T, so the trace is (k + 1) - sum_i
+    s_i^2 / (s_i^2 + mu), and the numerator is phi(mu)."""
+    den = (P.k + 1) - float(np.sum(P.s ** 2 / (P.s ** 2 + mu)))
+    return P.residual2(mu) / (den * den)
+
+
+GCV_GRID = 512
+
+
+def gcv_mu(P: SVDProblem) -> float:
+    """Minimiser of GCV over log(mu): the best of GCV_GRID points spread evenly
+    over [log(s_min^2) - 10, log(s_max^2) + 10] (s_min the smallest positive
+    singular value, floored at 1e-30 s_max), then golden-section search
+    between the neighbours of that point, to a bracket of 1e-12."""
+    s = P.s[P.s > 0]
+    smax2 = float(s[0] ** 2) if s.size else 1.0
+    smin2 = max(float(s[-1] ** 2), 1e-30 * smax2) if s.size else 1.0
+    lo, hi = math.log(smin2) - 10.0, math.log(smax2) + 10.0
+    xs = lo + (hi - lo) * np.arange(GCV_GRID) / (GCV_GRID - 1)
+    vals = [gcv(P, math.exp(x)) for x in xs]
+    i = int(np.argmin(vals))
+    a, b = xs[max(i - 1, 0)], xs[min(i + 1, GCV_GRID - 1)]
+    r = (math.sqrt(5.0) - 1.0) / 2.0
+    c, d = b - r * (b - a), a + r * (b - a)
+    fc, fd = gcv(P, math.exp(c)), gcv(P, math.exp(d))
+    while b - a > 1e-12:
+        if fc <= fd:
+            b, d, fd = d, c, fc
+            c = b - r * (b - a)
+            fc = gcv(P, math.exp(c))
+        else:
+            a, c, fc = c, d, fd
+            d = a + r * (b - a)
+            fd = gcv(P, math.exp(d))
+    return math.exp(0.5 * (a + b))
+
+
+def projected_tikhonov(H, beta, mu=None, delta=None, eta=1.01, rule="discrepancy"):
     """Solve the projected problem; ``mu`` fixed (>= 0) or, when ``mu`` is
-    None, chosen by the discrepancy principle with noise norm ``delta``.
+    None, chosen by the discrepancy principle with noise norm ``delta``
+    (``rule="discrepancy"``) or by minimising GCV (``rule="gcv"``).
 
     Returns dict(y, mu, flags, res_proj, res_ls)."""
     H = np.asarray(H, dtype=np.float64)
     k = H.shape[1]
     P = SVDProblem(H, beta)
     flags = 0
-    if mu is None:
+    if mu is None and rule == "gcv":
+        mu = gcv_mu(P)
+    elif mu is None:
         mu, flags = discrepancy_mu(P, eta * delta)
     if math.isinf(mu):
         y = np.zeros(k)

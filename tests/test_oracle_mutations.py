@@ -109,3 +109,25 @@ def test_reversed_assembly_is_caught(monkeypatch):
         return out
     monkeypatch.setattr(gm, "projected_tikhonov", bad)
     expect_failure(pins.test_matches_dense_direct_solve_on_krylov_space, 5)
+
+
+def test_gcv_trace_over_k_rows_is_caught(monkeypatch):
+    """The trace taken over k instead of k + 1 rows (dropping the identity's
+    extra row) is caught by both GCV pins."""
+    def bad_gcv(P, mu):
+        den = P.k - float(np.sum(P.s ** 2 / (P.s ** 2 + mu)))
+        return P.residual2(mu) / (den * den)
+    monkeypatch.setattr(pm, "gcv", bad_gcv)
+    monkeypatch.setattr(pins, "gcv", bad_gcv)
+    expect_failure(pins.test_gcv_matches_its_definition_with_explicit_matrices)
+    expect_failure(pins.test_gcv_minimiser_closed_form_for_equal_singular_values)
+
+
+def test_gcv_unsquared_denominator_is_caught(monkeypatch):
+    def bad_gcv(P, mu):
+        den = (P.k + 1) - float(np.sum(P.s ** 2 / (P.s ** 2 + mu)))
+        return P.residual2(mu) / den
+    monkeypatch.setattr(pm, "gcv", bad_gcv)
+    monkeypatch.setattr(pins, "gcv", bad_gcv)
+    expect_failure(pins.test_gcv_matches_its_definition_with_explicit_matrices)
+    expect_failure(pins.test_gcv_minimiser_closed_form_for_equal_singular_values)

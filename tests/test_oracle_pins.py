@@ -18,7 +18,7 @@ from oracle.operator import (Operator, phi, phi_einstein, band_to_dense,
 from oracle.sketch import Sketch, identity_sketch
 from oracle.arnoldi import sketched_global_arnoldi, FLAG_BREAKDOWN
 from oracle.projected import (projected_tikhonov, givens_residuals, solve_13,
-                              solve_14, ls_solve, SVDProblem, discrepancy_mu,
+                              solve_14, ls_solve, SVDProblem, discrepancy_mu, gcv, gcv_mu,
                               FLAG_DISCREP_UNREACHABLE, FLAG_MU_INF)
 from oracle.gmres import rtg_gmres
 from oracle.metrics import relative_error, psnr_paper, psnr_peak
@@ -372,6 +372,47 @@ def test_discrepancy_edge_cases():
     np.testing.assert_allclose(out["y"], ls_solve(H, beta), rtol=1e-10)
     out = projected_tikhonov(H, beta, delta=2.0, eta=1.0)
     assert out["flags"] == FLAG_MU_INF and np.all(out["y"] == 0)
+
+
+def test_gcv_matches_its_definition_with_explicit_matrices():
+    """GCV(mu) from the SVD against the printed definition evaluated with
+    dense matrices: y_mu from (14), the influence matrix H (H^T H + mu I)^-1 H^T
+    and the trace of I minus it over the k + 1 rows."""
+    H = random_hessenberg(7, seed=11)
+    beta = 2.5
+    P = SVDProblem(H, beta)
+    k = H.shape[1]
+    g = np.zeros(k + 1)
+    g[0] = beta
+    for mu in (1e-6, 1e-3, 0.1, 1.0, 30.0):
+        y = solve_14(H, beta, mu)
+        num = float(np.sum((H @ y - g) ** 2))
+        A = H @ np.linalg.solve(H.T @ H + mu * np.eye(k), H.T)
+        den = float(np.trace(np.eye(k + 1) - A))
+        np.testing.assert_allclose(gcv(P, mu), num / den ** 2, rtol=1e-9)
+
+
+def test_gcv_minimiser_closed_form_for_equal_singular_values():
+    """H = sigma Q[:, :k] (Q orthogonal): all singular values equal sigma, and
+    with t = mu / (sigma^2 + mu), a = ||U^T beta e1||^2, b = beta^2 - a,
+    GCV = (t^2 a + b) / (1 + k t)^2 is minimised at t = k b / a, i.e.
+    mu = sigma^2 t / (1 - t)."""
+    k, sigma, beta = 5, 1.7, 1.3
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        Q, _r = np.linalg.qr(rng.standard_normal((k + 1, k + 1)))
+        b = beta ** 2 * Q[0, k] ** 2
+        a = beta ** 2 - b
+        if 0 < k * b < 0.5 * a:
+            break
+    H = sigma * Q[:, :k]
+    t = k * b / a
+    mu_exact = sigma ** 2 * t / (1.0 - t)
+    mu = gcv_mu(SVDProblem(H, beta))
+    np.testing.assert_allclose(mu, mu_exact, rtol=1e-6)
+    out = projected_tikhonov(H, beta, rule="gcv")
+    np.testing.assert_allclose(out["mu"], mu_exact, rtol=1e-6)
+    np.testing.assert_allclose(out["y"], solve_14(H, beta, out["mu"]), rtol=1e-9)
 
 
 # --------------------------------------------------------------------------
