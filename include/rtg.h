@@ -79,7 +79,13 @@ typedef struct {
     double stop_res;  /* > 0: stop at the first j whose projected LS residual is
                          <= stop_res; <= 0: run m steps                          */
     double bd_tol;    /* breakdown threshold relative to ||S(Phi(V_j))||          */
+    int mu_rule;      /* when mu < 0: RTG_MU_DISCREPANCY (root of the projected
+                         residual at eta*delta) or RTG_MU_GCV (minimiser of the
+                         GCV function of the projected problem, Sec. 3; delta
+                         and eta unused)                                        */
 } rtg_params;
+
+enum { RTG_MU_DISCREPANCY = 0, RTG_MU_GCV = 1 };
 
 /* Result summary, written by the device at the end of a solve. */
 typedef struct {

@@ -11,8 +11,13 @@
 // is the projected residual; it increases from gamma^2 to beta^2 and the
 // discrepancy principle takes the root of phi(mu) = (eta delta)^2, found by
 // multisection (64 points per pass) in log(mu).  Then y = W diag(s / (s^2 + mu)) ghat, the filter
-// form of the stacked least-squares problem (13).  The kernel writes the
-// coefficients -y_j of the solution update and the result summary.
+// form of the stacked least-squares problem (13).  With the GCV rule (Sec. 3,
+// parameter selection via GCV) mu minimises
+//   GCV(mu) = phi(mu) / (1 + sum_i mu / (s_i^2 + mu))^2
+// (the trace of I - H (H^T H + mu I)^{-1} H^T over the k + 1 rows): the best
+// of 512 points spread over [log s_min^2 - 10, log s_max^2 + 10], then passes
+// of 64 points between the neighbours of the best point so far.  The kernel
+// writes the coefficients -y_j of the solution update and the result summary.
 #include "rtg_internal.h"
 
 namespace rtg {
@@ -152,7 +157,75 @@ __global__ void __launch_bounds__(1024) k_solve(const Desc* __restrict__ descs) 
         const double gp2 = gam * gam;
         double mu = d.mu;
         int flags = 0;
-        if (!d.mu_fixed) {
+        if (!d.mu_fixed && d.mu_rule == RTG_MU_GCV) {
+            // GCV at log(mu) = x, and the (value, position) minimum over the wave
+            auto gcv_at = [&](double x) {
+                const double mu_l = exp(x);
+                double ph = gp2, tr = 1.0;
+                for (int i = 0; i < k; ++i) {
+                    const double s2 = sig[i] * sig[i];
+                    const double f = mu_l / (s2 + mu_l);
+                    ph += f * f * gh[i] * gh[i];
+                    tr += s2 > 0.0 ? f : 1.0;
+                }
+                return ph / (tr * tr);
+            };
+            auto wave_argmin = [&](double v, int idx, double& vmin, int& imin) {
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) {
+                    const double ov = __shfl_xor(v, off, 64);
+                    const int oi = __shfl_xor(idx, off, 64);
+                    if (ov < v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+                }
+                vmin = v;
+                imin = idx;
+            };
+            double smax = 0.0, smin = INFINITY;
+            for (int i = lane; i < k; i += 64) {
+                smax = fmax(smax, sig[i]);
+                if (sig[i] > 0.0) smin = fmin(smin, sig[i]);
+            }
+            smax = wave_max(smax);
+            smin = -wave_max(-smin);
+            const double smax2 = smax > 0.0 ? smax * smax : 1.0;
+            const double smin2 = isfinite(smin) ? fmax(smin * smin, 1e-30 * smax2) : smax2;
+            const double glo = log(smin2) - 10.0, ghi = log(smax2) + 10.0;
+            // 512 grid points, eight per lane (the same grid as the oracle's)
+            double bv = INFINITY;
+            int bi = 0;
+            for (int q = 0; q < 8; ++q) {
+                const int pidx = 8 * lane + q;
+                const double v = gcv_at(glo + (ghi - glo) * (double)pidx / 511.0);
+                if (v < bv) { bv = v; bi = pidx; }
+            }
+            double vmin;
+            int imin;
+            wave_argmin(bv, bi, vmin, imin);
+            double lo = glo + (ghi - glo) * (double)max(imin - 1, 0) / 511.0;
+            double hi = glo + (ghi - glo) * (double)min(imin + 1, 511) / 511.0;
+            double xbest = glo + (ghi - glo) * (double)imin / 511.0;
+            for (int it = 0; it < 16; ++it) {
+                const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
+                double v = gcv_at(x);
+                if (!(v < vmin)) v = INFINITY;            // keep the best point so far when nothing beats it
+                int li;
+                double lv;
+                wave_argmin(v, lane, lv, li);
+                if (!(lv < INFINITY)) {                  // the best point is inside a bracket no lane improves:
+                    const double w = (hi - lo) / 65.0;   // shrink around it
+                    lo = fmax(lo, xbest - w);
+                    hi = fmin(hi, xbest + w);
+                } else {
+                    vmin = lv;
+                    xbest = lo + (hi - lo) * (double)(li + 1) / 65.0;
+                    const double w = (hi - lo) / 65.0;
+                    lo = xbest - w;
+                    hi = xbest + w;
+                }
+                if (!(hi - lo > 1e-12)) break;
+            }
+            mu = exp(xbest);
+        } else if (!d.mu_fixed) {
             const double t = d.eta * d.delta;
             const double t2 = t * t;
             if (t2 <= gp2) {

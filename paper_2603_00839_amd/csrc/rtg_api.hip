@@ -357,13 +357,16 @@ int run_solver(const Plan& plan, int count, int mmax, int bf16, bool any_x0, boo
 int validate_params(const rtg_params* prm) {
     if (!prm) return RTG_E_ARG;
     if (prm->basis_dtype != RTG_F32 && prm->basis_dtype != RTG_BF16) return RTG_E_ARG;
-    if (prm->mu < 0.0 && !(prm->delta >= 0.0 && prm->eta > 0.0)) return RTG_E_ARG;
+    if (prm->mu_rule != RTG_MU_DISCREPANCY && prm->mu_rule != RTG_MU_GCV) return RTG_E_ARG;
+    if (prm->mu < 0.0 && prm->mu_rule == RTG_MU_DISCREPANCY && !(prm->delta >= 0.0 && prm->eta > 0.0))
+        return RTG_E_ARG;
     if (!(prm->bd_tol >= 0.0)) return RTG_E_ARG;
     return RTG_OK;
 }
 
 void set_params(Desc& d, const rtg_params* prm) {
     d.mu_fixed = prm->mu >= 0.0 ? 1 : 0;
+    d.mu_rule = prm->mu_rule;
     d.mu = prm->mu >= 0.0 ? prm->mu : 0.0;
     d.delta = prm->delta;
     d.eta = prm->eta;

@@ -47,7 +47,8 @@ struct Desc {
     int has_om3;        // Om3 given (else identity, l3 == J)
     int n_i2t;          // ceil(I2 / TILE_TC)
     int ntile[NKIND];   // tiles of this problem per kernel kind
-    int mu_fixed;       // 1: mu given, 0: discrepancy principle
+    int mu_fixed;       // 1: mu given, 0: chosen by mu_rule
+    int mu_rule;        // RTG_MU_DISCREPANCY or RTG_MU_GCV
     int keep_last;      // form V_{m+1} after the last step (Arnoldi-only calls)
     int toeplitz;       // A1 and A2 are Toeplitz on their in-range entries (convolutions, zero BC)
     int unsketched;     // identity sketch: Frobenius inner products of the full tensors

@@ -33,7 +33,7 @@ class RTGError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int), ("basis_dtype", ctypes.c_int), ("mu", ctypes.c_double),
                 ("delta", ctypes.c_double), ("eta", ctypes.c_double), ("stop_res", ctypes.c_double),
-                ("bd_tol", ctypes.c_double)]
+                ("bd_tol", ctypes.c_double), ("mu_rule", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -300,8 +300,13 @@ def arnoldi(op: Operator, sk: Sketch, R0, m: int, basis_dtype: int = F32, bd_tol
     return {"H": H.t(), "beta": beta, "m_done": m_done, "V": V, "SV": SV, "ws": ws}
 
 
-def make_params(m, basis_dtype=F32, mu=-1.0, delta=0.0, eta=1.01, stop_res=0.0, bd_tol=1e-6) -> Params:
-    return Params(int(m), int(basis_dtype), float(mu), float(delta), float(eta), float(stop_res), float(bd_tol))
+MU_DISCREPANCY, MU_GCV = 0, 1
+
+
+def make_params(m, basis_dtype=F32, mu=-1.0, delta=0.0, eta=1.01, stop_res=0.0, bd_tol=1e-6,
+                mu_rule=MU_DISCREPANCY) -> Params:
+    return Params(int(m), int(basis_dtype), float(mu), float(delta), float(eta), float(stop_res), float(bd_tol),
+                  int(mu_rule))
 
 
 def read_info(info_buf) -> Info:
