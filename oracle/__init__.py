@@ -21,10 +21,12 @@ projected       Givens least squares, projected Tikhonov (eqs. (12)-(14)),
                 discrepancy-principle choice of mu.
 gmres           RTG-GMRES driver (algorithm "Block GMRES via Sketched Einstein
                 Product", Sec. 4.4).
+golub_kahan     sketched Block Golub-Kahan bidiagonalisation and its
+                regularised solve (Sec. 4.5).
 metrics         RE and PSNR (Sec. 5.5).
 cnn             float64 reference of the warm-start convolutional network.
 """
-from . import tensor_algebra, operator, sketch, arnoldi, projected, gmres, metrics  # noqa: F401
+from . import tensor_algebra, operator, sketch, arnoldi, projected, gmres, golub_kahan, metrics  # noqa: F401
 
 FLAG_BREAKDOWN = 1
 FLAG_DISCREP_UNREACHABLE = 2

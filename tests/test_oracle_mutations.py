@@ -131,3 +131,73 @@ def test_gcv_unsquared_denominator_is_caught(monkeypatch):
     monkeypatch.setattr(pins, "gcv", bad_gcv)
     expect_failure(pins.test_gcv_matches_its_definition_with_explicit_matrices)
     expect_failure(pins.test_gcv_minimiser_closed_form_for_equal_singular_values)
+
+
+# --------------------------------------------------------------------------
+# sketched Block Golub-Kahan (Sec. 4.5)
+# --------------------------------------------------------------------------
+import oracle.golub_kahan as gkm
+import test_oracle_gk as gkpins
+
+
+def _mutated_golub_kahan(kind):
+    def gk(phi, phi_t, sketch, R0, m, bd_tol=1e-12, stop_res=None, full_last=False):
+        def tnorm(X):
+            s = X if kind == "frobenius" else sketch(X)
+            return math.sqrt(frobenius(s, s))
+        adj = phi if kind == "forward" else phi_t
+        R0 = np.asarray(R0, dtype=np.float64)
+        beta1 = tnorm(R0)
+        U = [R0 / beta1]
+        Wt = adj(U[0])
+        alpha = tnorm(Wt)
+        V = [Wt / alpha]
+        B = np.zeros((m + 1, m))
+        for k in range(m):
+            B[k, k] = alpha
+            uk = U[max(k - 1, 0)] if kind == "index" else U[k]
+            W = phi(V[k]) - (0.0 if kind == "drop_alpha" else alpha) * uk
+            beta = tnorm(W)
+            B[k + 1, k] = beta
+            U.append(W / beta)
+            if k + 1 == m and not full_last:
+                break
+            Z = adj(U[k + 1]) - (0.0 if kind == "drop_beta" else beta) * V[k]
+            alpha = tnorm(Z)
+            V.append(Z / alpha)
+        return gkm.BidiagResult(U, V, B, beta1, m, 0, np.zeros(m))
+    return gk
+
+
+@pytest.mark.parametrize("kind", ["drop_alpha", "drop_beta", "index", "frobenius", "forward"])
+def test_golub_kahan_mistakes_are_caught(monkeypatch, kind):
+    """Each planted mistake in the bidiagonalisation fails at least one pin."""
+    bad = _mutated_golub_kahan(kind)
+    monkeypatch.setattr(gkm, "sketched_golub_kahan", bad)
+    monkeypatch.setattr(gkpins, "sketched_golub_kahan", bad)
+    failed = 0
+    for fn, args in [(gkpins.test_bases_span_the_normal_equation_krylov_spaces, (0,)),
+                     (gkpins.test_bidiagonal_relations_and_unit_sketched_norms, ()),
+                     (gkpins.test_identity_sketch_is_lsqr, ()),
+                     (gkpins.test_identity_sketch_lanczos_tridiagonal, ())]:
+        try:
+            fn(*args)
+        except Exception:
+            failed += 1
+    assert failed >= 1
+
+
+def test_golub_kahan_pins_pass_unmutated():
+    gkpins.test_bases_span_the_normal_equation_krylov_spaces(0)
+    gkpins.test_bidiagonal_relations_and_unit_sketched_norms()
+    gkpins.test_identity_sketch_is_lsqr()
+    gkpins.test_identity_sketch_lanczos_tridiagonal()
+
+
+def test_untransposed_channel_mix_in_the_adjoint_is_caught(monkeypatch):
+    def bad_t(self, X):
+        return mode_product(mode_product(mode_product(np.asarray(X, np.float64), self.A1.T, 0), self.A2.T, 1),
+                            self.B.T, 2)
+    monkeypatch.setattr(opm.Operator, "transpose_apply", bad_t)
+    expect_failure(gkpins.test_transpose_apply_is_the_frobenius_adjoint)
+    expect_failure(gkpins.test_bases_span_the_normal_equation_krylov_spaces, 0)
