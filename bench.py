@@ -12,7 +12,11 @@ Variants (each timed over the same number of steps):
   bf16_warm      bfloat16 basis and MFMA, started from a warm start X0;
                  --x0 learned uses the trained warm-start network (if its
                  weights exist), --x0 observation uses X0 = C.
-The JSON line reports the headline variant in "value" and both variants
+  fp32_unsketched  fp32_plain with the identity sketch (Frobenius inner
+                 products: the unsketched global GMRES)
+  fp32_gk        sketched Block Golub-Kahan (Sec. 4.5), float32 basis,
+                 X0 = 0, m = 50 columns
+The JSON line reports the headline variant in "value" and every variant
 under "variants", with restoration errors against the ground truth.
 
 Live measurement: the dominant byte mover of the headline variant (the
@@ -59,7 +63,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a device-to-device copy of MB megabytes (counter calibration)")
-    ap.add_argument("--only", choices=["fp32_plain", "bf16_warm", "fp32_unsketched"], default=None,
+    ap.add_argument("--only", choices=["fp32_plain", "bf16_warm", "fp32_unsketched", "fp32_gk"], default=None,
                     help="time one variant only (profiling runs)")
     return ap.parse_args()
 
@@ -116,6 +120,21 @@ def tile_bytes(n, es, m_eff, has_x0):
         b += (j + 1) * es * n
     b += (4 * n if has_x0 else 0) + m_eff * es * n + 4 * n
     return b
+
+
+def gk_tile_bytes(n, es, m_eff):
+    """Algorithmic bytes of the tile launches of one sketched Golub-Kahan
+    solve: sketch of R0 and U_1 = R0/beta_1 (read R0 twice, write U_1);
+    column c forms V_c (reads V_{c-1} from c = 2, writes V_c) and, before the
+    last column, U_{c+1} (reads U_c, writes U_{c+1}); the assembly reads
+    V_1..V_m and writes X.  The read of W is not counted (the method does not
+    need W in memory)."""
+    b = 2 * 4 * n + es * n
+    for c in range(1, m_eff + 1):
+        b += (es * n if c >= 2 else 0) + es * n
+        if c < m_eff:
+            b += 2 * es * n
+    return b + m_eff * es * n + 4 * n
 
 
 def time_variant(plan, steps, warmup, rtg, torch, kind, bytes_of, pre=None):
@@ -250,9 +269,17 @@ def main():
     torch.cuda.synchronize()
 
     results = {}
-    variants = [args.only] if args.only else ["fp32_plain", "bf16_warm", "fp32_unsketched"]
+    variants = [args.only] if args.only else ["fp32_plain", "bf16_warm", "fp32_unsketched", "fp32_gk"]
     for v in variants:
-        if v == "fp32_unsketched":
+        if v == "fp32_gk":
+            prm = [rtg.make_params(args.m, rtg.F32, delta=q["delta"], eta=1.01, method=rtg.METHOD_GOLUB_KAHAN)
+                   for q in probs]
+            plan = rtg.BatchPlan([op] * B, [q["sk"] for q in probs], [q["C"] for q in probs], [None] * B, prm)
+            r = time_variant(plan, args.steps, args.warmup, rtg, torch, rtg.KIND_TILE,
+                             lambda inf: gk_tile_bytes(n, 4, inf.iters))
+            r["kernel"] = ("k_tile", "k_tile.hip", "one-term AXPY + store + MFMA mode-1/2 sketch "
+                                                   "(Golub-Kahan, float32 basis)")
+        elif v == "fp32_unsketched":
             # the same solve with the identity sketch: Frobenius inner products of
             # the full tensors (the unsketched global GMRES the method improves on)
             sk_id = rtg.setup_sketch(I1, I2, J)

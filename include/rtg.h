@@ -83,13 +83,20 @@ typedef struct {
                          residual at eta*delta) or RTG_MU_GCV (minimiser of the
                          GCV function of the projected problem, Sec. 3; delta
                          and eta unused)                                        */
+    int method;       /* RTG_METHOD_GMRES: RTG-GMRES (Sec. 4.4);
+                         RTG_METHOD_GOLUB_KAHAN: sketched Block Golub-Kahan
+                         (Sec. 4.5), m columns of the lower bidiagonal matrix
+                         in place of the Hessenberg matrix, the same projected
+                         Tikhonov problem and mu rules                        */
 } rtg_params;
 
 enum { RTG_MU_DISCREPANCY = 0, RTG_MU_GCV = 1 };
+enum { RTG_METHOD_GMRES = 0, RTG_METHOD_GOLUB_KAHAN = 1 };
 
 /* Result summary, written by the device at the end of a solve. */
 typedef struct {
-    int iters;        /* number of Arnoldi steps taken (m_eff)                    */
+    int iters;        /* number of Arnoldi steps (Golub-Kahan: bidiagonal
+                         columns) taken (m_eff)                                   */
     int flags;        /* RTG_F_* bits                                            */
     double mu;        /* Tikhonov parameter used (inf if RTG_F_MU_INF)            */
     double beta;      /* ||R0||_Theta                                            */
@@ -159,13 +166,45 @@ int rtg_arnoldi(rtg_op op, rtg_sk sk, const float* R0, int m, int basis_dtype,
 int rtg_workspace_layout(rtg_op op, rtg_sk sk, int m, int basis_dtype,
                          size_t* v_offset, size_t* sv_offset);
 
-/* Full RTG-GMRES solve of one problem; info is a device pointer. */
+/* Workspace of one sketched Block Golub-Kahan solve (params.method =
+ * RTG_METHOD_GOLUB_KAHAN) with at most m columns: a second basis
+ * U_1..U_{m+1} with its sketches and the composed sketch matrices of the
+ * adjoint operator on top of rtg_workspace_bytes. */
+size_t rtg_gk_workspace_bytes(rtg_op op, rtg_sk sk, int m, int basis_dtype);
+
+/* m columns of the sketched Block Golub-Kahan bidiagonalisation from R0
+ * (Sec. 4.5, recurrences as for rtg_solve below).  Outputs (device): B,
+ * (m+1) x m column-major float64 lower bidiagonal (alpha_k on the diagonal,
+ * beta_{k+1} below it; zero past the computed part); *beta = beta_1;
+ * *m_done (< m after a breakdown: beta_{k+1} <= bd_tol ||S(Phi(V_k))|| or
+ * alpha_{k+1} <= bd_tol ||S(Phi^T(U_{k+1}))||).  The bases U_1..U_{m+1} and
+ * V_1..V_m stay in ws (rtg_gk_workspace_layout); ws_bytes >=
+ * rtg_gk_workspace_bytes.  Needs a sketch with at least one Om_k given. */
+int rtg_golub_kahan(rtg_op op, rtg_sk sk, const float* R0, int m, int basis_dtype,
+                    double bd_tol, void* ws, size_t ws_bytes,
+                    double* B, double* beta, int* m_done, void* stream);
+
+/* Offsets (bytes from ws) of V_1..V_{m+1} and U_1..U_{m+1} (consecutive
+ * tensors of basis_dtype) in the workspace of rtg_golub_kahan. */
+int rtg_gk_workspace_layout(rtg_op op, rtg_sk sk, int m, int basis_dtype,
+                            size_t* v_offset, size_t* u_offset);
+
+/* Full solve of one problem, RTG-GMRES or (params->method) sketched Block
+ * Golub-Kahan; info is a device pointer.
+ * Golub-Kahan (Sec. 4.5): beta_1 = ||R0||_Theta, U_1 = R0/beta_1,
+ * alpha_1 V_1 = Phi^T(U_1), then beta_{k+1} U_{k+1} = Phi(V_k) - alpha_k U_k
+ * and alpha_{k+1} V_{k+1} = Phi^T(U_{k+1}) - beta_{k+1} V_k with Theta-norms
+ * (Phi^T the Frobenius adjoint, X x_1 A1^T x_2 A2^T x_3 B); X = X0 + sum
+ * y_k V_k with y from min ||beta_1 e1 - B y||^2 + mu ||y||^2.  It needs a
+ * sketch with at least one Om_k given (RTG_E_ARG for the all-identity
+ * sketch) and a workspace of rtg_gk_workspace_bytes. */
 int rtg_solve(rtg_op op, rtg_sk sk, const float* C, const float* X0,
               const rtg_params* params, void* ws, size_t ws_bytes,
               float* X, rtg_info* info, void* stream);
 
 /* Many independent problems (uneven sizes allowed) solved together: every
- * stage is one launch over the tiles of all problems.  probs is a HOST array. */
+ * stage is one launch over the tiles of all problems.  probs is a HOST array.
+ * One basis type and one method per batch (RTG_E_ARG otherwise). */
 size_t rtg_batch_workspace_bytes(int count, const rtg_problem* probs);
 int rtg_solve_batched(int count, const rtg_problem* probs, void* ws,
                       size_t ws_bytes, void* stream);

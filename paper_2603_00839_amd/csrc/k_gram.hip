@@ -21,6 +21,17 @@
 //     for the next multi-AXPY (k_tile).
 // In the start mode it returns beta = ||S(R0)||; in the sketch-output mode it
 // writes the finished sketch in the column-major order of the C ABI.
+//
+// Golub-Kahan mode (Sec. 4.5): the newest tensor X_c of one side (V_c, or
+// U_c on the side of Phi^T) was sketched with Omega and with the composed
+// matrices of its side's operator, so s = S(Op(X_c)) is finished here as in
+// a step, and the next coefficient of the bidiagonal matrix is
+//   ||s - cf S(Y)||,  Y the other side's newest tensor, cf its coefficient
+// (alpha_c = ||S(Phi^T(U_c)) - beta_c S(V_{c-1})|| on the U side,
+//  beta_{c+1} = ||S(Phi(V_c)) - alpha_c S(U_c)|| on the V side),
+// summed element by element in float64.  The V side completes column c of
+// the bidiagonal matrix and takes the same Givens update and stopping
+// decisions as a GMRES step.
 #include "rtg_internal.h"
 
 namespace rtg {
@@ -178,7 +189,7 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
     const Desc& d = descs[p];
     const int wgi = b - starts[p];
     const int nwg = d.ntile[KIND_GRAM];
-    if (mode == GM_STEP && d.state[ST_ACTIVE] == 0) return;
+    if ((mode == GM_STEP || mode == GM_GK) && d.state[ST_ACTIVE] == 0) return;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nitems = (mode == GM_STEP) ? j + 1 : 1;
@@ -247,7 +258,8 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
     // composed first two matrices, so mode 3 is Om3 B^T
     // (Om3 B^T is banded when Om3 is the identity)
     const float* om3 = d.has_om3 ? d.om3 : nullptr;
-    if (mode == GM_STEP) finish_sketches<2>(d, q0, qn, d.PW, d.om3t, d.has_om3 ? -1 : d.rB, s_s, d.PV, om3, -1, s_v);
+    if (mode == GM_STEP || mode == GM_GK)
+        finish_sketches<2>(d, q0, qn, d.PW, d.om3t, d.has_om3 ? -1 : d.rB, s_s, d.PV, om3, -1, s_v);
     else finish_sketches<1>(d, q0, qn, d.PW, om3, -1, s_s, nullptr, nullptr, -1, nullptr);
     __syncthreads();
 
@@ -261,9 +273,39 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
         return;
     }
     const size_t Lsz = (size_t)d.L;
-    if (mode == GM_STEP) {
+    if (mode == GM_STEP || mode == GM_GK) {
         float* svj = d.SV + (size_t)(j - 1) * Lsz + (size_t)q0 * l3;
         for (int e = tid; e < E; e += 256) svj[e] = s_v[e];
+    }
+    if (mode == GM_GK) {
+        // shares of ||s - cf S(Y)||^2 and ||s||^2; Y is the other side's
+        // newest stored tensor (V_{c-1} for the U side, none at c = 1; U_c for
+        // the V side) and cf its entry of the bidiagonal matrix (beta_c,
+        // alpha_c), both written by earlier launches
+        const int c = j, mm = d.m;
+        const int prow = (d.gk == 1) ? c - 1 : c - 2;
+        const double cf = prow < 0 ? 0.0
+                                   : ((d.gk == 1) ? d.H[(size_t)(c - 1) * (mm + 1) + (c - 1)]
+                                                  : d.H[(size_t)(c - 2) * (mm + 1) + (c - 1)]);
+        const float* pv = d.SVx + (size_t)max(prow, 0) * Lsz + (size_t)q0 * l3;
+        double a0 = 0.0, a1 = 0.0;
+        for (int e = tid; e < E; e += 256) {
+            const double se = s_s[e];
+            const double t = se - (prow >= 0 ? cf * (double)pv[e] : 0.0);
+            a0 += t * t;
+            a1 += se * se;
+        }
+        a0 = wave_sum(a0);
+        a1 = wave_sum(a1);
+        if (lane == 0) {
+            ds[2 * wave] = a0;
+            ds[2 * wave + 1] = a1;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            wds[0] = (ds[0] + ds[2]) + (ds[4] + ds[6]);
+            wds[1] = (ds[1] + ds[3]) + (ds[5] + ds[7]);
+        }
     }
 
     // ---- shares of the inner products (float64): <S(V_i), s> and
@@ -273,6 +315,7 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
     // of each per lane, all loads in flight together (clamped indices,
     // masked: branch-free).
     const int nglob = (mode == GM_STEP) ? j - 1 : 0;
+    if (mode != GM_GK) {
     constexpr int IG = 4, EU = 12;
     for (int it0 = wave; it0 < nglob; it0 += 4 * IG) {
         const float* svb = d.SV + (size_t)q0 * l3;
@@ -329,6 +372,7 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
             }
         }
     }
+    }   // GMRES shares
 
     }   // sketched shares
 
@@ -422,6 +466,79 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
                 d.coef[MMAX + 1] = 0.f;
             } else {
                 d.coef[MMAX + 1] = (float)(1.0 / beta);
+            }
+        }
+        return;
+    }
+    if (mode == GM_GK) {
+        if (tid == 0) {
+            st[ST_COUNTER] = 0;
+            const int c = j;
+            const double nrm2 = ds[0];
+            const double nrm = sqrt(nrm2 > 0.0 ? nrm2 : 0.0), rho = sqrt(ds[1]);
+            const bool finite = isfinite(nrm) && isfinite(rho);
+            double* Hc = d.H + (size_t)(c - 1) * (m + 1);
+            if (d.gk == 2) {
+                // alpha_c, the diagonal entry of column c; V_c = (Phi^T(U_c) - beta_c V_{c-1}) / alpha_c
+                Hc[c - 1] = nrm;
+                if (c >= 2) d.coef[c - 2] = (float)d.H[(size_t)(c - 2) * (m + 1) + (c - 1)];
+                d.coef[MMAX + 1] = nrm > 0.0 ? (float)(1.0 / nrm) : 0.f;
+                if (!finite) {
+                    st[ST_FLAGS] |= RTG_F_NONFINITE;
+                    st[ST_MEFF] = c - 1;
+                    st[ST_ACTIVE] = 0;
+                } else if (nrm <= d.bd_tol * rho) {
+                    st[ST_FLAGS] |= RTG_F_BREAKDOWN;
+                    st[ST_MEFF] = c - 1;
+                    st[ST_ACTIVE] = 0;
+                }
+            } else {
+                // beta_{c+1} completes column c = (alpha_c, beta_{c+1}) in rows c-1, c;
+                // U_{c+1} = (Phi(V_c) - alpha_c U_c) / beta_{c+1}
+                const double alpha = Hc[c - 1];
+                Hc[c] = nrm;
+                // Givens update: of the earlier rotations only the last one
+                // meets a nonzero entry of this column
+                double* cs = d.gv;
+                double* sn = d.gv + m;
+                double* Rc = d.R + (size_t)(c - 1) * m;
+                for (int i = 0; i + 2 < c; ++i) Rc[i] = 0.0;
+                double r_prev = alpha;
+                if (c >= 2) {
+                    Rc[c - 2] = sn[c - 2] * alpha;
+                    r_prev = cs[c - 2] * alpha;
+                }
+                const double rr = hypot(r_prev, nrm);
+                const double cj = rr > 0.0 ? r_prev / rr : 1.0;
+                const double sj = rr > 0.0 ? nrm / rr : 0.0;
+                cs[c - 1] = cj;
+                sn[c - 1] = sj;
+                Rc[c - 1] = rr;
+                const double gj = gvec[c - 1];
+                gvec[c - 1] = cj * gj;
+                gvec[c] = -sj * gj;
+                const double res_ls = fabs(gvec[c]);
+                sc[SC_RESLS] = res_ls;
+                d.coef[c - 1] = (float)alpha;
+                d.coef[MMAX + 1] = nrm > 0.0 ? (float)(1.0 / nrm) : 0.f;
+                if (!finite) {
+                    st[ST_FLAGS] |= RTG_F_NONFINITE;
+                    st[ST_MEFF] = c - 1;
+                    st[ST_ACTIVE] = 0;
+                } else if (nrm <= d.bd_tol * rho) {
+                    st[ST_FLAGS] |= RTG_F_BREAKDOWN;
+                    st[ST_MEFF] = c;
+                    st[ST_ACTIVE] = 0;
+                } else if (d.stop_res > 0.0 && res_ls <= d.stop_res) {
+                    st[ST_MEFF] = c;
+                    st[ST_ACTIVE] = 0;
+                } else if (c >= m && !d.keep_last) {
+                    st[ST_MEFF] = c;
+                    st[ST_ACTIVE] = 0;
+                    if (d.stop_res > 0.0) st[ST_FLAGS] |= RTG_F_NOT_CONVERGED;
+                } else {
+                    st[ST_MEFF] = c;
+                }
             }
         }
         return;

@@ -6,8 +6,12 @@
 //   out = scale * (src - sum_{i<nterms} coef_i V_i)            (multi-AXPY)
 //
 // which is the orthogonalisation and normalisation of the Arnoldi step
-// (Sec. 4.3: W <- W - h_ij V_i, V_{j+1} = W / h_{j+1,j}) or the solution
-// update X = X0 + sum_j y_j V_j (Sec. 4.4), stores it, and/or sketches it:
+// (Sec. 4.3: W <- W - h_ij V_i, V_{j+1} = W / h_{j+1,j}), a Golub-Kahan
+// half-step (Sec. 4.5: one term, U_{k+1} = (Phi(V_k) - alpha_k U_k) / beta_{k+1}
+// or V_{k+1} = (Phi^T(U_{k+1}) - beta_{k+1} V_k) / alpha_{k+1}, where the
+// composed matrices belong to the operator of the side written) or the
+// solution update X = X0 + sum_j y_j V_j (Sec. 4.4), stores it, and/or
+// sketches it:
 //
 //   P[a, b] = sum_{i2 in tile} Om2[b, i2] sum_{i1} Om1[a, i1] out[i1, i2]
 //
@@ -66,7 +70,7 @@ struct TileSmem {
 template <bool BB, bool SPLIT, int RPW>
 __global__ void __launch_bounds__(256) k_tile(const Desc* __restrict__ descs,
                                               const int* __restrict__ starts, int count,
-                                              int mode, int nterms_arg, int dst_index) {
+                                              int mode, int nterms_arg, int dst_index, int t0) {
     using SM = TileSmem<BB, SPLIT, RPW>;
     constexpr int TC = TILE_TC;
     constexpr int SBR = TILE_SBR;
@@ -86,7 +90,8 @@ __global__ void __launch_bounds__(256) k_tile(const Desc* __restrict__ descs,
     const int p = find_problem(starts, count, b);
     const Desc& d = descs[p];
     const int tile = b - starts[p];
-    if (mode == TM_NEWV && d.state[ST_ACTIVE] == 0) return;
+    const bool newv = (mode == TM_NEWV || mode == TM_GKNEW);
+    if (newv && d.state[ST_ACTIVE] == 0) return;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -103,16 +108,18 @@ __global__ void __launch_bounds__(256) k_tile(const Desc* __restrict__ descs,
     const size_t es = BB ? 2 : 4;
 
     int nterms = 0;
-    if (mode == TM_NEWV) nterms = nterms_arg;
+    if (newv) nterms = nterms_arg;
     else if (mode == TM_ASSEMBLE) nterms = d.state[ST_MEFF];
-    const bool do_store = (mode == TM_NEWV || mode == TM_ASSEMBLE);
+    const int first = (mode == TM_GKNEW) ? t0 : 0;   // terms [first, nterms)
+    const bool do_store = (newv || mode == TM_ASSEMBLE);
     const bool do_sketch = (mode != TM_ASSEMBLE) && !d.unsketched;   // an identity sketch keeps no partials
-    const bool dual = (mode == TM_NEWV);
+    const bool dual = newv;
     const bool src_is_bf = BB && !SPLIT && (mode == TM_SKETCH_SRC);
 
     const void* src;
     if (mode == TM_SKETCH_SRC) src = d.R0src;
     else if (mode == TM_NEWV) src = (nterms == 0) ? d.R0src : (const void*)d.W;
+    else if (mode == TM_GKNEW) src = d.W;
     else src = d.X0;     // may be null: zero
 
     for (int i = tid; i < nterms; i += 256) coef_s[i] = d.coef[i];
@@ -191,16 +198,16 @@ __global__ void __launch_bounds__(256) k_tile(const Desc* __restrict__ descs,
         // (bfloat16 basis: 4 chunks) or half a term (float32: 4 of 8 chunks).
         constexpr int SPT = BB ? 1 : 2;          // stages per term
         constexpr int CPS = NCK / SPT;           // chunks per stage
-        const int nst = nterms * SPT;
+        const int nst = (nterms - first) * SPT;
         auto load_stage = [&](int st, u4* v) {
-            const int i = st / SPT, c0 = (st % SPT) * CPS;
+            const int i = first + st / SPT, c0 = (st % SPT) * CPS;
             const auto rv = make_rsrc((const char*)d.V + ((size_t)i * d.n + tile_off) * es, tile_elems * (int)es);
 #pragma unroll
             for (int u = 0; u < CPS; ++u)
                 v[u] = __builtin_amdgcn_raw_buffer_load_b128(rv, offs[c0 + u] * (unsigned)es, 0, 0);
         };
         auto apply_stage = [&](int st, const u4* v) {
-            const float ci = coef_s[st / SPT];
+            const float ci = coef_s[first + st / SPT];
             const int c0 = (st % SPT) * CPS;
 #pragma unroll
             for (int uu = 0; uu < CPS; ++uu)
@@ -231,7 +238,7 @@ __global__ void __launch_bounds__(256) k_tile(const Desc* __restrict__ descs,
         for (int u = 0; u < NCK; ++u)
 #pragma unroll
             for (int q = 0; q < CK; ++q) x[u][q] *= scale;
-        if (mode == TM_NEWV && BB) {
+        if (newv && BB) {
             const auto rd = make_rsrc((const char*)d.V + ((size_t)dst_index * d.n + tile_off) * 2, tile_elems * 2);
 #pragma unroll
             for (int u = 0; u < NCK; ++u) {
@@ -242,7 +249,7 @@ __global__ void __launch_bounds__(256) k_tile(const Desc* __restrict__ descs,
                 __builtin_amdgcn_raw_buffer_store_b128(pk, rd, offs[u] * 2u, 0, 0);
             }
         } else if (do_store) {
-            const char* db = (mode == TM_NEWV) ? (const char*)d.V + ((size_t)dst_index * d.n + tile_off) * 4
+            const char* db = newv ? (const char*)d.V + ((size_t)dst_index * d.n + tile_off) * 4
                                                : (const char*)d.X + tile_off * 4;
             const auto rd = make_rsrc(db, tile_elems * 4);
 #pragma unroll
@@ -366,17 +373,18 @@ __global__ void __launch_bounds__(256) k_tile(const Desc* __restrict__ descs,
     __syncthreads();
 
     // ---- mode-2 contraction: P[a][b] = sum_k Ys[a][k] Om2x[b][i20 + k]
-    float* Pt0 = (mode == TM_NEWV ? d.PV : d.PW) + (size_t)tile * l1 * l2;
+    float* Pt0 = (newv ? d.PV : d.PW) + (size_t)tile * l1 * l2;
     float* Pt1 = d.PW + (size_t)tile * l1 * l2;
     mode2_partials<TC, YP>(Ys, wave, lane, NRT, RT, l1, l2, I2, i20, ncol, d.om2, d.om2t, Pt0, Pt1);
 }
 
 hipError_t launch_tile(const Desc* d, const int* starts, int count, int total_tiles, int mode,
-                       int nterms, int dst_index, int basis_bf16, int src_bf16, int l1max, hipStream_t s) {
+                       int nterms, int dst_index, int basis_bf16, int src_bf16, int l1max, hipStream_t s,
+                       int first_term) {
 #define RTG_TILE(BBV, SPV, RPV)                                                                   \
     hipLaunchKernelGGL((k_tile<BBV, SPV, RPV>), dim3(total_tiles), dim3(256), 0, s, d, starts, count, \
-                       mode, nterms, dst_index)
-    const int rtiles = ((l1max + 15) / 16) * (mode == TM_NEWV ? 2 : 1);
+                       mode, nterms, dst_index, first_term)
+    const int rtiles = ((l1max + 15) / 16) * ((mode == TM_NEWV || mode == TM_GKNEW) ? 2 : 1);
     const bool small = rtiles <= 8;
     if (basis_bf16) {
         const bool split = mode == TM_SKETCH_SRC && !src_bf16;

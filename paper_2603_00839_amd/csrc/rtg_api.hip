@@ -37,6 +37,7 @@ struct rtg_op_s {
                     // a1p[k][i * WP + R + dd] = A1[i, i + dd], WP = 2R + 1 rounded up to 4
     int toeplitz;   // A1 and A2 are Toeplitz on their in-range entries (convolutions with zero BC)
     float* taps;    // their taps: taps[r1 + dd] = A1[i, i + dd], then RMAX_SPATIAL * 2 + 1 on, A2's
+    rtg_op_s* adj;  // the adjoint Phi^T(X) = X x_1 A1^T x_2 A2^T x_3 B (transposed bands), for Golub-Kahan
 };
 
 struct rtg_sk_s {
@@ -100,8 +101,64 @@ Layout problem_layout(const rtg_op_s* op, const rtg_sk_s* sk, int m, int bf16) {
     return L;
 }
 
-size_t plan_bytes(int count) {
-    return align_up((size_t)count * sizeof(Desc)) + align_up((size_t)NKIND * (count + 1) * sizeof(int));
+// Golub-Kahan keeps a second basis (U_1..U_{m+1}), its stored sketches and
+// the composed sketch matrices of Phi^T after the layout above; everything
+// else (W, the partials, the bidiagonal matrix in H, rotations, state) is
+// shared by the two sides, which never run at the same time.
+struct GKExtra {
+    size_t V, SV, ot1, ot1h, ot2, ot3, total;
+};
+
+GKExtra gk_extra_layout(const rtg_op_s* op, const rtg_sk_s* sk, int m, int bf16) {
+    GKExtra E{};
+    const size_t n = (size_t)op->I1 * op->I2 * op->J;
+    const size_t Ls = (size_t)sk->l1 * sk->l2 * sk->l3;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { off = align_up(off); size_t at = off; off += bytes; return at; };
+    E.V = take((size_t)(m + 1) * n * (bf16 ? 2 : 4));
+    E.SV = take((size_t)(m + 1) * Ls * sizeof(float));
+    E.ot1 = take(frag_elems(sk->l1, op->I1, FRAG_K_F32) * sizeof(float));
+    E.ot1h = take(2 * frag_elems(sk->l1, op->I1, FRAG_K_BF16) * sizeof(bf16_t));
+    E.ot2 = take((size_t)sk->l2 * op->I2 * sizeof(float));
+    E.ot3 = take((size_t)sk->l3 * op->J * sizeof(float));
+    E.total = align_up(off);
+    return E;
+}
+
+// The U side of a Golub-Kahan problem from its filled V side d: operator
+// Phi^T, its own basis, stored sketches and composed matrices at ub; the
+// rest of the workspace is shared.
+void fill_gk_sides(Desc& d, Desc& u, const rtg_op_s* op, const rtg_sk_s* sk, int m, int bf16, char* ub) {
+    const GKExtra E = gk_extra_layout(op, sk, m, bf16);
+    u = d;
+    const rtg_op_s* a = op->adj;
+    u.a1 = a->a1; u.a2 = a->a2; u.bb = a->bb;
+    u.a1t = a->a1t; u.a2t = a->a2t;
+    for (int k = 0; k < 3; ++k) u.a1p[k] = a->a1p[k];
+    u.toeplitz = a->toeplitz;
+    u.taps = a->taps;
+    u.V = ub + E.V;
+    u.SV = (float*)(ub + E.SV);
+    u.om1t = (const float*)(ub + E.ot1);
+    u.om1th = (const bf16_t*)(ub + E.ot1h);
+    u.om2t = (const float*)(ub + E.ot2);
+    u.om3t = (const float*)(ub + E.ot3);
+    d.gk = 1;
+    u.gk = 2;
+    d.SVx = u.SV;
+    u.SVx = d.SV;
+}
+
+size_t problem_bytes(const rtg_op_s* op, const rtg_sk_s* sk, int m, int bf16, int method) {
+    size_t b = problem_layout(op, sk, m, bf16).total;
+    if (method == RTG_METHOD_GOLUB_KAHAN) b += gk_extra_layout(op, sk, m, bf16).total;
+    return b;
+}
+
+// descriptors (nsides per problem: Golub-Kahan has a V side and a U side)
+// and the per-kernel tile prefix tables
+size_t plan_bytes(int count, int nsides = 1) {
+    return align_up((size_t)count * nsides * sizeof(Desc)) + align_up((size_t)NKIND * (count + 1) * sizeof(int));
 }
 
 int check_pair(const rtg_op_s* op, const rtg_sk_s* sk) {
@@ -196,8 +253,9 @@ struct Plan {
     int unsketched;    // every problem's sketch is the identity (a batch is all one or all the other)
 };
 
-int build_plan(std::vector<Desc>& descs, void* ws, hipStream_t s, Plan& plan) {
-    const int count = (int)descs.size();
+// descs holds nsides groups of count problems (the same shapes in each group)
+int build_plan(std::vector<Desc>& descs, void* ws, hipStream_t s, Plan& plan, int nsides = 1) {
+    const int count = (int)descs.size() / nsides;
     std::vector<int> starts((size_t)NKIND * (count + 1), 0);
     int maxJ = 1;
     for (auto& d : descs) maxJ = std::max(maxJ, d.J);
@@ -231,7 +289,7 @@ int build_plan(std::vector<Desc>& descs, void* ws, hipStream_t s, Plan& plan) {
     }
     char* base = (char*)ws;
     plan.d_desc = (Desc*)base;
-    plan.d_starts = (int*)(base + align_up((size_t)count * sizeof(Desc)));
+    plan.d_starts = (int*)(base + align_up(descs.size() * sizeof(Desc)));
     int rc = upload(plan.d_desc, descs.data(), descs.size() * sizeof(Desc), s);
     if (rc) return rc;
     return upload(plan.d_starts, starts.data(), starts.size() * sizeof(int), s);
@@ -354,10 +412,52 @@ int run_solver(const Plan& plan, int count, int mmax, int bf16, bool any_x0, boo
     return RTG_OK;
 }
 
+// Sketched Block Golub-Kahan (Sec. 4.5) for a prepared two-sided plan:
+// descriptors [0, count) are the V sides (operator Phi), [count, 2 count)
+// the U sides (operator Phi^T).  Each half-step is the sketched norm of the
+// next tensor in sketch space (Gram kernel, from the composed sketch of the
+// newest tensor and the other side's stored sketch), the operator applied to
+// the newest tensor (into W), and the one-term AXPY that stores the next
+// tensor with its two sketches.  The last column needs no U_{m+1}.
+int run_gk(const Plan& plan, int count, int mmax, int bf16, bool any_x0, bool solve, hipStream_t s) {
+    const int* sp = starts_of(plan, KIND_PHI, count);
+    const int* st = starts_of(plan, KIND_TILE, count);
+    const int* sg = starts_of(plan, KIND_GRAM, count);
+    const Desc* dV = plan.d_desc;
+    const Desc* dU = plan.d_desc + count;
+    const int tp = plan.total[KIND_PHI], tt = plan.total[KIND_TILE], tg = plan.total[KIND_GRAM];
+    RTG_HIP(launch_init(dV, count, s));
+    RTG_HIP(launch_compose(plan.d_desc, 2 * count, plan.compose_max, s));
+    if (any_x0) RTG_TIMED(0, launch_phi(dV, sp, count, tp, PS_X0, 0, plan.rmax, plan.phi_jt, 0, s));
+    // beta_1 = ||R0||_Theta, U_1 = R0 / beta_1 (with S(U_1) and S(Phi^T(U_1)))
+    RTG_TIMED(1, launch_tile(dU, st, count, tt, TM_SKETCH_SRC, 0, 0, bf16, 0, plan.l1max, s));
+    RTG_TIMED(2, launch_gram(dU, sg, count, tg, GM_START, 0, nullptr, s));
+    RTG_TIMED(1, launch_tile(dU, st, count, tt, TM_NEWV, 0, 0, bf16, 0, plan.l1max, s));
+    for (int c = 1; c <= mmax; ++c) {
+        // alpha_c; V_c = (Phi^T(U_c) - beta_c V_{c-1}) / alpha_c
+        RTG_TIMED(2, launch_gram(dU, sg, count, tg, GM_GK, c, nullptr, s));
+        RTG_TIMED(0, launch_phi(dU, sp, count, tp, PS_BASIS, c - 1, plan.rmax, plan.phi_jt, bf16, s));
+        RTG_TIMED(1, launch_tile(dV, st, count, tt, TM_GKNEW, c - 1, c - 1, bf16, 0, plan.l1max, s,
+                                 c >= 2 ? c - 2 : 0));
+        // beta_{c+1}, column c of B, Givens and stop test; U_{c+1} = (Phi(V_c) - alpha_c U_c) / beta_{c+1}
+        RTG_TIMED(2, launch_gram(dV, sg, count, tg, GM_GK, c, nullptr, s));
+        if (c < mmax || !solve) {   // the bidiagonalisation alone also forms U_{m+1}
+            RTG_TIMED(0, launch_phi(dV, sp, count, tp, PS_BASIS, c - 1, plan.rmax, plan.phi_jt, bf16, s));
+            RTG_TIMED(1, launch_tile(dU, st, count, tt, TM_GKNEW, c, c, bf16, 0, plan.l1max, s, c - 1));
+        }
+    }
+    if (solve) {
+        RTG_TIMED(3, launch_solve(dV, count, mmax, s));
+        RTG_TIMED(1, launch_tile(dV, st, count, tt, TM_ASSEMBLE, 0, 0, bf16, 0, plan.l1max, s));
+    }
+    return RTG_OK;
+}
+
 int validate_params(const rtg_params* prm) {
     if (!prm) return RTG_E_ARG;
     if (prm->basis_dtype != RTG_F32 && prm->basis_dtype != RTG_BF16) return RTG_E_ARG;
     if (prm->mu_rule != RTG_MU_DISCREPANCY && prm->mu_rule != RTG_MU_GCV) return RTG_E_ARG;
+    if (prm->method != RTG_METHOD_GMRES && prm->method != RTG_METHOD_GOLUB_KAHAN) return RTG_E_ARG;
     if (prm->mu < 0.0 && prm->mu_rule == RTG_MU_DISCREPANCY && !(prm->delta >= 0.0 && prm->eta > 0.0))
         return RTG_E_ARG;
     if (!(prm->bd_tol >= 0.0)) return RTG_E_ARG;
@@ -390,15 +490,15 @@ const char* rtg_status_string(int status) {
     }
 }
 
-int rtg_setup_operator(int I1, int I2, int J, const float* a1_band, int r1, const float* a2_band,
-                       int r2, const float* b_band, int rB, rtg_op* out) {
+static int setup_op(int I1, int I2, int J, const float* a1_band, int r1, const float* a2_band,
+                    int r2, const float* b_band, int rB, rtg_op* out) {
     if (!out || !a1_band || !a2_band || !b_band) return RTG_E_ARG;
     *out = nullptr;
     if (I1 < 8 || I2 < 1 || J < 1 || (I1 % 8) != 0) return RTG_E_SHAPE;
     if (r1 < 0 || r2 < 0 || rB < 0 || r1 > RMAX_SPATIAL || r2 > RMAX_SPATIAL || rB > RMAX_B) return RTG_E_SHAPE;
     if (r1 >= I1 || (r2 >= I2 && I2 > 1) || (rB >= J && J > 1)) return RTG_E_SHAPE;
     rtg_op_s* op = new rtg_op_s{I1, I2, J, r1, r2, rB, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                {nullptr, nullptr, nullptr}, 0, nullptr};
+                                {nullptr, nullptr, nullptr}, 0, nullptr, nullptr};
     // Toeplitz bands (a convolution with zero boundary conditions, such as the
     // blurs of Sec. 5): A[i, i + dd] the same for every row i with i + dd in
     // range, compared bit for bit.  Entries pointing outside the matrix are
@@ -468,8 +568,36 @@ int rtg_setup_operator(int I1, int I2, int J, const float* a1_band, int r1, cons
     return RTG_OK;
 }
 
+int rtg_setup_operator(int I1, int I2, int J, const float* a1_band, int r1, const float* a2_band,
+                       int r2, const float* b_band, int rB, rtg_op* out) {
+    int rc = setup_op(I1, I2, J, a1_band, r1, a2_band, r2, b_band, rB, out);
+    if (rc) return rc;
+    // the adjoint operator Phi^T (Golub-Kahan): every band transposed,
+    // M^T[i, i + dd] = M[i + dd, i], zero where row i + dd leaves the matrix
+    auto transposed = [](const float* band, int I, int r) {
+        const int w = 2 * r + 1;
+        std::vector<float> t((size_t)I * w, 0.f);
+        for (int i = 0; i < I; ++i)
+            for (int dd = -r; dd <= r; ++dd)
+                if (i + dd >= 0 && i + dd < I) t[(size_t)i * w + r + dd] = band[(size_t)(i + dd) * w + r - dd];
+        return t;
+    };
+    const std::vector<float> a1 = transposed(a1_band, I1, r1), a2 = transposed(a2_band, I2, r2),
+                             b = transposed(b_band, J, rB);
+    rtg_op adj = nullptr;
+    rc = setup_op(I1, I2, J, a1.data(), r1, a2.data(), r2, b.data(), rB, &adj);
+    if (rc) {
+        rtg_destroy_operator(*out);
+        *out = nullptr;
+        return rc;
+    }
+    (*out)->adj = adj;
+    return RTG_OK;
+}
+
 int rtg_destroy_operator(rtg_op op) {
     if (!op) return RTG_OK;
+    if (op->adj) rtg_destroy_operator(op->adj);
     if (op->a1) (void)hipFree(op->a1);
     if (op->a2) (void)hipFree(op->a2);
     if (op->bb) (void)hipFree(op->bb);
@@ -589,7 +717,7 @@ int rtg_sketch(rtg_sk sk, int x_dtype, const void* X, float* SX, void* ws, size_
         return RTG_OK;
     }
     rtg_op_s dummy{sk->I1, sk->I2, sk->J, 0, 0, 0, nullptr, nullptr, nullptr, nullptr, nullptr,
-                   {nullptr, nullptr, nullptr}, 0, nullptr};
+                   {nullptr, nullptr, nullptr}, 0, nullptr, nullptr};
     Layout L = problem_layout(&dummy, sk, 1, x_dtype == RTG_BF16);
     std::vector<Desc> descs(1);
     fill_desc(descs[0], &dummy, sk, 1, x_dtype == RTG_BF16, nullptr, L);
@@ -651,24 +779,74 @@ int rtg_arnoldi(rtg_op op, rtg_sk sk, const float* R0, int m, int basis_dtype, d
 
 size_t rtg_batch_workspace_bytes(int count, const rtg_problem* probs) {
     if (count < 1 || !probs) return 0;
-    size_t total = plan_bytes(count);
+    const int method = probs[0].params.method;
+    size_t total = plan_bytes(count, method == RTG_METHOD_GOLUB_KAHAN ? 2 : 1);
     for (int p = 0; p < count; ++p) {
         const rtg_problem& q = probs[p];
         if (check_pair(q.op, q.sk) || check_m(q.sk, q.params.m)) return 0;
-        total += problem_layout(q.op, q.sk, q.params.m, q.params.basis_dtype == RTG_BF16).total;
+        if (q.params.method != method) return 0;
+        total += problem_bytes(q.op, q.sk, q.params.m, q.params.basis_dtype == RTG_BF16, method);
     }
     return total;
+}
+
+size_t rtg_gk_workspace_bytes(rtg_op op, rtg_sk sk, int m, int basis_dtype) {
+    if (check_pair(op, sk) || check_m(sk, m)) return 0;
+    return plan_bytes(1, 2) + problem_bytes(op, sk, m, basis_dtype == RTG_BF16, RTG_METHOD_GOLUB_KAHAN);
+}
+
+int rtg_gk_workspace_layout(rtg_op op, rtg_sk sk, int m, int basis_dtype, size_t* v_offset, size_t* u_offset) {
+    int rc = check_pair(op, sk);
+    if (rc) return rc;
+    if ((rc = check_m(sk, m))) return rc;
+    const int bf16 = basis_dtype == RTG_BF16;
+    const Layout L = problem_layout(op, sk, m, bf16);
+    const GKExtra E = gk_extra_layout(op, sk, m, bf16);
+    if (v_offset) *v_offset = plan_bytes(1, 2) + L.V;
+    if (u_offset) *u_offset = plan_bytes(1, 2) + L.total + E.V;
+    return RTG_OK;
+}
+
+int rtg_golub_kahan(rtg_op op, rtg_sk sk, const float* R0, int m, int basis_dtype, double bd_tol, void* ws,
+                    size_t ws_bytes, double* B, double* beta, int* m_done, void* stream) {
+    int rc = check_pair(op, sk);
+    if (rc) return rc;
+    if ((rc = check_m(sk, m))) return rc;
+    if (!R0 || !ws || !B || !beta || !m_done) return RTG_E_ARG;
+    if (basis_dtype != RTG_F32 && basis_dtype != RTG_BF16) return RTG_E_ARG;
+    if (!aligned16(R0) || !aligned16(ws) || !(bd_tol >= 0.0)) return RTG_E_ARG;
+    if (sk->identity || !op->adj) return RTG_E_ARG;
+    const int bf16 = basis_dtype == RTG_BF16;
+    if (ws_bytes < rtg_gk_workspace_bytes(op, sk, m, basis_dtype)) return RTG_E_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    const Layout L = problem_layout(op, sk, m, bf16);
+    char* base = (char*)ws + plan_bytes(1, 2);
+    std::vector<Desc> descs(2);
+    fill_desc(descs[0], op, sk, m, bf16, base, L);
+    descs[0].R0src = R0;
+    descs[0].bd_tol = bd_tol;
+    descs[0].keep_last = 1;
+    fill_gk_sides(descs[0], descs[1], op, sk, m, bf16, base + L.total);
+    Plan plan;
+    if ((rc = build_plan(descs, ws, s, plan, 2))) return rc;
+    if ((rc = run_gk(plan, 1, m, bf16, false, false, s))) return rc;
+    RTG_HIP(launch_finish_arnoldi(plan.d_desc, B, beta, m_done, m, s));
+    return RTG_OK;
 }
 
 int rtg_solve_batched(int count, const rtg_problem* probs, void* ws, size_t ws_bytes, void* stream) {
     if (count < 1 || !probs || !ws || !aligned16(ws)) return RTG_E_ARG;
     int bf16 = -1;
+    const int method = probs[0].params.method;
+    const bool gk = method == RTG_METHOD_GOLUB_KAHAN;
     for (int p = 0; p < count; ++p) {
         const rtg_problem& q = probs[p];
         int rc = check_pair(q.op, q.sk);
         if (rc) return rc;
         if ((rc = check_m(q.sk, q.params.m))) return rc;
         if ((rc = validate_params(&q.params))) return rc;
+        if (q.params.method != method) return RTG_E_ARG;     // one method per batch
+        if (gk && (q.sk->identity || !q.op->adj)) return RTG_E_ARG;
         if (!q.C || !q.X || !q.info) return RTG_E_ARG;
         if (!aligned16(q.C) || !aligned16(q.X) || (q.X0 && !aligned16(q.X0))) return RTG_E_ARG;
         const int b = q.params.basis_dtype == RTG_BF16;
@@ -679,15 +857,17 @@ int rtg_solve_batched(int count, const rtg_problem* probs, void* ws, size_t ws_b
     if (need == 0) return RTG_E_SHAPE;
     if (ws_bytes < need) return RTG_E_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
-    std::vector<Desc> descs(count);
-    size_t off = plan_bytes(count);
+    const int nsides = gk ? 2 : 1;
+    std::vector<Desc> descs((size_t)count * nsides);
+    size_t off = plan_bytes(count, nsides);
     int mmax = 0;
     bool any_x0 = false;
     for (int p = 0; p < count; ++p) {
         const rtg_problem& q = probs[p];
         Layout L = problem_layout(q.op, q.sk, q.params.m, bf16);
+        char* base = (char*)ws + off;
         Desc& d = descs[p];
-        fill_desc(d, q.op, q.sk, q.params.m, bf16, (char*)ws + off, L);
+        fill_desc(d, q.op, q.sk, q.params.m, bf16, base, L);
         set_params(d, &q.params);
         d.C = q.C;
         d.X0 = q.X0;
@@ -695,12 +875,17 @@ int rtg_solve_batched(int count, const rtg_problem* probs, void* ws, size_t ws_b
         d.info = q.info;
         d.R0src = q.X0 ? (const void*)d.W : (const void*)q.C;
         off += L.total;
+        if (gk) {
+            fill_gk_sides(d, descs[(size_t)count + p], q.op, q.sk, q.params.m, bf16, (char*)ws + off);
+            off += gk_extra_layout(q.op, q.sk, q.params.m, bf16).total;
+        }
         mmax = std::max(mmax, q.params.m);
         any_x0 = any_x0 || q.X0 != nullptr;
     }
     Plan plan;
-    int rc = build_plan(descs, ws, s, plan);
+    int rc = build_plan(descs, ws, s, plan, nsides);
     if (rc) return rc;
+    if (gk) return run_gk(plan, count, mmax, bf16, any_x0, true, s);
     return run_solver(plan, count, mmax, bf16, any_x0, true, false, s);
 }
 

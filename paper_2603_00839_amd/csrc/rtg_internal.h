@@ -52,6 +52,8 @@ struct Desc {
     int keep_last;      // form V_{m+1} after the last step (Arnoldi-only calls)
     int toeplitz;       // A1 and A2 are Toeplitz on their in-range entries (convolutions, zero BC)
     int unsketched;     // identity sketch: Frobenius inner products of the full tensors
+    int gk;             // sketched Block Golub-Kahan: 1 = the V side (operator Phi), 2 = the U side
+                        // (operator Phi^T, transposed bands); 0 = RTG-GMRES
     long long n;        // I1*I2*J
     long long L;        // l1*l2*l3
     // operator / sketch (device)
@@ -88,6 +90,7 @@ struct Desc {
     float* PW;          // sketch partials of W: (J*n_i2t) x (l1*l2)
     float* PV;          // sketch partials of the newest basis tensor
     float* SV;          // (m+1) x L sketched basis
+    const float* SVx;   // Golub-Kahan: the other side's sketched basis
     double* dots;       // ntile[GRAM] x (m+2) x 2 partial inner products
     double* G;          // (m+1) x (m+1) Gram matrix of the sketched basis
     double* H;          // (m+1) x m Hessenberg, column-major
@@ -253,7 +256,7 @@ hipError_t launch_phi_single(int I1, int I2, int J, int r1, int r2, int rB, cons
                              const float* C, float* dst, hipStream_t s);
 hipError_t launch_tile(const Desc* d, const int* starts, int count, int total_tiles,
                        int mode, int nterms, int dst_index, int basis_bf16, int src_bf16,
-                       int l1max, hipStream_t s);
+                       int l1max, hipStream_t s, int first_term = 0);
 hipError_t launch_step(const Desc* d, const int* starts, int count, int total_tiles, int j, int rmax,
                        int basis_bf16, int l1max, int toeplitz, hipStream_t s);
 hipError_t launch_gram(const Desc* d, const int* starts, int count, int total_tiles,
@@ -265,9 +268,12 @@ hipError_t launch_finish_arnoldi(const Desc* d, double* H, double* beta, int* m_
                                  int m, hipStream_t s);
 
 // k_tile modes
-enum TileMode { TM_NEWV = 1, TM_ASSEMBLE = 2, TM_SKETCH_SRC = 3 };
+// (TM_GKNEW: a new Golub-Kahan basis tensor from W and the terms
+// [first_term, nterms) of this side's basis)
+enum TileMode { TM_NEWV = 1, TM_ASSEMBLE = 2, TM_SKETCH_SRC = 3, TM_GKNEW = 4 };
 // k_phi source selection
 enum PhiSrc { PS_BASIS = 0, PS_X0 = 1 };
 // k_gram modes
-enum GramMode { GM_START = 0, GM_STEP = 1, GM_SKETCH_OUT = 2 };
+// (GM_GK: one Golub-Kahan half-step, the sketched norm of the next tensor)
+enum GramMode { GM_START = 0, GM_STEP = 1, GM_SKETCH_OUT = 2, GM_GK = 3 };
 }  // namespace rtg

@@ -7,7 +7,8 @@ device layout of the library: a C-contiguous torch tensor of shape
 
 The functions keep the names of the C entry points without the ``rtg_``
 prefix: setup_operator, apply_operator, setup_sketch, sketch,
-workspace_bytes, arnoldi, workspace_layout, solve, solve_batched.
+workspace_bytes, gk_workspace_bytes, arnoldi, golub_kahan, workspace_layout,
+gk_workspace_layout, solve, solve_batched.
 """
 from __future__ import annotations
 
@@ -33,7 +34,7 @@ class RTGError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int), ("basis_dtype", ctypes.c_int), ("mu", ctypes.c_double),
                 ("delta", ctypes.c_double), ("eta", ctypes.c_double), ("stop_res", ctypes.c_double),
-                ("bd_tol", ctypes.c_double), ("mu_rule", ctypes.c_int)]
+                ("bd_tol", ctypes.c_double), ("mu_rule", ctypes.c_int), ("method", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -70,8 +71,12 @@ def load_library():
         "rtg_sketch": (c_int, [c_vp, c_int, c_vp, c_vp, c_vp, c_sz, c_vp]),
         "rtg_destroy_sketch": (c_int, [c_vp]),
         "rtg_workspace_bytes": (c_sz, [c_vp, c_vp, c_int, c_int]),
+        "rtg_gk_workspace_bytes": (c_sz, [c_vp, c_vp, c_int, c_int]),
         "rtg_arnoldi": (c_int, [c_vp, c_vp, c_vp, c_int, c_int, c_d, c_vp, c_sz, c_vp, c_vp, c_vp, c_vp]),
         "rtg_workspace_layout": (c_int, [c_vp, c_vp, c_int, c_int, ctypes.POINTER(c_sz), ctypes.POINTER(c_sz)]),
+        "rtg_golub_kahan": (c_int, [c_vp, c_vp, c_vp, c_int, c_int, c_d, c_vp, c_sz, c_vp, c_vp, c_vp, c_vp]),
+        "rtg_gk_workspace_layout": (c_int, [c_vp, c_vp, c_int, c_int, ctypes.POINTER(c_sz),
+                                            ctypes.POINTER(c_sz)]),
         "rtg_solve": (c_int, [c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(Params), c_vp, c_sz, c_vp, c_vp, c_vp]),
         "rtg_batch_workspace_bytes": (c_sz, [c_int, ctypes.POINTER(Problem)]),
         "rtg_solve_batched": (c_int, [c_int, ctypes.POINTER(Problem), c_vp, c_sz, c_vp]),
@@ -301,12 +306,52 @@ def arnoldi(op: Operator, sk: Sketch, R0, m: int, basis_dtype: int = F32, bd_tol
 
 
 MU_DISCREPANCY, MU_GCV = 0, 1
+METHOD_GMRES, METHOD_GOLUB_KAHAN = 0, 1
 
 
 def make_params(m, basis_dtype=F32, mu=-1.0, delta=0.0, eta=1.01, stop_res=0.0, bd_tol=1e-6,
-                mu_rule=MU_DISCREPANCY) -> Params:
+                mu_rule=MU_DISCREPANCY, method=METHOD_GMRES) -> Params:
     return Params(int(m), int(basis_dtype), float(mu), float(delta), float(eta), float(stop_res), float(bd_tol),
-                  int(mu_rule))
+                  int(mu_rule), int(method))
+
+
+def gk_workspace_bytes(op: Operator, sk: Sketch, m: int, basis_dtype: int = F32) -> int:
+    n = lib().rtg_gk_workspace_bytes(op.handle, sk.handle, m, basis_dtype)
+    if n == 0:
+        raise RTGError("rtg_gk_workspace_bytes: invalid sizes")
+    return n
+
+
+def gk_workspace_layout(op: Operator, sk: Sketch, m: int, basis_dtype: int = F32):
+    v = ctypes.c_size_t()
+    u = ctypes.c_size_t()
+    _check(lib().rtg_gk_workspace_layout(op.handle, sk.handle, m, basis_dtype, ctypes.byref(v), ctypes.byref(u)),
+           "rtg_gk_workspace_layout")
+    return v.value, u.value
+
+
+def golub_kahan(op: Operator, sk: Sketch, R0, m: int, basis_dtype: int = F32, bd_tol: float = 1e-6, ws=None):
+    """m columns of the sketched Block Golub-Kahan bidiagonalisation.
+    Returns a dict with B ((m+1) x m float64 lower bidiagonal), beta (beta_1),
+    m_done, and views U ((m+1, J, I2, I1)) and V ((m+1, ...); V_1..V_m
+    written) into the workspace."""
+    torch = _torch()
+    _check_tensor(R0, op.device_shape, "R0")
+    nbytes = gk_workspace_bytes(op, sk, m, basis_dtype)
+    if ws is None or ws.numel() < nbytes:
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=R0.device)
+    B = torch.zeros((m, m + 1), dtype=torch.float64, device=R0.device)   # column-major (m+1) x m
+    beta = torch.zeros(1, dtype=torch.float64, device=R0.device)
+    m_done = torch.zeros(1, dtype=torch.int32, device=R0.device)
+    _check(lib().rtg_golub_kahan(op.handle, sk.handle, _ptr(R0), m, basis_dtype, bd_tol, _ptr(ws), ws.numel(),
+                                 _ptr(B), _ptr(beta), _ptr(m_done), _stream()), "rtg_golub_kahan")
+    voff, uoff = gk_workspace_layout(op, sk, m, basis_dtype)
+    esz = 2 if basis_dtype == BF16 else 4
+    n = int(np.prod(op.shape))
+    vdt = torch.bfloat16 if basis_dtype == BF16 else torch.float32
+    V = ws[voff:voff + (m + 1) * n * esz].view(vdt).view((m + 1,) + op.device_shape)
+    U = ws[uoff:uoff + (m + 1) * n * esz].view(vdt).view((m + 1,) + op.device_shape)
+    return {"B": B.t(), "beta": beta, "m_done": m_done, "U": U, "V": V, "ws": ws}
 
 
 def read_info(info_buf) -> Info:
@@ -321,15 +366,19 @@ def info_buffer(device="cuda"):
 
 def solve(op: Operator, sk: Sketch, C, X0=None, params: Optional[Params] = None, out=None, ws=None,
           info_buf=None):
-    """One RTG-GMRES solve; returns (X, info_buf) with the info left on the
-    device (read it with read_info)."""
+    """One RTG-GMRES (or, with params.method, sketched Block Golub-Kahan)
+    solve; returns (X, info_buf) with the info left on the device (read it
+    with read_info)."""
     torch = _torch()
     _check_tensor(C, op.device_shape, "C")
     if X0 is not None:
         _check_tensor(X0, op.device_shape, "X0")
     if params is None:
         raise RTGError("params required")
-    nbytes = workspace_bytes(op, sk, params.m, params.basis_dtype)
+    if params.method == METHOD_GOLUB_KAHAN:
+        nbytes = gk_workspace_bytes(op, sk, params.m, params.basis_dtype)
+    else:
+        nbytes = workspace_bytes(op, sk, params.m, params.basis_dtype)
     if ws is None or ws.numel() < nbytes:
         ws = torch.empty(nbytes, dtype=torch.uint8, device=C.device)
     if out is None:
