@@ -75,20 +75,70 @@ def phi_einstein(X, A1, A2, B) -> np.ndarray:
 def convolve_psf_zero_bc(X, P) -> np.ndarray:
     """Direct 2-D convolution of every channel with a (2r+1) x (2r+1) PSF,
     zero boundary conditions (eq. (57) generalised to any odd PSF size):
-    C[i, j, k] = sum_{a,b} P[r - a, r - b] X[i + a, j + b, k]."""
+    C[i, j, k] = sum_{a,b} P[r - a, r - b] X[i + a, j + b, k],
+    summed as one shifted copy of X per PSF entry (terms whose X index leaves
+    the image are zero)."""
     X = np.asarray(X, np.float64)
     P = np.asarray(P, np.float64)
     r = (P.shape[0] - 1) // 2
-    I1, I2, J = X.shape
+    I1, I2, _ = X.shape
     out = np.zeros_like(X)
-    for i in range(I1):
-        for j in range(I2):
-            for a in range(-r, r + 1):
-                for b in range(-r, r + 1):
-                    ii, jj = i + a, j + b
-                    if 0 <= ii < I1 and 0 <= jj < I2:
-                        out[i, j, :] += P[r - a, r - b] * X[ii, jj, :]
+    for a in range(-r, r + 1):
+        for b in range(-r, r + 1):
+            i_lo, i_hi = max(0, -a), min(I1, I1 - a)      # output rows with 0 <= i + a < I1
+            j_lo, j_hi = max(0, -b), min(I2, I2 - b)
+            if i_lo >= i_hi or j_lo >= j_hi:
+                continue
+            out[i_lo:i_hi, j_lo:j_hi, :] += P[r - a, r - b] * X[i_lo + a:i_hi + a, j_lo + b:j_hi + b, :]
     return out
+
+
+def psf_tensor(P, I1: int, I2: int) -> np.ndarray:
+    """Fourth-order blur tensor built directly from the PSF entries (eqs.
+    (56)-(57)): a[i1, i2, k1, k2] = P[r - (k1 - i1), r - (k2 - i2)] when both
+    offsets lie within the PSF, else 0 (tiny sizes only)."""
+    P = np.asarray(P, np.float64)
+    r = (P.shape[0] - 1) // 2
+    a = np.zeros((I1, I2, I1, I2))
+    for i1 in range(I1):
+        for i2 in range(I2):
+            for k1 in range(max(0, i1 - r), min(I1, i1 + r + 1)):
+                for k2 in range(max(0, i2 - r), min(I2, i2 + r + 1)):
+                    a[i1, i2, k1, k2] = P[r - (k1 - i1), r - (k2 - i2)]
+    return a
+
+
+class PSFOperator:
+    """Phi(X) = (A *_2 X) *_1 B with A built from a general (non-separable)
+    PSF (eqs. (56)-(57)): every channel convolved with P (zero boundary
+    conditions), then the channel mix, (X *_1 B)[.., j] = sum_k X[.., k] B[k, j]."""
+
+    def __init__(self, psf, b_band, dims):
+        self.P = np.asarray(psf, np.float64)
+        self.B = band_to_dense(b_band)
+        self.dims = tuple(dims)
+
+    @property
+    def shape(self):
+        return self.dims
+
+    def __call__(self, X: np.ndarray) -> np.ndarray:
+        return mode_product(convolve_psf_zero_bc(X, self.P), self.B.T, 2)
+
+    def transpose_apply(self, Y: np.ndarray) -> np.ndarray:
+        """Adjoint w.r.t. <.,.>_F: the channel mix transposed, then the
+        convolution with the PSF rotated by 180 degrees."""
+        return convolve_psf_zero_bc(mode_product(np.asarray(Y, np.float64), self.B, 2), self.P[::-1, ::-1])
+
+    def dense(self) -> np.ndarray:
+        """n x n matrix of vec(Phi(X)) (column-major vec), column by column."""
+        n = int(np.prod(self.dims))
+        M = np.empty((n, n))
+        for c in range(n):
+            e = np.zeros(n)
+            e[c] = 1.0
+            M[:, c] = self(e.reshape(self.dims, order="F")).ravel(order="F")
+        return M
 
 
 def make_observation(op: Operator, x_true, noise_dir, nu):

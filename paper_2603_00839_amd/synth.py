@@ -267,6 +267,87 @@ def make_image_problem(name, seed, I1, I2, n_rect, grf, sigma, r, nu, l1, l2, m,
     )
 
 
+def rotated_gaussian_psf(r: int, s_major: float, s_minor: float, theta: float) -> np.ndarray:
+    """Non-separable PSF of size (2r+1) x (2r+1): an anisotropic Gaussian
+    whose axes are rotated by theta (a general PSF P of eq. (57); row index
+    along i1, column index along i2, centre at [r, r]), normalised to sum 1.
+    For theta not a multiple of pi/2 and unequal widths it is not an outer
+    product of two tap vectors."""
+    d = np.arange(-r, r + 1, dtype=np.float64)
+    a, b = np.meshgrid(d, d, indexing="ij")
+    c, s = math.cos(theta), math.sin(theta)
+    u = c * a + s * b
+    v = -s * a + c * b
+    P = np.exp(-0.5 * (u / s_major) ** 2 - 0.5 * (v / s_minor) ** 2)
+    return P / P.sum()
+
+
+@dataclasses.dataclass
+class PSFProblem:
+    """Canonical float32 inputs of a restoration problem with a general
+    (non-separable) PSF applied to every channel, then the channel mix B."""
+    name: str
+    x_true: np.ndarray          # (I1, I2, J) float32
+    psf: np.ndarray             # (2r+1, 2r+1) float32, orientation of eq. (57)
+    b_band: np.ndarray          # (J, 2 rB + 1) float32
+    om1: Optional[np.ndarray]
+    om2: Optional[np.ndarray]
+    om3: Optional[np.ndarray]
+    noise_dir: np.ndarray
+    nu: float
+    m: int
+
+    @property
+    def dims(self):
+        return self.x_true.shape
+
+    @property
+    def r(self):
+        return (self.psf.shape[0] - 1) // 2
+
+    @property
+    def rB(self):
+        return (self.b_band.shape[1] - 1) // 2
+
+
+def psf_problem(seed: int, I1: int, I2: int, J: int = 3, r: int = 4, l1: int = 16, l2: int = 16,
+                l3: Optional[int] = None, m: int = 20, nu: float = 1e-2, n_rect: int = 20,
+                grf: bool = False, s_major: float = 2.0, s_minor: float = 0.8,
+                theta: float = 0.6) -> PSFProblem:
+    """Rectangles (+ optional Gaussian random field) blurred by a rotated
+    anisotropic Gaussian PSF of radius r, the 3x3-style channel mix (or a
+    random band for J != 3), Gaussian sketches (Om3 only when l3 < J)."""
+    rs = streams(seed)
+    x = rectangles(rs["image"], I1, I2, J, n_rect)
+    if grf:
+        x = x + gaussian_random_field(rs["image"], I1, I2, J)
+    if J == 3:
+        b_band = dense_to_band(channel_mix(3), 2)
+    else:
+        b_band = rs["aux"].uniform(0.05, 0.3, (J, 3))
+        b_band[:, 1] += 0.5
+        b_band[0, 0] = 0.0
+        b_band[-1, 2] = 0.0
+    l3v = J if l3 is None else l3
+    return PSFProblem(
+        name=f"psf_{I1}x{I2}x{J}_r{r}",
+        x_true=_f32(x),
+        psf=_f32(rotated_gaussian_psf(r, s_major, s_minor, theta)),
+        b_band=_f32(b_band),
+        om1=_f32(sketch_matrix(rs["omega"], l1, I1)),
+        om2=_f32(sketch_matrix(rs["omega"], l2, I2)),
+        om3=_f32(sketch_matrix(rs["omega"], l3v, J)) if l3v < J else None,
+        noise_dir=_f32(rs["noise"].standard_normal((I1, I2, J))),
+        nu=float(nu), m=int(m),
+    )
+
+
+def cfg2_psf(seed: int = 0) -> PSFProblem:
+    """512x512x3 like cfg2, blurred by a 9x9 rotated anisotropic Gaussian
+    PSF (widths 2.0 and 0.8 px, axes at 0.6 rad): a non-separable blur."""
+    return psf_problem(seed, 512, 512, 3, r=4, l1=64, l2=64, m=50, nu=1e-3, n_rect=200, grf=True)
+
+
 def cfg1(seed: int = 0) -> Problem:
     """32x32x3 colour image, 20 rectangles; sigma 1.5, r 4; nu 1e-2;
     sketch 16x16x3; m = 20."""

@@ -201,3 +201,37 @@ def test_untransposed_channel_mix_in_the_adjoint_is_caught(monkeypatch):
     monkeypatch.setattr(opm.Operator, "transpose_apply", bad_t)
     expect_failure(gkpins.test_transpose_apply_is_the_frobenius_adjoint)
     expect_failure(gkpins.test_bases_span_the_normal_equation_krylov_spaces, 0)
+
+
+# --------------------------------------------------------------------------
+# general PSF operator (eqs. (56)-(57))
+# --------------------------------------------------------------------------
+import test_oracle_psf as psfpins
+
+
+def test_unflipped_psf_is_caught(monkeypatch):
+    good = opm.convolve_psf_zero_bc
+
+    def bad(X, P):
+        return good(X, np.asarray(P)[::-1, ::-1])
+    monkeypatch.setattr(opm, "convolve_psf_zero_bc", bad)
+    monkeypatch.setattr(psfpins, "convolve_psf_zero_bc", bad)
+    expect_failure(psfpins.test_shift_sum_equals_elementwise_definition)
+    expect_failure(psfpins.test_psf_operator_matches_fourth_order_einstein_form)
+
+
+def test_transposed_psf_is_caught(monkeypatch):
+    good_call = opm.PSFOperator.__call__
+
+    def bad_call(self, X):
+        return mode_product(opm.convolve_psf_zero_bc(X, self.P.T), self.B.T, 2)
+    monkeypatch.setattr(opm.PSFOperator, "__call__", bad_call)
+    expect_failure(psfpins.test_psf_operator_matches_fourth_order_einstein_form)
+    monkeypatch.setattr(opm.PSFOperator, "__call__", good_call)
+
+
+def test_unrotated_psf_adjoint_is_caught(monkeypatch):
+    def bad_t(self, Y):
+        return opm.convolve_psf_zero_bc(mode_product(np.asarray(Y, np.float64), self.B, 2), self.P)
+    monkeypatch.setattr(opm.PSFOperator, "transpose_apply", bad_t)
+    expect_failure(psfpins.test_psf_adjoint)
