@@ -124,6 +124,18 @@ int rtg_setup_operator(int I1, int I2, int J,
                        const float* a1_band, int r1,
                        const float* a2_band, int r2,
                        const float* b_band, int rB, rtg_op* out);
+/* General (non-separable) PSF (eqs. (56)-(57)): Phi(X) = (A *_2 X) *_1 B with
+ * A built from a (2r+1) x (2r+1) PSF, every channel convolved with zero
+ * boundary conditions, (A *_2 X)[i1,i2,k] = sum_{a,b} P[r-a][r-b] X[i1+a,i2+b,k]
+ * for |a|, |b| <= r.  psf is a HOST array, row-major P[r + a][r + b] with the
+ * row index along i1 (centre at [r][r]); b_band as above.  Requires
+ * 0 <= r <= 12, r < I1, r < I2 (or I2 = 1), 0 <= rB < J (rB <= 8).  Solves
+ * with such an operator sketch each W = Phi(V_j) after forming it (the
+ * composed sketch matrices need separable factors), so a step costs one more
+ * pass over W; one kind of operator per batch (RTG_E_ARG otherwise), and
+ * Golub-Kahan is refused for it (RTG_E_ARG). */
+int rtg_setup_operator_psf(int I1, int I2, int J, const float* psf, int r,
+                           const float* b_band, int rB, rtg_op* out);
 /* Y = Phi(X)  (C == NULL)  or  Y = C - Phi(X)  (C != NULL); X of x_dtype. */
 int rtg_apply_operator(rtg_op op, int x_dtype, const void* X, const float* C,
                        float* Y, void* stream);

@@ -258,8 +258,10 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
     // composed first two matrices, so mode 3 is Om3 B^T
     // (Om3 B^T is banded when Om3 is the identity)
     const float* om3 = d.has_om3 ? d.om3 : nullptr;
+    // (a general PSF: the W partials are those of W itself, mode 3 is Om3)
     if (mode == GM_STEP || mode == GM_GK)
-        finish_sketches<2>(d, q0, qn, d.PW, d.om3t, d.has_om3 ? -1 : d.rB, s_s, d.PV, om3, -1, s_v);
+        finish_sketches<2>(d, q0, qn, d.PW, d.st ? om3 : d.om3t, (d.st || d.has_om3) ? -1 : d.rB, s_s, d.PV, om3,
+                           -1, s_v);
     else finish_sketches<1>(d, q0, qn, d.PW, om3, -1, s_s, nullptr, nullptr, -1, nullptr);
     __syncthreads();
 

@@ -15,6 +15,13 @@
 // rows (again wave-uniform coefficients), and accumulates B-weighted results
 // in registers.  Global loads and stores run along i1, the contiguous mode.
 // R (a template tier 4/8/12) bounds r1, r2; actual widths are runtime.
+//
+// General (non-separable) PSF (eqs. (56)-(57)): with ST the two passes are
+// replaced by the 2-D stencil
+//   U[i1,i2] = sum_{a,b} St[a,b] X_k[i1 + a, i2 + b],  |a|, |b| <= r,
+// St the PSF rotated by 180 degrees (the weight of each shifted pixel), read
+// from LDS as wave-uniform broadcasts; lane = row, eight columns per lane,
+// one slab row (8 + 2R columns) in registers per stencil row.
 #include "rtg_internal.h"
 
 namespace rtg {
@@ -27,6 +34,7 @@ struct PhiArgs {
     const void* src;
     const float* C;   // residual mode when non-null: Y = C - Phi(X)
     float* dst;
+    const float* st;  // stencil ((2 r1 + 1)^2, [a + r1][b + r1]) of a general PSF, else null
 };
 
 __device__ __forceinline__ int xcd_remap(int b, int G) {
@@ -39,7 +47,7 @@ __device__ __forceinline__ int xcd_remap(int b, int G) {
     return x * q + min(x, rem) + slot;
 }
 
-template <int R, bool BF16IN, int JT>
+template <int R, bool BF16IN, int JT, bool ST>
 __device__ __forceinline__ void phi_tile(const PhiArgs& a, int tile, float* smem) {
     constexpr int T1 = PHI_T1, T2 = PHI_T2;
     constexpr int SR = T1 + 2 * R;       // slab rows
@@ -51,6 +59,7 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int tile, float* smem
     float* S = smem;                     // [SC][SRP]
     float* Z = S + SC * SRP;             // [SC][ZRP]
     float* A1c = Z + SC * ZRP;           // [T1][WP]: A1[i1, i1 + d], d = t - R (0 outside the band)
+    float* Stc = A1c;                    // ST: [2R + 1][2R + 1] stencil (fits in T1 WP floats)
     float* A2c = A1c + T1 * WP;          // [T2][WP]
     float* Bc = A2c + T2 * WP;           // [NKB][JT]: B[k, j0 + jj]
 
@@ -73,15 +82,24 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int tile, float* smem
 
     // band coefficients of this tile, zero-padded to R taps (no branches in
     // the passes; reads are LDS broadcasts)
-    for (int e = tid; e < T1 * WP; e += 256) {
-        const int row = e / WP, t = e % WP, dd = t - R;
-        const int i1 = i10 + row;
-        A1c[e] = (t <= 2 * R && dd >= -r1 && dd <= r1 && i1 < I1) ? a.a1[(size_t)i1 * w1 + r1 + dd] : 0.f;
-    }
-    for (int e = tid; e < T2 * WP; e += 256) {
-        const int col = e / WP, t = e % WP, dd = t - R;
-        const int i2 = i20 + col;
-        A2c[e] = (t <= 2 * R && dd >= -r2 && dd <= r2 && i2 < I2) ? a.a2[(size_t)i2 * w2 + r2 + dd] : 0.f;
+    if constexpr (ST) {
+        static_assert((2 * R + 1) * (2 * R + 1) <= T1 * WP, "stencil fits the band-coefficient area");
+        for (int e = tid; e < (2 * R + 1) * (2 * R + 1); e += 256) {
+            const int da = e / (2 * R + 1) - R, db = e % (2 * R + 1) - R;
+            Stc[e] = (da >= -r1 && da <= r1 && db >= -r1 && db <= r1) ? a.st[(size_t)(da + r1) * w1 + db + r1]
+                                                                       : 0.f;
+        }
+    } else {
+        for (int e = tid; e < T1 * WP; e += 256) {
+            const int row = e / WP, t = e % WP, dd = t - R;
+            const int i1 = i10 + row;
+            A1c[e] = (t <= 2 * R && dd >= -r1 && dd <= r1 && i1 < I1) ? a.a1[(size_t)i1 * w1 + r1 + dd] : 0.f;
+        }
+        for (int e = tid; e < T2 * WP; e += 256) {
+            const int col = e / WP, t = e % WP, dd = t - R;
+            const int i2 = i20 + col;
+            A2c[e] = (t <= 2 * R && dd >= -r2 && dd <= r2 && i2 < I2) ? a.a2[(size_t)i2 * w2 + r2 + dd] : 0.f;
+        }
     }
     for (int e = tid; e < NKB * JT; e += 256) {
         const int kk = e / JT, jj = e % JT;
@@ -125,6 +143,23 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int tile, float* smem
         }
         if (k + 1 < khi) load_slab(k + 1);
         __syncthreads();
+        float u[8];
+        if constexpr (ST) {
+            // ---- 2-D stencil: lane = row, columns 8 wave + o
+#pragma unroll
+            for (int o = 0; o < 8; ++o) u[o] = 0.f;
+#pragma unroll
+            for (int ta = 0; ta <= 2 * R; ++ta) {
+                float in[8 + 2 * R];
+#pragma unroll
+                for (int e = 0; e < 8 + 2 * R; ++e) in[e] = S[(wave * 8 + e) * SRP + lane + ta];
+                const float* cr = Stc + ta * (2 * R + 1);
+#pragma unroll
+                for (int o = 0; o < 8; ++o)
+#pragma unroll
+                    for (int tb = 0; tb <= 2 * R; ++tb) u[o] = fmaf(cr[tb], in[o + tb], u[o]);
+            }
+        } else {
         // ---- i1 pass: Z[c][row] = sum_d A1[i1, i1+d] S[c][row + R + d]
         // lanes across slab columns, wave handles rows [16 wave, 16 wave + 16)
         if (lane < SC) {
@@ -149,7 +184,6 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int tile, float* smem
         float in2[8 + 2 * R];
 #pragma unroll
         for (int e = 0; e < 8 + 2 * R; ++e) in2[e] = Z[(wave * 8 + e) * ZRP + lane];
-        float u[8];
 #pragma unroll
         for (int o = 0; o < 8; ++o) {
             const float* cr = A2c + (wave * 8 + o) * WP;
@@ -158,6 +192,7 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int tile, float* smem
             for (int t = 0; t <= 2 * R; ++t) s = fmaf(cr[t], in2[o + t], s);
             u[o] = s;
         }
+        }   // separable passes
         // ---- mode 3: output channel j receives B[k, j] * U (|j - k| <= rB)
 #pragma unroll
         for (int jj = 0; jj < JT; ++jj) {
@@ -203,13 +238,13 @@ constexpr int phi_smem_floats() {
            (PHI_T1 + PHI_T2) * (((2 * R + 1) + 3) / 4 * 4) + (JT + 2 * RMAX_B) * JT;
 }
 
-template <int R, bool BF16IN, int JT>
+template <int R, bool BF16IN, int JT, bool ST>
 __global__ void __launch_bounds__(256) k_phi_single(PhiArgs a) {
     __shared__ float smem[phi_smem_floats<R, JT>()];
-    phi_tile<R, BF16IN, JT>(a, xcd_remap(blockIdx.x, gridDim.x), smem);
+    phi_tile<R, BF16IN, JT, ST>(a, xcd_remap(blockIdx.x, gridDim.x), smem);
 }
 
-template <int R, bool BF16IN, int JT>
+template <int R, bool BF16IN, int JT, bool ST>
 __global__ void __launch_bounds__(256) k_phi_batched(const Desc* __restrict__ descs,
                                                      const int* __restrict__ starts, int count,
                                                      int src_sel, int src_index) {
@@ -221,6 +256,7 @@ __global__ void __launch_bounds__(256) k_phi_batched(const Desc* __restrict__ de
     PhiArgs a;
     a.I1 = d.I1; a.I2 = d.I2; a.J = d.J; a.r1 = d.r1; a.r2 = d.r2; a.rB = d.rB;
     a.a1 = d.a1; a.a2 = d.a2; a.bb = d.bb;
+    a.st = d.st;
     if (src_sel == PS_BASIS) {
         const size_t es = d.bf16 ? 2 : 4;
         a.src = (const char*)d.V + (size_t)src_index * d.n * es;
@@ -231,7 +267,7 @@ __global__ void __launch_bounds__(256) k_phi_batched(const Desc* __restrict__ de
         a.C = d.C;
     }
     a.dst = d.W;
-    phi_tile<R, BF16IN, JT>(a, b - starts[p], smem);
+    phi_tile<R, BF16IN, JT, ST>(a, b - starts[p], smem);
 }
 
 static int phi_tier(int r) { return r <= 4 ? 4 : (r <= 8 ? 8 : 12); }
@@ -243,34 +279,38 @@ int phi_tiles(int I1, int I2, int J, int jt) {
 }
 
 hipError_t launch_phi_single(int I1, int I2, int J, int r1, int r2, int rB, const float* a1,
-                             const float* a2, const float* bb, const void* src, int bf16_in,
+                             const float* a2, const float* bb, const float* st, const void* src, int bf16_in,
                              const float* C, float* dst, hipStream_t s) {
-    PhiArgs a{I1, I2, J, r1, r2, rB, a1, a2, bb, src, C, dst};
+    PhiArgs a{I1, I2, J, r1, r2, rB, a1, a2, bb, src, C, dst, st};
     const int jt = phi_jt(J);
     const int tiles = phi_tiles(I1, I2, J, jt);
     const int tier = phi_tier(r1 > r2 ? r1 : r2);
-#define RTG_PHI_SINGLE(RR, JJ)                                                                      \
-    if (bf16_in) hipLaunchKernelGGL((k_phi_single<RR, true, JJ>), dim3(tiles), dim3(256), 0, s, a); \
-    else hipLaunchKernelGGL((k_phi_single<RR, false, JJ>), dim3(tiles), dim3(256), 0, s, a);
+#define RTG_PHI_SINGLE_S(RR, JJ, SS)                                                                    \
+    if (bf16_in) hipLaunchKernelGGL((k_phi_single<RR, true, JJ, SS>), dim3(tiles), dim3(256), 0, s, a); \
+    else hipLaunchKernelGGL((k_phi_single<RR, false, JJ, SS>), dim3(tiles), dim3(256), 0, s, a);
+#define RTG_PHI_SINGLE(RR, JJ) if (st) { RTG_PHI_SINGLE_S(RR, JJ, true) } else { RTG_PHI_SINGLE_S(RR, JJ, false) }
 #define RTG_PHI_SINGLE_J(RR) if (jt == 4) { RTG_PHI_SINGLE(RR, 4) } else { RTG_PHI_SINGLE(RR, 8) }
     if (tier == 4) { RTG_PHI_SINGLE_J(4) } else if (tier == 8) { RTG_PHI_SINGLE_J(8) } else { RTG_PHI_SINGLE_J(12) }
 #undef RTG_PHI_SINGLE_J
 #undef RTG_PHI_SINGLE
+#undef RTG_PHI_SINGLE_S
     return hipGetLastError();
 }
 
 hipError_t launch_phi(const Desc* d, const int* starts, int count, int total_tiles, int src_sel,
-                      int src_index, int rmax, int jt, int bf16_in, hipStream_t s) {
+                      int src_index, int rmax, int jt, int bf16_in, hipStream_t s, int stencil) {
     const int tier = phi_tier(rmax);
-#define RTG_PHI_BATCH(RR, JJ)                                                                   \
-    if (bf16_in) hipLaunchKernelGGL((k_phi_batched<RR, true, JJ>), dim3(total_tiles), dim3(256), 0, s, \
-                                    d, starts, count, src_sel, src_index);                     \
-    else hipLaunchKernelGGL((k_phi_batched<RR, false, JJ>), dim3(total_tiles), dim3(256), 0, s, \
+#define RTG_PHI_BATCH_S(RR, JJ, SS)                                                                    \
+    if (bf16_in) hipLaunchKernelGGL((k_phi_batched<RR, true, JJ, SS>), dim3(total_tiles), dim3(256), 0, s, \
+                                    d, starts, count, src_sel, src_index);                             \
+    else hipLaunchKernelGGL((k_phi_batched<RR, false, JJ, SS>), dim3(total_tiles), dim3(256), 0, s,     \
                             d, starts, count, src_sel, src_index);
+#define RTG_PHI_BATCH(RR, JJ) if (stencil) { RTG_PHI_BATCH_S(RR, JJ, true) } else { RTG_PHI_BATCH_S(RR, JJ, false) }
 #define RTG_PHI_BATCH_J(RR) if (jt == 4) { RTG_PHI_BATCH(RR, 4) } else { RTG_PHI_BATCH(RR, 8) }
     if (tier == 4) { RTG_PHI_BATCH_J(4) } else if (tier == 8) { RTG_PHI_BATCH_J(8) } else { RTG_PHI_BATCH_J(12) }
 #undef RTG_PHI_BATCH_J
 #undef RTG_PHI_BATCH
+#undef RTG_PHI_BATCH_S
     return hipGetLastError();
 }
 

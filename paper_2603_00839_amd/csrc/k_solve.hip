@@ -330,6 +330,7 @@ __global__ void k_init(const Desc* __restrict__ descs) {
 __global__ void k_compose(const Desc* __restrict__ descs, int nbc) {
     const int p = blockIdx.x / nbc, part = blockIdx.x % nbc;
     const Desc& d = descs[p];
+    if (d.st != nullptr) return;          // a general PSF: no banded factors to compose
     const int I1 = d.I1, I2 = d.I2, J = d.J, l1 = d.l1, l2 = d.l2, l3 = d.l3;
     const int r1 = d.r1, r2 = d.r2, rB = d.rB;
     const int wB = 2 * rB + 1;

@@ -91,7 +91,7 @@ __global__ void __launch_bounds__(256) k_tile(const Desc* __restrict__ descs,
     const Desc& d = descs[p];
     const int tile = b - starts[p];
     const bool newv = (mode == TM_NEWV || mode == TM_GKNEW);
-    if (newv && d.state[ST_ACTIVE] == 0) return;
+    if ((newv || mode == TM_SKETCH_W) && d.state[ST_ACTIVE] == 0) return;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -113,11 +113,12 @@ __global__ void __launch_bounds__(256) k_tile(const Desc* __restrict__ descs,
     const int first = (mode == TM_GKNEW) ? t0 : 0;   // terms [first, nterms)
     const bool do_store = (newv || mode == TM_ASSEMBLE);
     const bool do_sketch = (mode != TM_ASSEMBLE) && !d.unsketched;   // an identity sketch keeps no partials
-    const bool dual = newv;
+    const bool dual = newv && d.st == nullptr;   // a general PSF has no composed sketch matrices
     const bool src_is_bf = BB && !SPLIT && (mode == TM_SKETCH_SRC);
 
     const void* src;
     if (mode == TM_SKETCH_SRC) src = d.R0src;
+    else if (mode == TM_SKETCH_W) src = d.W;
     else if (mode == TM_NEWV) src = (nterms == 0) ? d.R0src : (const void*)d.W;
     else if (mode == TM_GKNEW) src = d.W;
     else src = d.X0;     // may be null: zero
@@ -387,7 +388,7 @@ hipError_t launch_tile(const Desc* d, const int* starts, int count, int total_ti
     const int rtiles = ((l1max + 15) / 16) * ((mode == TM_NEWV || mode == TM_GKNEW) ? 2 : 1);
     const bool small = rtiles <= 8;
     if (basis_bf16) {
-        const bool split = mode == TM_SKETCH_SRC && !src_bf16;
+        const bool split = (mode == TM_SKETCH_SRC || mode == TM_SKETCH_W) && !src_bf16;
         if (split) { if (small) RTG_TILE(true, true, 2); else RTG_TILE(true, true, 4); }
         else { if (small) RTG_TILE(true, false, 2); else RTG_TILE(true, false, 4); }
     } else {

@@ -38,6 +38,8 @@ struct rtg_op_s {
     int toeplitz;   // A1 and A2 are Toeplitz on their in-range entries (convolutions with zero BC)
     float* taps;    // their taps: taps[r1 + dd] = A1[i, i + dd], then RMAX_SPATIAL * 2 + 1 on, A2's
     rtg_op_s* adj;  // the adjoint Phi^T(X) = X x_1 A1^T x_2 A2^T x_3 B (transposed bands), for Golub-Kahan
+    float* st;      // general PSF (rtg_setup_operator_psf): stencil st[(a + r) (2r + 1) + b + r], the weight of
+                    // X[i1 + a, i2 + b] (the PSF rotated by 180 degrees); r1 = r2 = r, no bands
 };
 
 struct rtg_sk_s {
@@ -193,6 +195,7 @@ void fill_desc(Desc& d, const rtg_op_s* op, const rtg_sk_s* sk, int m, int bf16,
     for (int k = 0; k < 3; ++k) d.a1p[k] = op->a1p[k];
     d.toeplitz = op->toeplitz;
     d.taps = op->taps;
+    d.st = op->st;
     d.unsketched = sk->identity;
     d.om1 = sk->om1; d.om1h = sk->om1h; d.om2 = sk->om2; d.om3 = sk->om3;
     d.om1f = sk->om1f; d.om1hf = sk->om1hf;
@@ -251,6 +254,7 @@ struct Plan {
     bool step_ok;      // the fused step kernel applies (32-bit byte offsets into a basis vector)
     int toeplitz;      // every problem's bands are Toeplitz
     int unsketched;    // every problem's sketch is the identity (a batch is all one or all the other)
+    int stencil;       // every problem's operator is a general PSF (all or none)
 };
 
 // descs holds nsides groups of count problems (the same shapes in each group)
@@ -277,8 +281,10 @@ int build_plan(std::vector<Desc>& descs, void* ws, hipStream_t s, Plan& plan, in
     plan.step_ok = true;
     plan.toeplitz = 1;
     plan.unsketched = descs.empty() ? 0 : descs[0].unsketched;
+    plan.stencil = (!descs.empty() && descs[0].st) ? 1 : 0;
     for (auto& d : descs) {
         if (d.unsketched != plan.unsketched) return RTG_E_ARG;
+        if ((d.st != nullptr) != (plan.stencil != 0)) return RTG_E_ARG;
         if (d.unsketched && d.n * 4 > 0x7FFFFFFFll) return RTG_E_SHAPE;
         plan.toeplitz = plan.toeplitz && d.toeplitz;
         plan.step_ok = plan.step_ok && d.n * 2 <= 0x7FFFFFFFll &&
@@ -361,13 +367,42 @@ int run_solver(const Plan& plan, int count, int mmax, int bf16, bool any_x0, boo
         // Frobenius products of the full tensors, and the tile kernel forms
         // V_{j+1} without sketching.
         const int us = 1;
-        if (any_x0) RTG_TIMED(0, launch_phi(plan.d_desc, sp, count, plan.total[KIND_PHI], PS_X0, 0, plan.rmax, plan.phi_jt, 0, s));
+        if (any_x0)
+            RTG_TIMED(0, launch_phi(plan.d_desc, sp, count, plan.total[KIND_PHI], PS_X0, 0, plan.rmax, plan.phi_jt, 0,
+                                    s, plan.stencil));
         RTG_TIMED(2, launch_gram(plan.d_desc, sg, count, plan.total[KIND_GRAM], GM_START, 0, nullptr, s, us));
         RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_NEWV, 0, 0, bf16, 0, plan.l1max, s));
         for (int j = 1; j <= mmax; ++j) {
             RTG_TIMED(0, launch_phi(plan.d_desc, sp, count, plan.total[KIND_PHI], PS_BASIS, j - 1, plan.rmax,
-                                    plan.phi_jt, bf16, s));
+                                    plan.phi_jt, bf16, s, plan.stencil));
             RTG_TIMED(2, launch_gram(plan.d_desc, sg, count, plan.total[KIND_GRAM], GM_STEP, j, nullptr, s, us));
+            if (j < mmax || last_newv)
+                RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_NEWV, j, j, bf16, 0,
+                                         plan.l1max, s));
+        }
+        if (solve) {
+            RTG_TIMED(3, launch_solve(plan.d_desc, count, mmax, s));
+            RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_ASSEMBLE, 0, 0, bf16, 0,
+                                     plan.l1max, s));
+        }
+        return RTG_OK;
+    }
+    if (plan.stencil) {
+        // General PSF: no composed sketch matrices.  Step j forms W = Phi(V_j),
+        // sketches W, then the Gram step and V_{j+1} with its sketch.
+        if (any_x0)
+            RTG_TIMED(0, launch_phi(plan.d_desc, sp, count, plan.total[KIND_PHI], PS_X0, 0, plan.rmax, plan.phi_jt, 0,
+                                    s, 1));
+        RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_SKETCH_SRC, 0, 0, bf16, 0,
+                                 plan.l1max, s));
+        RTG_TIMED(2, launch_gram(plan.d_desc, sg, count, plan.total[KIND_GRAM], GM_START, 0, nullptr, s));
+        RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_NEWV, 0, 0, bf16, 0, plan.l1max, s));
+        for (int j = 1; j <= mmax; ++j) {
+            RTG_TIMED(0, launch_phi(plan.d_desc, sp, count, plan.total[KIND_PHI], PS_BASIS, j - 1, plan.rmax,
+                                    plan.phi_jt, bf16, s, 1));
+            RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_SKETCH_W, 0, 0, bf16, 0,
+                                     plan.l1max, s));
+            RTG_TIMED(2, launch_gram(plan.d_desc, sg, count, plan.total[KIND_GRAM], GM_STEP, j, nullptr, s));
             if (j < mmax || last_newv)
                 RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_NEWV, j, j, bf16, 0,
                                          plan.l1max, s));
@@ -595,9 +630,38 @@ int rtg_setup_operator(int I1, int I2, int J, const float* a1_band, int r1, cons
     return RTG_OK;
 }
 
+int rtg_setup_operator_psf(int I1, int I2, int J, const float* psf, int r, const float* b_band, int rB,
+                           rtg_op* out) {
+    if (!out || !psf || !b_band) return RTG_E_ARG;
+    *out = nullptr;
+    if (I1 < 8 || I2 < 1 || J < 1 || (I1 % 8) != 0) return RTG_E_SHAPE;
+    if (r < 0 || rB < 0 || r > RMAX_SPATIAL || rB > RMAX_B) return RTG_E_SHAPE;
+    if (r >= I1 || (r >= I2 && I2 > 1) || (rB >= J && J > 1)) return RTG_E_SHAPE;
+    rtg_op_s* op = new rtg_op_s{I1, I2, J, r, r, rB, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                {nullptr, nullptr, nullptr}, 0, nullptr, nullptr, nullptr};
+    // the weight of X[i1 + a, i2 + b] is P[r - a][r - b] (eq. (57))
+    const int w = 2 * r + 1;
+    std::vector<float> st((size_t)w * w);
+    for (int a = -r; a <= r; ++a)
+        for (int b = -r; b <= r; ++b) st[(size_t)(a + r) * w + b + r] = psf[(size_t)(r - a) * w + r - b];
+    const size_t nb = (size_t)J * (2 * rB + 1);
+    if (hipMalloc(&op->st, st.size() * 4) != hipSuccess || hipMalloc(&op->bb, nb * 4) != hipSuccess) {
+        rtg_destroy_operator(op);
+        return RTG_E_NOMEM;
+    }
+    if (hipMemcpy(op->st, st.data(), st.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(op->bb, b_band, nb * 4, hipMemcpyHostToDevice) != hipSuccess) {
+        rtg_destroy_operator(op);
+        return RTG_E_HIP;
+    }
+    *out = op;
+    return RTG_OK;
+}
+
 int rtg_destroy_operator(rtg_op op) {
     if (!op) return RTG_OK;
     if (op->adj) rtg_destroy_operator(op->adj);
+    if (op->st) (void)hipFree(op->st);
     if (op->a1) (void)hipFree(op->a1);
     if (op->a2) (void)hipFree(op->a2);
     if (op->bb) (void)hipFree(op->bb);
@@ -613,7 +677,7 @@ int rtg_destroy_operator(rtg_op op) {
 int rtg_apply_operator(rtg_op op, int x_dtype, const void* X, const float* C, float* Y, void* stream) {
     if (!op || !X || !Y) return RTG_E_ARG;
     if (x_dtype != RTG_F32 && x_dtype != RTG_BF16) return RTG_E_ARG;
-    if (launch_phi_single(op->I1, op->I2, op->J, op->r1, op->r2, op->rB, op->a1, op->a2, op->bb, X,
+    if (launch_phi_single(op->I1, op->I2, op->J, op->r1, op->r2, op->rB, op->a1, op->a2, op->bb, op->st, X,
                           x_dtype == RTG_BF16, C, Y, (hipStream_t)stream) != hipSuccess)
         return RTG_E_HIP;
     return RTG_OK;

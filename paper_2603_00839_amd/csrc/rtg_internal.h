@@ -64,6 +64,9 @@ struct Desc {
     const float* a2t;
     const float* a1p[3];          // A1 band rows zero-padded to the tiers R = 4, 8, 12 (row stride 2R+1 rounded up to 4)
     const float* taps;            // toeplitz: A1 taps at [r1 + dd], A2 taps at [2 RMAX_SPATIAL + 1 + r2 + dd]
+    const float* st;              // general PSF: stencil [a + r1][b + r1] (weight of X[i1 + a, i2 + b]),
+                                  // r1 = r2; the bands are then absent and the sketch of W = Phi(V) is
+                                  // taken from W itself (no composed matrices)
     const float* om1;
     const bf16_t* om1h;           // bfloat16 copy of Om1
     const float* om1f;            // Om1 in operand order, FRAG_K_F32
@@ -250,9 +253,10 @@ namespace rtg {
 int phi_jt(int max_j);
 int phi_tiles(int I1, int I2, int J, int jt);
 hipError_t launch_phi(const Desc* d, const int* starts, int count, int total_tiles,
-                      int src_sel, int src_index, int rmax, int jt, int bf16_in, hipStream_t s);
+                      int src_sel, int src_index, int rmax, int jt, int bf16_in, hipStream_t s,
+                      int stencil = 0);
 hipError_t launch_phi_single(int I1, int I2, int J, int r1, int r2, int rB, const float* a1,
-                             const float* a2, const float* bb, const void* src, int bf16_in,
+                             const float* a2, const float* bb, const float* st, const void* src, int bf16_in,
                              const float* C, float* dst, hipStream_t s);
 hipError_t launch_tile(const Desc* d, const int* starts, int count, int total_tiles,
                        int mode, int nterms, int dst_index, int basis_bf16, int src_bf16,
@@ -270,7 +274,9 @@ hipError_t launch_finish_arnoldi(const Desc* d, double* H, double* beta, int* m_
 // k_tile modes
 // (TM_GKNEW: a new Golub-Kahan basis tensor from W and the terms
 // [first_term, nterms) of this side's basis)
-enum TileMode { TM_NEWV = 1, TM_ASSEMBLE = 2, TM_SKETCH_SRC = 3, TM_GKNEW = 4 };
+// (TM_SKETCH_W: the sketch of the stored W, for operators without composed
+// sketch matrices)
+enum TileMode { TM_NEWV = 1, TM_ASSEMBLE = 2, TM_SKETCH_SRC = 3, TM_GKNEW = 4, TM_SKETCH_W = 5 };
 // k_phi source selection
 enum PhiSrc { PS_BASIS = 0, PS_X0 = 1 };
 // k_gram modes

@@ -6,7 +6,7 @@ device layout of the library: a C-contiguous torch tensor of shape
 (J, I2, I1), i.e. column-major X[i1, i2, j] with i1 fastest.
 
 The functions keep the names of the C entry points without the ``rtg_``
-prefix: setup_operator, apply_operator, setup_sketch, sketch,
+prefix: setup_operator, setup_operator_psf, apply_operator, setup_sketch, sketch,
 workspace_bytes, gk_workspace_bytes, arnoldi, golub_kahan, workspace_layout,
 gk_workspace_layout, solve, solve_batched.
 """
@@ -71,6 +71,7 @@ def load_library():
         "rtg_sketch": (c_int, [c_vp, c_int, c_vp, c_vp, c_vp, c_sz, c_vp]),
         "rtg_destroy_sketch": (c_int, [c_vp]),
         "rtg_workspace_bytes": (c_sz, [c_vp, c_vp, c_int, c_int]),
+        "rtg_setup_operator_psf": (c_int, [c_int, c_int, c_int, c_vp, c_int, c_vp, c_int, c_vp]),
         "rtg_gk_workspace_bytes": (c_sz, [c_vp, c_vp, c_int, c_int]),
         "rtg_arnoldi": (c_int, [c_vp, c_vp, c_vp, c_int, c_int, c_d, c_vp, c_sz, c_vp, c_vp, c_vp, c_vp]),
         "rtg_workspace_layout": (c_int, [c_vp, c_vp, c_int, c_int, ctypes.POINTER(c_sz), ctypes.POINTER(c_sz)]),
@@ -186,6 +187,29 @@ class Operator:
 
 def setup_operator(I1, I2, J, a1_band, a2_band, b_band) -> Operator:
     return Operator(I1, I2, J, a1_band, a2_band, b_band)
+
+
+class PSFOperator(Operator):
+    """Handle of rtg_setup_operator_psf: a general (2r+1) x (2r+1) PSF
+    (float32 host array, row index along i1) and the band of B."""
+
+    def __init__(self, I1, I2, J, psf, b_band):
+        self.shape = (int(I1), int(I2), int(J))
+        P = np.ascontiguousarray(psf, dtype=np.float32)
+        bb = np.ascontiguousarray(b_band, dtype=np.float32)
+        if P.ndim != 2 or P.shape[0] != P.shape[1] or P.shape[0] % 2 != 1:
+            raise RTGError("psf must be (2r+1) x (2r+1)")
+        r = (P.shape[0] - 1) // 2
+        self.r1 = self.r2 = r
+        self.rB = (bb.shape[1] - 1) // 2
+        h = ctypes.c_void_p()
+        _check(lib().rtg_setup_operator_psf(I1, I2, J, _fptr(P), r, _fptr(bb), self.rB, ctypes.byref(h)),
+               "rtg_setup_operator_psf")
+        self.handle = h
+
+
+def setup_operator_psf(I1, I2, J, psf, b_band) -> PSFOperator:
+    return PSFOperator(I1, I2, J, psf, b_band)
 
 
 def destroy_operator(op: Operator):
