@@ -58,3 +58,41 @@ def rtg_gmres(phi, sketch, C, m, X0=None, mu: Optional[float] = None,
 
 def true_residual(phi, C, X) -> float:
     return fro_norm(np.asarray(C, np.float64) - phi(X))
+
+
+@dataclasses.dataclass
+class RestartResult:
+    X: np.ndarray
+    iters: int               # Arnoldi steps over all cycles
+    cycles: int              # cycles that took at least one step
+    flags: int
+    last: SolveResult
+
+
+FLAG_NOT_CONVERGED = 16
+
+
+def rtg_gmres_restarted(phi, sketch, C, m, restarts, stop_res, X0=None, mu: Optional[float] = None,
+                        delta: Optional[float] = None, eta: float = 1.01, bd_tol: float = 1e-12,
+                        mu_rule: str = "discrepancy") -> RestartResult:
+    """Restarted RTG-GMRES(m): the algorithm of Sec. 4.4 ends a solve by
+    testing the sketched norm of the true residual, ||C - Phi(X_m)||_Theta <
+    eps; while that test fails, another solve starts from X_0 = X_m, at most
+    ``restarts`` times.  Each solve stops early when its projected
+    least-squares residual reaches eps (``stop_res``); NOT_CONVERGED is set
+    when the last solve ran all m steps without reaching it."""
+    C = np.asarray(C, dtype=np.float64)
+    X = np.zeros_like(C) if X0 is None else np.asarray(X0, dtype=np.float64)
+    iters, cycles, flags, last = 0, 0, 0, None
+    for cycle in range(restarts + 1):
+        if cycle > 0 and sketch.norm(C - phi(X)) < stop_res:
+            break
+        last = rtg_gmres(phi, sketch, C, m, X0=X, mu=mu, delta=delta, eta=eta, bd_tol=bd_tol,
+                         stop_res=stop_res, mu_rule=mu_rule)
+        X = last.X
+        iters += last.m_eff
+        cycles += 1
+        reached = (last.m_eff < m or bool(last.flags & 1)
+                   or (last.arnoldi.ls_res.size > 0 and last.arnoldi.ls_res[-1] <= stop_res))
+        flags = (last.flags & ~FLAG_NOT_CONVERGED) | (0 if reached else FLAG_NOT_CONVERGED)
+    return RestartResult(X, iters, cycles, flags, last)

@@ -235,3 +235,14 @@ def test_unrotated_psf_adjoint_is_caught(monkeypatch):
         return opm.convolve_psf_zero_bc(mode_product(np.asarray(Y, np.float64), self.B, 2), self.P)
     monkeypatch.setattr(opm.PSFOperator, "transpose_apply", bad_t)
     expect_failure(psfpins.test_psf_adjoint)
+
+
+def test_restart_from_the_old_start_is_caught(monkeypatch):
+    """Restarting every cycle from the first X0 instead of X_m never
+    converges: the dense-solution pin fails."""
+    good = gm.rtg_gmres
+
+    def stuck(phi, sketch, C, m, X0=None, **kw):
+        return good(phi, sketch, C, m, X0=None, **kw)
+    monkeypatch.setattr(gm, "rtg_gmres", stuck)
+    expect_failure(pins.test_restarted_gmres_converges_to_the_dense_solution)

@@ -467,3 +467,53 @@ def test_metrics_closed_forms():
     np.testing.assert_allclose(psnr_paper(xt, xt + e), 10 * np.log10(c / 0.01), rtol=1e-12)
     mse = np.mean(e ** 2)
     np.testing.assert_allclose(psnr_peak(xt, xt + e, peak=1.0), -10 * np.log10(mse), rtol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# restarted RTG-GMRES (the residual test that ends the algorithm of Sec. 4.4)
+# --------------------------------------------------------------------------
+from oracle.gmres import rtg_gmres_restarted
+
+
+def _well_conditioned_problem(seed):
+    """A diagonally dominant (so GMRES(m) converges when restarted),
+    non-symmetric operator on a small image."""
+    p = synth.small_problem(seed, 8, 6, 2, 2, 1, 1, 8, 6, 2, m=4, random_bands=True)
+    a1 = p.a1_band.astype(np.float64).copy()
+    a1[:, 2] += 4.0
+    a2 = p.a2_band.astype(np.float64).copy()
+    a2[:, 1] += 2.0
+    bb = p.b_band.astype(np.float64).copy()
+    bb[:, 1] += 2.0
+    return p, Operator(a1, a2, bb)
+
+
+def test_restarted_gmres_converges_to_the_dense_solution():
+    p, op = _well_conditioned_problem(21)
+    A = op.dense()
+    c = ta.vec(p.x_true) + 0.1
+    x_exact = np.linalg.solve(A, c)
+    eps = 1e-11 * np.linalg.norm(c)
+    res = rtg_gmres_restarted(op, identity_sketch(), c.reshape(p.dims, order="F"), 4, 60, eps, mu=0.0)
+    assert rel(ta.vec(res.X), x_exact) < 1e-8
+    assert res.flags == 0 and res.cycles > 1
+    # a cycle count that stops short leaves the residual above eps and flags it
+    short = rtg_gmres_restarted(op, identity_sketch(), c.reshape(p.dims, order="F"), 4, 1, eps, mu=0.0)
+    assert short.cycles == 2 and short.iters == 8 and short.flags == 16
+    assert np.linalg.norm(c - A @ ta.vec(short.X)) > eps
+
+
+def test_restarted_gmres_residuals_decrease_and_zero_restarts_is_plain():
+    p, op = _well_conditioned_problem(22)
+    A = op.dense()
+    c = ta.vec(p.x_true)
+    C = c.reshape(p.dims, order="F")
+    r_prev = np.linalg.norm(c)
+    for k in range(4):
+        res = rtg_gmres_restarted(op, identity_sketch(), C, 3, k, 1e-300, mu=0.0)
+        r = np.linalg.norm(c - A @ ta.vec(res.X))
+        assert r < r_prev
+        r_prev = r
+    plain = rtg_gmres(op, identity_sketch(), C, 3, mu=0.0)
+    zero = rtg_gmres_restarted(op, identity_sketch(), C, 3, 0, 1e-300, mu=0.0)
+    np.testing.assert_array_equal(zero.X, plain.X)
