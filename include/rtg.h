@@ -88,6 +88,11 @@ typedef struct {
                          (Sec. 4.5), m columns of the lower bidiagonal matrix
                          in place of the Hessenberg matrix, the same projected
                          Tikhonov problem and mu rules                        */
+    int restarts;     /* restarted RTG-GMRES: while ||C - Phi(X)||_Theta >= eps
+                         (eps = stop_res > 0, required) after a solve, start
+                         another from X0 = X, at most `restarts` times (0 =
+                         none; RTG-GMRES only).  rtg_info then reports the
+                         last solve, with iters summed over all of them      */
 } rtg_params;
 
 enum { RTG_MU_DISCREPANCY = 0, RTG_MU_GCV = 1 };
@@ -159,7 +164,8 @@ int rtg_sketch(rtg_sk sk, int x_dtype, const void* X, float* SX,
 int rtg_destroy_sketch(rtg_sk sk);
 
 /* ---- Arnoldi and solve ----------------------------------------------------- */
-/* Workspace of one problem with at most m steps and the given basis type. */
+/* Workspace of one problem with at most m steps and the given basis type
+ * (RTG-GMRES, also with restarts). */
 size_t rtg_workspace_bytes(rtg_op op, rtg_sk sk, int m, int basis_dtype);
 
 /* m steps of the sketched global Arnoldi process from R0 (Sec. 4.3):

@@ -459,6 +459,13 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
         if (tid == 0) {
             st[ST_COUNTER] = 0;
             const double beta = sqrt(ds[0]);
+            // a restart cycle (j > 0) starts only while ||R0||_Theta >= eps
+            // (the residual test that ends the algorithm of Sec. 4.4)
+            if (j > 0 && (st[ST_SKIP] != 0 || (d.stop_res > 0.0 && beta < d.stop_res))) {
+                st[ST_SKIP] = 1;
+                st[ST_ACTIVE] = 0;
+                return;
+            }
             sc[SC_BETA] = beta;
             gvec[0] = beta;
             if (!(beta > 0.0) || !isfinite(beta)) {

@@ -61,11 +61,13 @@ __global__ void __launch_bounds__(1024) k_solve(const Desc* __restrict__ descs) 
     const double beta = d.scal[SC_BETA];
     const double* gvec = d.gv + 2 * m;
 
+    if (d.state[ST_SKIP]) return;         // a restart cycle this problem sits out
+    const int done = d.state[ST_ITERS];   // steps of earlier restart cycles
     if (k == 0) {
         if (tid == 0) {
             d.coef[MMAX + 1] = 1.f;
             rtg_info inf;
-            inf.iters = 0;
+            inf.iters = done;
             inf.flags = d.state[ST_FLAGS];
             inf.mu = 0.0;
             inf.beta = beta;
@@ -298,8 +300,9 @@ __global__ void __launch_bounds__(1024) k_solve(const Desc* __restrict__ descs) 
             d.coef[MMAX + 1] = 1.f;
             d.scal[SC_MU] = mu;
             d.scal[SC_RESPROJ] = sqrt(rp2);
+            d.state[ST_ITERS] = done + k;
             rtg_info inf;
-            inf.iters = k;
+            inf.iters = done + k;
             inf.flags = flags;
             inf.mu = mu;
             inf.beta = beta;
@@ -310,10 +313,35 @@ __global__ void __launch_bounds__(1024) k_solve(const Desc* __restrict__ descs) 
     }
 }
 
-__global__ void k_init(const Desc* __restrict__ descs) {
+// cycle 0: a fresh solve.  cycle c > 0 (restarted RTG-GMRES): a new cycle
+// from X0 = X; a problem out of restarts, or one that sat out an earlier
+// cycle (its residual was below eps), sits this one out too; the others
+// keep their step count and flags (but for NOT_CONVERGED, which the cycle
+// decides anew).
+__global__ void k_init(const Desc* __restrict__ descs, int cycle) {
     const Desc& d = descs[blockIdx.x];
     const int tid = threadIdx.x;
-    if (tid < NSTATE) d.state[tid] = (tid == ST_ACTIVE) ? 1 : 0;
+    if (cycle > 0) {
+        const bool sit_out = cycle > d.restarts || d.state[ST_SKIP] != 0;
+        __syncthreads();                      // every thread has read the state
+        if (sit_out) {
+            if (tid == 0) {
+                d.state[ST_SKIP] = 1;
+                d.state[ST_ACTIVE] = 0;
+            }
+            return;
+        }
+        if (tid < NSTATE) {
+            const int v = d.state[tid];
+            int nv = 0;
+            if (tid == ST_ACTIVE) nv = 1;
+            else if (tid == ST_ITERS) nv = v;
+            else if (tid == ST_FLAGS) nv = v & ~RTG_F_NOT_CONVERGED;
+            d.state[tid] = nv;
+        }
+    } else if (tid < NSTATE) {
+        d.state[tid] = (tid == ST_ACTIVE) ? 1 : 0;
+    }
     if (tid < NSCAL) d.scal[tid] = 0.0;
     const int m = d.m;
     for (int e = tid; e < (m + 1) * m; e += blockDim.x) d.H[e] = 0.0;
@@ -408,8 +436,8 @@ hipError_t launch_solve(const Desc* d, int count, int mmax, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_init(const Desc* d, int count, hipStream_t s) {
-    hipLaunchKernelGGL(k_init, dim3(count), dim3(256), 0, s, d);
+hipError_t launch_init(const Desc* d, int count, hipStream_t s, int cycle) {
+    hipLaunchKernelGGL(k_init, dim3(count), dim3(256), 0, s, d, cycle);
     return hipGetLastError();
 }
 

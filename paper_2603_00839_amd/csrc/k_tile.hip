@@ -92,6 +92,7 @@ __global__ void __launch_bounds__(256) k_tile(const Desc* __restrict__ descs,
     const int tile = b - starts[p];
     const bool newv = (mode == TM_NEWV || mode == TM_GKNEW);
     if ((newv || mode == TM_SKETCH_W) && d.state[ST_ACTIVE] == 0) return;
+    if (mode == TM_ASSEMBLE && d.state[ST_SKIP] != 0) return;   // X stays (restart cycle sat out)
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;

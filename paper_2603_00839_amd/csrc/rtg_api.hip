@@ -157,10 +157,12 @@ size_t problem_bytes(const rtg_op_s* op, const rtg_sk_s* sk, int m, int bf16, in
     return b;
 }
 
-// descriptors (nsides per problem: Golub-Kahan has a V side and a U side)
-// and the per-kernel tile prefix tables
-size_t plan_bytes(int count, int nsides = 1) {
-    return align_up((size_t)count * nsides * sizeof(Desc)) + align_up((size_t)NKIND * (count + 1) * sizeof(int));
+// descriptors (nsides per problem: Golub-Kahan has a V side and a U side;
+// restarted solves keep a second copy for the restart cycles) and the
+// per-kernel tile prefix tables
+size_t plan_bytes(int count, int nsides = 1, bool restart = false) {
+    return align_up((size_t)count * nsides * (restart ? 2 : 1) * sizeof(Desc)) +
+           align_up((size_t)NKIND * (count + 1) * sizeof(int));
 }
 
 int check_pair(const rtg_op_s* op, const rtg_sk_s* sk) {
@@ -255,10 +257,13 @@ struct Plan {
     int toeplitz;      // every problem's bands are Toeplitz
     int unsketched;    // every problem's sketch is the identity (a batch is all one or all the other)
     int stencil;       // every problem's operator is a general PSF (all or none)
+    Desc* d_desc_r;    // restart cycles: the descriptors with X0 = X (null without restarts)
 };
 
-// descs holds nsides groups of count problems (the same shapes in each group)
-int build_plan(std::vector<Desc>& descs, void* ws, hipStream_t s, Plan& plan, int nsides = 1) {
+// descs holds nsides groups of count problems (the same shapes in each group);
+// with restart, the restart-cycle copies (X0 = X, R0 from W) follow them
+int build_plan(std::vector<Desc>& descs, void* ws, hipStream_t s, Plan& plan, int nsides = 1,
+               bool restart = false) {
     const int count = (int)descs.size() / nsides;
     std::vector<int> starts((size_t)NKIND * (count + 1), 0);
     int maxJ = 1;
@@ -295,9 +300,20 @@ int build_plan(std::vector<Desc>& descs, void* ws, hipStream_t s, Plan& plan, in
     }
     char* base = (char*)ws;
     plan.d_desc = (Desc*)base;
-    plan.d_starts = (int*)(base + align_up(descs.size() * sizeof(Desc)));
-    int rc = upload(plan.d_desc, descs.data(), descs.size() * sizeof(Desc), s);
+    plan.d_desc_r = nullptr;
+    const size_t nd = descs.size();
+    plan.d_starts = (int*)(base + align_up(nd * (restart ? 2 : 1) * sizeof(Desc)));
+    int rc = upload(plan.d_desc, descs.data(), nd * sizeof(Desc), s);
     if (rc) return rc;
+    if (restart) {
+        std::vector<Desc> rd(descs);
+        for (auto& d : rd) {
+            d.X0 = d.X;
+            d.R0src = d.W;
+        }
+        plan.d_desc_r = plan.d_desc + nd;
+        if ((rc = upload(plan.d_desc_r, rd.data(), nd * sizeof(Desc), s))) return rc;
+    }
     return upload(plan.d_starts, starts.data(), starts.size() * sizeof(int), s);
 }
 
@@ -355,12 +371,16 @@ struct TimedLaunch {
 #define RTG_TIMED(kind, call) RTG_TIMED_ON(kind, s, call)
 
 // Arnoldi loop + (optionally) solve and assembly for a prepared plan.
+// cycle > 0: a restart cycle of restarted RTG-GMRES, on the descriptor copies
+// whose X0 is the output X (R0 = C - Phi(X)).
 int run_solver(const Plan& plan, int count, int mmax, int bf16, bool any_x0, bool solve,
-               bool last_newv, hipStream_t s) {
+               bool last_newv, hipStream_t s, int cycle = 0) {
+    const Desc* dd = cycle > 0 ? plan.d_desc_r : plan.d_desc;
+    if (cycle > 0) any_x0 = true;
     const int* sp = starts_of(plan, KIND_PHI, count);
     const int* st = starts_of(plan, KIND_TILE, count);
     const int* sg = starts_of(plan, KIND_GRAM, count);
-    RTG_HIP(launch_init(plan.d_desc, count, s));
+    RTG_HIP(launch_init(dd, count, s, cycle));
     if (plan.unsketched) {
         // Identity sketch (unsketched global GMRES, the Omega = I form of the
         // method): W = Phi(V_j) is formed first, the Gram kernel takes the
@@ -368,21 +388,21 @@ int run_solver(const Plan& plan, int count, int mmax, int bf16, bool any_x0, boo
         // V_{j+1} without sketching.
         const int us = 1;
         if (any_x0)
-            RTG_TIMED(0, launch_phi(plan.d_desc, sp, count, plan.total[KIND_PHI], PS_X0, 0, plan.rmax, plan.phi_jt, 0,
+            RTG_TIMED(0, launch_phi(dd, sp, count, plan.total[KIND_PHI], PS_X0, 0, plan.rmax, plan.phi_jt, 0,
                                     s, plan.stencil));
-        RTG_TIMED(2, launch_gram(plan.d_desc, sg, count, plan.total[KIND_GRAM], GM_START, 0, nullptr, s, us));
-        RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_NEWV, 0, 0, bf16, 0, plan.l1max, s));
+        RTG_TIMED(2, launch_gram(dd, sg, count, plan.total[KIND_GRAM], GM_START, cycle, nullptr, s, us));
+        RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_NEWV, 0, 0, bf16, 0, plan.l1max, s));
         for (int j = 1; j <= mmax; ++j) {
-            RTG_TIMED(0, launch_phi(plan.d_desc, sp, count, plan.total[KIND_PHI], PS_BASIS, j - 1, plan.rmax,
+            RTG_TIMED(0, launch_phi(dd, sp, count, plan.total[KIND_PHI], PS_BASIS, j - 1, plan.rmax,
                                     plan.phi_jt, bf16, s, plan.stencil));
-            RTG_TIMED(2, launch_gram(plan.d_desc, sg, count, plan.total[KIND_GRAM], GM_STEP, j, nullptr, s, us));
+            RTG_TIMED(2, launch_gram(dd, sg, count, plan.total[KIND_GRAM], GM_STEP, j, nullptr, s, us));
             if (j < mmax || last_newv)
-                RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_NEWV, j, j, bf16, 0,
+                RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_NEWV, j, j, bf16, 0,
                                          plan.l1max, s));
         }
         if (solve) {
-            RTG_TIMED(3, launch_solve(plan.d_desc, count, mmax, s));
-            RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_ASSEMBLE, 0, 0, bf16, 0,
+            RTG_TIMED(3, launch_solve(dd, count, mmax, s));
+            RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_ASSEMBLE, 0, 0, bf16, 0,
                                      plan.l1max, s));
         }
         return RTG_OK;
@@ -391,34 +411,34 @@ int run_solver(const Plan& plan, int count, int mmax, int bf16, bool any_x0, boo
         // General PSF: no composed sketch matrices.  Step j forms W = Phi(V_j),
         // sketches W, then the Gram step and V_{j+1} with its sketch.
         if (any_x0)
-            RTG_TIMED(0, launch_phi(plan.d_desc, sp, count, plan.total[KIND_PHI], PS_X0, 0, plan.rmax, plan.phi_jt, 0,
+            RTG_TIMED(0, launch_phi(dd, sp, count, plan.total[KIND_PHI], PS_X0, 0, plan.rmax, plan.phi_jt, 0,
                                     s, 1));
-        RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_SKETCH_SRC, 0, 0, bf16, 0,
+        RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_SKETCH_SRC, 0, 0, bf16, 0,
                                  plan.l1max, s));
-        RTG_TIMED(2, launch_gram(plan.d_desc, sg, count, plan.total[KIND_GRAM], GM_START, 0, nullptr, s));
-        RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_NEWV, 0, 0, bf16, 0, plan.l1max, s));
+        RTG_TIMED(2, launch_gram(dd, sg, count, plan.total[KIND_GRAM], GM_START, cycle, nullptr, s));
+        RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_NEWV, 0, 0, bf16, 0, plan.l1max, s));
         for (int j = 1; j <= mmax; ++j) {
-            RTG_TIMED(0, launch_phi(plan.d_desc, sp, count, plan.total[KIND_PHI], PS_BASIS, j - 1, plan.rmax,
+            RTG_TIMED(0, launch_phi(dd, sp, count, plan.total[KIND_PHI], PS_BASIS, j - 1, plan.rmax,
                                     plan.phi_jt, bf16, s, 1));
-            RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_SKETCH_W, 0, 0, bf16, 0,
+            RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_SKETCH_W, 0, 0, bf16, 0,
                                      plan.l1max, s));
-            RTG_TIMED(2, launch_gram(plan.d_desc, sg, count, plan.total[KIND_GRAM], GM_STEP, j, nullptr, s));
+            RTG_TIMED(2, launch_gram(dd, sg, count, plan.total[KIND_GRAM], GM_STEP, j, nullptr, s));
             if (j < mmax || last_newv)
-                RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_NEWV, j, j, bf16, 0,
+                RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_NEWV, j, j, bf16, 0,
                                          plan.l1max, s));
         }
         if (solve) {
-            RTG_TIMED(3, launch_solve(plan.d_desc, count, mmax, s));
-            RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_ASSEMBLE, 0, 0, bf16, 0,
+            RTG_TIMED(3, launch_solve(dd, count, mmax, s));
+            RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_ASSEMBLE, 0, 0, bf16, 0,
                                      plan.l1max, s));
         }
         return RTG_OK;
     }
-    RTG_HIP(launch_compose(plan.d_desc, count, plan.compose_max, s));
-    if (any_x0) RTG_TIMED(0, launch_phi(plan.d_desc, sp, count, plan.total[KIND_PHI], PS_X0, 0, plan.rmax, plan.phi_jt, 0, s));
-    RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_SKETCH_SRC, 0, 0, bf16, 0, plan.l1max, s));
-    RTG_TIMED(2, launch_gram(plan.d_desc, sg, count, plan.total[KIND_GRAM], GM_START, 0, nullptr, s));
-    RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_NEWV, 0, 0, bf16, 0, plan.l1max, s));
+    if (cycle == 0) RTG_HIP(launch_compose(dd, count, plan.compose_max, s));   // restart cycles reuse them
+    if (any_x0) RTG_TIMED(0, launch_phi(dd, sp, count, plan.total[KIND_PHI], PS_X0, 0, plan.rmax, plan.phi_jt, 0, s));
+    RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_SKETCH_SRC, 0, 0, bf16, 0, plan.l1max, s));
+    RTG_TIMED(2, launch_gram(dd, sg, count, plan.total[KIND_GRAM], GM_START, cycle, nullptr, s));
+    RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_NEWV, 0, 0, bf16, 0, plan.l1max, s));
     for (int j = 1; j <= mmax; ++j) {
         // S(V_j) and S(Phi(V_j)) come from the pass that formed V_j.  With a
         // bfloat16 basis the step kernel recomputes Phi(V_j) tile by tile (W
@@ -427,22 +447,22 @@ int run_solver(const Plan& plan, int count, int mmax, int bf16, bool any_x0, boo
         // there (the fused kernel's float32 variant runs at lower occupancy).
         // The same two kernels serve a bfloat16 basis whose vectors reach
         // 2^31 bytes (the fused kernel addresses them with 32-bit offsets).
-        RTG_TIMED(2, launch_gram(plan.d_desc, sg, count, plan.total[KIND_GRAM], GM_STEP, j, nullptr, s));
+        RTG_TIMED(2, launch_gram(dd, sg, count, plan.total[KIND_GRAM], GM_STEP, j, nullptr, s));
         if (j < mmax || last_newv) {
             if (bf16 && plan.step_ok) {
-                RTG_TIMED(4, launch_step(plan.d_desc, st, count, plan.total[KIND_TILE], j, plan.rmax, bf16, plan.l1max,
+                RTG_TIMED(4, launch_step(dd, st, count, plan.total[KIND_TILE], j, plan.rmax, bf16, plan.l1max,
                                          plan.toeplitz, s));
             } else {
-                RTG_TIMED(0, launch_phi(plan.d_desc, sp, count, plan.total[KIND_PHI], PS_BASIS, j - 1, plan.rmax,
+                RTG_TIMED(0, launch_phi(dd, sp, count, plan.total[KIND_PHI], PS_BASIS, j - 1, plan.rmax,
                                         plan.phi_jt, bf16, s));
-                RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_NEWV, j, j, bf16, 0,
+                RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_NEWV, j, j, bf16, 0,
                                          plan.l1max, s));
             }
         }
     }
     if (solve) {
-        RTG_TIMED(3, launch_solve(plan.d_desc, count, mmax, s));
-        RTG_TIMED(1, launch_tile(plan.d_desc, st, count, plan.total[KIND_TILE], TM_ASSEMBLE, 0, 0, bf16, 0, plan.l1max, s));
+        RTG_TIMED(3, launch_solve(dd, count, mmax, s));
+        RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_ASSEMBLE, 0, 0, bf16, 0, plan.l1max, s));
     }
     return RTG_OK;
 }
@@ -493,6 +513,9 @@ int validate_params(const rtg_params* prm) {
     if (prm->basis_dtype != RTG_F32 && prm->basis_dtype != RTG_BF16) return RTG_E_ARG;
     if (prm->mu_rule != RTG_MU_DISCREPANCY && prm->mu_rule != RTG_MU_GCV) return RTG_E_ARG;
     if (prm->method != RTG_METHOD_GMRES && prm->method != RTG_METHOD_GOLUB_KAHAN) return RTG_E_ARG;
+    // restarts: a tolerance eps (stop_res) is what ends them; RTG-GMRES only
+    if (prm->restarts < 0 || prm->restarts > 10000) return RTG_E_ARG;
+    if (prm->restarts > 0 && (!(prm->stop_res > 0.0) || prm->method != RTG_METHOD_GMRES)) return RTG_E_ARG;
     if (prm->mu < 0.0 && prm->mu_rule == RTG_MU_DISCREPANCY && !(prm->delta >= 0.0 && prm->eta > 0.0))
         return RTG_E_ARG;
     if (!(prm->bd_tol >= 0.0)) return RTG_E_ARG;
@@ -507,6 +530,7 @@ void set_params(Desc& d, const rtg_params* prm) {
     d.eta = prm->eta;
     d.stop_res = prm->stop_res;
     d.bd_tol = prm->bd_tol;
+    d.restarts = prm->restarts;
 }
 
 }  // namespace
@@ -801,7 +825,8 @@ int rtg_sketch(rtg_sk sk, int x_dtype, const void* X, float* SX, void* ws, size_
 
 size_t rtg_workspace_bytes(rtg_op op, rtg_sk sk, int m, int basis_dtype) {
     if (check_pair(op, sk) || check_m(sk, m)) return 0;
-    return plan_bytes(1) + problem_layout(op, sk, m, basis_dtype == RTG_BF16).total;
+    // (room for the restart-cycle descriptor copy of rtg_solve with restarts)
+    return plan_bytes(1, 1, true) + problem_layout(op, sk, m, basis_dtype == RTG_BF16).total;
 }
 
 int rtg_workspace_layout(rtg_op op, rtg_sk sk, int m, int basis_dtype, size_t* v_offset, size_t* sv_offset) {
@@ -844,7 +869,9 @@ int rtg_arnoldi(rtg_op op, rtg_sk sk, const float* R0, int m, int basis_dtype, d
 size_t rtg_batch_workspace_bytes(int count, const rtg_problem* probs) {
     if (count < 1 || !probs) return 0;
     const int method = probs[0].params.method;
-    size_t total = plan_bytes(count, method == RTG_METHOD_GOLUB_KAHAN ? 2 : 1);
+    bool restart = false;
+    for (int p = 0; p < count; ++p) restart = restart || probs[p].params.restarts > 0;
+    size_t total = plan_bytes(count, method == RTG_METHOD_GOLUB_KAHAN ? 2 : 1, restart);
     for (int p = 0; p < count; ++p) {
         const rtg_problem& q = probs[p];
         if (check_pair(q.op, q.sk) || check_m(q.sk, q.params.m)) return 0;
@@ -922,8 +949,10 @@ int rtg_solve_batched(int count, const rtg_problem* probs, void* ws, size_t ws_b
     if (ws_bytes < need) return RTG_E_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     const int nsides = gk ? 2 : 1;
+    int rmax = 0;
+    for (int p = 0; p < count; ++p) rmax = std::max(rmax, probs[p].params.restarts);
     std::vector<Desc> descs((size_t)count * nsides);
-    size_t off = plan_bytes(count, nsides);
+    size_t off = plan_bytes(count, nsides, rmax > 0);
     int mmax = 0;
     bool any_x0 = false;
     for (int p = 0; p < count; ++p) {
@@ -947,10 +976,16 @@ int rtg_solve_batched(int count, const rtg_problem* probs, void* ws, size_t ws_b
         any_x0 = any_x0 || q.X0 != nullptr;
     }
     Plan plan;
-    int rc = build_plan(descs, ws, s, plan, nsides);
+    int rc = build_plan(descs, ws, s, plan, nsides, rmax > 0);
     if (rc) return rc;
     if (gk) return run_gk(plan, count, mmax, bf16, any_x0, true, s);
-    return run_solver(plan, count, mmax, bf16, any_x0, true, false, s);
+    if ((rc = run_solver(plan, count, mmax, bf16, any_x0, true, false, s))) return rc;
+    // restarted RTG-GMRES: every cycle is launched for the whole batch; a
+    // problem whose residual is below eps, or whose restarts are spent, sits
+    // the cycle out on the device (no host synchronisation)
+    for (int c = 1; c <= rmax; ++c)
+        if ((rc = run_solver(plan, count, mmax, bf16, true, true, false, s, c))) return rc;
+    return RTG_OK;
 }
 
 int rtg_event_timing_enable(int kind_mask) {

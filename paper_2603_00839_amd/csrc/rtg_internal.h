@@ -33,7 +33,9 @@ constexpr int GRAM_CH = 256;
 enum KernelKind { KIND_PHI = 0, KIND_TILE = 1, KIND_GRAM = 2, NKIND = 3 };
 
 // state[] slots (int)
-enum { ST_ACTIVE = 0, ST_MEFF = 1, ST_FLAGS = 2, ST_COUNTER = 3, NSTATE = 16 };
+// (ST_ITERS: steps of the finished restart cycles; ST_SKIP: this problem sits
+// out the current restart cycle, X and its info stay as they are)
+enum { ST_ACTIVE = 0, ST_MEFF = 1, ST_FLAGS = 2, ST_COUNTER = 3, ST_ITERS = 4, ST_SKIP = 5, NSTATE = 16 };
 // scal[] slots (double)
 enum { SC_BETA = 0, SC_MU = 1, SC_RESPROJ = 2, SC_RESLS = 3, SC_RHO = 4, NSCAL = 16 };
 
@@ -52,6 +54,7 @@ struct Desc {
     int keep_last;      // form V_{m+1} after the last step (Arnoldi-only calls)
     int toeplitz;       // A1 and A2 are Toeplitz on their in-range entries (convolutions, zero BC)
     int unsketched;     // identity sketch: Frobenius inner products of the full tensors
+    int restarts;       // restart cycles after the first (restarted RTG-GMRES), 0 = none
     int gk;             // sketched Block Golub-Kahan: 1 = the V side (operator Phi), 2 = the U side
                         // (operator Phi^T, transposed bands); 0 = RTG-GMRES
     long long n;        // I1*I2*J
@@ -266,7 +269,7 @@ hipError_t launch_step(const Desc* d, const int* starts, int count, int total_ti
 hipError_t launch_gram(const Desc* d, const int* starts, int count, int total_tiles,
                        int mode, int j, float* sketch_out, hipStream_t s, int unsketched = 0);
 hipError_t launch_solve(const Desc* d, int count, int mmax, hipStream_t s);
-hipError_t launch_init(const Desc* d, int count, hipStream_t s);
+hipError_t launch_init(const Desc* d, int count, hipStream_t s, int cycle = 0);
 hipError_t launch_compose(const Desc* d, int count, int max_entries, hipStream_t s);
 hipError_t launch_finish_arnoldi(const Desc* d, double* H, double* beta, int* m_done,
                                  int m, hipStream_t s);

@@ -34,7 +34,8 @@ class RTGError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int), ("basis_dtype", ctypes.c_int), ("mu", ctypes.c_double),
                 ("delta", ctypes.c_double), ("eta", ctypes.c_double), ("stop_res", ctypes.c_double),
-                ("bd_tol", ctypes.c_double), ("mu_rule", ctypes.c_int), ("method", ctypes.c_int)]
+                ("bd_tol", ctypes.c_double), ("mu_rule", ctypes.c_int), ("method", ctypes.c_int),
+                ("restarts", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -334,9 +335,9 @@ METHOD_GMRES, METHOD_GOLUB_KAHAN = 0, 1
 
 
 def make_params(m, basis_dtype=F32, mu=-1.0, delta=0.0, eta=1.01, stop_res=0.0, bd_tol=1e-6,
-                mu_rule=MU_DISCREPANCY, method=METHOD_GMRES) -> Params:
+                mu_rule=MU_DISCREPANCY, method=METHOD_GMRES, restarts=0) -> Params:
     return Params(int(m), int(basis_dtype), float(mu), float(delta), float(eta), float(stop_res), float(bd_tol),
-                  int(mu_rule), int(method))
+                  int(mu_rule), int(method), int(restarts))
 
 
 def gk_workspace_bytes(op: Operator, sk: Sketch, m: int, basis_dtype: int = F32) -> int:

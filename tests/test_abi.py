@@ -70,8 +70,9 @@ def test_setup_rejects_bad_shapes_before_touching_the_device(lib):
 
 
 def test_params_struct_layout_matches_header():
-    assert ctypes.sizeof(rtg.Params) == 4 + 4 + 5 * 8 + 8      # mu_rule and method
+    assert ctypes.sizeof(rtg.Params) == 4 + 4 + 5 * 8 + 16     # mu_rule, method, restarts + padding
     assert rtg.Params.mu_rule.offset == 4 + 4 + 5 * 8
     assert rtg.Params.method.offset == 4 + 4 + 5 * 8 + 4
+    assert rtg.Params.restarts.offset == 4 + 4 + 5 * 8 + 8
     assert ctypes.sizeof(rtg.Info) == 4 + 4 + 4 * 8
     assert rtg.Problem.params.offset == 5 * 8

@@ -1,0 +1,97 @@
+"""Restarted RTG-GMRES (restart from X_m while ||C - Phi(X_m)||_Theta >= eps,
+the residual test that ends the algorithm of Sec. 4.4) on the GPU against
+the float64 oracle: total steps, flags and X; a batch whose problems have
+different restart counts and step limits (one sits later cycles out, one
+runs out of restarts); the argument errors."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2603_00839_amd import synth
+from oracle.gmres import rtg_gmres_restarted
+from oracle.operator import Operator
+from oracle.sketch import Sketch
+import _util as U
+
+pytestmark = pytest.mark.gpu
+
+
+def banner(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+def dominant_problem(seed, I1, I2, J, l1, l2, m):
+    """Diagonally dominant non-symmetric bands: restarted GMRES(m) converges."""
+    p = synth.small_problem(seed, I1, I2, J, 2, 1, 1, l1, l2, J, m, random_bands=True)
+    a1 = p.a1_band.copy()
+    a1[:, 2] += 4.0
+    a2 = p.a2_band.copy()
+    a2[:, 1] += 2.0
+    bb = p.b_band.copy()
+    bb[:, 1] += 2.0
+    op_o = Operator(a1, a2, bb)
+    sk_o = Sketch(p.om1, p.om2, p.om3)
+    C = (op_o(p.x_true) + 0.01 * p.noise_dir).astype(np.float32)
+    return p, a1, a2, bb, op_o, sk_o, C
+
+
+def gpu_ops(p, a1, a2, bb):
+    from paper_2603_00839_amd import rtg
+    I1, I2, J = p.dims
+    return rtg.setup_operator(I1, I2, J, a1, a2, bb), rtg.setup_sketch(I1, I2, J, p.om1, p.om2, p.om3)
+
+
+def check(info, X, ref, tag=""):
+    print(f"{tag} iters {info.iters} ({ref.iters}) cycles ({ref.cycles}) flags {info.flags} ({ref.flags}) "
+          f"rel {U.rel(X, ref.X):.3e}", file=sys.stderr)
+    assert info.iters == ref.iters and info.flags == ref.flags
+    assert U.rel(X, ref.X) < 1e-4
+
+
+@pytest.mark.parametrize("m,restarts,frac", [(4, 8, 1e-4), (6, 3, 1e-3), (3, 20, 1e-5)])
+def test_restarted_solve_matches_oracle(m, restarts, frac):
+    from paper_2603_00839_amd import rtg
+    banner("restarted", m, restarts, frac)
+    p, a1, a2, bb, op_o, sk_o, C = dominant_problem(31, 48, 40, 3, 12, 10, m)
+    op_g, sk_g = gpu_ops(p, a1, a2, bb)
+    eps = frac * sk_o.norm(C)
+    ref = rtg_gmres_restarted(op_o, sk_o, C, m, restarts, eps, mu=0.0)
+    prm = rtg.make_params(m, rtg.F32, mu=0.0, stop_res=eps, restarts=restarts)
+    Xg, ib = rtg.solve(op_g, sk_g, U.to_dev(C), None, prm)
+    check(rtg.read_info(ib), U.from_dev(Xg), ref)
+    assert ref.cycles > 1
+
+
+def test_restarted_batch_mixed_counts():
+    import torch
+    from paper_2603_00839_amd import rtg
+    banner("restarted batch")
+    cases = [(48, 40, 3, 4, 0), (64, 24, 2, 5, 3), (40, 40, 3, 3, 12)]
+    ops, sks, Cs, prms, refs = [], [], [], [], []
+    for I1, I2, J, m, restarts in cases:
+        p, a1, a2, bb, op_o, sk_o, C = dominant_problem(60 + I1, I1, I2, J, 8, 8, m)
+        op_g, sk_g = gpu_ops(p, a1, a2, bb)
+        eps = 1e-4 * sk_o.norm(C)
+        ops.append(op_g); sks.append(sk_g); Cs.append(U.to_dev(C))
+        prms.append(rtg.make_params(m, rtg.F32, mu=0.0, stop_res=eps, restarts=restarts))
+        refs.append(rtg_gmres_restarted(op_o, sk_o, C, m, restarts, eps, mu=0.0))
+    plan = rtg.solve_batched(ops, sks, Cs, [None] * 3, prms)
+    torch.cuda.synchronize()
+    for b, ref in enumerate(refs):
+        check(plan.infos()[b], U.from_dev(plan.outs[b]), ref, tag=f"problem {b}")
+
+
+def test_restart_argument_errors():
+    import torch
+    from paper_2603_00839_amd import rtg
+    banner("restart argument errors")
+    p, a1, a2, bb, op_o, sk_o, C = dominant_problem(5, 32, 16, 3, 8, 8, 4)
+    op_g, sk_g = gpu_ops(p, a1, a2, bb)
+    Cd = U.to_dev(C)
+    with pytest.raises(rtg.RTGError):        # restarts need eps
+        rtg.solve(op_g, sk_g, Cd, None, rtg.make_params(4, rtg.F32, mu=0.0, restarts=2))
+    with pytest.raises(rtg.RTGError):        # RTG-GMRES only
+        rtg.solve(op_g, sk_g, Cd, None, rtg.make_params(4, rtg.F32, mu=0.0, stop_res=1e-3, restarts=2,
+                                                        method=rtg.METHOD_GOLUB_KAHAN))
+    torch.cuda.synchronize()
