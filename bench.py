@@ -16,6 +16,9 @@ Variants (each timed over the same number of steps):
                  products: the unsketched global GMRES)
   fp32_gk        sketched Block Golub-Kahan (Sec. 4.5), float32 basis,
                  X0 = 0, m = 50 columns
+  fp32_psf       the same images blurred by a 9x9 non-separable PSF
+                 (rotated anisotropic Gaussian, eq. (57)), float32 basis,
+                 m = 50 (W sketched after it is formed)
 The JSON line reports the headline variant in "value" and every variant
 under "variants", with restoration errors against the ground truth.
 
@@ -63,7 +66,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a device-to-device copy of MB megabytes (counter calibration)")
-    ap.add_argument("--only", choices=["fp32_plain", "bf16_warm", "fp32_unsketched", "fp32_gk"], default=None,
+    ap.add_argument("--only", choices=["fp32_plain", "bf16_warm", "fp32_unsketched", "fp32_gk", "fp32_psf"],
+                    default=None,
                     help="time one variant only (profiling runs)")
     return ap.parse_args()
 
@@ -80,6 +84,27 @@ def make_batch(B, device):
         p = synth.cfg2(b)
         if op is None:
             op = rtg.setup_operator(*p.dims, p.a1_band, p.a2_band, p.b_band)
+        sk = rtg.setup_sketch(*p.dims, p.om1, p.om2, p.om3)
+        xt = torch.from_numpy(synth.to_device_layout(p.x_true)).to(device)
+        g = torch.from_numpy(synth.to_device_layout(p.noise_dir)).to(device)
+        chat = rtg.apply_operator(op, xt)
+        delta = p.nu * float(torch.linalg.vector_norm(chat.double()))
+        C = (chat + g * (delta / float(torch.linalg.vector_norm(g.double())))).contiguous()
+        probs.append(dict(p=p, sk=sk, xt=xt, C=C, delta=delta))
+    return op, probs
+
+
+def make_psf_batch(B, device):
+    """B problems of the non-separable PSF workload (seeds 0..B-1), the
+    observation formed on the GPU with the library's operator plus noise."""
+    import torch
+    from paper_2603_00839_amd import rtg, synth
+    probs = []
+    op = None
+    for b in range(B):
+        p = synth.cfg2_psf(b)
+        if op is None:
+            op = rtg.setup_operator_psf(*p.dims, p.psf, p.b_band)
         sk = rtg.setup_sketch(*p.dims, p.om1, p.om2, p.om3)
         xt = torch.from_numpy(synth.to_device_layout(p.x_true)).to(device)
         g = torch.from_numpy(synth.to_device_layout(p.noise_dir)).to(device)
@@ -120,6 +145,12 @@ def tile_bytes(n, es, m_eff, has_x0):
         b += (j + 1) * es * n
     b += (4 * n if has_x0 else 0) + m_eff * es * n + 4 * n
     return b
+
+
+def phi_bytes(n, es, m_eff):
+    """Algorithmic bytes of the operator launches of one solve whose W is
+    formed in memory: step j reads V_j and writes W = Phi(V_j)."""
+    return m_eff * (es * n + 4 * n)
 
 
 def gk_tile_bytes(n, es, m_eff):
@@ -269,9 +300,17 @@ def main():
     torch.cuda.synchronize()
 
     results = {}
-    variants = [args.only] if args.only else ["fp32_plain", "bf16_warm", "fp32_unsketched", "fp32_gk"]
+    variants = [args.only] if args.only else ["fp32_plain", "bf16_warm", "fp32_unsketched", "fp32_gk", "fp32_psf"]
     for v in variants:
-        if v == "fp32_gk":
+        if v == "fp32_psf":
+            op_p, probs_p = make_psf_batch(B, dev)
+            prm = [rtg.make_params(args.m, rtg.F32, delta=q["delta"], eta=1.01) for q in probs_p]
+            plan = rtg.BatchPlan([op_p] * B, [q["sk"] for q in probs_p], [q["C"] for q in probs_p], [None] * B, prm)
+            r = time_variant(plan, args.steps, args.warmup, rtg, torch, rtg.KIND_PHI,
+                             lambda inf: phi_bytes(n, 4, inf.iters))
+            r["kernel"] = ("k_phi", "k_operator.hip", "2-D stencil of a general PSF + channel mix (float32)")
+            res = [rel_err(plan.outs[b], probs_p[b]["xt"]) for b in range(B)]
+        elif v == "fp32_gk":
             prm = [rtg.make_params(args.m, rtg.F32, delta=q["delta"], eta=1.01, method=rtg.METHOD_GOLUB_KAHAN)
                    for q in probs]
             plan = rtg.BatchPlan([op] * B, [q["sk"] for q in probs], [q["C"] for q in probs], [None] * B, prm)
@@ -304,7 +343,8 @@ def main():
                              lambda inf: step_bytes(n, 2, inf.iters), pre=pre)
             r["kernel"] = ("k_step", "k_step.hip", "Arnoldi step: operator per tile + multi-AXPY + store + "
                                                    "dual MFMA sketch (bfloat16 basis)")
-        res = [rel_err(plan.outs[b], probs[b]["xt"]) for b in range(B)]
+        if v != "fp32_psf":
+            res = [rel_err(plan.outs[b], probs[b]["xt"]) for b in range(B)]
         r["re_mean"] = float(np.mean(res))
         r["re_p0"] = res[0]
         r["iters_mean"] = float(np.mean([i.iters for i in r["infos"]]))
