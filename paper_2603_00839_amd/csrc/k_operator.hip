@@ -25,10 +25,13 @@
 // chunks, so that 16-byte LDS reads with lanes across columns are free of
 // bank conflicts.  (Measured: 58.8 -> 48.3 us per launch of the 9x9 PSF on
 // 16 x 512x512x3.  The separable passes measured no faster this way, 65 us
-// against 61 us at two instead of three workgroups per CU, and keep
-// register staging, as do bfloat16 input and tensors of 2^31 bytes or more.)
-// Coefficient rows are padded to multiples of 4 floats and read from LDS 16
-// bytes at a time.
+// against 61 us at two instead of three workgroups per CU.)  Other float32
+// input below 2^31 bytes is staged through registers in the same 16-byte
+// chunks and layout by buffer loads that read zeros past the range (one
+// load and one LDS write per four values: the single-word staging's index
+// arithmetic had made the kernel VALU-bound); bfloat16 input and larger
+// tensors keep single-word staging.  Coefficient rows are padded to
+// multiples of 4 floats and read from LDS 16 bytes at a time.
 //
 // General (non-separable) PSF (eqs. (56)-(57)): with ST the two passes are
 // replaced by the 2-D stencil
@@ -61,25 +64,32 @@ __device__ __forceinline__ int xcd_remap(int b, int G) {
     return x * q + min(x, rem) + slot;
 }
 
-template <int R, int JT, bool DMA>
+// slab staging: SL_SCALAR (single-word loads through registers; bfloat16
+// input, tensors of 2^31 bytes or more), SL_VEC (16-byte buffer loads through
+// registers), SL_DMA (asynchronous global-to-LDS loads, general PSF)
+enum { SL_SCALAR = 0, SL_VEC = 1, SL_DMA = 2 };
+
+template <int R, int JT, int SL>
 struct PhiLayout {
     static constexpr int T1 = PHI_T1, T2 = PHI_T2;
     static constexpr int SR = T1 + 2 * R;                 // slab rows
     static constexpr int SC = T2 + 2 * R;                 // slab columns (<= 64)
-    static constexpr int CPC = ((SR / 4) % 2 == 0) ? SR / 4 + 1 : SR / 4;   // DMA: odd chunks per column
-    static constexpr int SRP = DMA ? 4 * CPC : SR + 1;    // slab column stride (floats)
-    static constexpr int NBUF = DMA ? 3 : 1;              // slabs in LDS (DMA: every input channel, J <= 3)
+    static constexpr int CPC = ((SR / 4) % 2 == 0) ? SR / 4 + 1 : SR / 4;   // 16-byte chunks: odd per column
+    static constexpr int SRP = SL != SL_SCALAR ? 4 * CPC : SR + 1;          // slab column stride (floats)
+    static constexpr int NBUF = SL == SL_DMA ? 3 : 1;     // slabs in LDS (DMA: every input channel, J <= 3)
     static constexpr int ZRP = T1 + 1;
     static constexpr int WP = ((2 * R + 1) + 3) / 4 * 4;  // padded taps per band row
     static constexpr int NKB = JT + 2 * RMAX_B;           // input channels per tile (max)
     static constexpr int FLOATS = NBUF * SC * SRP + SC * ZRP + (T1 + T2) * WP + NKB * JT;
 };
 
-template <int R, bool BF16IN, int JT, bool ST, bool DMA>
+template <int R, bool BF16IN, int JT, bool ST, int SL>
 __device__ __forceinline__ void phi_tile(const PhiArgs& a, int tile, float* smem) {
-    static_assert(!(DMA && BF16IN), "asynchronous slab loads take float32 input");
+    constexpr bool DMA = SL == SL_DMA, VEC = SL != SL_SCALAR;
+    static_assert(!(VEC && BF16IN), "16-byte slab loads take float32 input");
     static_assert(!DMA || JT == 4, "asynchronous slab loads: one tile holds every channel (J <= 3)");
-    using LY = PhiLayout<R, JT, DMA>;
+    typedef float f4v __attribute__((ext_vector_type(4)));
+    using LY = PhiLayout<R, JT, SL>;
     constexpr int T1 = PHI_T1, T2 = PHI_T2;
     constexpr int SR = LY::SR, SC = LY::SC, SRP = LY::SRP, NBUF = LY::NBUF, CPC = LY::CPC;
     constexpr int ZRP = LY::ZRP, WP = LY::WP, NKB = LY::NKB;
@@ -112,7 +122,7 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int tile, float* smem
     // DMA: slab of input channel k into buffer b (chunk c: column c / CPC,
     // rows 4 (c % CPC) .. + 3; the last chunk of a column is padding)
     const auto rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(a.src), (short)0,
-                                                        DMA ? (int)(plane * (size_t)J * 4) : 0, 0x00020000);
+                                                        VEC ? (int)(plane * (size_t)J * 4) : 0, 0x00020000);
     auto dma_slab = [&](int k, int b) {
         float* Sd = Sall + b * SC * SRP;
         constexpr int NCH = SC * CPC;
@@ -171,7 +181,6 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int tile, float* smem
     // one padded coefficient row from LDS, 16 bytes a read (rows start at
     // multiples of 4 floats of a 16-byte aligned area)
     auto load_row = [](const float* row, float (&cf)[WP]) {
-        typedef float f4v __attribute__((ext_vector_type(4)));
 #pragma unroll
         for (int q = 0; q < WP / 4; ++q) {
             const f4v v = *(const f4v*)(row + 4 * q);
@@ -183,7 +192,23 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int tile, float* smem
     // Register staging: the slab of the next input channel is loaded into
     // registers while the current one is processed (all loads of a slab are
     // issued together).
-    constexpr int NLD = DMA ? 1 : (SR * SC + 255) / 256;
+    constexpr int NLD = VEC ? 1 : (SR * SC + 255) / 256;
+    // SL_VEC: the slab in 16-byte chunks (the layout of the asynchronous
+    // loads), zeros past the buffer range
+    constexpr int NCHV = SC * CPC;
+    constexpr int NLD4 = (SL == SL_VEC) ? (NCHV + 255) / 256 : 1;
+    f4v pre4[NLD4];
+    auto load_slab4 = [&](int k) {
+#pragma unroll
+        for (int it = 0; it < NLD4; ++it) {
+            const int c = it * 256 + tid;
+            const int col = c / CPC, rc = c % CPC;
+            const int i1 = i10 - R + 4 * rc, i2 = i20 - R + col;
+            const bool ok = (c < NCHV) & (rc < SR / 4) & (i1 >= 0) & (i1 < I1) & (i2 >= 0) & (i2 < I2);
+            const unsigned off = ok ? (unsigned)(((size_t)k * plane + (size_t)i2 * I1 + i1) * 4) : 0x80000000u;
+            pre4[it] = __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(rsrc, off, 0, 0));
+        }
+    };
     const float* srcf = (const float*)a.src;
     const bf16_t* srch = (const bf16_t*)a.src;
     float pre[NLD];
@@ -200,7 +225,8 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int tile, float* smem
             pre[it] = inb ? v : 0.f;
         }
     };
-    if constexpr (!DMA) load_slab(klo);
+    if constexpr (SL == SL_VEC) load_slab4(klo);
+    else if constexpr (SL == SL_SCALAR) load_slab(klo);
     for (int kk = 0; kk < nk; ++kk) {
         const int k = klo + kk;
         float* S = Sall + (kk % NBUF) * SC * SRP;
@@ -208,6 +234,15 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int tile, float* smem
             // every slab was requested before the coefficients were staged
             if (kk == 0) __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's loads landed
             __syncthreads();                                    // everyone's; Z free
+        } else if constexpr (SL == SL_VEC) {
+            __syncthreads();
+#pragma unroll
+            for (int it = 0; it < NLD4; ++it) {
+                const int c = it * 256 + tid;
+                if (c < NCHV) *(f4v*)(S + 4 * c) = pre4[it];   // column c / CPC, rows 4 (c % CPC) ..
+            }
+            if (k + 1 < khi) load_slab4(k + 1);
+            __syncthreads();
         } else {
             __syncthreads();
             // ---- stage the slab of channel k (zero boundary conditions)
@@ -244,8 +279,7 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int tile, float* smem
             for (int blk = 0; blk < 2; ++blk) {
                 const int rbase = wave * 16 + blk * 8;
                 float in[8 + 2 * R];
-                if constexpr (DMA) {
-                    typedef float f4v __attribute__((ext_vector_type(4)));
+                if constexpr (VEC) {
 #pragma unroll
                     for (int q = 0; q < (8 + 2 * R) / 4; ++q) {
                         const f4v v = *(const f4v*)(S + lane * SRP + rbase + 4 * q);
@@ -321,17 +355,17 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int tile, float* smem
     }
 }
 
-template <int R, bool BF16IN, int JT, bool ST, bool DMA>
+template <int R, bool BF16IN, int JT, bool ST, int SL>
 __global__ void __launch_bounds__(256) k_phi_single(PhiArgs a) {
-    __shared__ __attribute__((aligned(16))) float smem[PhiLayout<R, JT, DMA>::FLOATS];
-    phi_tile<R, BF16IN, JT, ST, DMA>(a, xcd_remap(blockIdx.x, gridDim.x), smem);
+    __shared__ __attribute__((aligned(16))) float smem[PhiLayout<R, JT, SL>::FLOATS];
+    phi_tile<R, BF16IN, JT, ST, SL>(a, xcd_remap(blockIdx.x, gridDim.x), smem);
 }
 
-template <int R, bool BF16IN, int JT, bool ST, bool DMA>
+template <int R, bool BF16IN, int JT, bool ST, int SL>
 __global__ void __launch_bounds__(256) k_phi_batched(const Desc* __restrict__ descs,
                                                      const int* __restrict__ starts, int count,
                                                      int src_sel, int src_index) {
-    __shared__ __attribute__((aligned(16))) float smem[PhiLayout<R, JT, DMA>::FLOATS];
+    __shared__ __attribute__((aligned(16))) float smem[PhiLayout<R, JT, SL>::FLOATS];
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int p = find_problem(starts, count, b);
     const Desc& d = descs[p];
@@ -350,7 +384,7 @@ __global__ void __launch_bounds__(256) k_phi_batched(const Desc* __restrict__ de
         a.C = d.C;
     }
     a.dst = d.W;
-    phi_tile<R, BF16IN, JT, ST, DMA>(a, b - starts[p], smem);
+    phi_tile<R, BF16IN, JT, ST, SL>(a, b - starts[p], smem);
 }
 
 static int phi_tier(int r) { return r <= 4 ? 4 : (r <= 8 ? 8 : 12); }
@@ -368,13 +402,15 @@ hipError_t launch_phi_single(int I1, int I2, int J, int r1, int r2, int rB, cons
     const int jt = phi_jt(J);
     const int tiles = phi_tiles(I1, I2, J, jt);
     const int tier = phi_tier(r1 > r2 ? r1 : r2);
-    // asynchronous slab loads (general PSF): float32 input of at most three
-    // channels, 32-bit byte offsets
-    const bool dma = !bf16_in && J <= 3 && (size_t)I1 * I2 * J * 4 <= 0x7FFFFFFFull;
-#define RTG_PHI_SINGLE_S(RR, JJ, SS)                                                                           \
-    if (bf16_in) hipLaunchKernelGGL((k_phi_single<RR, true, JJ, SS, false>), dim3(tiles), dim3(256), 0, s, a); \
-    else if (dma && SS && JJ == 4) hipLaunchKernelGGL((k_phi_single<RR, false, 4, SS, true>), dim3(tiles), dim3(256), 0, s, a); \
-    else hipLaunchKernelGGL((k_phi_single<RR, false, JJ, SS, false>), dim3(tiles), dim3(256), 0, s, a);
+    // 16-byte slab loads need 32-bit byte offsets into the float32 input;
+    // asynchronous ones (general PSF) every channel in one tile (J <= 3)
+    const bool vec = !bf16_in && (size_t)I1 * I2 * J * 4 <= 0x7FFFFFFFull;
+    const bool dma = vec && st != nullptr && J <= 3;
+#define RTG_PHI_SINGLE_S(RR, JJ, SS)                                                                            \
+    if (bf16_in) hipLaunchKernelGGL((k_phi_single<RR, true, JJ, SS, SL_SCALAR>), dim3(tiles), dim3(256), 0, s, a); \
+    else if (dma && JJ == 4) hipLaunchKernelGGL((k_phi_single<RR, false, 4, SS, SL_DMA>), dim3(tiles), dim3(256), 0, s, a); \
+    else if (vec) hipLaunchKernelGGL((k_phi_single<RR, false, JJ, SS, SL_VEC>), dim3(tiles), dim3(256), 0, s, a);  \
+    else hipLaunchKernelGGL((k_phi_single<RR, false, JJ, SS, SL_SCALAR>), dim3(tiles), dim3(256), 0, s, a);
 #define RTG_PHI_SINGLE(RR, JJ) if (st) { RTG_PHI_SINGLE_S(RR, JJ, true) } else { RTG_PHI_SINGLE_S(RR, JJ, false) }
 #define RTG_PHI_SINGLE_J(RR) if (jt == 4) { RTG_PHI_SINGLE(RR, 4) } else { RTG_PHI_SINGLE(RR, 8) }
     if (tier == 4) { RTG_PHI_SINGLE_J(4) } else if (tier == 8) { RTG_PHI_SINGLE_J(8) } else { RTG_PHI_SINGLE_J(12) }
@@ -384,23 +420,28 @@ hipError_t launch_phi_single(int I1, int I2, int J, int r1, int r2, int rB, cons
     return hipGetLastError();
 }
 
+// slab: 0 = single-word staging only, 1 = 16-byte loads possible (float32
+// inputs below 2^31 bytes), 2 = also asynchronous loads (and J <= 3)
 hipError_t launch_phi(const Desc* d, const int* starts, int count, int total_tiles, int src_sel,
-                      int src_index, int rmax, int jt, int bf16_in, hipStream_t s, int stencil, int dma) {
+                      int src_index, int rmax, int jt, int bf16_in, hipStream_t s, int stencil, int slab) {
     const int tier = phi_tier(rmax);
-    dma = dma && !bf16_in;
-#define RTG_PHI_BATCH_S(RR, JJ, SS)                                                                           \
-    if (bf16_in) hipLaunchKernelGGL((k_phi_batched<RR, true, JJ, SS, false>), dim3(total_tiles), dim3(256), 0, s, \
-                                    d, starts, count, src_sel, src_index);                                    \
-    else if (dma && SS && JJ == 4) hipLaunchKernelGGL((k_phi_batched<RR, false, 4, SS, true>), dim3(total_tiles), \
-                                                dim3(256), 0, s, d, starts, count, src_sel, src_index);       \
-    else hipLaunchKernelGGL((k_phi_batched<RR, false, JJ, SS, false>), dim3(total_tiles), dim3(256), 0, s,     \
-                            d, starts, count, src_sel, src_index);
+    const bool vec = !bf16_in && slab >= 1;
+    const bool dma = vec && stencil && slab >= 2;
+#define RTG_PHI_BATCH_K(RR, BB, JJ, SS, LL)                                                                      \
+    hipLaunchKernelGGL((k_phi_batched<RR, BB, JJ, SS, LL>), dim3(total_tiles), dim3(256), 0, s, d, starts, count, \
+                       src_sel, src_index);
+#define RTG_PHI_BATCH_S(RR, JJ, SS)                                         \
+    if (bf16_in) { RTG_PHI_BATCH_K(RR, true, JJ, SS, SL_SCALAR) }          \
+    else if (dma && JJ == 4) { RTG_PHI_BATCH_K(RR, false, 4, SS, SL_DMA) } \
+    else if (vec) { RTG_PHI_BATCH_K(RR, false, JJ, SS, SL_VEC) }           \
+    else { RTG_PHI_BATCH_K(RR, false, JJ, SS, SL_SCALAR) }
 #define RTG_PHI_BATCH(RR, JJ) if (stencil) { RTG_PHI_BATCH_S(RR, JJ, true) } else { RTG_PHI_BATCH_S(RR, JJ, false) }
 #define RTG_PHI_BATCH_J(RR) if (jt == 4) { RTG_PHI_BATCH(RR, 4) } else { RTG_PHI_BATCH(RR, 8) }
     if (tier == 4) { RTG_PHI_BATCH_J(4) } else if (tier == 8) { RTG_PHI_BATCH_J(8) } else { RTG_PHI_BATCH_J(12) }
 #undef RTG_PHI_BATCH_J
 #undef RTG_PHI_BATCH
 #undef RTG_PHI_BATCH_S
+#undef RTG_PHI_BATCH_K
     return hipGetLastError();
 }
 

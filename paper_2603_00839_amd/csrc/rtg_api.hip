@@ -257,8 +257,8 @@ struct Plan {
     int toeplitz;      // every problem's bands are Toeplitz
     int unsketched;    // every problem's sketch is the identity (a batch is all one or all the other)
     int stencil;       // every problem's operator is a general PSF (all or none)
-    int phi_dma;       // float32 operator inputs of at most three channels and below 2^31 bytes:
-                       // asynchronous slab loads
+    int phi_dma;       // operator slab loads: 1 = 16-byte (float32 inputs below 2^31 bytes),
+                       // 2 = also asynchronous (and at most three channels), 0 = single-word
     Desc* d_desc_r;    // restart cycles: the descriptors with X0 = X (null without restarts)
 };
 
@@ -289,11 +289,12 @@ int build_plan(std::vector<Desc>& descs, void* ws, hipStream_t s, Plan& plan, in
     plan.toeplitz = 1;
     plan.unsketched = descs.empty() ? 0 : descs[0].unsketched;
     plan.stencil = (!descs.empty() && descs[0].st) ? 1 : 0;
-    plan.phi_dma = 1;
+    plan.phi_dma = 2;
     for (auto& d : descs) {
         if (d.unsketched != plan.unsketched) return RTG_E_ARG;
         if ((d.st != nullptr) != (plan.stencil != 0)) return RTG_E_ARG;
-        if (d.n * 4 > 0x7FFFFFFFll || d.J > 3) plan.phi_dma = 0;
+        if (d.n * 4 > 0x7FFFFFFFll) plan.phi_dma = 0;
+        else if (d.J > 3) plan.phi_dma = std::min(plan.phi_dma, 1);
         if (d.unsketched && d.n * 4 > 0x7FFFFFFFll) return RTG_E_SHAPE;
         plan.toeplitz = plan.toeplitz && d.toeplitz;
         plan.step_ok = plan.step_ok && d.n * 2 <= 0x7FFFFFFFll &&
