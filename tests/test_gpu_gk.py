@@ -199,3 +199,22 @@ def test_gk_argument_errors():
     with pytest.raises(rtg.RTGError):
         rtg.solve(op_g, sk_g, C, None, bad)
     torch.cuda.synchronize()
+
+
+def test_gk_bf16_basis_solve_restores_like_the_oracle():
+    """Golub-Kahan with a bfloat16 basis (operator and AXPY tiles on the
+    bfloat16 tensors, norms in float64): the restoration error stays within
+    1 % of the float64 oracle's Golub-Kahan solve."""
+    from paper_2603_00839_amd import rtg
+    banner("gk bf16 solve")
+    p = synth.cfg1(0)
+    op_o, sk_o = U.oracle_pair(p)
+    op_g, sk_g = U.gpu_pair(p)
+    C, delta = U.observation(p)
+    prm = rtg.make_params(20, rtg.BF16, delta=delta, eta=1.01, method=rtg.METHOD_GOLUB_KAHAN)
+    Xg, ib = rtg.solve(op_g, sk_g, U.to_dev(C), None, prm)
+    ref = rgk_solve(op_o, sk_o, C, 20, delta=delta, eta=1.01)
+    re_g, re_o = U.rel(U.from_dev(Xg), p.x_true), U.rel(ref.X, p.x_true)
+    info = rtg.read_info(ib)
+    print(f"iters {info.iters} ({ref.m_eff}) RE bf16 {re_g:.5f} oracle {re_o:.5f}", file=sys.stderr)
+    assert re_g <= 1.01 * re_o

@@ -95,3 +95,36 @@ def test_restart_argument_errors():
         rtg.solve(op_g, sk_g, Cd, None, rtg.make_params(4, rtg.F32, mu=0.0, stop_res=1e-3, restarts=2,
                                                         method=rtg.METHOD_GOLUB_KAHAN))
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("kind", ["psf", "identity"])
+def test_restarts_with_general_psf_and_identity_sketch(kind):
+    """Restart cycles through the other operator/sketch paths: a general
+    (non-separable) PSF, where W is sketched after it is formed, and the
+    identity sketch (Frobenius inner products)."""
+    from paper_2603_00839_amd import rtg
+    from oracle.operator import PSFOperator
+    from oracle.sketch import identity_sketch
+    banner("restarted", kind)
+    if kind == "psf":
+        p = synth.psf_problem(41, 48, 40, 3, r=3, l1=12, l2=10, m=4)
+        P = p.psf.astype(np.float64).copy()
+        P[3, 3] += 2.0                       # a dominant centre tap: restarts converge
+        P = P.astype(np.float32)
+        op_o = PSFOperator(P, p.b_band, p.dims)
+        sk_o = Sketch(p.om1, p.om2, p.om3)
+        op_g = rtg.setup_operator_psf(48, 40, 3, P, p.b_band)
+        sk_g = rtg.setup_sketch(48, 40, 3, p.om1, p.om2, p.om3)
+        C = (op_o(p.x_true) + 0.01 * p.noise_dir).astype(np.float32)
+    else:
+        p, a1, a2, bb, op_o, _, C = dominant_problem(43, 48, 40, 3, 12, 10, 4)
+        op_g, _ = gpu_ops(p, a1, a2, bb)
+        sk_o = identity_sketch()
+        sk_g = rtg.setup_sketch(48, 40, 3)
+    m, restarts = 4, 10
+    eps = 1e-4 * sk_o.norm(C)
+    ref = rtg_gmres_restarted(op_o, sk_o, C, m, restarts, eps, mu=0.0)
+    prm = rtg.make_params(m, rtg.F32, mu=0.0, stop_res=eps, restarts=restarts)
+    Xg, ib = rtg.solve(op_g, sk_g, U.to_dev(C), None, prm)
+    check(rtg.read_info(ib), U.from_dev(Xg), ref)
+    assert ref.cycles > 1
