@@ -11,8 +11,13 @@
  * inner products <X,Y>_Theta = <S(X), S(Y)>_F with the mode-wise sketch
  * S(X) = X x_1 Om1 x_2 Om2 x_3 Om3 (Sec. 3.1), followed by the projected
  * Tikhonov problem  min ||beta e1 - H y||^2 + mu ||y||^2  (eqs. (12)-(13)),
- * mu fixed or chosen by the discrepancy principle, and X = X0 + sum_j y_j V_j
- * (algorithm "Block GMRES via Sketched Einstein Product", Sec. 4.4).
+ * mu fixed or chosen by the discrepancy principle or by GCV (Sec. 3), and
+ * X = X0 + sum_j y_j V_j (algorithm "Block GMRES via Sketched Einstein
+ * Product", Sec. 4.4).  Also: sketched Block Golub-Kahan in place of the
+ * Arnoldi process (Sec. 4.5; rtg_params.method), a general non-separable PSF
+ * in place of A1 (x) A2 (eqs. (56)-(57); rtg_setup_operator_psf), restarted
+ * RTG-GMRES (rtg_params.restarts), the identity sketch (unsketched global
+ * GMRES), batches of uneven problems and a learned warm start.
  *
  * Conventions for every entry point
  * ---------------------------------
@@ -31,7 +36,8 @@
  * - Return codes (synchronous, host-side): RTG_OK or a negative RTG_E_*.
  *   Numerical outcomes are reported in device-resident rtg_info.flags.
  * - Ownership: all tensors and workspaces are caller-owned device memory.
- *   Handles own small device copies of the bands and sketch factors and are
+ *   Handles own small device copies of the bands (and of their transposes,
+ *   the adjoint operator of Golub-Kahan) and sketch factors and are
  *   immutable after setup: one handle may be used concurrently on several
  *   streams with separate workspaces.  Compute calls never allocate.
  */
@@ -62,7 +68,10 @@ enum {
 
 /* numerical outcome flags (rtg_info.flags, device side) */
 enum {
-    RTG_F_BREAKDOWN = 1,           /* h_{j+1,j} <= bd_tol ||S(Phi(V_j))||: solved at j  */
+    RTG_F_BREAKDOWN = 1,           /* h_{j+1,j} <= bd_tol ||S(Phi(V_j))||: solved at j
+                                      (Golub-Kahan: beta_{k+1} or alpha_{k+1} below
+                                      bd_tol times the sketched norm of Phi(V_k) or
+                                      Phi^T(U_{k+1}); solved with the complete columns) */
     RTG_F_DISCREP_UNREACHABLE = 2, /* LS residual already above eta*delta: mu = 0      */
     RTG_F_MU_INF = 4,              /* eta*delta >= beta: y = 0, X = X0                  */
     RTG_F_NONFINITE = 8,           /* NaN/Inf met in a coefficient                     */
@@ -71,9 +80,10 @@ enum {
 
 /* Solver parameters. */
 typedef struct {
-    int m;            /* maximum number of Arnoldi steps, 1 <= m <= 96            */
+    int m;            /* maximum number of Arnoldi steps (Golub-Kahan: columns),
+                         1 <= m <= 96                                            */
     int basis_dtype;  /* RTG_F32 or RTG_BF16: storage of V_j (and MFMA precision) */
-    double mu;        /* >= 0: fixed Tikhonov parameter; < 0: discrepancy principle */
+    double mu;        /* >= 0: fixed Tikhonov parameter; < 0: chosen by mu_rule    */
     double delta;     /* absolute noise-norm estimate ||E||_F (discrepancy)       */
     double eta;       /* discrepancy safety factor (1.01 is customary)            */
     double stop_res;  /* > 0: stop at the first j whose projected LS residual is
@@ -105,7 +115,9 @@ typedef struct {
     int flags;        /* RTG_F_* bits                                            */
     double mu;        /* Tikhonov parameter used (inf if RTG_F_MU_INF)            */
     double beta;      /* ||R0||_Theta                                            */
-    double res_proj;  /* ||beta e1 - H y||_2 = ||S(C - Phi(X))||_F (Sec. 4.4)     */
+    double res_proj;  /* ||beta e1 - H y||_2, which is ||S(C - Phi(X))||_F for
+                         RTG-GMRES (Theta-orthonormal basis, Sec. 4.4); for
+                         Golub-Kahan the same norm with the bidiagonal matrix */
     double res_ls;    /* least-squares residual of the projected problem (11S)    */
 } rtg_info;
 
@@ -197,7 +209,8 @@ size_t rtg_gk_workspace_bytes(rtg_op op, rtg_sk sk, int m, int basis_dtype);
  * *m_done (< m after a breakdown: beta_{k+1} <= bd_tol ||S(Phi(V_k))|| or
  * alpha_{k+1} <= bd_tol ||S(Phi^T(U_{k+1}))||).  The bases U_1..U_{m+1} and
  * V_1..V_m stay in ws (rtg_gk_workspace_layout); ws_bytes >=
- * rtg_gk_workspace_bytes.  Needs a sketch with at least one Om_k given. */
+ * rtg_gk_workspace_bytes.  Needs a sketch with at least one Om_k given and
+ * a banded operator (RTG_E_ARG otherwise: a general PSF has no adjoint here). */
 int rtg_golub_kahan(rtg_op op, rtg_sk sk, const float* R0, int m, int basis_dtype,
                     double bd_tol, void* ws, size_t ws_bytes,
                     double* B, double* beta, int* m_done, void* stream);
@@ -222,7 +235,8 @@ int rtg_solve(rtg_op op, rtg_sk sk, const float* C, const float* X0,
 
 /* Many independent problems (uneven sizes allowed) solved together: every
  * stage is one launch over the tiles of all problems.  probs is a HOST array.
- * One basis type and one method per batch (RTG_E_ARG otherwise). */
+ * One basis type, one method and one kind of operator (banded or general
+ * PSF) per batch (RTG_E_ARG otherwise). */
 size_t rtg_batch_workspace_bytes(int count, const rtg_problem* probs);
 int rtg_solve_batched(int count, const rtg_problem* probs, void* ws,
                       size_t ws_bytes, void* stream);
