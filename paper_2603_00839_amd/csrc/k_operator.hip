@@ -31,7 +31,10 @@
 // load and one LDS write per four values: the single-word staging's index
 // arithmetic had made the kernel VALU-bound); bfloat16 input and larger
 // tensors keep single-word staging.  Coefficient rows are padded to
-// multiples of 4 floats and read from LDS 16 bytes at a time.
+// multiples of 4 floats and read from LDS 16 bytes at a time; Toeplitz bands
+// (TP) keep their taps in wave-uniform registers instead (counters had
+// shown 22% of wave cycles waiting to issue LDS instructions, most of them
+// coefficient reads: 49.1 -> 36.1 us per separable launch).
 //
 // General (non-separable) PSF (eqs. (56)-(57)): with ST the two passes are
 // replaced by the 2-D stencil
@@ -52,6 +55,8 @@ struct PhiArgs {
     const float* C;   // residual mode when non-null: Y = C - Phi(X)
     float* dst;
     const float* st;  // stencil ((2 r1 + 1)^2, [a + r1][b + r1]) of a general PSF, else null
+    const float* taps;  // Toeplitz bands (convolutions): A1 taps at [r1 + dd], A2 taps at
+                        // [2 RMAX_SPATIAL + 1 + r2 + dd]; null for general bands
 };
 
 __device__ __forceinline__ int xcd_remap(int b, int G) {
@@ -83,8 +88,12 @@ struct PhiLayout {
     static constexpr int FLOATS = NBUF * SC * SRP + SC * ZRP + (T1 + T2) * WP + NKB * JT;
 };
 
-template <int R, bool BF16IN, int JT, bool ST, int SL>
+// TP: Toeplitz bands (the blurs of Sec. 5 are convolutions): the taps are
+// held in wave-uniform registers for the whole tile instead of a
+// coefficient row per output row and column read from LDS.
+template <int R, bool BF16IN, int JT, bool ST, int SL, bool TP>
 __device__ __forceinline__ void phi_tile(const PhiArgs& a, int tile, float* smem) {
+    static_assert(!(TP && ST), "Toeplitz taps are for separable bands");
     constexpr bool DMA = SL == SL_DMA, VEC = SL != SL_SCALAR;
     static_assert(!(VEC && BF16IN), "16-byte slab loads take float32 input");
     static_assert(!DMA || JT == 4, "asynchronous slab loads: one tile holds every channel (J <= 3)");
@@ -155,7 +164,7 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int tile, float* smem
                          ? a.st[(size_t)(da + r1) * w1 + db + r1]
                          : 0.f;
         }
-    } else {
+    } else if constexpr (!TP) {
         for (int e = tid; e < T1 * WP; e += 256) {
             const int row = e / WP, t = e % WP, dd = t - R;
             const int i1 = i10 + row;
@@ -178,6 +187,17 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int tile, float* smem
     for (int jj = 0; jj < JT; ++jj)
 #pragma unroll
         for (int o = 0; o < 8; ++o) acc[jj][o] = 0.f;
+    float tA1[WP], tA2[WP];                 // TP: the taps, zero past the band
+    if constexpr (TP) {
+#pragma unroll
+        for (int t = 0; t < WP; ++t) {
+            const int dd = t - R;
+            const float v1 = (t <= 2 * R && dd >= -r1 && dd <= r1) ? *gptr(a.taps + r1 + dd) : 0.f;
+            const float v2 = (t <= 2 * R && dd >= -r2 && dd <= r2) ? *gptr(a.taps + 2 * RMAX_SPATIAL + 1 + r2 + dd) : 0.f;
+            tA1[t] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v1)));
+            tA2[t] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v2)));
+        }
+    }
     // one padded coefficient row from LDS, 16 bytes a read (rows start at
     // multiples of 4 floats of a 16-byte aligned area)
     auto load_row = [](const float* row, float (&cf)[WP]) {
@@ -293,7 +313,12 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int tile, float* smem
 #pragma unroll
                 for (int o = 0; o < 8; ++o) {
                     float cf[WP];
-                    load_row(A1c + (rbase + o) * WP, cf);
+                    if constexpr (TP) {
+#pragma unroll
+                        for (int t = 0; t < WP; ++t) cf[t] = tA1[t];
+                    } else {
+                        load_row(A1c + (rbase + o) * WP, cf);
+                    }
                     float s = 0.f;
 #pragma unroll
                     for (int t = 0; t <= 2 * R; ++t) s = fmaf(cf[t], in[o + t], s);
@@ -309,7 +334,12 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int tile, float* smem
 #pragma unroll
         for (int o = 0; o < 8; ++o) {
             float cf[WP];
-            load_row(A2c + (wave * 8 + o) * WP, cf);
+            if constexpr (TP) {
+#pragma unroll
+                for (int t = 0; t < WP; ++t) cf[t] = tA2[t];
+            } else {
+                load_row(A2c + (wave * 8 + o) * WP, cf);
+            }
             float s = 0.f;
 #pragma unroll
             for (int t = 0; t <= 2 * R; ++t) s = fmaf(cf[t], in2[o + t], s);
@@ -355,13 +385,13 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int tile, float* smem
     }
 }
 
-template <int R, bool BF16IN, int JT, bool ST, int SL>
+template <int R, bool BF16IN, int JT, bool ST, int SL, bool TP>
 __global__ void __launch_bounds__(256) k_phi_single(PhiArgs a) {
     __shared__ __attribute__((aligned(16))) float smem[PhiLayout<R, JT, SL>::FLOATS];
-    phi_tile<R, BF16IN, JT, ST, SL>(a, xcd_remap(blockIdx.x, gridDim.x), smem);
+    phi_tile<R, BF16IN, JT, ST, SL, TP>(a, xcd_remap(blockIdx.x, gridDim.x), smem);
 }
 
-template <int R, bool BF16IN, int JT, bool ST, int SL>
+template <int R, bool BF16IN, int JT, bool ST, int SL, bool TP>
 __global__ void __launch_bounds__(256) k_phi_batched(const Desc* __restrict__ descs,
                                                      const int* __restrict__ starts, int count,
                                                      int src_sel, int src_index) {
@@ -374,6 +404,7 @@ __global__ void __launch_bounds__(256) k_phi_batched(const Desc* __restrict__ de
     a.I1 = d.I1; a.I2 = d.I2; a.J = d.J; a.r1 = d.r1; a.r2 = d.r2; a.rB = d.rB;
     a.a1 = d.a1; a.a2 = d.a2; a.bb = d.bb;
     a.st = d.st;
+    a.taps = TP ? d.taps : nullptr;
     if (src_sel == PS_BASIS) {
         const size_t es = d.bf16 ? 2 : 4;
         a.src = (const char*)d.V + (size_t)src_index * d.n * es;
@@ -384,7 +415,7 @@ __global__ void __launch_bounds__(256) k_phi_batched(const Desc* __restrict__ de
         a.C = d.C;
     }
     a.dst = d.W;
-    phi_tile<R, BF16IN, JT, ST, SL>(a, b - starts[p], smem);
+    phi_tile<R, BF16IN, JT, ST, SL, TP>(a, b - starts[p], smem);
 }
 
 static int phi_tier(int r) { return r <= 4 ? 4 : (r <= 8 ? 8 : 12); }
@@ -396,45 +427,55 @@ int phi_tiles(int I1, int I2, int J, int jt) {
 }
 
 hipError_t launch_phi_single(int I1, int I2, int J, int r1, int r2, int rB, const float* a1,
-                             const float* a2, const float* bb, const float* st, const void* src, int bf16_in,
-                             const float* C, float* dst, hipStream_t s) {
-    PhiArgs a{I1, I2, J, r1, r2, rB, a1, a2, bb, src, C, dst, st};
+                             const float* a2, const float* bb, const float* st, const float* taps,
+                             const void* src, int bf16_in, const float* C, float* dst, hipStream_t s) {
+    PhiArgs a{I1, I2, J, r1, r2, rB, a1, a2, bb, src, C, dst, st, taps};
     const int jt = phi_jt(J);
     const int tiles = phi_tiles(I1, I2, J, jt);
     const int tier = phi_tier(r1 > r2 ? r1 : r2);
     // 16-byte slab loads need 32-bit byte offsets into the float32 input;
-    // asynchronous ones (general PSF) every channel in one tile (J <= 3)
+    // asynchronous ones (general PSF) every channel in one tile (J <= 3);
+    // Toeplitz taps in registers with the 16-byte staging
     const bool vec = !bf16_in && (size_t)I1 * I2 * J * 4 <= 0x7FFFFFFFull;
     const bool dma = vec && st != nullptr && J <= 3;
-#define RTG_PHI_SINGLE_S(RR, JJ, SS)                                                                            \
-    if (bf16_in) hipLaunchKernelGGL((k_phi_single<RR, true, JJ, SS, SL_SCALAR>), dim3(tiles), dim3(256), 0, s, a); \
-    else if (dma && JJ == 4) hipLaunchKernelGGL((k_phi_single<RR, false, 4, SS, SL_DMA>), dim3(tiles), dim3(256), 0, s, a); \
-    else if (vec) hipLaunchKernelGGL((k_phi_single<RR, false, JJ, SS, SL_VEC>), dim3(tiles), dim3(256), 0, s, a);  \
-    else hipLaunchKernelGGL((k_phi_single<RR, false, JJ, SS, SL_SCALAR>), dim3(tiles), dim3(256), 0, s, a);
+    const bool tp = vec && st == nullptr && taps != nullptr;
+#define RTG_PHI_SINGLE_K(RR, BB, JJ, SS, LL, TT) \
+    hipLaunchKernelGGL((k_phi_single<RR, BB, JJ, SS, LL, TT>), dim3(tiles), dim3(256), 0, s, a);
+#define RTG_PHI_SINGLE_S(RR, JJ, SS)                                                     \
+    if (bf16_in) { RTG_PHI_SINGLE_K(RR, true, JJ, SS, SL_SCALAR, false) }               \
+    else if (dma && JJ == 4) { RTG_PHI_SINGLE_K(RR, false, 4, SS, SL_DMA, false) }     \
+    else if (tp && !SS) { RTG_PHI_SINGLE_K(RR, false, JJ, false, SL_VEC, true) }        \
+    else if (vec) { RTG_PHI_SINGLE_K(RR, false, JJ, SS, SL_VEC, false) }                \
+    else { RTG_PHI_SINGLE_K(RR, false, JJ, SS, SL_SCALAR, false) }
 #define RTG_PHI_SINGLE(RR, JJ) if (st) { RTG_PHI_SINGLE_S(RR, JJ, true) } else { RTG_PHI_SINGLE_S(RR, JJ, false) }
 #define RTG_PHI_SINGLE_J(RR) if (jt == 4) { RTG_PHI_SINGLE(RR, 4) } else { RTG_PHI_SINGLE(RR, 8) }
     if (tier == 4) { RTG_PHI_SINGLE_J(4) } else if (tier == 8) { RTG_PHI_SINGLE_J(8) } else { RTG_PHI_SINGLE_J(12) }
 #undef RTG_PHI_SINGLE_J
 #undef RTG_PHI_SINGLE
 #undef RTG_PHI_SINGLE_S
+#undef RTG_PHI_SINGLE_K
     return hipGetLastError();
 }
 
 // slab: 0 = single-word staging only, 1 = 16-byte loads possible (float32
-// inputs below 2^31 bytes), 2 = also asynchronous loads (and J <= 3)
+// inputs below 2^31 bytes), 2 = also asynchronous loads (and J <= 3);
+// toeplitz: every problem's bands are Toeplitz (taps in registers)
 hipError_t launch_phi(const Desc* d, const int* starts, int count, int total_tiles, int src_sel,
-                      int src_index, int rmax, int jt, int bf16_in, hipStream_t s, int stencil, int slab) {
+                      int src_index, int rmax, int jt, int bf16_in, hipStream_t s, int stencil, int slab,
+                      int toeplitz) {
     const int tier = phi_tier(rmax);
     const bool vec = !bf16_in && slab >= 1;
     const bool dma = vec && stencil && slab >= 2;
-#define RTG_PHI_BATCH_K(RR, BB, JJ, SS, LL)                                                                      \
-    hipLaunchKernelGGL((k_phi_batched<RR, BB, JJ, SS, LL>), dim3(total_tiles), dim3(256), 0, s, d, starts, count, \
+    const bool tp = vec && !stencil && toeplitz;
+#define RTG_PHI_BATCH_K(RR, BB, JJ, SS, LL, TT)                                                                      \
+    hipLaunchKernelGGL((k_phi_batched<RR, BB, JJ, SS, LL, TT>), dim3(total_tiles), dim3(256), 0, s, d, starts, count, \
                        src_sel, src_index);
-#define RTG_PHI_BATCH_S(RR, JJ, SS)                                         \
-    if (bf16_in) { RTG_PHI_BATCH_K(RR, true, JJ, SS, SL_SCALAR) }          \
-    else if (dma && JJ == 4) { RTG_PHI_BATCH_K(RR, false, 4, SS, SL_DMA) } \
-    else if (vec) { RTG_PHI_BATCH_K(RR, false, JJ, SS, SL_VEC) }           \
-    else { RTG_PHI_BATCH_K(RR, false, JJ, SS, SL_SCALAR) }
+#define RTG_PHI_BATCH_S(RR, JJ, SS)                                                   \
+    if (bf16_in) { RTG_PHI_BATCH_K(RR, true, JJ, SS, SL_SCALAR, false) }             \
+    else if (dma && JJ == 4) { RTG_PHI_BATCH_K(RR, false, 4, SS, SL_DMA, false) }   \
+    else if (tp && !SS) { RTG_PHI_BATCH_K(RR, false, JJ, false, SL_VEC, true) }      \
+    else if (vec) { RTG_PHI_BATCH_K(RR, false, JJ, SS, SL_VEC, false) }              \
+    else { RTG_PHI_BATCH_K(RR, false, JJ, SS, SL_SCALAR, false) }
 #define RTG_PHI_BATCH(RR, JJ) if (stencil) { RTG_PHI_BATCH_S(RR, JJ, true) } else { RTG_PHI_BATCH_S(RR, JJ, false) }
 #define RTG_PHI_BATCH_J(RR) if (jt == 4) { RTG_PHI_BATCH(RR, 4) } else { RTG_PHI_BATCH(RR, 8) }
     if (tier == 4) { RTG_PHI_BATCH_J(4) } else if (tier == 8) { RTG_PHI_BATCH_J(8) } else { RTG_PHI_BATCH_J(12) }

@@ -394,12 +394,12 @@ int run_solver(const Plan& plan, int count, int mmax, int bf16, bool any_x0, boo
         const int us = 1;
         if (any_x0)
             RTG_TIMED(0, launch_phi(dd, sp, count, plan.total[KIND_PHI], PS_X0, 0, plan.rmax, plan.phi_jt, 0,
-                                    s, plan.stencil, plan.phi_dma));
+                                    s, plan.stencil, plan.phi_dma, plan.toeplitz));
         RTG_TIMED(2, launch_gram(dd, sg, count, plan.total[KIND_GRAM], GM_START, cycle, nullptr, s, us));
         RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_NEWV, 0, 0, bf16, 0, plan.l1max, s));
         for (int j = 1; j <= mmax; ++j) {
             RTG_TIMED(0, launch_phi(dd, sp, count, plan.total[KIND_PHI], PS_BASIS, j - 1, plan.rmax,
-                                    plan.phi_jt, bf16, s, plan.stencil, plan.phi_dma));
+                                    plan.phi_jt, bf16, s, plan.stencil, plan.phi_dma, plan.toeplitz));
             RTG_TIMED(2, launch_gram(dd, sg, count, plan.total[KIND_GRAM], GM_STEP, j, nullptr, s, us));
             if (j < mmax || last_newv)
                 RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_NEWV, j, j, bf16, 0,
@@ -417,14 +417,14 @@ int run_solver(const Plan& plan, int count, int mmax, int bf16, bool any_x0, boo
         // sketches W, then the Gram step and V_{j+1} with its sketch.
         if (any_x0)
             RTG_TIMED(0, launch_phi(dd, sp, count, plan.total[KIND_PHI], PS_X0, 0, plan.rmax, plan.phi_jt, 0,
-                                    s, 1, plan.phi_dma));
+                                    s, 1, plan.phi_dma, plan.toeplitz));
         RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_SKETCH_SRC, 0, 0, bf16, 0,
                                  plan.l1max, s));
         RTG_TIMED(2, launch_gram(dd, sg, count, plan.total[KIND_GRAM], GM_START, cycle, nullptr, s));
         RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_NEWV, 0, 0, bf16, 0, plan.l1max, s));
         for (int j = 1; j <= mmax; ++j) {
             RTG_TIMED(0, launch_phi(dd, sp, count, plan.total[KIND_PHI], PS_BASIS, j - 1, plan.rmax,
-                                    plan.phi_jt, bf16, s, 1, plan.phi_dma));
+                                    plan.phi_jt, bf16, s, 1, plan.phi_dma, plan.toeplitz));
             RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_SKETCH_W, 0, 0, bf16, 0,
                                      plan.l1max, s));
             RTG_TIMED(2, launch_gram(dd, sg, count, plan.total[KIND_GRAM], GM_STEP, j, nullptr, s));
@@ -440,7 +440,7 @@ int run_solver(const Plan& plan, int count, int mmax, int bf16, bool any_x0, boo
         return RTG_OK;
     }
     if (cycle == 0) RTG_HIP(launch_compose(dd, count, plan.compose_max, s));   // restart cycles reuse them
-    if (any_x0) RTG_TIMED(0, launch_phi(dd, sp, count, plan.total[KIND_PHI], PS_X0, 0, plan.rmax, plan.phi_jt, 0, s, 0, plan.phi_dma));
+    if (any_x0) RTG_TIMED(0, launch_phi(dd, sp, count, plan.total[KIND_PHI], PS_X0, 0, plan.rmax, plan.phi_jt, 0, s, 0, plan.phi_dma, plan.toeplitz));
     RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_SKETCH_SRC, 0, 0, bf16, 0, plan.l1max, s));
     RTG_TIMED(2, launch_gram(dd, sg, count, plan.total[KIND_GRAM], GM_START, cycle, nullptr, s));
     RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_NEWV, 0, 0, bf16, 0, plan.l1max, s));
@@ -459,7 +459,7 @@ int run_solver(const Plan& plan, int count, int mmax, int bf16, bool any_x0, boo
                                          plan.toeplitz, s));
             } else {
                 RTG_TIMED(0, launch_phi(dd, sp, count, plan.total[KIND_PHI], PS_BASIS, j - 1, plan.rmax,
-                                        plan.phi_jt, bf16, s, 0, plan.phi_dma));
+                                        plan.phi_jt, bf16, s, 0, plan.phi_dma, plan.toeplitz));
                 RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_NEWV, j, j, bf16, 0,
                                          plan.l1max, s));
             }
@@ -488,7 +488,7 @@ int run_gk(const Plan& plan, int count, int mmax, int bf16, bool any_x0, bool so
     const int tp = plan.total[KIND_PHI], tt = plan.total[KIND_TILE], tg = plan.total[KIND_GRAM];
     RTG_HIP(launch_init(dV, count, s));
     RTG_HIP(launch_compose(plan.d_desc, 2 * count, plan.compose_max, s));
-    if (any_x0) RTG_TIMED(0, launch_phi(dV, sp, count, tp, PS_X0, 0, plan.rmax, plan.phi_jt, 0, s, 0, plan.phi_dma));
+    if (any_x0) RTG_TIMED(0, launch_phi(dV, sp, count, tp, PS_X0, 0, plan.rmax, plan.phi_jt, 0, s, 0, plan.phi_dma, plan.toeplitz));
     // beta_1 = ||R0||_Theta, U_1 = R0 / beta_1 (with S(U_1) and S(Phi^T(U_1)))
     RTG_TIMED(1, launch_tile(dU, st, count, tt, TM_SKETCH_SRC, 0, 0, bf16, 0, plan.l1max, s));
     RTG_TIMED(2, launch_gram(dU, sg, count, tg, GM_START, 0, nullptr, s));
@@ -496,13 +496,13 @@ int run_gk(const Plan& plan, int count, int mmax, int bf16, bool any_x0, bool so
     for (int c = 1; c <= mmax; ++c) {
         // alpha_c; V_c = (Phi^T(U_c) - beta_c V_{c-1}) / alpha_c
         RTG_TIMED(2, launch_gram(dU, sg, count, tg, GM_GK, c, nullptr, s));
-        RTG_TIMED(0, launch_phi(dU, sp, count, tp, PS_BASIS, c - 1, plan.rmax, plan.phi_jt, bf16, s, 0, plan.phi_dma));
+        RTG_TIMED(0, launch_phi(dU, sp, count, tp, PS_BASIS, c - 1, plan.rmax, plan.phi_jt, bf16, s, 0, plan.phi_dma, plan.toeplitz));
         RTG_TIMED(1, launch_tile(dV, st, count, tt, TM_GKNEW, c - 1, c - 1, bf16, 0, plan.l1max, s,
                                  c >= 2 ? c - 2 : 0));
         // beta_{c+1}, column c of B, Givens and stop test; U_{c+1} = (Phi(V_c) - alpha_c U_c) / beta_{c+1}
         RTG_TIMED(2, launch_gram(dV, sg, count, tg, GM_GK, c, nullptr, s));
         if (c < mmax || !solve) {   // the bidiagonalisation alone also forms U_{m+1}
-            RTG_TIMED(0, launch_phi(dV, sp, count, tp, PS_BASIS, c - 1, plan.rmax, plan.phi_jt, bf16, s, 0, plan.phi_dma));
+            RTG_TIMED(0, launch_phi(dV, sp, count, tp, PS_BASIS, c - 1, plan.rmax, plan.phi_jt, bf16, s, 0, plan.phi_dma, plan.toeplitz));
             RTG_TIMED(1, launch_tile(dU, st, count, tt, TM_GKNEW, c, c, bf16, 0, plan.l1max, s, c - 1));
         }
     }
@@ -706,7 +706,8 @@ int rtg_destroy_operator(rtg_op op) {
 int rtg_apply_operator(rtg_op op, int x_dtype, const void* X, const float* C, float* Y, void* stream) {
     if (!op || !X || !Y) return RTG_E_ARG;
     if (x_dtype != RTG_F32 && x_dtype != RTG_BF16) return RTG_E_ARG;
-    if (launch_phi_single(op->I1, op->I2, op->J, op->r1, op->r2, op->rB, op->a1, op->a2, op->bb, op->st, X,
+    if (launch_phi_single(op->I1, op->I2, op->J, op->r1, op->r2, op->rB, op->a1, op->a2, op->bb, op->st,
+                          op->toeplitz ? op->taps : nullptr, X,
                           x_dtype == RTG_BF16, C, Y, (hipStream_t)stream) != hipSuccess)
         return RTG_E_HIP;
     return RTG_OK;

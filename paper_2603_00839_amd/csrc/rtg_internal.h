@@ -257,10 +257,10 @@ int phi_jt(int max_j);
 int phi_tiles(int I1, int I2, int J, int jt);
 hipError_t launch_phi(const Desc* d, const int* starts, int count, int total_tiles,
                       int src_sel, int src_index, int rmax, int jt, int bf16_in, hipStream_t s,
-                      int stencil = 0, int slab = 0);
+                      int stencil = 0, int slab = 0, int toeplitz = 0);
 hipError_t launch_phi_single(int I1, int I2, int J, int r1, int r2, int rB, const float* a1,
-                             const float* a2, const float* bb, const float* st, const void* src, int bf16_in,
-                             const float* C, float* dst, hipStream_t s);
+                             const float* a2, const float* bb, const float* st, const float* taps,
+                             const void* src, int bf16_in, const float* C, float* dst, hipStream_t s);
 hipError_t launch_tile(const Desc* d, const int* starts, int count, int total_tiles,
                        int mode, int nterms, int dst_index, int basis_bf16, int src_bf16,
                        int l1max, hipStream_t s, int first_term = 0);
