@@ -19,6 +19,10 @@ Variants (each timed over the same number of steps):
   fp32_psf       the same images blurred by a 9x9 non-separable PSF
                  (rotated anisotropic Gaussian, eq. (57)), float32 basis,
                  m = 50 (W sketched after it is formed)
+  bf16_uneven    256 images of uneven size (sides 64..512, sigma U(1,3),
+                 noise U[1e-3, 1e-2], sketches of a quarter of each mode) in
+                 one batch, bfloat16 basis, X0 = 0, m = 40; solves/s counts
+                 those 256 problems per step
 The JSON line reports the headline variant in "value" and every variant
 under "variants", with restoration errors against the ground truth.
 
@@ -66,7 +70,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a device-to-device copy of MB megabytes (counter calibration)")
-    ap.add_argument("--only", choices=["fp32_plain", "bf16_warm", "fp32_unsketched", "fp32_gk", "fp32_psf"],
+    ap.add_argument("--only", choices=["fp32_plain", "bf16_warm", "fp32_unsketched", "fp32_gk", "fp32_psf",
+                                       "bf16_uneven"],
                     default=None,
                     help="time one variant only (profiling runs)")
     return ap.parse_args()
@@ -113,6 +118,25 @@ def make_psf_batch(B, device):
         C = (chat + g * (delta / float(torch.linalg.vector_norm(g.double())))).contiguous()
         probs.append(dict(p=p, sk=sk, xt=xt, C=C, delta=delta))
     return op, probs
+
+
+def make_uneven_batch(device):
+    """The 256 uneven problems (seed 0), observations formed on the GPU with
+    each problem's operator plus noise of its level."""
+    import numpy as np
+    import torch
+    from paper_2603_00839_amd import rtg, synth
+    probs = []
+    for p in synth.cfg4(0, 256, m=40):
+        op = rtg.setup_operator(*p.dims, p.a1_band, p.a2_band, p.b_band)
+        sk = rtg.setup_sketch(*p.dims, p.om1, p.om2, p.om3)
+        xt = torch.from_numpy(synth.to_device_layout(p.x_true)).to(device)
+        g = torch.from_numpy(synth.to_device_layout(p.noise_dir)).to(device)
+        chat = rtg.apply_operator(op, xt)
+        delta = p.nu * float(torch.linalg.vector_norm(chat.double()))
+        C = (chat + g * (delta / float(torch.linalg.vector_norm(g.double())))).contiguous()
+        probs.append(dict(p=p, op=op, sk=sk, xt=xt, C=C, delta=delta, n=int(np.prod(p.dims))))
+    return probs
 
 
 def rel_err(x, xt):
@@ -203,11 +227,12 @@ def time_variant(plan, steps, warmup, rtg, torch, kind, bytes_of, pre=None):
     }
 
 
-def recorded_traffic(kernel_src):
+def recorded_traffic(kernel_src, variant):
     """HBM traffic per launch measured with rocprofv3 counters (FETCH_SIZE and
     WRITE_SIZE, scaled by a copy-kernel calibration) and recorded with the
     SHA-256 of the kernel source it was measured on; None when the kernel
-    source has changed since (or nothing was recorded)."""
+    source has changed since, when nothing was recorded, or when the
+    record is of another workload (the record names the variant)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
@@ -218,7 +243,7 @@ def recorded_traffic(kernel_src):
     with open(src, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
     ent = rec.get(kernel_src)
-    if not ent or ent.get("source_sha256") != sha:
+    if not ent or ent.get("source_sha256") != sha or ent.get("variant", "bf16_warm") != variant:
         return None
     return ent["bytes_per_launch"]
 
@@ -300,9 +325,27 @@ def main():
     torch.cuda.synchronize()
 
     results = {}
-    variants = [args.only] if args.only else ["fp32_plain", "bf16_warm", "fp32_unsketched", "fp32_gk", "fp32_psf"]
+    variants = [args.only] if args.only else ["fp32_plain", "bf16_warm", "fp32_unsketched", "fp32_gk", "fp32_psf",
+                                              "bf16_uneven"]
     for v in variants:
-        if v == "fp32_psf":
+        if v == "bf16_uneven":
+            probs_u = make_uneven_batch(dev)
+            Bu = len(probs_u)
+            prm = [rtg.make_params(40, rtg.BF16, delta=q["delta"], eta=1.01) for q in probs_u]
+            plan = rtg.BatchPlan([q["op"] for q in probs_u], [q["sk"] for q in probs_u], [q["C"] for q in probs_u],
+                                 [None] * Bu, prm)
+            ns = [q["n"] for q in probs_u]
+            it = {"i": 0}
+
+            def bytes_u(inf, it=it):
+                b = step_bytes(ns[it["i"] % Bu], 2, inf.iters)
+                it["i"] += 1
+                return b
+            r = time_variant(plan, args.steps, args.warmup, rtg, torch, rtg.KIND_STEP, bytes_u)
+            r["kernel"] = ("k_step", "k_step.hip", "Arnoldi step, bfloat16 basis, 256 uneven problems")
+            res = [rel_err(plan.outs[b], probs_u[b]["xt"]) for b in range(Bu)]
+            r["solves_per_step"] = Bu
+        elif v == "fp32_psf":
             op_p, probs_p = make_psf_batch(B, dev)
             prm = [rtg.make_params(args.m, rtg.F32, delta=q["delta"], eta=1.01) for q in probs_p]
             plan = rtg.BatchPlan([op_p] * B, [q["sk"] for q in probs_p], [q["C"] for q in probs_p], [None] * B, prm)
@@ -343,13 +386,13 @@ def main():
                              lambda inf: step_bytes(n, 2, inf.iters), pre=pre)
             r["kernel"] = ("k_step", "k_step.hip", "Arnoldi step: operator per tile + multi-AXPY + store + "
                                                    "dual MFMA sketch (bfloat16 basis)")
-        if v != "fp32_psf":
+        if v not in ("fp32_psf", "bf16_uneven"):
             res = [rel_err(plan.outs[b], probs[b]["xt"]) for b in range(B)]
         r["re_mean"] = float(np.mean(res))
         r["re_p0"] = res[0]
         r["iters_mean"] = float(np.mean([i.iters for i in r["infos"]]))
         r["flags"] = sorted({i.flags for i in r["infos"]})
-        r["solves_per_s"] = B * args.steps / r["seconds"]
+        r["solves_per_s"] = r.get("solves_per_step", B) * args.steps / r["seconds"]
         r["ms_per_step"] = 1e3 * r["seconds"] / args.steps
         results[v] = r
         del plan
@@ -364,7 +407,7 @@ def main():
     H = results[head]
     gbs = H["k_bytes"] / (H["k_ms"] * 1e-3) / 1e9 if H["k_ms"] > 0 else 0.0
     bpl = H["k_bytes"] / max(H["k_launches"], 1)
-    traffic = recorded_traffic(H["kernel"][1])
+    traffic = recorded_traffic(H["kernel"][1], head)
     out = {
         "metric": METRIC,
         "value": H["solves_per_s"],
