@@ -68,6 +68,8 @@ def parse():
     ap.add_argument("--x0", choices=["learned", "observation"], default="learned")
     ap.add_argument("--headline", choices=["auto", "fp32_plain", "bf16_warm"], default="auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time every batch with the library's default launch shapes")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a device-to-device copy of MB megabytes (counter calibration)")
     ap.add_argument("--only", choices=["fp32_plain", "bf16_warm", "fp32_unsketched", "fp32_gk", "fp32_psf",
@@ -279,6 +281,18 @@ def cpu_baseline(problem0):
             "seconds": dt, "re": relative_error(p.x_true, r.X), "mu": r.mu}
 
 
+def tune_plan(plan, args, pre=None):
+    """Launch shapes for this batch: picked by the library's autotuner
+    (outside the timed region; X0 formed first where the step computes it),
+    or the defaults with --no-autotune."""
+    if args.no_autotune:
+        return {"autotuned": False, **plan.tune().as_dict()}
+    if pre is not None:
+        pre()
+    t, ms = plan.autotune(reps=3)
+    return {"autotuned": True, "loop_ms": ms, **t.as_dict()}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -341,6 +355,7 @@ def main():
                 b = step_bytes(ns[it["i"] % Bu], 2, inf.iters)
                 it["i"] += 1
                 return b
+            tune = tune_plan(plan, args)
             r = time_variant(plan, args.steps, args.warmup, rtg, torch, rtg.KIND_STEP, bytes_u)
             r["kernel"] = ("k_step", "k_step.hip", "Arnoldi step, bfloat16 basis, 256 uneven problems")
             res = [rel_err(plan.outs[b], probs_u[b]["xt"]) for b in range(Bu)]
@@ -349,6 +364,7 @@ def main():
             op_p, probs_p = make_psf_batch(B, dev)
             prm = [rtg.make_params(args.m, rtg.F32, delta=q["delta"], eta=1.01) for q in probs_p]
             plan = rtg.BatchPlan([op_p] * B, [q["sk"] for q in probs_p], [q["C"] for q in probs_p], [None] * B, prm)
+            tune = tune_plan(plan, args)
             r = time_variant(plan, args.steps, args.warmup, rtg, torch, rtg.KIND_PHI,
                              lambda inf: phi_bytes(n, 4, inf.iters))
             r["kernel"] = ("k_phi", "k_operator.hip", "2-D stencil of a general PSF + channel mix (float32)")
@@ -357,6 +373,7 @@ def main():
             prm = [rtg.make_params(args.m, rtg.F32, delta=q["delta"], eta=1.01, method=rtg.METHOD_GOLUB_KAHAN)
                    for q in probs]
             plan = rtg.BatchPlan([op] * B, [q["sk"] for q in probs], [q["C"] for q in probs], [None] * B, prm)
+            tune = tune_plan(plan, args)
             r = time_variant(plan, args.steps, args.warmup, rtg, torch, rtg.KIND_TILE,
                              lambda inf: gk_tile_bytes(n, 4, inf.iters))
             r["kernel"] = ("k_tile", "k_tile.hip", "one-term AXPY + store + MFMA mode-1/2 sketch "
@@ -367,6 +384,7 @@ def main():
             sk_id = rtg.setup_sketch(I1, I2, J)
             prm = [rtg.make_params(args.m, rtg.F32, delta=q["delta"], eta=1.01) for q in probs]
             plan = rtg.BatchPlan([op] * B, [sk_id] * B, [q["C"] for q in probs], [None] * B, prm)
+            tune = tune_plan(plan, args)
             r = time_variant(plan, args.steps, args.warmup, rtg, torch, rtg.KIND_GRAM,
                              lambda inf: frob_bytes(n, 4, inf.iters))
             r["kernel"] = ("k_gram", "k_gram.hip", "Frobenius inner products of the full tensors "
@@ -374,6 +392,7 @@ def main():
         elif v == "fp32_plain":
             prm = [rtg.make_params(args.m, rtg.F32, delta=q["delta"], eta=1.01) for q in probs]
             plan = rtg.BatchPlan([op] * B, [q["sk"] for q in probs], [q["C"] for q in probs], [None] * B, prm)
+            tune = tune_plan(plan, args)
             r = time_variant(plan, args.steps, args.warmup, rtg, torch, rtg.KIND_TILE,
                              lambda inf: tile_bytes(n, 4, inf.iters, False))
             r["kernel"] = ("k_tile", "k_tile.hip", "multi-AXPY + store + MFMA mode-1/2 sketch (float32 basis)")
@@ -382,12 +401,14 @@ def main():
                                    stop_res=(1.01 * q["delta"] if args.warm_stop == "discrepancy" else 0.0))
                    for q in probs]
             plan = rtg.BatchPlan([op] * B, [q["sk"] for q in probs], [q["C"] for q in probs], X0s, prm)
+            tune = tune_plan(plan, args, pre)
             r = time_variant(plan, args.steps, args.warmup, rtg, torch, rtg.KIND_STEP,
                              lambda inf: step_bytes(n, 2, inf.iters), pre=pre)
             r["kernel"] = ("k_step", "k_step.hip", "Arnoldi step: operator per tile + multi-AXPY + store + "
                                                    "dual MFMA sketch (bfloat16 basis)")
         if v not in ("fp32_psf", "bf16_uneven"):
             res = [rel_err(plan.outs[b], probs[b]["xt"]) for b in range(B)]
+        r["tune"] = tune
         r["re_mean"] = float(np.mean(res))
         r["re_p0"] = res[0]
         r["iters_mean"] = float(np.mean([i.iters for i in r["infos"]]))
@@ -438,9 +459,10 @@ def main():
             "avg_launch_us": 1e3 * H["k_ms"] / max(H["k_launches"], 1),
             "bytes_per_launch": bpl,
         },
+        "launch_shapes": H["tune"],
         "variants": {k: {"solves_per_s": v["solves_per_s"], "ms_per_step": v["ms_per_step"],
                          "re_mean": v["re_mean"], "re_problem0": v["re_p0"], "iters_mean": v["iters_mean"],
-                         "flags": v["flags"], "kernel": v["kernel"][0],
+                         "flags": v["flags"], "kernel": v["kernel"][0], "tune": v["tune"],
                          "kernel_gbs": (v["k_bytes"] / (v["k_ms"] * 1e-3) / 1e9 if v["k_ms"] > 0 else 0.0)}
                      for k, v in results.items()},
     }

@@ -241,6 +241,59 @@ size_t rtg_batch_workspace_bytes(int count, const rtg_problem* probs);
 int rtg_solve_batched(int count, const rtg_problem* probs, void* ws,
                       size_t ws_bytes, void* stream);
 
+/* ---- tile autotuner (the batching form's launch shapes) --------------------
+ * The launch shapes of a batch: every combination that the fields allow is
+ * a correct solve of the same problems (they change which thread computes
+ * what, not the arithmetic), so the choice is a matter of speed.  A process-
+ * wide table (host memory, guarded by a mutex) maps a batch's shape key --
+ * count, method, basis type and, per problem, the sizes, band half-widths,
+ * sketch sizes, operator kind, m and whether X0 is given -- to a choice;
+ * rtg_solve_batched and rtg_solve use the table's entry for their key, and
+ * the library defaults (every field -1) when there is none.
+ * Fields (-1: the default for that batch):
+ *   phi_jt        operator kernel: output channels per tile, 4 or 8
+ *   phi_slab      operator slab staging: 0 single-word loads, 1 16-byte loads
+ *                 (float32 inputs under 2^31 bytes), 2 asynchronous
+ *                 global-to-LDS loads (general PSF with J <= 3)
+ *   phi_toeplitz  1: the taps of Toeplitz bands in registers (separable
+ *                 operators whose bands are all Toeplitz, phi_slab >= 1);
+ *                 0: band rows streamed through LDS
+ *   tile_rows     tile kernel: 16-row sketch tiles per wave, 2 (used where
+ *                 the stacked sketch rows fit, else 4) or 4
+ *   step_rows     fused bfloat16 Arnoldi step: the same, 2 or 4
+ *   step_toeplitz fused step: 1 Toeplitz taps (all bands Toeplitz), 0 band rows */
+typedef struct {
+    int phi_jt;
+    int phi_slab;
+    int phi_toeplitz;
+    int tile_rows;
+    int step_rows;
+    int step_toeplitz;
+    int reserved[2];  /* zero */
+} rtg_tune;           /* 32 bytes */
+
+/* Time the batch's solve (the Arnoldi or Golub-Kahan loop; no projected
+ * solve, no assembly, the outputs X and info untouched) under candidate
+ * shapes -- the operator fields first, then the tile rows, then the fused
+ * step's fields, each group with the others at their best so far -- on
+ * stream, the minimum over reps >= 1 runs of each candidate (hipEvents),
+ * and record the fastest in the table.  Synchronous.  *chosen receives the
+ * choice with every field resolved (no -1), *best_ms (may be NULL) its
+ * time.  The workspace is that of rtg_batch_workspace_bytes; its contents
+ * are overwritten.  Argument errors as rtg_solve_batched. */
+int rtg_autotune_batched(int count, const rtg_problem* probs, void* ws,
+                         size_t ws_bytes, int reps, rtg_tune* chosen,
+                         double* best_ms, void* stream);
+/* Record a choice for the batch's key (RTG_E_ARG for a field outside the
+ * values above or one the batch cannot use: phi_slab 1 or 2 for inputs of
+ * 2^31 bytes or more, phi_slab 2 for a separable operator or J > 3,
+ * toeplitz fields for non-Toeplitz bands or a general PSF, nonzero reserved). */
+int rtg_tune_set(int count, const rtg_problem* probs, const rtg_tune* tune);
+/* The choice a solve of this batch would use, every field resolved. */
+int rtg_tune_get(int count, const rtg_problem* probs, rtg_tune* tune);
+/* Forget every recorded choice. */
+int rtg_tune_clear(void);
+
 /* ---- learned warm start ----------------------------------------------------
  * X0 = C + f(C), f = six 3x3 zero-padded convolutions 3 -> 32 -> 32 -> 32 ->
  * 32 -> 32 -> 3 with biases and ReLU after the first five (38,755

@@ -396,10 +396,10 @@ __global__ void __launch_bounds__(256) k_step(const Desc* __restrict__ descs, co
 // Only bfloat16-basis variants exist: with a float32 basis the solver forms
 // W with the operator kernel and uses the tile kernel (faster there).
 hipError_t launch_step(const Desc* d, const int* starts, int count, int total_tiles, int j, int rmax,
-                       int basis_bf16, int l1max, int toeplitz, hipStream_t s) {
+                       int basis_bf16, int l1max, int toeplitz, hipStream_t s, int rows) {
     if (!basis_bf16) return hipErrorInvalidValue;
     const int tier = rmax <= 4 ? 4 : (rmax <= 8 ? 8 : 12);
-    const bool small = 2 * ((l1max + 15) / 16) <= 8;
+    const bool small = 2 * ((l1max + 15) / 16) <= 8 && rows != 4;
 #define RTG_STEP(RR, RPV)                                                                               \
     if (toeplitz)                                                                                       \
         hipLaunchKernelGGL((k_step<RR, RPV, true>), dim3(total_tiles), dim3(256), 0, s, d, starts, count, j); \

@@ -382,12 +382,12 @@ __global__ void __launch_bounds__(256) k_tile(const Desc* __restrict__ descs,
 
 hipError_t launch_tile(const Desc* d, const int* starts, int count, int total_tiles, int mode,
                        int nterms, int dst_index, int basis_bf16, int src_bf16, int l1max, hipStream_t s,
-                       int first_term) {
+                       int first_term, int rows) {
 #define RTG_TILE(BBV, SPV, RPV)                                                                   \
     hipLaunchKernelGGL((k_tile<BBV, SPV, RPV>), dim3(total_tiles), dim3(256), 0, s, d, starts, count, \
                        mode, nterms, dst_index, first_term)
     const int rtiles = ((l1max + 15) / 16) * ((mode == TM_NEWV || mode == TM_GKNEW) ? 2 : 1);
-    const bool small = rtiles <= 8;
+    const bool small = rtiles <= 8 && rows != 4;
     if (basis_bf16) {
         const bool split = (mode == TM_SKETCH_SRC || mode == TM_SKETCH_W) && !src_bf16;
         if (split) { if (small) RTG_TILE(true, true, 2); else RTG_TILE(true, true, 4); }

@@ -24,6 +24,9 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <limits>
+#include <map>
+#include <mutex>
 #include <vector>
 
 struct rtg_op_s {
@@ -259,18 +262,24 @@ struct Plan {
     int stencil;       // every problem's operator is a general PSF (all or none)
     int phi_dma;       // operator slab loads: 1 = 16-byte (float32 inputs below 2^31 bytes),
                        // 2 = also asynchronous (and at most three channels), 0 = single-word
+    int phi_toep;      // operator: Toeplitz taps in registers
+    int step_toep;     // fused step: Toeplitz taps
+    int tile_rows;     // sketch tiles per wave of the tile kernel (2 where they fit, or 4)
+    int step_rows;     // the same for the fused step
     Desc* d_desc_r;    // restart cycles: the descriptors with X0 = X (null without restarts)
 };
 
 // descs holds nsides groups of count problems (the same shapes in each group);
-// with restart, the restart-cycle copies (X0 = X, R0 from W) follow them
+// with restart, the restart-cycle copies (X0 = X, R0 from W) follow them.
+// tune: the launch shapes (resolved, no -1), clamped to what the batch can
+// use; null for the library defaults.
 int build_plan(std::vector<Desc>& descs, void* ws, hipStream_t s, Plan& plan, int nsides = 1,
-               bool restart = false) {
+               bool restart = false, const rtg_tune* tune = nullptr) {
     const int count = (int)descs.size() / nsides;
     std::vector<int> starts((size_t)NKIND * (count + 1), 0);
     int maxJ = 1;
     for (auto& d : descs) maxJ = std::max(maxJ, d.J);
-    plan.phi_jt = phi_jt(maxJ);
+    plan.phi_jt = (tune && (tune->phi_jt == 4 || tune->phi_jt == 8)) ? tune->phi_jt : phi_jt(maxJ);
     for (auto& d : descs)
         if (d.ntile[KIND_PHI] > 0) d.ntile[KIND_PHI] = phi_tiles(d.I1, d.I2, d.J, plan.phi_jt);
     plan.rmax = 1;
@@ -302,6 +311,17 @@ int build_plan(std::vector<Desc>& descs, void* ws, hipStream_t s, Plan& plan, in
         plan.rmax = std::max(plan.rmax, std::max(d.r1, d.r2));
         if (!d.unsketched) plan.l1max = std::max(plan.l1max, d.l1);
         plan.compose_max = std::max(plan.compose_max, (int)compose_mode1_entries(d.l1, d.I1) + d.l2 * d.I2 + d.l3 * d.J);
+    }
+    plan.phi_toep = plan.toeplitz;
+    plan.step_toep = plan.toeplitz;
+    plan.tile_rows = 2;
+    plan.step_rows = 2;
+    if (tune) {
+        if (tune->phi_slab >= 0) plan.phi_dma = std::min(plan.phi_dma, tune->phi_slab);
+        if (tune->phi_toeplitz >= 0) plan.phi_toep = plan.toeplitz && tune->phi_toeplitz;
+        if (tune->step_toeplitz >= 0) plan.step_toep = plan.toeplitz && tune->step_toeplitz;
+        if (tune->tile_rows == 4) plan.tile_rows = 4;
+        if (tune->step_rows == 4) plan.step_rows = 4;
     }
     char* base = (char*)ws;
     plan.d_desc = (Desc*)base;
@@ -394,21 +414,21 @@ int run_solver(const Plan& plan, int count, int mmax, int bf16, bool any_x0, boo
         const int us = 1;
         if (any_x0)
             RTG_TIMED(0, launch_phi(dd, sp, count, plan.total[KIND_PHI], PS_X0, 0, plan.rmax, plan.phi_jt, 0,
-                                    s, plan.stencil, plan.phi_dma, plan.toeplitz));
+                                    s, plan.stencil, plan.phi_dma, plan.phi_toep));
         RTG_TIMED(2, launch_gram(dd, sg, count, plan.total[KIND_GRAM], GM_START, cycle, nullptr, s, us));
-        RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_NEWV, 0, 0, bf16, 0, plan.l1max, s));
+        RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_NEWV, 0, 0, bf16, 0, plan.l1max, s, 0, plan.tile_rows));
         for (int j = 1; j <= mmax; ++j) {
             RTG_TIMED(0, launch_phi(dd, sp, count, plan.total[KIND_PHI], PS_BASIS, j - 1, plan.rmax,
-                                    plan.phi_jt, bf16, s, plan.stencil, plan.phi_dma, plan.toeplitz));
+                                    plan.phi_jt, bf16, s, plan.stencil, plan.phi_dma, plan.phi_toep));
             RTG_TIMED(2, launch_gram(dd, sg, count, plan.total[KIND_GRAM], GM_STEP, j, nullptr, s, us));
             if (j < mmax || last_newv)
                 RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_NEWV, j, j, bf16, 0,
-                                         plan.l1max, s));
+                                         plan.l1max, s, 0, plan.tile_rows));
         }
         if (solve) {
             RTG_TIMED(3, launch_solve(dd, count, mmax, s));
             RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_ASSEMBLE, 0, 0, bf16, 0,
-                                     plan.l1max, s));
+                                     plan.l1max, s, 0, plan.tile_rows));
         }
         return RTG_OK;
     }
@@ -417,33 +437,33 @@ int run_solver(const Plan& plan, int count, int mmax, int bf16, bool any_x0, boo
         // sketches W, then the Gram step and V_{j+1} with its sketch.
         if (any_x0)
             RTG_TIMED(0, launch_phi(dd, sp, count, plan.total[KIND_PHI], PS_X0, 0, plan.rmax, plan.phi_jt, 0,
-                                    s, 1, plan.phi_dma, plan.toeplitz));
+                                    s, 1, plan.phi_dma, plan.phi_toep));
         RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_SKETCH_SRC, 0, 0, bf16, 0,
-                                 plan.l1max, s));
+                                 plan.l1max, s, 0, plan.tile_rows));
         RTG_TIMED(2, launch_gram(dd, sg, count, plan.total[KIND_GRAM], GM_START, cycle, nullptr, s));
-        RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_NEWV, 0, 0, bf16, 0, plan.l1max, s));
+        RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_NEWV, 0, 0, bf16, 0, plan.l1max, s, 0, plan.tile_rows));
         for (int j = 1; j <= mmax; ++j) {
             RTG_TIMED(0, launch_phi(dd, sp, count, plan.total[KIND_PHI], PS_BASIS, j - 1, plan.rmax,
-                                    plan.phi_jt, bf16, s, 1, plan.phi_dma, plan.toeplitz));
+                                    plan.phi_jt, bf16, s, 1, plan.phi_dma, plan.phi_toep));
             RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_SKETCH_W, 0, 0, bf16, 0,
-                                     plan.l1max, s));
+                                     plan.l1max, s, 0, plan.tile_rows));
             RTG_TIMED(2, launch_gram(dd, sg, count, plan.total[KIND_GRAM], GM_STEP, j, nullptr, s));
             if (j < mmax || last_newv)
                 RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_NEWV, j, j, bf16, 0,
-                                         plan.l1max, s));
+                                         plan.l1max, s, 0, plan.tile_rows));
         }
         if (solve) {
             RTG_TIMED(3, launch_solve(dd, count, mmax, s));
             RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_ASSEMBLE, 0, 0, bf16, 0,
-                                     plan.l1max, s));
+                                     plan.l1max, s, 0, plan.tile_rows));
         }
         return RTG_OK;
     }
     if (cycle == 0) RTG_HIP(launch_compose(dd, count, plan.compose_max, s));   // restart cycles reuse them
-    if (any_x0) RTG_TIMED(0, launch_phi(dd, sp, count, plan.total[KIND_PHI], PS_X0, 0, plan.rmax, plan.phi_jt, 0, s, 0, plan.phi_dma, plan.toeplitz));
-    RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_SKETCH_SRC, 0, 0, bf16, 0, plan.l1max, s));
+    if (any_x0) RTG_TIMED(0, launch_phi(dd, sp, count, plan.total[KIND_PHI], PS_X0, 0, plan.rmax, plan.phi_jt, 0, s, 0, plan.phi_dma, plan.phi_toep));
+    RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_SKETCH_SRC, 0, 0, bf16, 0, plan.l1max, s, 0, plan.tile_rows));
     RTG_TIMED(2, launch_gram(dd, sg, count, plan.total[KIND_GRAM], GM_START, cycle, nullptr, s));
-    RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_NEWV, 0, 0, bf16, 0, plan.l1max, s));
+    RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_NEWV, 0, 0, bf16, 0, plan.l1max, s, 0, plan.tile_rows));
     for (int j = 1; j <= mmax; ++j) {
         // S(V_j) and S(Phi(V_j)) come from the pass that formed V_j.  With a
         // bfloat16 basis the step kernel recomputes Phi(V_j) tile by tile (W
@@ -456,18 +476,18 @@ int run_solver(const Plan& plan, int count, int mmax, int bf16, bool any_x0, boo
         if (j < mmax || last_newv) {
             if (bf16 && plan.step_ok) {
                 RTG_TIMED(4, launch_step(dd, st, count, plan.total[KIND_TILE], j, plan.rmax, bf16, plan.l1max,
-                                         plan.toeplitz, s));
+                                         plan.step_toep, s, plan.step_rows));
             } else {
                 RTG_TIMED(0, launch_phi(dd, sp, count, plan.total[KIND_PHI], PS_BASIS, j - 1, plan.rmax,
-                                        plan.phi_jt, bf16, s, 0, plan.phi_dma, plan.toeplitz));
+                                        plan.phi_jt, bf16, s, 0, plan.phi_dma, plan.phi_toep));
                 RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_NEWV, j, j, bf16, 0,
-                                         plan.l1max, s));
+                                         plan.l1max, s, 0, plan.tile_rows));
             }
         }
     }
     if (solve) {
         RTG_TIMED(3, launch_solve(dd, count, mmax, s));
-        RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_ASSEMBLE, 0, 0, bf16, 0, plan.l1max, s));
+        RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_ASSEMBLE, 0, 0, bf16, 0, plan.l1max, s, 0, plan.tile_rows));
     }
     return RTG_OK;
 }
@@ -488,27 +508,27 @@ int run_gk(const Plan& plan, int count, int mmax, int bf16, bool any_x0, bool so
     const int tp = plan.total[KIND_PHI], tt = plan.total[KIND_TILE], tg = plan.total[KIND_GRAM];
     RTG_HIP(launch_init(dV, count, s));
     RTG_HIP(launch_compose(plan.d_desc, 2 * count, plan.compose_max, s));
-    if (any_x0) RTG_TIMED(0, launch_phi(dV, sp, count, tp, PS_X0, 0, plan.rmax, plan.phi_jt, 0, s, 0, plan.phi_dma, plan.toeplitz));
+    if (any_x0) RTG_TIMED(0, launch_phi(dV, sp, count, tp, PS_X0, 0, plan.rmax, plan.phi_jt, 0, s, 0, plan.phi_dma, plan.phi_toep));
     // beta_1 = ||R0||_Theta, U_1 = R0 / beta_1 (with S(U_1) and S(Phi^T(U_1)))
-    RTG_TIMED(1, launch_tile(dU, st, count, tt, TM_SKETCH_SRC, 0, 0, bf16, 0, plan.l1max, s));
+    RTG_TIMED(1, launch_tile(dU, st, count, tt, TM_SKETCH_SRC, 0, 0, bf16, 0, plan.l1max, s, 0, plan.tile_rows));
     RTG_TIMED(2, launch_gram(dU, sg, count, tg, GM_START, 0, nullptr, s));
-    RTG_TIMED(1, launch_tile(dU, st, count, tt, TM_NEWV, 0, 0, bf16, 0, plan.l1max, s));
+    RTG_TIMED(1, launch_tile(dU, st, count, tt, TM_NEWV, 0, 0, bf16, 0, plan.l1max, s, 0, plan.tile_rows));
     for (int c = 1; c <= mmax; ++c) {
         // alpha_c; V_c = (Phi^T(U_c) - beta_c V_{c-1}) / alpha_c
         RTG_TIMED(2, launch_gram(dU, sg, count, tg, GM_GK, c, nullptr, s));
-        RTG_TIMED(0, launch_phi(dU, sp, count, tp, PS_BASIS, c - 1, plan.rmax, plan.phi_jt, bf16, s, 0, plan.phi_dma, plan.toeplitz));
+        RTG_TIMED(0, launch_phi(dU, sp, count, tp, PS_BASIS, c - 1, plan.rmax, plan.phi_jt, bf16, s, 0, plan.phi_dma, plan.phi_toep));
         RTG_TIMED(1, launch_tile(dV, st, count, tt, TM_GKNEW, c - 1, c - 1, bf16, 0, plan.l1max, s,
                                  c >= 2 ? c - 2 : 0));
         // beta_{c+1}, column c of B, Givens and stop test; U_{c+1} = (Phi(V_c) - alpha_c U_c) / beta_{c+1}
         RTG_TIMED(2, launch_gram(dV, sg, count, tg, GM_GK, c, nullptr, s));
         if (c < mmax || !solve) {   // the bidiagonalisation alone also forms U_{m+1}
-            RTG_TIMED(0, launch_phi(dV, sp, count, tp, PS_BASIS, c - 1, plan.rmax, plan.phi_jt, bf16, s, 0, plan.phi_dma, plan.toeplitz));
-            RTG_TIMED(1, launch_tile(dU, st, count, tt, TM_GKNEW, c, c, bf16, 0, plan.l1max, s, c - 1));
+            RTG_TIMED(0, launch_phi(dV, sp, count, tp, PS_BASIS, c - 1, plan.rmax, plan.phi_jt, bf16, s, 0, plan.phi_dma, plan.phi_toep));
+            RTG_TIMED(1, launch_tile(dU, st, count, tt, TM_GKNEW, c, c, bf16, 0, plan.l1max, s, c - 1, plan.tile_rows));
         }
     }
     if (solve) {
         RTG_TIMED(3, launch_solve(dV, count, mmax, s));
-        RTG_TIMED(1, launch_tile(dV, st, count, tt, TM_ASSEMBLE, 0, 0, bf16, 0, plan.l1max, s));
+        RTG_TIMED(1, launch_tile(dV, st, count, tt, TM_ASSEMBLE, 0, 0, bf16, 0, plan.l1max, s, 0, plan.tile_rows));
     }
     return RTG_OK;
 }
@@ -823,7 +843,7 @@ int rtg_sketch(rtg_sk sk, int x_dtype, const void* X, float* SX, void* ws, size_
     int rc = build_plan(descs, ws, s, plan);
     if (rc) return rc;
     RTG_HIP(launch_tile(plan.d_desc, starts_of(plan, KIND_TILE, 1), 1, plan.total[KIND_TILE], TM_SKETCH_SRC,
-                        0, 0, x_dtype == RTG_BF16, x_dtype == RTG_BF16, plan.l1max, s));
+                        0, 0, x_dtype == RTG_BF16, x_dtype == RTG_BF16, plan.l1max, s, 0, plan.tile_rows));
     RTG_HIP(launch_gram(plan.d_desc, starts_of(plan, KIND_GRAM, 1), 1, plan.total[KIND_GRAM], GM_SKETCH_OUT,
                         0, SX, s));
     return RTG_OK;
@@ -931,7 +951,19 @@ int rtg_golub_kahan(rtg_op op, rtg_sk sk, const float* R0, int m, int basis_dtyp
     return RTG_OK;
 }
 
-int rtg_solve_batched(int count, const rtg_problem* probs, void* ws, size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Descriptors and loop bounds of one batch, after the checks of
+// rtg_solve_batched.
+struct Batch {
+    std::vector<Desc> descs;
+    int nsides = 1, rmax = 0, mmax = 0, bf16 = 0;
+    bool gk = false, any_x0 = false;
+};
+
+int prepare_batch(int count, const rtg_problem* probs, void* ws, size_t ws_bytes, Batch& bt) {
     if (count < 1 || !probs || !ws || !aligned16(ws)) return RTG_E_ARG;
     int bf16 = -1;
     const int method = probs[0].params.method;
@@ -953,19 +985,20 @@ int rtg_solve_batched(int count, const rtg_problem* probs, void* ws, size_t ws_b
     const size_t need = rtg_batch_workspace_bytes(count, probs);
     if (need == 0) return RTG_E_SHAPE;
     if (ws_bytes < need) return RTG_E_WORKSPACE;
-    hipStream_t s = (hipStream_t)stream;
-    const int nsides = gk ? 2 : 1;
-    int rmax = 0;
-    for (int p = 0; p < count; ++p) rmax = std::max(rmax, probs[p].params.restarts);
-    std::vector<Desc> descs((size_t)count * nsides);
-    size_t off = plan_bytes(count, nsides, rmax > 0);
-    int mmax = 0;
-    bool any_x0 = false;
+    bt.gk = gk;
+    bt.bf16 = bf16;
+    bt.nsides = gk ? 2 : 1;
+    bt.rmax = 0;
+    for (int p = 0; p < count; ++p) bt.rmax = std::max(bt.rmax, probs[p].params.restarts);
+    bt.descs.assign((size_t)count * bt.nsides, Desc{});
+    size_t off = plan_bytes(count, bt.nsides, bt.rmax > 0);
+    bt.mmax = 0;
+    bt.any_x0 = false;
     for (int p = 0; p < count; ++p) {
         const rtg_problem& q = probs[p];
         Layout L = problem_layout(q.op, q.sk, q.params.m, bf16);
         char* base = (char*)ws + off;
-        Desc& d = descs[p];
+        Desc& d = bt.descs[p];
         fill_desc(d, q.op, q.sk, q.params.m, bf16, base, L);
         set_params(d, &q.params);
         d.C = q.C;
@@ -975,22 +1008,263 @@ int rtg_solve_batched(int count, const rtg_problem* probs, void* ws, size_t ws_b
         d.R0src = q.X0 ? (const void*)d.W : (const void*)q.C;
         off += L.total;
         if (gk) {
-            fill_gk_sides(d, descs[(size_t)count + p], q.op, q.sk, q.params.m, bf16, (char*)ws + off);
+            fill_gk_sides(d, bt.descs[(size_t)count + p], q.op, q.sk, q.params.m, bf16, (char*)ws + off);
             off += gk_extra_layout(q.op, q.sk, q.params.m, bf16).total;
         }
-        mmax = std::max(mmax, q.params.m);
-        any_x0 = any_x0 || q.X0 != nullptr;
+        bt.mmax = std::max(bt.mmax, q.params.m);
+        bt.any_x0 = bt.any_x0 || q.X0 != nullptr;
     }
-    Plan plan;
-    int rc = build_plan(descs, ws, s, plan, nsides, rmax > 0);
+    return RTG_OK;
+}
+
+// ---- launch shapes per batch shape (the autotuner's table)
+struct TuneTable {
+    std::mutex mu;
+    std::map<std::vector<long long>, rtg_tune> entries;
+};
+
+TuneTable& tune_table() {
+    static TuneTable t;
+    return t;
+}
+
+// The shape key of a batch (handles already checked).
+std::vector<long long> batch_key(int count, const rtg_problem* probs) {
+    std::vector<long long> k{count, probs[0].params.method, probs[0].params.basis_dtype};
+    for (int p = 0; p < count; ++p) {
+        const rtg_op_s* op = probs[p].op;
+        const rtg_sk_s* sk = probs[p].sk;
+        const long long row[] = {op->I1, op->I2, op->J, op->r1, op->r2, op->rB, sk->l1, sk->l2, sk->l3,
+                                 sk->identity, op->st != nullptr, op->toeplitz, probs[p].params.m,
+                                 probs[p].X0 != nullptr};
+        k.insert(k.end(), row, row + sizeof(row) / sizeof(row[0]));
+    }
+    return k;
+}
+
+// What a batch can use: slab staging up to slab_cap, Toeplitz taps when
+// toep_ok, and where the operator kernel, the fused step and the tile
+// kernel's two-row form run at all.
+struct TuneCaps {
+    int maxJ = 1, slab_cap = 2;
+    bool toep_ok = true, stencil = false, phi_runs = true, step_runs = false;
+};
+
+TuneCaps tune_caps(int count, const rtg_problem* probs) {
+    TuneCaps c;
+    c.stencil = probs[0].op->st != nullptr;
+    bool big = false, bf16 = probs[0].params.basis_dtype == RTG_BF16, step_ok = true, x0 = false;
+    bool unsk = probs[0].sk->identity != 0;
+    for (int p = 0; p < count; ++p) {
+        const rtg_op_s* op = probs[p].op;
+        const size_t n = (size_t)op->I1 * op->I2 * op->J;
+        c.maxJ = std::max(c.maxJ, op->J);
+        big = big || n * 4 > 0x7FFFFFFFull;
+        step_ok = step_ok && n * 2 <= 0x7FFFFFFFull && op->a1p[0] != nullptr &&
+                  frag_elems(probs[p].sk->l1, op->I1, FRAG_K_BF16) * 4 <= 0x7FFFFFFFull;
+        c.toep_ok = c.toep_ok && op->toeplitz;
+        x0 = x0 || probs[p].X0 != nullptr;
+    }
+    c.toep_ok = c.toep_ok && !c.stencil;
+    c.slab_cap = big ? 0 : ((c.stencil && c.maxJ <= 3) ? 2 : 1);
+    const bool gk = probs[0].params.method == RTG_METHOD_GOLUB_KAHAN;
+    c.step_runs = bf16 && step_ok && !c.stencil && !unsk && !gk;
+    c.phi_runs = !c.step_runs || x0;
+    return c;
+}
+
+// Every -1 replaced by the default; RTG_E_ARG for a value outside the
+// documented set or one the batch cannot use.
+int resolve_tune(const TuneCaps& c, const rtg_tune& in, rtg_tune& out) {
+    if (in.reserved[0] != 0 || in.reserved[1] != 0) return RTG_E_ARG;
+    auto one_of = [](int v, int a, int b) { return v == -1 || v == a || v == b; };
+    if (!one_of(in.phi_jt, 4, 8) || !one_of(in.tile_rows, 2, 4) || !one_of(in.step_rows, 2, 4)) return RTG_E_ARG;
+    if (!one_of(in.phi_toeplitz, 0, 1) || !one_of(in.step_toeplitz, 0, 1)) return RTG_E_ARG;
+    if (in.phi_slab < -1 || in.phi_slab > c.slab_cap) return RTG_E_ARG;
+    if ((in.phi_toeplitz == 1 || in.step_toeplitz == 1) && !c.toep_ok) return RTG_E_ARG;
+    out = rtg_tune{};
+    out.phi_jt = in.phi_jt >= 0 ? in.phi_jt : phi_jt(c.maxJ);
+    out.phi_slab = in.phi_slab >= 0 ? in.phi_slab : c.slab_cap;
+    if (in.phi_toeplitz == 1 && out.phi_slab < 1) return RTG_E_ARG;
+    out.phi_toeplitz = in.phi_toeplitz >= 0 ? in.phi_toeplitz : ((c.toep_ok && out.phi_slab >= 1) ? 1 : 0);
+    out.tile_rows = in.tile_rows >= 0 ? in.tile_rows : 2;
+    out.step_rows = in.step_rows >= 0 ? in.step_rows : 2;
+    out.step_toeplitz = in.step_toeplitz >= 0 ? in.step_toeplitz : (c.toep_ok ? 1 : 0);
+    return RTG_OK;
+}
+
+rtg_tune tune_unset() {
+    rtg_tune t;
+    t.phi_jt = t.phi_slab = t.phi_toeplitz = t.tile_rows = t.step_rows = t.step_toeplitz = -1;
+    t.reserved[0] = t.reserved[1] = 0;
+    return t;
+}
+
+// the recorded choice for a batch (unset fields when there is none)
+rtg_tune lookup_tune(int count, const rtg_problem* probs) {
+    const auto key = batch_key(count, probs);
+    TuneTable& tt = tune_table();
+    std::lock_guard<std::mutex> lock(tt.mu);
+    auto it = tt.entries.find(key);
+    return it == tt.entries.end() ? tune_unset() : it->second;
+}
+
+// The Arnoldi (or Golub-Kahan) loop of a prepared batch, no solve: what the
+// autotuner times.
+int run_loop(const Plan& plan, const Batch& bt, int count, hipStream_t s) {
+    if (bt.gk) return run_gk(plan, count, bt.mmax, bt.bf16, bt.any_x0, false, s);
+    return run_solver(plan, count, bt.mmax, bt.bf16, bt.any_x0, false, false, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int rtg_solve_batched(int count, const rtg_problem* probs, void* ws, size_t ws_bytes, void* stream) {
+    Batch bt;
+    int rc = prepare_batch(count, probs, ws, ws_bytes, bt);
     if (rc) return rc;
-    if (gk) return run_gk(plan, count, mmax, bf16, any_x0, true, s);
-    if ((rc = run_solver(plan, count, mmax, bf16, any_x0, true, false, s))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    rtg_tune tune;
+    if ((rc = resolve_tune(tune_caps(count, probs), lookup_tune(count, probs), tune))) return rc;
+    Plan plan;
+    if ((rc = build_plan(bt.descs, ws, s, plan, bt.nsides, bt.rmax > 0, &tune))) return rc;
+    if (bt.gk) return run_gk(plan, count, bt.mmax, bt.bf16, bt.any_x0, true, s);
+    if ((rc = run_solver(plan, count, bt.mmax, bt.bf16, bt.any_x0, true, false, s))) return rc;
     // restarted RTG-GMRES: every cycle is launched for the whole batch; a
     // problem whose residual is below eps, or whose restarts are spent, sits
     // the cycle out on the device (no host synchronisation)
-    for (int c = 1; c <= rmax; ++c)
-        if ((rc = run_solver(plan, count, mmax, bf16, true, true, false, s, c))) return rc;
+    for (int c = 1; c <= bt.rmax; ++c)
+        if ((rc = run_solver(plan, count, bt.mmax, bt.bf16, true, true, false, s, c))) return rc;
+    return RTG_OK;
+}
+
+int rtg_tune_set(int count, const rtg_problem* probs, const rtg_tune* tune) {
+    if (count < 1 || !probs || !tune) return RTG_E_ARG;
+    for (int p = 0; p < count; ++p) {
+        int rc = check_pair(probs[p].op, probs[p].sk);
+        if (rc) return rc;
+    }
+    rtg_tune resolved;
+    int rc = resolve_tune(tune_caps(count, probs), *tune, resolved);
+    if (rc) return rc;
+    TuneTable& tt = tune_table();
+    std::lock_guard<std::mutex> lock(tt.mu);
+    tt.entries[batch_key(count, probs)] = resolved;
+    return RTG_OK;
+}
+
+int rtg_tune_get(int count, const rtg_problem* probs, rtg_tune* tune) {
+    if (count < 1 || !probs || !tune) return RTG_E_ARG;
+    for (int p = 0; p < count; ++p) {
+        int rc = check_pair(probs[p].op, probs[p].sk);
+        if (rc) return rc;
+    }
+    return resolve_tune(tune_caps(count, probs), lookup_tune(count, probs), *tune);
+}
+
+int rtg_tune_clear(void) {
+    TuneTable& tt = tune_table();
+    std::lock_guard<std::mutex> lock(tt.mu);
+    tt.entries.clear();
+    return RTG_OK;
+}
+
+int rtg_autotune_batched(int count, const rtg_problem* probs, void* ws, size_t ws_bytes, int reps,
+                         rtg_tune* chosen, double* best_ms, void* stream) {
+    if (reps < 1 || !chosen) return RTG_E_ARG;
+    Batch bt;
+    int rc = prepare_batch(count, probs, ws, ws_bytes, bt);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const TuneCaps caps = tune_caps(count, probs);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return RTG_E_HIP;
+    }
+    // one untimed run (code objects loaded, caches warm), then the minimum
+    // over reps timed runs
+    auto time_of = [&](const rtg_tune& t, double& ms) -> int {
+        std::vector<Desc> descs(bt.descs);
+        Plan plan;
+        int r = build_plan(descs, ws, s, plan, bt.nsides, false, &t);
+        if (r) return r;
+        if ((r = run_loop(plan, bt, count, s))) return r;
+        ms = std::numeric_limits<double>::infinity();
+        for (int k = 0; k < reps; ++k) {
+            if (hipEventRecord(e0, s) != hipSuccess) return RTG_E_HIP;
+            if ((r = run_loop(plan, bt, count, s))) return r;
+            float t_ms = 0.f;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&t_ms, e0, e1) != hipSuccess)
+                return RTG_E_HIP;
+            ms = std::min(ms, (double)t_ms);
+        }
+        return RTG_OK;
+    };
+    rtg_tune best;
+    double best_t = 0.0;
+    rc = resolve_tune(caps, tune_unset(), best);
+    if (!rc) rc = time_of(best, best_t);
+    // one group of fields at a time, the others at their best so far
+    auto try_group = [&](const std::vector<rtg_tune>& cands) -> int {
+        for (const rtg_tune& c : cands) {
+            double t = 0.0;
+            int r = time_of(c, t);
+            if (r) return r;
+            if (t < best_t) {
+                best_t = t;
+                best = c;
+            }
+        }
+        return RTG_OK;
+    };
+    if (!rc && caps.phi_runs) {
+        std::vector<rtg_tune> cands;
+        for (int jt : {4, 8}) {
+            if (jt == 8 && caps.maxJ <= 4) continue;   // half of every tile would be empty
+            for (int slab = 0; slab <= caps.slab_cap; ++slab)
+                for (int tp = 0; tp <= ((caps.toep_ok && slab >= 1) ? 1 : 0); ++tp) {
+                    rtg_tune c = best;
+                    c.phi_jt = jt;
+                    c.phi_slab = slab;
+                    c.phi_toeplitz = tp;
+                    cands.push_back(c);
+                }
+        }
+        rc = try_group(cands);
+    }
+    if (!rc) {
+        std::vector<rtg_tune> cands;
+        for (int rows : {2, 4}) {
+            rtg_tune c = best;
+            c.tile_rows = rows;
+            cands.push_back(c);
+        }
+        rc = try_group(cands);
+    }
+    if (!rc && caps.step_runs) {
+        std::vector<rtg_tune> cands;
+        for (int rows : {2, 4})
+            for (int tp = 0; tp <= (caps.toep_ok ? 1 : 0); ++tp) {
+                rtg_tune c = best;
+                c.step_rows = rows;
+                c.step_toeplitz = tp;
+                cands.push_back(c);
+            }
+        rc = try_group(cands);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    {
+        TuneTable& tt = tune_table();
+        std::lock_guard<std::mutex> lock(tt.mu);
+        tt.entries[batch_key(count, probs)] = best;
+    }
+    *chosen = best;
+    if (best_ms) *best_ms = best_t;
     return RTG_OK;
 }
 

@@ -263,9 +263,11 @@ hipError_t launch_phi_single(int I1, int I2, int J, int r1, int r2, int rB, cons
                              const void* src, int bf16_in, const float* C, float* dst, hipStream_t s);
 hipError_t launch_tile(const Desc* d, const int* starts, int count, int total_tiles,
                        int mode, int nterms, int dst_index, int basis_bf16, int src_bf16,
-                       int l1max, hipStream_t s, int first_term = 0);
+                       int l1max, hipStream_t s, int first_term = 0, int rows = 2);
+// rows (tile and step kernels): 16-row sketch tiles per wave, 2 where the
+// stacked sketch rows fit (the default), or 4
 hipError_t launch_step(const Desc* d, const int* starts, int count, int total_tiles, int j, int rmax,
-                       int basis_bf16, int l1max, int toeplitz, hipStream_t s);
+                       int basis_bf16, int l1max, int toeplitz, hipStream_t s, int rows = 2);
 hipError_t launch_gram(const Desc* d, const int* starts, int count, int total_tiles,
                        int mode, int j, float* sketch_out, hipStream_t s, int unsketched = 0);
 hipError_t launch_solve(const Desc* d, int count, int mmax, hipStream_t s);

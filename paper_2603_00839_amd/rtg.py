@@ -49,6 +49,27 @@ class Problem(ctypes.Structure):
                 ("info", ctypes.c_void_p)]
 
 
+class Tune(ctypes.Structure):
+    """Launch shapes of a batch (rtg_tune); -1 = the library default."""
+    _fields_ = [("phi_jt", ctypes.c_int), ("phi_slab", ctypes.c_int), ("phi_toeplitz", ctypes.c_int),
+                ("tile_rows", ctypes.c_int), ("step_rows", ctypes.c_int), ("step_toeplitz", ctypes.c_int),
+                ("reserved", ctypes.c_int * 2)]
+
+    FIELDS = ("phi_jt", "phi_slab", "phi_toeplitz", "tile_rows", "step_rows", "step_toeplitz")
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f in self.FIELDS}
+
+
+def make_tune(**fields) -> Tune:
+    t = Tune()
+    for f in Tune.FIELDS:
+        setattr(t, f, int(fields.pop(f, -1)))
+    if fields:
+        raise RTGError(f"unknown tune fields {sorted(fields)}")
+    return t
+
+
 def header_symbols() -> List[str]:
     """Entry points declared in include/rtg.h."""
     with open(HEADER) as f:
@@ -82,6 +103,11 @@ def load_library():
         "rtg_solve": (c_int, [c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(Params), c_vp, c_sz, c_vp, c_vp, c_vp]),
         "rtg_batch_workspace_bytes": (c_sz, [c_int, ctypes.POINTER(Problem)]),
         "rtg_solve_batched": (c_int, [c_int, ctypes.POINTER(Problem), c_vp, c_sz, c_vp]),
+        "rtg_autotune_batched": (c_int, [c_int, ctypes.POINTER(Problem), c_vp, c_sz, c_int, ctypes.POINTER(Tune),
+                                         ctypes.POINTER(c_d), c_vp]),
+        "rtg_tune_set": (c_int, [c_int, ctypes.POINTER(Problem), ctypes.POINTER(Tune)]),
+        "rtg_tune_get": (c_int, [c_int, ctypes.POINTER(Problem), ctypes.POINTER(Tune)]),
+        "rtg_tune_clear": (c_int, []),
         "rtg_cnn_state_bytes": (c_sz, []),
         "rtg_cnn_workspace_bytes": (c_sz, [c_int, c_int, c_int]),
         "rtg_cnn_init": (c_int, [c_vp, fp, c_vp]),
@@ -453,6 +479,32 @@ class BatchPlan:
     def infos(self) -> List[Info]:
         raw = self.info.cpu().numpy()
         return [Info.from_buffer_copy(raw[p].tobytes()) for p in range(self.count)]
+
+    def autotune(self, reps: int = 3):
+        """Time candidate launch shapes on this batch (rtg_autotune_batched)
+        and record the fastest for every later run of a batch of the same
+        shapes; returns (Tune, best_ms).  Synchronous; the outputs are not
+        written."""
+        t, ms = Tune(), ctypes.c_double()
+        _check(lib().rtg_autotune_batched(self.count, self.arr, _ptr(self.ws), self.ws.numel(), int(reps),
+                                          ctypes.byref(t), ctypes.byref(ms), _stream()),
+               "rtg_autotune_batched")
+        return t, ms.value
+
+    def set_tune(self, tune: Tune):
+        """Record launch shapes for batches of these shapes (rtg_tune_set)."""
+        _check(lib().rtg_tune_set(self.count, self.arr, ctypes.byref(tune)), "rtg_tune_set")
+
+    def tune(self) -> Tune:
+        """The launch shapes a run of this batch uses (rtg_tune_get)."""
+        t = Tune()
+        _check(lib().rtg_tune_get(self.count, self.arr, ctypes.byref(t)), "rtg_tune_get")
+        return t
+
+
+def tune_clear():
+    """Forget every recorded launch-shape choice (rtg_tune_clear)."""
+    _check(lib().rtg_tune_clear(), "rtg_tune_clear")
 
 
 def solve_batched(ops, sks, Cs, X0s, params, outs=None) -> BatchPlan:

@@ -76,3 +76,27 @@ def test_params_struct_layout_matches_header():
     assert rtg.Params.restarts.offset == 4 + 4 + 5 * 8 + 8
     assert ctypes.sizeof(rtg.Info) == 4 + 4 + 4 * 8
     assert rtg.Problem.params.offset == 5 * 8
+
+
+def test_tune_struct_layout_matches_header():
+    assert ctypes.sizeof(rtg.Tune) == 32
+    for i, f in enumerate(rtg.Tune.FIELDS):
+        assert getattr(rtg.Tune, f).offset == 4 * i
+    t = rtg.make_tune(tile_rows=4)
+    assert t.as_dict() == dict(phi_jt=-1, phi_slab=-1, phi_toeplitz=-1, tile_rows=4, step_rows=-1, step_toeplitz=-1)
+    with pytest.raises(rtg.RTGError):
+        rtg.make_tune(rows=2)
+
+
+def test_tune_calls_check_arguments_on_the_host(lib):
+    t = rtg.Tune()
+    ms = ctypes.c_double()
+    assert lib.rtg_tune_clear() == 0
+    assert lib.rtg_tune_set(0, None, ctypes.byref(t)) == -1
+    assert lib.rtg_tune_get(1, None, ctypes.byref(t)) == -1
+    assert lib.rtg_autotune_batched(1, None, None, 0, 1, ctypes.byref(t), ctypes.byref(ms), None) == -1
+    # a problem with null handles
+    arr = (rtg.Problem * 1)()
+    assert lib.rtg_tune_set(1, arr, ctypes.byref(t)) == -1
+    assert lib.rtg_tune_get(1, arr, None) == -1
+    assert lib.rtg_autotune_batched(1, arr, None, 0, 0, ctypes.byref(t), None, None) == -1
