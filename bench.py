@@ -229,12 +229,13 @@ def time_variant(plan, steps, warmup, rtg, torch, kind, bytes_of, pre=None):
     }
 
 
-def recorded_traffic(kernel_src, variant):
+def recorded_traffic(kernel_src, variant, tune):
     """HBM traffic per launch measured with rocprofv3 counters (FETCH_SIZE and
     WRITE_SIZE, scaled by a copy-kernel calibration) and recorded with the
     SHA-256 of the kernel source it was measured on; None when the kernel
-    source has changed since, when nothing was recorded, or when the
-    record is of another workload (the record names the variant)."""
+    source has changed since, when nothing was recorded, when the record is
+    of another workload (the record names the variant) or of other launch
+    shapes than this run's (the record names them)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
@@ -246,6 +247,9 @@ def recorded_traffic(kernel_src, variant):
         sha = hashlib.sha256(f.read()).hexdigest()
     ent = rec.get(kernel_src)
     if not ent or ent.get("source_sha256") != sha or ent.get("variant", "bf16_warm") != variant:
+        return None
+    shapes = ent.get("launch_shapes")
+    if not shapes or any(tune.get(k) != v for k, v in shapes.items()):
         return None
     return ent["bytes_per_launch"]
 
@@ -428,7 +432,7 @@ def main():
     H = results[head]
     gbs = H["k_bytes"] / (H["k_ms"] * 1e-3) / 1e9 if H["k_ms"] > 0 else 0.0
     bpl = H["k_bytes"] / max(H["k_launches"], 1)
-    traffic = recorded_traffic(H["kernel"][1], head)
+    traffic = recorded_traffic(H["kernel"][1], head, H["tune"])
     out = {
         "metric": METRIC,
         "value": H["solves_per_s"],
