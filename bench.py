@@ -23,6 +23,12 @@ Variants (each timed over the same number of steps):
                  noise U[1e-3, 1e-2], sketches of a quarter of each mode) in
                  one batch, bfloat16 basis, X0 = 0, m = 40; solves/s counts
                  those 256 problems per step
+  fp32_video     --video-batch 256x256x64 grayscale videos (spatial sigma 2,
+                 temporal box blur of width 5, noise 1e-3, sketch 48x48x16),
+                 float32 basis, X0 = 0, m = 80
+  bf16_video     the same videos, bfloat16 basis from X0 = C, m = 80
+Each batch is autotuned (rtg_autotune_batched) before its timed region
+unless --no-autotune; the chosen launch shapes are reported.
 The JSON line reports the headline variant in "value" and every variant
 under "variants", with restoration errors against the ground truth.
 
@@ -32,7 +38,7 @@ for the float32 one) is bracketed by HIP events on its launch stream inside
 the library; its algorithmic bytes (the tensor reads and writes the method
 needs) over its measured time give the roofline entry.  "traffic" is the
 rocprofv3-measured HBM traffic per launch recorded under profiles/ for the
-same kernel source (null once the source has changed).  The CPU baseline
+same kernel source and launch shapes (null once either differs).  The CPU baseline
 times the float64 oracle on one problem of the same workload on the host
 cores.
 
@@ -68,12 +74,13 @@ def parse():
     ap.add_argument("--x0", choices=["learned", "observation"], default="learned")
     ap.add_argument("--headline", choices=["auto", "fp32_plain", "bf16_warm"], default="auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--video-batch", type=int, default=4, help="videos per step of the video variants")
     ap.add_argument("--no-autotune", action="store_true",
                     help="time every batch with the library's default launch shapes")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a device-to-device copy of MB megabytes (counter calibration)")
     ap.add_argument("--only", choices=["fp32_plain", "bf16_warm", "fp32_unsketched", "fp32_gk", "fp32_psf",
-                                       "bf16_uneven"],
+                                       "bf16_uneven", "fp32_video", "bf16_video"],
                     default=None,
                     help="time one variant only (profiling runs)")
     return ap.parse_args()
@@ -112,6 +119,28 @@ def make_psf_batch(B, device):
         p = synth.cfg2_psf(b)
         if op is None:
             op = rtg.setup_operator_psf(*p.dims, p.psf, p.b_band)
+        sk = rtg.setup_sketch(*p.dims, p.om1, p.om2, p.om3)
+        xt = torch.from_numpy(synth.to_device_layout(p.x_true)).to(device)
+        g = torch.from_numpy(synth.to_device_layout(p.noise_dir)).to(device)
+        chat = rtg.apply_operator(op, xt)
+        delta = p.nu * float(torch.linalg.vector_norm(chat.double()))
+        C = (chat + g * (delta / float(torch.linalg.vector_norm(g.double())))).contiguous()
+        probs.append(dict(p=p, sk=sk, xt=xt, C=C, delta=delta))
+    return op, probs
+
+
+def make_video_batch(B, device):
+    """B videos of the video workload (256x256x64 grayscale, spatial sigma 2,
+    temporal box blur of width 5, noise 1e-3, sketch 48x48x16; seeds
+    0..B-1), observations formed on the GPU with the library's operator."""
+    import torch
+    from paper_2603_00839_amd import rtg, synth
+    probs = []
+    op = None
+    for b in range(B):
+        p = synth.cfg3(b)
+        if op is None:
+            op = rtg.setup_operator(*p.dims, p.a1_band, p.a2_band, p.b_band)
         sk = rtg.setup_sketch(*p.dims, p.om1, p.om2, p.om3)
         xt = torch.from_numpy(synth.to_device_layout(p.x_true)).to(device)
         g = torch.from_numpy(synth.to_device_layout(p.noise_dir)).to(device)
@@ -344,9 +373,31 @@ def main():
 
     results = {}
     variants = [args.only] if args.only else ["fp32_plain", "bf16_warm", "fp32_unsketched", "fp32_gk", "fp32_psf",
-                                              "bf16_uneven"]
+                                              "bf16_uneven", "fp32_video", "bf16_video"]
     for v in variants:
-        if v == "bf16_uneven":
+        if v in ("fp32_video", "bf16_video"):
+            # the video workload: float32 basis from X0 = 0, or a bfloat16
+            # basis from X0 = C (the network is trained on colour images);
+            # m = 80 steps (the discrepancy level is not reached within them)
+            Bv = args.video_batch
+            op_v, probs_v = make_video_batch(Bv, dev)
+            nv = probs_v[0]["p"].dims[0] * probs_v[0]["p"].dims[1] * probs_v[0]["p"].dims[2]
+            bfv = v == "bf16_video"
+            prm = [rtg.make_params(80, rtg.BF16 if bfv else rtg.F32, delta=q["delta"], eta=1.01) for q in probs_v]
+            plan = rtg.BatchPlan([op_v] * Bv, [q["sk"] for q in probs_v], [q["C"] for q in probs_v],
+                                 [q["C"] for q in probs_v] if bfv else [None] * Bv, prm)
+            tune = tune_plan(plan, args)
+            if bfv:
+                r = time_variant(plan, args.steps, args.warmup, rtg, torch, rtg.KIND_STEP,
+                                 lambda inf: step_bytes(nv, 2, inf.iters))
+                r["kernel"] = ("k_step", "k_step.hip", "Arnoldi step, bfloat16 basis, 256x256x64 videos")
+            else:
+                r = time_variant(plan, args.steps, args.warmup, rtg, torch, rtg.KIND_TILE,
+                                 lambda inf: tile_bytes(nv, 4, inf.iters, False))
+                r["kernel"] = ("k_tile", "k_tile.hip", "multi-AXPY + store + MFMA sketch, 256x256x64 videos")
+            res = [rel_err(plan.outs[b], probs_v[b]["xt"]) for b in range(Bv)]
+            r["solves_per_step"] = Bv
+        elif v == "bf16_uneven":
             probs_u = make_uneven_batch(dev)
             Bu = len(probs_u)
             prm = [rtg.make_params(40, rtg.BF16, delta=q["delta"], eta=1.01) for q in probs_u]
@@ -410,7 +461,7 @@ def main():
                              lambda inf: step_bytes(n, 2, inf.iters), pre=pre)
             r["kernel"] = ("k_step", "k_step.hip", "Arnoldi step: operator per tile + multi-AXPY + store + "
                                                    "dual MFMA sketch (bfloat16 basis)")
-        if v not in ("fp32_psf", "bf16_uneven"):
+        if v not in ("fp32_psf", "bf16_uneven", "fp32_video", "bf16_video"):
             res = [rel_err(plan.outs[b], probs[b]["xt"]) for b in range(B)]
         r["tune"] = tune
         r["re_mean"] = float(np.mean(res))

@@ -1,0 +1,94 @@
+"""The video workload at its full size: 256x256x64 grayscale frames, spatial
+Gaussian blur (sigma 2, half-bandwidth 6), temporal box blur of width 5 as
+the mode-3 band, noise 1e-3, sketch 48x48x16 (Om3 given), m = 80.
+
+* Arnoldi prefix: the first four steps on the GPU against the float64
+  oracle on the same R0 = C (beta within 1e-5, H within 1e-4), and the
+  Arnoldi relation Phi(V_j) = sum_i h_ij V_i on the stored float32 basis
+  (the oracle's operator, 1e-5).
+* float32 solve, discrepancy mu: beta against the oracle's ||S(C)|| (1e-5);
+  the projected residual the solver reports equals ||S(C - Phi(X))||
+  recomputed through the library (a property of the Theta-orthonormal basis
+  at any size, 1e-3 relative); the restoration error is finite and below
+  that of the observation.  (A float64 oracle solve of 80 steps at 4.2 M
+  elements is too slow for a test; the oracle checks the prefix above.)
+* bfloat16 basis from X0 = C, the same 80 steps: the restoration error
+  within 1 % of the float32 solve's.  (At m = 80 neither solve reaches the
+  discrepancy level: both report RTG_F_DISCREP_UNREACHABLE and take mu = 0.)
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2603_00839_amd import synth
+from oracle.arnoldi import sketched_global_arnoldi
+from oracle.metrics import relative_error
+import _util as U
+
+pytestmark = pytest.mark.gpu
+
+
+def banner(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def video():
+    banner("video problem set-up")
+    p = synth.cfg3(0)
+    C, delta = U.observation(p)
+    return p, C, delta
+
+
+def test_video_arnoldi_prefix_matches_oracle(video):
+    from paper_2603_00839_amd import rtg
+    p, C, _ = video
+    banner("video arnoldi prefix")
+    m = 4
+    op_o, sk_o = U.oracle_pair(p)
+    op_g, sk_g = U.gpu_pair(p)
+    out = rtg.arnoldi(op_g, sk_g, U.to_dev(C), m, bd_tol=1e-10)
+    H = out["H"].cpu().numpy()
+    ar = sketched_global_arnoldi(op_o, sk_o, C, m)
+    print(f"beta {out['beta'].item():.6e} ({ar.beta:.6e}) H maxrel {U.maxrel(H, ar.H):.2e}", file=sys.stderr)
+    assert int(out["m_done"].item()) == m
+    np.testing.assert_allclose(out["beta"].item(), ar.beta, rtol=1e-5)
+    assert U.maxrel(H, ar.H) < 1e-4
+    V = [U.from_dev(out["V"][i]) for i in range(m + 1)]
+    for j in range(m):
+        lhs = op_o(V[j])
+        rhs = sum(H[i, j] * V[i] for i in range(j + 2))
+        assert U.rel(rhs, lhs) < 1e-5, j
+
+
+def test_video_solve_fp32_and_bf16(video):
+    import torch
+    from paper_2603_00839_amd import rtg
+    p, C, delta = video
+    banner("video solve fp32, m = 80")
+    _, sk_o = U.oracle_pair(p)
+    op_g, sk_g = U.gpu_pair(p)
+    Cd = U.to_dev(C)
+    prm = rtg.make_params(80, rtg.F32, delta=delta, eta=1.01)
+    X, ib = rtg.solve(op_g, sk_g, Cd, None, prm)
+    info = rtg.read_info(ib)
+    R = rtg.apply_operator(op_g, X, C=Cd)
+    sr = float(torch.linalg.vector_norm(rtg.sketch(sk_g, R).double()))
+    re32 = relative_error(p.x_true, U.from_dev(X))
+    re_obs = relative_error(p.x_true, C)
+    print(f"fp32: iters {info.iters} flags {info.flags} mu {info.mu:.4e} beta {info.beta:.6e} "
+          f"res_proj {info.res_proj:.6e} ||S(C - Phi(X))|| {sr:.6e} RE {re32:.5f} (observation {re_obs:.5f})",
+          file=sys.stderr)
+    assert 1 <= info.iters <= 80
+    np.testing.assert_allclose(info.beta, sk_o.norm(C), rtol=1e-5)
+    assert abs(sr - info.res_proj) <= 1e-3 * info.res_proj
+    assert np.isfinite(re32) and re32 < re_obs
+    banner("video solve bf16 from X0 = C, m = 80")
+    prm16 = rtg.make_params(80, rtg.BF16, delta=delta, eta=1.01)
+    X16, ib16 = rtg.solve(op_g, sk_g, Cd, Cd, prm16)
+    info16 = rtg.read_info(ib16)
+    re16 = relative_error(p.x_true, U.from_dev(X16))
+    print(f"bf16: iters {info16.iters} flags {info16.flags} RE {re16:.5f} (fp32 {re32:.5f})", file=sys.stderr)
+    assert info16.iters == 80 and info16.flags == info.flags
+    assert re16 <= 1.01 * re32
