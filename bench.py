@@ -65,7 +65,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--m", type=int, default=50)
     ap.add_argument("--m-warm", type=int, default=10, help="Arnoldi steps of the warm-started BF16 solve")
     ap.add_argument("--warm-stop", choices=["fixed", "discrepancy"], default="discrepancy",
@@ -258,13 +258,13 @@ def time_variant(plan, steps, warmup, rtg, torch, kind, bytes_of, pre=None):
     }
 
 
-def recorded_traffic(kernel_src, variant, tune):
+def recorded_traffic(kernel_src, variant, tune, batch):
     """HBM traffic per launch measured with rocprofv3 counters (FETCH_SIZE and
     WRITE_SIZE, scaled by a copy-kernel calibration) and recorded with the
     SHA-256 of the kernel source it was measured on; None when the kernel
     source has changed since, when nothing was recorded, when the record is
-    of another workload (the record names the variant) or of other launch
-    shapes than this run's (the record names them)."""
+    of another workload (the record names the variant and the batch size) or
+    of other launch shapes than this run's (the record names them)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
@@ -276,6 +276,8 @@ def recorded_traffic(kernel_src, variant, tune):
         sha = hashlib.sha256(f.read()).hexdigest()
     ent = rec.get(kernel_src)
     if not ent or ent.get("source_sha256") != sha or ent.get("variant", "bf16_warm") != variant:
+        return None
+    if ent.get("batch") != batch:
         return None
     shapes = ent.get("launch_shapes")
     if not shapes or any(tune.get(k) != v for k, v in shapes.items()):
@@ -483,7 +485,7 @@ def main():
     H = results[head]
     gbs = H["k_bytes"] / (H["k_ms"] * 1e-3) / 1e9 if H["k_ms"] > 0 else 0.0
     bpl = H["k_bytes"] / max(H["k_launches"], 1)
-    traffic = recorded_traffic(H["kernel"][1], head, H["tune"])
+    traffic = recorded_traffic(H["kernel"][1], head, H["tune"], B)
     out = {
         "metric": METRIC,
         "value": H["solves_per_s"],
