@@ -331,8 +331,8 @@ def tune_plan(plan, args, pre=None):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design "
-                                   "note (independent problems per GPU), not implemented"}))
+        print(json.dumps({"error": "bench.py runs on one GPU only: sharding over several GPUs "
+                                   "(independent problems per GPU) is not implemented"}))
         sys.exit(2)
     import numpy as np
     import torch

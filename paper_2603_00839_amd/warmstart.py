@@ -5,8 +5,8 @@ k_cnn.hip) is trained on pairs (C, X) where X is what the plain float32
 RTG-GMRES solver of this library returns for C: 128x128x3 synthetic images
 (rectangles + Gaussian random field), Gaussian blur sigma ~ U(1,3), noise
 1e-3..1e-2, sketch 16x16x3, m = 50, discrepancy-principle mu.  The solver then
-corrects from X0, so the plain solver is both the source of the labels and
-the judge of the warm start's error.
+corrects from X0, so the plain solver both supplies the labels and removes
+whatever error the warm start leaves.
 
 Usage (on a GPU):  python -m paper_2603_00839_amd.warmstart train --count 20000
 """
