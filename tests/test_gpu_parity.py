@@ -143,6 +143,36 @@ def test_arnoldi_parity_and_relation():
         np.testing.assert_allclose(np.linalg.norm(SV[i]), sk_o.norm(V[i]), rtol=1e-5)
 
 
+@pytest.mark.parametrize("shape", [(32, 64, 40, 2, 2, 2, 16, 16, 8), (24, 96, 20, 3, 2, 1, 12, 24, 20)])
+def test_arnoldi_and_solve_many_channels(shape):
+    """Many channels (J = 40 with Om3 given, J = 20 without): every sketch
+    pair's finish in the Gram step sums J x (column tiles) partials per
+    buffer through the mode-3 factor.  H against the oracle, the Arnoldi
+    relation on the stored basis, and the solve."""
+    from paper_2603_00839_amd import rtg
+    I1, I2, J, r1, r2, rB, l1, l2, l3 = shape
+    banner("many channels", shape)
+    m = 8
+    p = synth.small_problem(90 + J, I1, I2, J, r1, r2, rB, l1, l2, l3, m, random_bands=True)
+    op_o, sk_o = U.oracle_pair(p)
+    op_g, sk_g = U.gpu_pair(p)
+    C, _ = U.observation(p)
+    out = rtg.arnoldi(op_g, sk_g, U.to_dev(C), m, bd_tol=1e-10)
+    H = out["H"].cpu().numpy()
+    ar = __import__("oracle.arnoldi", fromlist=["x"]).sketched_global_arnoldi(op_o, sk_o, C, m)
+    assert int(out["m_done"].item()) == m
+    np.testing.assert_allclose(out["beta"].item(), ar.beta, rtol=1e-5)
+    assert U.maxrel(H, ar.H) < 1e-4, U.maxrel(H, ar.H)
+    V = [U.from_dev(out["V"][i]) for i in range(m + 1)]
+    for j in range(m):
+        assert U.rel(sum(H[i, j] * V[i] for i in range(j + 2)), op_o(V[j])) < 1e-5
+    X, info, ref = solve_both(p)
+    print(f"{shape}: H maxrel {U.maxrel(H, ar.H):.2e} solve iters {info.iters} ({ref.m_eff}) rel {U.rel(X, ref.X):.2e}",
+          file=sys.stderr)
+    assert info.iters == ref.m_eff and info.flags == ref.flags
+    assert U.rel(X, ref.X) < 1e-4
+
+
 def solve_both(p, basis="f32", mu=None, X0=None, stop_res=0.0, m=None):
     from paper_2603_00839_amd import rtg
     op_o, sk_o = U.oracle_pair(p)
