@@ -119,6 +119,75 @@ __device__ __forceinline__ void finish_sketches(const Desc& d, int q0, int qn,
     }
 }
 
+// Split form of the finish (gram_split): thread (t, sl) = (tid % CHS, tid /
+// CHS) sums, for pair q0 + t, the column tiles of channels [sl cps, (sl + 1)
+// cps) (cps = ceil(J / GRAM_SPL)) and applies their columns of M (m3, or the
+// identity); the GRAM_SPL slices' l3 values are then added through LDS (red:
+// NB x GRAM_SPL x CHS x 16 floats) in slice order.
+template <int NB>
+__device__ __forceinline__ void finish_sketches_split(const Desc& d, int q0, int qn,
+                                                      const float* __restrict__ P0, const float* __restrict__ m30,
+                                                      float* out0, const float* __restrict__ P1,
+                                                      const float* __restrict__ m31, float* out1, float* red) {
+    constexpr int CHS = GRAM_CH_SPLIT, SPL = GRAM_SPL, G = 16, U = 8;
+    const int tid = threadIdx.x;
+    const int L12 = d.l1 * d.l2, J = d.J, nt2 = d.n_i2t, l3 = d.l3;
+    const int t = tid % CHS, sl = tid / CHS;
+    const int cps = (J + SPL - 1) / SPL;
+    const int c_lo = sl * cps, c_hi = min(J, c_lo + cps);
+    float a0[G], a1[G];
+#pragma unroll
+    for (int c3 = 0; c3 < G; ++c3) { a0[c3] = 0.f; a1[c3] = 0.f; }
+    if (t < qn) {
+        const int q = q0 + t;
+        for (int c = c_lo; c < c_hi; ++c) {
+            float s0 = 0.f, s1 = 0.f;
+            for (int t0 = 0; t0 < nt2; t0 += U) {
+                float v0[U], v1[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const size_t off = ((size_t)c * nt2 + min(t0 + u, nt2 - 1)) * L12 + q;
+                    v0[u] = *gptr(P0 + off);
+                    if constexpr (NB > 1) v1[u] = *gptr(P1 + off);
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const bool ok = t0 + u < nt2;
+                    s0 += ok ? v0[u] : 0.f;
+                    if constexpr (NB > 1) s1 += ok ? v1[u] : 0.f;
+                }
+            }
+#pragma unroll
+            for (int c3 = 0; c3 < G; ++c3) {
+                if (c3 >= l3) break;
+                const float w0 = m30 ? *gptr(m30 + (size_t)c3 * J + c) : (c3 == c ? 1.f : 0.f);
+                a0[c3] = fmaf(w0, s0, a0[c3]);
+                if constexpr (NB > 1) {
+                    const float w1 = m31 ? *gptr(m31 + (size_t)c3 * J + c) : (c3 == c ? 1.f : 0.f);
+                    a1[c3] = fmaf(w1, s1, a1[c3]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int c3 = 0; c3 < G; ++c3) {
+        red[((size_t)sl * CHS + t) * G + c3] = a0[c3];
+        if constexpr (NB > 1) red[((size_t)(SPL + sl) * CHS + t) * G + c3] = a1[c3];
+    }
+    __syncthreads();
+    for (int e = tid; e < CHS * G; e += blockDim.x) {
+        const int to = e / G, c3 = e % G;
+        if (to >= qn || c3 >= l3) continue;
+        float s0 = 0.f, s1 = 0.f;
+        for (int s2 = 0; s2 < SPL; ++s2) {
+            s0 += red[((size_t)s2 * CHS + to) * G + c3];
+            if constexpr (NB > 1) s1 += red[((size_t)(SPL + s2) * CHS + to) * G + c3];
+        }
+        out0[to * l3 + c3] = s0;
+        if constexpr (NB > 1) out1[to * l3 + c3] = s1;
+    }
+}
+
 // Sum of 16 values over a wave in 17 shuffles: each of the first four levels
 // halves the set a lane keeps (the lane bit of the level's offset picks the
 // half), the last two add across neighbours, so that afterwards lanes
@@ -249,7 +318,10 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
         }
     } else {
     const int L12 = d.l1 * d.l2, l3 = d.l3;
-    const int CH = gram_pairs_per_block(l3);
+    const int CH = gram_pairs_per_block(l3, d.J, d.n_i2t);
+    const bool split = gram_split(l3, d.J, d.n_i2t);
+    static_assert(2 * GRAM_SPL * GRAM_CH_SPLIT * 16 * sizeof(float) <= sizeof(double) * GLDS * GLDS,
+                  "the split finish's reduction fits the G block's LDS");
     const int q0 = wgi * CH;
     const int qn = min(CH, L12 - q0);
     const int E = qn * l3;
@@ -259,7 +331,13 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
     // (Om3 B^T is banded when Om3 is the identity)
     const float* om3 = d.has_om3 ? d.om3 : nullptr;
     // (a general PSF: the W partials are those of W itself, mode 3 is Om3)
-    if (mode == GM_STEP || mode == GM_GK)
+    // (the split form reduces through the LDS of the G block, which only the
+    // tail fills, after the barrier below)
+    if (split) {
+        if (mode == GM_STEP || mode == GM_GK)
+            finish_sketches_split<2>(d, q0, qn, d.PW, d.st ? om3 : d.om3t, s_s, d.PV, om3, s_v, (float*)sG);
+        else finish_sketches_split<1>(d, q0, qn, d.PW, om3, s_s, nullptr, nullptr, nullptr, (float*)sG);
+    } else if (mode == GM_STEP || mode == GM_GK)
         finish_sketches<2>(d, q0, qn, d.PW, d.st ? om3 : d.om3t, (d.st || d.has_om3) ? -1 : d.rB, s_s, d.PV, om3,
                            -1, s_v);
     else finish_sketches<1>(d, q0, qn, d.PW, om3, -1, s_s, nullptr, nullptr, -1, nullptr);

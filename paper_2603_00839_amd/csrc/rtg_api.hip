@@ -76,7 +76,7 @@ Layout problem_layout(const rtg_op_s* op, const rtg_sk_s* sk, int m, int bf16) {
     const size_t es = bf16 ? 2 : 4;
     L.n_i2t = (op->I2 + TILE_TC - 1) / TILE_TC;
     L.ntile_tile = op->J * L.n_i2t;
-    const int ch = gram_pairs_per_block(sk->l3);
+    const int ch = gram_pairs_per_block(sk->l3, op->J, L.n_i2t);
     L.ntile_gram = sk->identity ? frob_wgs((long long)n) : (sk->l1 * sk->l2 + ch - 1) / ch;
     L.ntile_phi = phi_tiles(op->I1, op->I2, op->J, phi_jt(op->J));
     // an identity sketch keeps no partials, stored sketches or composed matrices

@@ -162,8 +162,17 @@ __device__ __forceinline__ int xcd_tile(int b, int total) {
 constexpr int FROB_CHUNK = 4096;
 __host__ __device__ inline int frob_wgs(long long n) { return (int)((n + FROB_CHUNK - 1) / FROB_CHUNK); }
 
+// Sketched-Gram workgroups whose pairs carry many partials (J channels x nt2
+// column tiles above 48 per buffer) and few finished values (l3 <= 16) finish
+// each pair with GRAM_SPL threads, each over a slice of the channels, and
+// take GRAM_CH_SPLIT pairs.
+constexpr int GRAM_SPL = 8;
+constexpr int GRAM_CH_SPLIT = 256 / GRAM_SPL;
+__host__ __device__ inline bool gram_split(int l3, int J, int nt2) { return J * nt2 > 48 && l3 <= 16; }
+
 // (a, b) pairs of the sketch owned by one sketched-Gram workgroup
-__host__ __device__ inline int gram_pairs_per_block(int l3) {
+__host__ __device__ inline int gram_pairs_per_block(int l3, int J, int nt2) {
+    if (gram_split(l3, J, nt2)) return GRAM_CH_SPLIT;
     int ch = 4096 / (l3 > 0 ? l3 : 1);
     if (ch > GRAM_CH) ch = GRAM_CH;
     if (ch < 1) ch = 1;

@@ -143,12 +143,24 @@ def test_arnoldi_parity_and_relation():
         np.testing.assert_allclose(np.linalg.norm(SV[i]), sk_o.norm(V[i]), rtol=1e-5)
 
 
-@pytest.mark.parametrize("shape", [(32, 64, 40, 2, 2, 2, 16, 16, 8), (24, 96, 20, 3, 2, 1, 12, 24, 20)])
+MANY_CHANNELS = [
+    # (I1, I2, J, r1, r2, rB, l1, l2, l3): J x (32-column tiles) above 48 and
+    # l3 <= 16 take the Gram step's split finish (32 pairs per workgroup,
+    # eight threads per pair): Om3 given (J = 40, l3 = 8) and the identity
+    # (J = l3 = 16, four workgroups of 32 pairs); J = 20 with l3 = 20 keeps
+    # the one-thread-per-pair finish
+    (32, 64, 40, 2, 2, 2, 16, 16, 8),
+    (16, 128, 16, 2, 2, 1, 8, 16, 16),
+    (24, 96, 20, 3, 2, 1, 12, 24, 20),
+]
+
+
+@pytest.mark.parametrize("shape", MANY_CHANNELS)
 def test_arnoldi_and_solve_many_channels(shape):
-    """Many channels (J = 40 with Om3 given, J = 20 without): every sketch
-    pair's finish in the Gram step sums J x (column tiles) partials per
-    buffer through the mode-3 factor.  H against the oracle, the Arnoldi
-    relation on the stored basis, and the solve."""
+    """Many channels: every sketch pair's finish in the Gram step sums
+    J x (column tiles) partials per buffer through the mode-3 factor.  H
+    against the oracle, the Arnoldi relation on the stored basis, and the
+    solve."""
     from paper_2603_00839_amd import rtg
     I1, I2, J, r1, r2, rB, l1, l2, l3 = shape
     banner("many channels", shape)
@@ -169,6 +181,30 @@ def test_arnoldi_and_solve_many_channels(shape):
     X, info, ref = solve_both(p)
     print(f"{shape}: H maxrel {U.maxrel(H, ar.H):.2e} solve iters {info.iters} ({ref.m_eff}) rel {U.rel(X, ref.X):.2e}",
           file=sys.stderr)
+    assert info.iters == ref.m_eff and info.flags == ref.flags
+    assert U.rel(X, ref.X) < 1e-4
+
+
+@pytest.mark.parametrize("shape", MANY_CHANNELS[:2])
+def test_golub_kahan_many_channels(shape):
+    """Sketched Golub-Kahan through the split finish of the Gram step (both
+    sides' sketches finished with the mode-3 factor): X and the step count
+    against the oracle."""
+    from paper_2603_00839_amd import rtg
+    from oracle.golub_kahan import rgk_solve
+    I1, I2, J, r1, r2, rB, l1, l2, l3 = shape
+    banner("golub-kahan many channels", shape)
+    m = 8
+    p = synth.small_problem(70 + J, I1, I2, J, r1, r2, rB, l1, l2, l3, m, random_bands=True)
+    op_o, sk_o = U.oracle_pair(p)
+    op_g, sk_g = U.gpu_pair(p)
+    C, delta = U.observation(p)
+    prm = rtg.make_params(m, rtg.F32, delta=delta, eta=1.01, method=rtg.METHOD_GOLUB_KAHAN)
+    Xg, ib = rtg.solve(op_g, sk_g, U.to_dev(C), None, prm)
+    info = rtg.read_info(ib)
+    ref = rgk_solve(op_o, sk_o, C, m, delta=delta, eta=1.01)
+    X = U.from_dev(Xg)
+    print(f"{shape}: GK iters {info.iters} ({ref.m_eff}) rel {U.rel(X, ref.X):.2e}", file=sys.stderr)
     assert info.iters == ref.m_eff and info.flags == ref.flags
     assert U.rel(X, ref.X) < 1e-4
 
