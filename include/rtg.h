@@ -261,7 +261,10 @@ int rtg_solve_batched(int count, const rtg_problem* probs, void* ws,
  *   tile_rows     tile kernel: 16-row sketch tiles per wave, 2 (used where
  *                 the stacked sketch rows fit, else 4) or 4
  *   step_rows     fused bfloat16 Arnoldi step: the same, 2 or 4
- *   step_toeplitz fused step: 1 Toeplitz taps (all bands Toeplitz), 0 band rows */
+ *   step_toeplitz fused step: 1 Toeplitz taps (all bands Toeplitz), 0 band rows
+ *   gram_pairs    sketched inner products: (a, b) sketch pairs per workgroup,
+ *                 256, 512 or 1024 (capped at 4096 / l3 finished values; never
+ *                 below the library's own choice for the problem) */
 typedef struct {
     int phi_jt;
     int phi_slab;
@@ -269,13 +272,15 @@ typedef struct {
     int tile_rows;
     int step_rows;
     int step_toeplitz;
-    int reserved[2];  /* zero */
+    int gram_pairs;
+    int reserved;     /* zero */
 } rtg_tune;           /* 32 bytes */
 
 /* Time the batch's solve (the Arnoldi or Golub-Kahan loop; no projected
  * solve, no assembly, the outputs X and info untouched) under candidate
- * shapes -- the operator fields first, then the tile rows, then the fused
- * step's fields, each group with the others at their best so far -- on
+ * shapes -- the operator fields first, then the tile rows, the Gram pairs,
+ * then the fused step's fields, each group with the others at their best so
+ * far -- on
  * stream, the minimum over reps >= 1 runs of each candidate (hipEvents),
  * and record the fastest in the table.  Synchronous.  *chosen receives the
  * choice with every field resolved (no -1), *best_ms (may be NULL) its

@@ -318,8 +318,8 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
         }
     } else {
     const int L12 = d.l1 * d.l2, l3 = d.l3;
-    const int CH = gram_pairs_per_block(l3, d.J, d.n_i2t);
     const bool split = gram_split(l3, d.J, d.n_i2t);
+    const int CH = (!split && d.gram_ch > 0) ? d.gram_ch : gram_pairs_per_block(l3, d.J, d.n_i2t);
     static_assert(2 * GRAM_SPL * GRAM_CH_SPLIT * 16 * sizeof(float) <= sizeof(double) * GLDS * GLDS,
                   "the split finish's reduction fits the G block's LDS");
     const int q0 = wgi * CH;

@@ -282,6 +282,18 @@ int build_plan(std::vector<Desc>& descs, void* ws, hipStream_t s, Plan& plan, in
     plan.phi_jt = (tune && (tune->phi_jt == 4 || tune->phi_jt == 8)) ? tune->phi_jt : phi_jt(maxJ);
     for (auto& d : descs)
         if (d.ntile[KIND_PHI] > 0) d.ntile[KIND_PHI] = phi_tiles(d.I1, d.I2, d.J, plan.phi_jt);
+    // sketched-Gram chunks: at least the default (the dots area of the
+    // workspace holds the default's workgroup count), at most 4096 finished
+    // values per workgroup
+    for (auto& d : descs) {
+        d.gram_ch = 0;
+        if (!tune || tune->gram_pairs <= 0 || d.unsketched || gram_split(d.l3, d.J, d.n_i2t)) continue;
+        const int def = gram_pairs_per_block(d.l3, d.J, d.n_i2t);
+        const int ch = std::max(def, std::min(tune->gram_pairs, 4096 / std::max(d.l3, 1)));
+        if (ch == def) continue;
+        d.gram_ch = ch;
+        d.ntile[KIND_GRAM] = (d.l1 * d.l2 + ch - 1) / ch;
+    }
     plan.rmax = 1;
     for (int k = 0; k < NKIND; ++k) {
         int acc = 0;
@@ -1048,6 +1060,7 @@ std::vector<long long> batch_key(int count, const rtg_problem* probs) {
 struct TuneCaps {
     int maxJ = 1, slab_cap = 2;
     bool toep_ok = true, stencil = false, phi_runs = true, step_runs = false;
+    bool gram_runs = false;   // some problem's Gram chunk follows gram_pairs
 };
 
 TuneCaps tune_caps(int count, const rtg_problem* probs) {
@@ -1064,6 +1077,8 @@ TuneCaps tune_caps(int count, const rtg_problem* probs) {
                   frag_elems(probs[p].sk->l1, op->I1, FRAG_K_BF16) * 4 <= 0x7FFFFFFFull;
         c.toep_ok = c.toep_ok && op->toeplitz;
         x0 = x0 || probs[p].X0 != nullptr;
+        const rtg_sk_s* sk = probs[p].sk;
+        c.gram_runs = c.gram_runs || (!sk->identity && !gram_split(sk->l3, op->J, (op->I2 + TILE_TC - 1) / TILE_TC));
     }
     c.toep_ok = c.toep_ok && !c.stencil;
     c.slab_cap = big ? 0 : ((c.stencil && c.maxJ <= 3) ? 2 : 1);
@@ -1076,7 +1091,8 @@ TuneCaps tune_caps(int count, const rtg_problem* probs) {
 // Every -1 replaced by the default; RTG_E_ARG for a value outside the
 // documented set or one the batch cannot use.
 int resolve_tune(const TuneCaps& c, const rtg_tune& in, rtg_tune& out) {
-    if (in.reserved[0] != 0 || in.reserved[1] != 0) return RTG_E_ARG;
+    if (in.reserved != 0) return RTG_E_ARG;
+    if (in.gram_pairs != -1 && in.gram_pairs != 256 && in.gram_pairs != 512 && in.gram_pairs != 1024) return RTG_E_ARG;
     auto one_of = [](int v, int a, int b) { return v == -1 || v == a || v == b; };
     if (!one_of(in.phi_jt, 4, 8) || !one_of(in.tile_rows, 2, 4) || !one_of(in.step_rows, 2, 4)) return RTG_E_ARG;
     if (!one_of(in.phi_toeplitz, 0, 1) || !one_of(in.step_toeplitz, 0, 1)) return RTG_E_ARG;
@@ -1090,13 +1106,14 @@ int resolve_tune(const TuneCaps& c, const rtg_tune& in, rtg_tune& out) {
     out.tile_rows = in.tile_rows >= 0 ? in.tile_rows : 2;
     out.step_rows = in.step_rows >= 0 ? in.step_rows : 2;
     out.step_toeplitz = in.step_toeplitz >= 0 ? in.step_toeplitz : (c.toep_ok ? 1 : 0);
+    out.gram_pairs = in.gram_pairs >= 0 ? in.gram_pairs : GRAM_CH;
     return RTG_OK;
 }
 
 rtg_tune tune_unset() {
     rtg_tune t;
-    t.phi_jt = t.phi_slab = t.phi_toeplitz = t.tile_rows = t.step_rows = t.step_toeplitz = -1;
-    t.reserved[0] = t.reserved[1] = 0;
+    t.phi_jt = t.phi_slab = t.phi_toeplitz = t.tile_rows = t.step_rows = t.step_toeplitz = t.gram_pairs = -1;
+    t.reserved = 0;
     return t;
 }
 
@@ -1240,6 +1257,15 @@ int rtg_autotune_batched(int count, const rtg_problem* probs, void* ws, size_t w
         for (int rows : {2, 4}) {
             rtg_tune c = best;
             c.tile_rows = rows;
+            cands.push_back(c);
+        }
+        rc = try_group(cands);
+    }
+    if (!rc && caps.gram_runs) {
+        std::vector<rtg_tune> cands;
+        for (int gp : {256, 512, 1024}) {
+            rtg_tune c = best;
+            c.gram_pairs = gp;
             cands.push_back(c);
         }
         rc = try_group(cands);

@@ -53,6 +53,7 @@ struct Desc {
     int mu_rule;        // RTG_MU_DISCREPANCY or RTG_MU_GCV
     int keep_last;      // form V_{m+1} after the last step (Arnoldi-only calls)
     int toeplitz;       // A1 and A2 are Toeplitz on their in-range entries (convolutions, zero BC)
+    int gram_ch;        // (a, b) pairs per sketched-Gram workgroup chosen for the batch (0: the default)
     int unsketched;     // identity sketch: Frobenius inner products of the full tensors
     int restarts;       // restart cycles after the first (restarted RTG-GMRES), 0 = none
     int gk;             // sketched Block Golub-Kahan: 1 = the V side (operator Phi), 2 = the U side

@@ -53,9 +53,9 @@ class Tune(ctypes.Structure):
     """Launch shapes of a batch (rtg_tune); -1 = the library default."""
     _fields_ = [("phi_jt", ctypes.c_int), ("phi_slab", ctypes.c_int), ("phi_toeplitz", ctypes.c_int),
                 ("tile_rows", ctypes.c_int), ("step_rows", ctypes.c_int), ("step_toeplitz", ctypes.c_int),
-                ("reserved", ctypes.c_int * 2)]
+                ("gram_pairs", ctypes.c_int), ("reserved", ctypes.c_int)]
 
-    FIELDS = ("phi_jt", "phi_slab", "phi_toeplitz", "tile_rows", "step_rows", "step_toeplitz")
+    FIELDS = ("phi_jt", "phi_slab", "phi_toeplitz", "tile_rows", "step_rows", "step_toeplitz", "gram_pairs")
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f in self.FIELDS}

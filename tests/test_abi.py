@@ -82,8 +82,10 @@ def test_tune_struct_layout_matches_header():
     assert ctypes.sizeof(rtg.Tune) == 32
     for i, f in enumerate(rtg.Tune.FIELDS):
         assert getattr(rtg.Tune, f).offset == 4 * i
+    assert rtg.Tune.reserved.offset == 28
     t = rtg.make_tune(tile_rows=4)
-    assert t.as_dict() == dict(phi_jt=-1, phi_slab=-1, phi_toeplitz=-1, tile_rows=4, step_rows=-1, step_toeplitz=-1)
+    assert t.as_dict() == dict(phi_jt=-1, phi_slab=-1, phi_toeplitz=-1, tile_rows=4, step_rows=-1, step_toeplitz=-1,
+                               gram_pairs=-1)
     with pytest.raises(rtg.RTGError):
         rtg.make_tune(rows=2)
 

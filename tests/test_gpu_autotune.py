@@ -1,7 +1,8 @@
 """The batching form's tile autotuner (rtg_autotune_batched, rtg_tune_*).
 
-* Every launch shape the autotuner may choose, forced in turn through
-  rtg_tune_set, on small uneven batches of four kinds: float32 RTG-GMRES
+* Every launch shape the autotuner may choose (operator tiles, staging and
+  taps, sketch rows per wave, Gram pairs per workgroup), forced in turn
+  through rtg_tune_set, on small uneven batches of four kinds: float32 RTG-GMRES
   (Toeplitz bands, J = 3 and 5 so that both channel tiles are candidates),
   the fused bfloat16 step with X0, sketched Golub-Kahan, and a general PSF
   (J = 3: asynchronous slab loads are a candidate).  float32 kinds: X within
@@ -90,11 +91,12 @@ def candidates(kind, maxJ):
     slabs = [0, 1, 2] if (kind == "psf" and maxJ <= 3) else [0, 1]
     phi = [dict(phi_jt=jt, phi_slab=sl, phi_toeplitz=tp)
            for jt in jts for sl in slabs for tp in ([0, 1] if (kind != "psf" and sl >= 1) else [0])]
+    gram = [dict(gram_pairs=g) for g in (256, 512, 1024)]
     if kind == "bf16":
         step = [dict(step_rows=r, step_toeplitz=tp) for r in (2, 4) for tp in (0, 1)]
         # the step group against both tile forms, the operator group (R0 only) once
-        return ([dict(tile_rows=tr, **st) for tr in (2, 4) for st in step] + phi)
-    return [dict(tile_rows=tr, **ph) for tr in (2, 4) for ph in phi]
+        return ([dict(tile_rows=tr, **st) for tr in (2, 4) for st in step] + phi + gram)
+    return [dict(tile_rows=tr, **ph) for tr in (2, 4) for ph in phi] + gram
 
 
 def solve(plan):
@@ -163,12 +165,12 @@ def test_tune_set_refuses_impossible_choices():
     banner("tune errors")
     plan, _, _ = make_batch("fp32")
     bad = [dict(phi_jt=6), dict(tile_rows=3), dict(step_rows=1), dict(phi_slab=2),   # separable: no async slabs
-           dict(phi_slab=3), dict(phi_toeplitz=2), dict(phi_slab=0, phi_toeplitz=1)]
+           dict(phi_slab=3), dict(phi_toeplitz=2), dict(phi_slab=0, phi_toeplitz=1), dict(gram_pairs=300)]
     for c in bad:
         with pytest.raises(rtg.RTGError):
             plan.set_tune(rtg.make_tune(**c))
     t = rtg.make_tune()
-    t.reserved[0] = 1
+    t.reserved = 1
     with pytest.raises(rtg.RTGError):
         plan.set_tune(t)
     # random (non-Toeplitz) bands: no Toeplitz forms
