@@ -77,6 +77,9 @@ def parse():
     ap.add_argument("--video-batch", type=int, default=4, help="videos per step of the video variants")
     ap.add_argument("--no-autotune", action="store_true",
                     help="time every batch with the library's default launch shapes")
+    ap.add_argument("--tune", default="", metavar="FIELD=V,...",
+                    help="time every batch with these launch shapes (rtg_tune fields; the rest default), "
+                         "no autotuning")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a device-to-device copy of MB megabytes (counter calibration)")
     ap.add_argument("--only", choices=["fp32_plain", "bf16_warm", "fp32_unsketched", "fp32_gk", "fp32_psf",
@@ -320,6 +323,11 @@ def tune_plan(plan, args, pre=None):
     """Launch shapes for this batch: picked by the library's autotuner
     (outside the timed region; X0 formed first where the step computes it),
     or the defaults with --no-autotune."""
+    if args.tune:
+        from paper_2603_00839_amd import rtg
+        fields = dict(kv.split("=", 1) for kv in args.tune.split(",") if kv)
+        plan.set_tune(rtg.make_tune(**{k: int(v) for k, v in fields.items()}))
+        return {"autotuned": False, **plan.tune().as_dict()}
     if args.no_autotune:
         return {"autotuned": False, **plan.tune().as_dict()}
     if pre is not None:
