@@ -41,6 +41,25 @@ class ArnoldiResult:
     ls_res: np.ndarray           # Givens LS residual after each step
 
 
+def orthogonalise(SV: List[np.ndarray], V: List[np.ndarray], s: np.ndarray, W: np.ndarray,
+                  reorth: bool = True):
+    """Column j of H from s = S(W), W = Phi(V_j), against the basis V_1..V_j
+    with sketches SV_i = S(V_i): modified Gram-Schmidt in sketch space, in
+    the algorithm's order (h_ij = <V_i, W>_Theta, then W <- W - h_ij V_i,
+    i = 1..j), with the same updates applied to the full-space W, and (with
+    reorth) one more pass of the same form whose coefficients are added.
+    Returns (h_1j..h_jj, the orthogonalised s, the orthogonalised W)."""
+    j = len(V)
+    h = np.zeros(j)
+    for _ in range(2 if reorth else 1):
+        for i in range(j):
+            hi = frobenius(SV[i], s)
+            h[i] += hi
+            s = s - hi * SV[i]
+            W = W - hi * V[i]
+    return h, s, W
+
+
 def sketched_global_arnoldi(phi: Callable, sketch: Callable, R0: np.ndarray,
                             m: int, reorth: bool = True, bd_tol: float = 1e-12,
                             stop_res: Optional[float] = None) -> ArnoldiResult:
@@ -59,12 +78,8 @@ def sketched_global_arnoldi(phi: Callable, sketch: Callable, R0: np.ndarray,
         W = phi(V[j])
         s = sketch(W)
         rho = math.sqrt(frobenius(s, s))
-        for _ in range(2 if reorth else 1):
-            for i in range(j + 1):
-                h = frobenius(SV[i], s)
-                H[i, j] += h
-                s = s - h * SV[i]
-                W = W - h * V[i]
+        h, s, W = orthogonalise(SV[:j + 1], V[:j + 1], s, W, reorth)
+        H[:j + 1, j] = h
         hn = math.sqrt(frobenius(s, s))
         H[j + 1, j] = hn
         ls_res.append(givens_residuals(H[:j + 2, :j + 1], beta)[-1])

@@ -103,3 +103,41 @@ def test_first_adam_step_is_signed_learning_rate():
     for k in ("w", "b"):
         g = grads[0][k]
         np.testing.assert_allclose(before[0][k] - params[0][k], 1e-2 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+
+
+def test_adam_constant_gradient_moves_by_signed_rate_every_step():
+    """With a constant gradient g the bias-corrected moments are exactly g
+    and g^2 at every step (m_t = (1 - b1^t) g, v_t = (1 - b2^t) g^2), so each
+    of the steps moves by lr g / (|g| + eps)."""
+    g = np.array([0.5, -2.0, 1e-3, 7.0])
+    p = [{"w": np.array([1.0, 2.0, 3.0, 4.0])}]
+    opt = cnn.Adam(p, lr=0.05)
+    for t in range(1, 6):
+        before = p[0]["w"].copy()
+        opt.step(p, [{"w": g.copy()}])
+        np.testing.assert_allclose(before - p[0]["w"], 0.05 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=0)
+
+
+def test_adam_two_gradients_against_hand_worked_moments():
+    """g = 1 then g = 3 on a scalar, lr 0.1, beta1 0.9, beta2 0.999.
+    Step 1: m = 0.1, v = 0.001, corrections 0.1 and 0.001: the step is
+    0.1 * 1 / (1 + eps).  Step 2: m = 0.9 * 0.1 + 0.1 * 3 = 0.39 and
+    v = 0.999 * 0.001 + 0.001 * 9 = 0.009999, corrections 1 - 0.81 = 0.19 and
+    1 - 0.998001 = 0.001999, so m_hat = 39/19 and v_hat = 9999/1999."""
+    p = [{"w": np.array([0.0])}]
+    opt = cnn.Adam(p, lr=0.1)
+    opt.step(p, [{"w": np.array([1.0])}])
+    np.testing.assert_allclose(p[0]["w"][0], -0.1 / (1.0 + 1e-8), rtol=1e-14)
+    np.testing.assert_allclose(opt.m[0]["w"][0], 0.1, rtol=1e-14)
+    np.testing.assert_allclose(opt.v[0]["w"][0], 0.001, rtol=1e-14)
+    opt.step(p, [{"w": np.array([3.0])}])
+    np.testing.assert_allclose(opt.m[0]["w"][0], 0.39, rtol=1e-14)
+    np.testing.assert_allclose(opt.v[0]["w"][0], 0.009999, rtol=1e-13)
+    step2 = 0.1 * (39.0 / 19.0) / (math.sqrt(9999.0 / 1999.0) + 1e-8)
+    np.testing.assert_allclose(p[0]["w"][0], -0.1 / (1.0 + 1e-8) - step2, rtol=1e-13)
+    # a different learning rate at step 3 scales only that step
+    m3, v3 = 0.9 * 0.39 + 0.1 * (-1.0), 0.999 * 0.009999 + 0.001 * 1.0
+    c1, c2 = 1.0 - 0.9 ** 3, 1.0 - 0.999 ** 3
+    before = p[0]["w"][0]
+    opt.step(p, [{"w": np.array([-1.0])}], lr=0.02)
+    np.testing.assert_allclose(before - p[0]["w"][0], 0.02 * (m3 / c1) / (math.sqrt(v3 / c2) + 1e-8), rtol=1e-12)
