@@ -75,7 +75,9 @@ enum {
     RTG_F_DISCREP_UNREACHABLE = 2, /* LS residual already above eta*delta: mu = 0      */
     RTG_F_MU_INF = 4,              /* eta*delta >= beta: y = 0, X = X0                  */
     RTG_F_NONFINITE = 8,           /* NaN/Inf met in a coefficient                     */
-    RTG_F_NOT_CONVERGED = 16       /* stop_res requested and not reached within m      */
+    RTG_F_NOT_CONVERGED = 16,      /* stop_res requested and not reached within m      */
+    RTG_F_FALLBACK = 32            /* rtg_solve_batched_fallback: the result is the
+                                      plain solver's re-solve of this problem          */
 };
 
 /* Solver parameters. */
@@ -240,6 +242,29 @@ int rtg_solve(rtg_op op, rtg_sk sk, const float* C, const float* X0,
 size_t rtg_batch_workspace_bytes(int count, const rtg_problem* probs);
 int rtg_solve_batched(int count, const rtg_problem* probs, void* ws,
                       size_t ws_bytes, void* stream);
+
+/* The plain solver as the fallback of warm-started (or otherwise shortened)
+ * solves.  The batch is solved as by rtg_solve_batched; then every problem
+ * whose flags meet fail_mask (a set of RTG_F_* bits, typically
+ * RTG_F_NOT_CONVERGED | RTG_F_NONFINITE: a solve stopped at stop_res that did
+ * not reach it within m steps, or met a non-finite value) is solved again by
+ * the plain solver: RTG-GMRES (Sec. 4.4) from X0 = 0 with fb_m steps and
+ * basis type fb_basis, the problem's own mu rule, delta, eta and bd_tol, no
+ * stop_res and no restarts.  That result replaces X and info, and its flags
+ * carry RTG_F_FALLBACK.  SYNCHRONOUS: the flags are read back to the host
+ * (one small copy) before the re-solves are enqueued, and the call returns
+ * once they are enqueued.  *n_fallback receives the number of re-solved
+ * problems.  ws_bytes >= rtg_fallback_workspace_bytes(count, probs, fb_m,
+ * fb_basis), which covers the batch and the largest single re-solve; the
+ * re-solves run as many at a time as ws_bytes holds.  Argument errors as
+ * rtg_solve_batched, RTG_E_ARG for fail_mask bits outside RTG_F_BREAKDOWN ..
+ * RTG_F_NOT_CONVERGED or a bad fb_basis, RTG_E_SHAPE for an fb_m the
+ * problems' sketches cannot take (0 from the size query). */
+size_t rtg_fallback_workspace_bytes(int count, const rtg_problem* probs,
+                                    int fb_m, int fb_basis);
+int rtg_solve_batched_fallback(int count, const rtg_problem* probs, int fb_m,
+                               int fb_basis, int fail_mask, void* ws,
+                               size_t ws_bytes, int* n_fallback, void* stream);
 
 /* ---- tile autotuner (the batching form's launch shapes) --------------------
  * The launch shapes of a batch: every combination that the fields allow is

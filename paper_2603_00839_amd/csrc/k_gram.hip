@@ -595,24 +595,28 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
                     Rc[c - 2] = sn[c - 2] * alpha;
                     r_prev = cs[c - 2] * alpha;
                 }
+                const double gj = gvec[c - 1];
+                if (!finite) {
+                    // the solve keeps the c - 1 complete columns: their
+                    // rotations and g_1..g_c stay as the last step left them
+                    st[ST_FLAGS] |= RTG_F_NONFINITE;
+                    st[ST_MEFF] = c - 1;
+                    st[ST_ACTIVE] = 0;
+                    return;
+                }
                 const double rr = hypot(r_prev, nrm);
                 const double cj = rr > 0.0 ? r_prev / rr : 1.0;
                 const double sj = rr > 0.0 ? nrm / rr : 0.0;
                 cs[c - 1] = cj;
                 sn[c - 1] = sj;
                 Rc[c - 1] = rr;
-                const double gj = gvec[c - 1];
                 gvec[c - 1] = cj * gj;
                 gvec[c] = -sj * gj;
                 const double res_ls = fabs(gvec[c]);
                 sc[SC_RESLS] = res_ls;
                 d.coef[c - 1] = (float)alpha;
                 d.coef[MMAX + 1] = nrm > 0.0 ? (float)(1.0 / nrm) : 0.f;
-                if (!finite) {
-                    st[ST_FLAGS] |= RTG_F_NONFINITE;
-                    st[ST_MEFF] = c - 1;
-                    st[ST_ACTIVE] = 0;
-                } else if (nrm <= d.bd_tol * rho) {
+                if (nrm <= d.bd_tol * rho) {
                     st[ST_FLAGS] |= RTG_F_BREAKDOWN;
                     st[ST_MEFF] = c;
                     st[ST_ACTIVE] = 0;
@@ -712,6 +716,15 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
         const double hn = sqrt(hn2 > 0.0 ? hn2 : 0.0);
         const double rho = sqrt(nrm2);
         finite = finite && isfinite(hn);
+        if (!finite) {
+            // the solve keeps the jm complete columns: the rotations, R and
+            // g_1..g_j stay as step jm left them (so gamma_j = g_j is the
+            // residual of the jm-step problem)
+            st[ST_FLAGS] |= RTG_F_NONFINITE;
+            st[ST_MEFF] = jm;
+            st[ST_ACTIVE] = 0;
+            return;
+        }
         // Hessenberg column
         double* Hc = d.H + (size_t)jm * (m + 1);
         for (int i = 0; i < j; ++i) Hc[i] = hs[i];
@@ -741,11 +754,7 @@ __global__ void __launch_bounds__(256) k_gram(const Desc* __restrict__ descs,
         for (int i = 0; i < j; ++i) d.coef[i] = (float)hs[i];
         d.coef[MMAX + 1] = hn > 0.0 ? (float)(1.0 / hn) : 0.f;
         // stopping decisions
-        if (!finite) {
-            st[ST_FLAGS] |= RTG_F_NONFINITE;
-            st[ST_MEFF] = jm;
-            st[ST_ACTIVE] = 0;
-        } else if (hn <= d.bd_tol * rho) {
+        if (hn <= d.bd_tol * rho) {
             st[ST_FLAGS] |= RTG_F_BREAKDOWN;
             st[ST_MEFF] = j;
             st[ST_ACTIVE] = 0;

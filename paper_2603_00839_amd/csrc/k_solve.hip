@@ -340,7 +340,7 @@ __global__ void k_init(const Desc* __restrict__ descs, int cycle) {
             d.state[tid] = nv;
         }
     } else if (tid < NSTATE) {
-        d.state[tid] = (tid == ST_ACTIVE) ? 1 : 0;
+        d.state[tid] = (tid == ST_ACTIVE) ? 1 : ((tid == ST_FLAGS && d.fallback) ? RTG_F_FALLBACK : 0);
     }
     if (tid < NSCAL) d.scal[tid] = 0.0;
     const int m = d.m;

@@ -1133,14 +1133,14 @@ int run_loop(const Plan& plan, const Batch& bt, int count, hipStream_t s) {
     return run_solver(plan, count, bt.mmax, bt.bf16, bt.any_x0, false, false, s);
 }
 
-}  // namespace
-
-extern "C" {
-
-int rtg_solve_batched(int count, const rtg_problem* probs, void* ws, size_t ws_bytes, void* stream) {
+// The batched solve; fallback marks every problem's result as the plain
+// solver's re-solve (RTG_F_FALLBACK in its flags).
+int solve_batched(int count, const rtg_problem* probs, void* ws, size_t ws_bytes, hipStream_t stream,
+                  int fallback) {
     Batch bt;
     int rc = prepare_batch(count, probs, ws, ws_bytes, bt);
     if (rc) return rc;
+    for (auto& d : bt.descs) d.fallback = fallback;
     hipStream_t s = (hipStream_t)stream;
     rtg_tune tune;
     if ((rc = resolve_tune(tune_caps(count, probs), lookup_tune(count, probs), tune))) return rc;
@@ -1153,6 +1153,96 @@ int rtg_solve_batched(int count, const rtg_problem* probs, void* ws, size_t ws_b
     // the cycle out on the device (no host synchronisation)
     for (int c = 1; c <= bt.rmax; ++c)
         if ((rc = run_solver(plan, count, bt.mmax, bt.bf16, true, true, false, s, c))) return rc;
+    return RTG_OK;
+}
+
+// The plain solver's parameters for the re-solve of a problem: its own mu
+// rule and noise level, m steps of RTG-GMRES from X0 = 0 with the given
+// basis type, no early stop and no restarts.
+rtg_params plain_params(const rtg_params& p, int m, int basis_dtype) {
+    rtg_params q = p;
+    q.m = m;
+    q.basis_dtype = basis_dtype;
+    q.stop_res = 0.0;
+    q.restarts = 0;
+    q.method = RTG_METHOD_GMRES;
+    return q;
+}
+
+rtg_problem plain_problem(const rtg_problem& p, int m, int basis_dtype) {
+    rtg_problem q = p;
+    q.X0 = nullptr;
+    q.params = plain_params(p.params, m, basis_dtype);
+    return q;
+}
+
+__global__ void k_gather_flags(const Desc* __restrict__ descs, int count, int* __restrict__ out) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < count) out[p] = descs[p].info->flags;
+}
+
+constexpr int FALLBACK_MASK_ALL = RTG_F_BREAKDOWN | RTG_F_DISCREP_UNREACHABLE | RTG_F_MU_INF | RTG_F_NONFINITE |
+                                  RTG_F_NOT_CONVERGED;
+
+}  // namespace
+
+extern "C" {
+
+int rtg_solve_batched(int count, const rtg_problem* probs, void* ws, size_t ws_bytes, void* stream) {
+    return solve_batched(count, probs, ws, ws_bytes, (hipStream_t)stream, 0);
+}
+
+size_t rtg_fallback_workspace_bytes(int count, const rtg_problem* probs, int fb_m, int fb_basis) {
+    if (count < 1 || !probs || (fb_basis != RTG_F32 && fb_basis != RTG_BF16)) return 0;
+    size_t need = rtg_batch_workspace_bytes(count, probs);
+    if (need == 0) return 0;
+    for (int p = 0; p < count; ++p) {
+        const rtg_problem q = plain_problem(probs[p], fb_m, fb_basis);
+        const size_t b = rtg_batch_workspace_bytes(1, &q);
+        if (b == 0) return 0;
+        need = std::max(need, b);
+    }
+    return need + align_up((size_t)count * sizeof(int));
+}
+
+int rtg_solve_batched_fallback(int count, const rtg_problem* probs, int fb_m, int fb_basis, int fail_mask,
+                               void* ws, size_t ws_bytes, int* n_fallback, void* stream) {
+    if (!n_fallback || (fail_mask & ~FALLBACK_MASK_ALL) != 0) return RTG_E_ARG;
+    *n_fallback = 0;
+    if (fb_basis != RTG_F32 && fb_basis != RTG_BF16) return RTG_E_ARG;
+    if (count < 1 || !probs || !ws) return RTG_E_ARG;
+    for (int p = 0; p < count; ++p) {
+        const rtg_params q = plain_params(probs[p].params, fb_m, fb_basis);
+        int rc = validate_params(&q);
+        if (rc) return rc;
+    }
+    const size_t need = rtg_fallback_workspace_bytes(count, probs, fb_m, fb_basis);
+    if (need == 0) return RTG_E_SHAPE;
+    if (ws_bytes < need) return RTG_E_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = solve_batched(count, probs, ws, ws_bytes, s, 0);
+    if (rc) return rc;
+    // the flags of every problem, gathered through the batch's descriptors
+    // (at the start of the workspace) into its last bytes, then read back
+    int* dflags = (int*)((char*)ws + need - align_up((size_t)count * sizeof(int)));
+    hipLaunchKernelGGL(k_gather_flags, dim3((count + 255) / 256), dim3(256), 0, s, (const Desc*)ws, count, dflags);
+    RTG_HIP(hipGetLastError());
+    std::vector<int> flags((size_t)count, 0);
+    RTG_HIP(hipMemcpyAsync(flags.data(), dflags, (size_t)count * sizeof(int), hipMemcpyDeviceToHost, s));
+    RTG_HIP(hipStreamSynchronize(s));
+    std::vector<rtg_problem> redo;
+    for (int p = 0; p < count; ++p)
+        if (flags[p] & fail_mask) redo.push_back(plain_problem(probs[p], fb_m, fb_basis));
+    *n_fallback = (int)redo.size();
+    // re-solve them with the plain solver, as many at a time as the
+    // workspace holds (each one alone fits: checked above)
+    size_t first = 0;
+    while (first < redo.size()) {
+        size_t n = 1;
+        while (first + n < redo.size() && rtg_batch_workspace_bytes((int)(n + 1), redo.data() + first) <= ws_bytes) ++n;
+        if ((rc = solve_batched((int)n, redo.data() + first, ws, ws_bytes, s, 1))) return rc;
+        first += n;
+    }
     return RTG_OK;
 }
 

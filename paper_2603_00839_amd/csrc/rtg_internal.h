@@ -58,6 +58,8 @@ struct Desc {
     int restarts;       // restart cycles after the first (restarted RTG-GMRES), 0 = none
     int gk;             // sketched Block Golub-Kahan: 1 = the V side (operator Phi), 2 = the U side
                         // (operator Phi^T, transposed bands); 0 = RTG-GMRES
+    int fallback;       // a re-solve by the plain solver after a failed warm-started solve:
+                        // RTG_F_FALLBACK is set in its flags from the start
     long long n;        // I1*I2*J
     long long L;        // l1*l2*l3
     // operator / sketch (device)

@@ -25,6 +25,7 @@ HEADER = os.path.join(HERE, "..", "include", "rtg.h")
 
 F32, BF16 = 0, 1
 FLAG_BREAKDOWN, FLAG_DISCREP_UNREACHABLE, FLAG_MU_INF, FLAG_NONFINITE, FLAG_NOT_CONVERGED = 1, 2, 4, 8, 16
+FLAG_FALLBACK = 32
 
 
 class RTGError(RuntimeError):
@@ -103,6 +104,9 @@ def load_library():
         "rtg_solve": (c_int, [c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(Params), c_vp, c_sz, c_vp, c_vp, c_vp]),
         "rtg_batch_workspace_bytes": (c_sz, [c_int, ctypes.POINTER(Problem)]),
         "rtg_solve_batched": (c_int, [c_int, ctypes.POINTER(Problem), c_vp, c_sz, c_vp]),
+        "rtg_fallback_workspace_bytes": (c_sz, [c_int, ctypes.POINTER(Problem), c_int, c_int]),
+        "rtg_solve_batched_fallback": (c_int, [c_int, ctypes.POINTER(Problem), c_int, c_int, c_int, c_vp, c_sz,
+                                               ctypes.POINTER(c_int), c_vp]),
         "rtg_autotune_batched": (c_int, [c_int, ctypes.POINTER(Problem), c_vp, c_sz, c_int, ctypes.POINTER(Tune),
                                          ctypes.POINTER(c_d), c_vp]),
         "rtg_tune_set": (c_int, [c_int, ctypes.POINTER(Problem), ctypes.POINTER(Tune)]),
@@ -443,10 +447,14 @@ def solve(op: Operator, sk: Sketch, C, X0=None, params: Optional[Params] = None,
 
 class BatchPlan:
     """Problems, outputs and workspace of one rtg_solve_batched call, kept so
-    the same batch can be re-run (e.g. in a timing loop)."""
+    the same batch can be re-run (e.g. in a timing loop).  With fallback =
+    (m, basis_dtype[, fail_mask]) run() calls rtg_solve_batched_fallback: the
+    problems whose flags meet fail_mask (default NOT_CONVERGED | NONFINITE)
+    are solved again by the plain solver (X0 = 0, m steps); run() is then
+    synchronous and n_fallback holds the number of re-solved problems."""
 
     def __init__(self, ops: Sequence[Operator], sks: Sequence[Sketch], Cs, X0s, params: Sequence[Params],
-                 outs=None, device="cuda"):
+                 outs=None, device="cuda", fallback=None):
         torch = _torch()
         self.count = len(ops)
         self.ops, self.sks, self.Cs, self.X0s = list(ops), list(sks), list(Cs), list(X0s)
@@ -466,12 +474,28 @@ class BatchPlan:
             arr[p].params = params[p]
             arr[p].info = self.info[p].data_ptr()
         self.arr = arr
-        nbytes = lib().rtg_batch_workspace_bytes(self.count, arr)
+        self.fallback = None
+        self.n_fallback = 0
+        if fallback is not None:
+            fb_m, fb_basis = int(fallback[0]), int(fallback[1])
+            mask = int(fallback[2]) if len(fallback) > 2 else FLAG_NOT_CONVERGED | FLAG_NONFINITE
+            self.fallback = (fb_m, fb_basis, mask)
+            nbytes = lib().rtg_fallback_workspace_bytes(self.count, arr, fb_m, fb_basis)
+        else:
+            nbytes = lib().rtg_batch_workspace_bytes(self.count, arr)
         if nbytes == 0:
-            raise RTGError("rtg_batch_workspace_bytes: invalid problem")
+            raise RTGError("workspace size query: invalid problem")
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
 
     def run(self):
+        if self.fallback is not None:
+            n = ctypes.c_int(0)
+            fb_m, fb_basis, mask = self.fallback
+            _check(lib().rtg_solve_batched_fallback(self.count, self.arr, fb_m, fb_basis, mask, _ptr(self.ws),
+                                                    self.ws.numel(), ctypes.byref(n), _stream()),
+                   "rtg_solve_batched_fallback")
+            self.n_fallback = n.value
+            return self.outs
         _check(lib().rtg_solve_batched(self.count, self.arr, _ptr(self.ws), self.ws.numel(), _stream()),
                "rtg_solve_batched")
         return self.outs
