@@ -3,13 +3,18 @@ uneven size (sides 64..512 in steps of 16, sigma ~ U(1,3), noise in
 [1e-3, 1e-2], sketches of a quarter of each spatial mode, m = 40) solved in
 one batch, one launch per stage.
 
-* The three smallest problems against the float64 oracle (X within 1e-4).
+* The three smallest and the two largest problems against the float64
+  oracle (X within 1e-4, the same steps, flags and mu; their restoration
+  errors also against the stored oracle results of tests/golden/oracle_re.json,
+  which the benchmark reports beside its own).
 * Every problem: the projected residual the solver reports equals the
   sketched norm of its true residual, ||S(C - Phi(X))||, recomputed through
   the library's operator and sketch (a property of the Theta-orthonormal
   basis that holds at any size), within 1e-3 relative; every restoration
   finite, with relative error below 0.5.
 """
+import json
+import os
 import sys
 
 import numpy as np
@@ -17,6 +22,7 @@ import pytest
 
 from paper_2603_00839_amd import synth
 from oracle.gmres import rtg_gmres
+from oracle.metrics import relative_error
 import _util as U
 
 pytestmark = pytest.mark.gpu
@@ -43,8 +49,12 @@ def test_uneven_batch_of_256_full_size():
     torch.cuda.synchronize()
     infos = plan.infos()
     # sampled problems against the oracle
-    small = sorted(range(len(probs)), key=lambda i: int(np.prod(probs[i].dims)))[:3]
-    for i in small:
+    order = sorted(range(len(probs)), key=lambda i: (int(np.prod(probs[i].dims)), i))
+    sample = order[:3] + order[-2:]
+    with open(os.path.join(os.path.dirname(__file__), "golden", "oracle_re.json")) as f:
+        gold = json.load(f)["uneven"]
+    assert sorted(int(k) for k in gold) == sorted(sample)
+    for i in sample:
         op_o, sk_o = U.oracle_pair(probs[i])
         C, delta = obs[i]
         ref = rtg_gmres(op_o, sk_o, C, 40, delta=delta, eta=1.01)
@@ -54,6 +64,7 @@ def test_uneven_batch_of_256_full_size():
         assert infos[i].iters == ref.m_eff and infos[i].flags == ref.flags
         np.testing.assert_allclose(infos[i].mu, ref.mu, rtol=1e-3)
         assert U.rel(X, ref.X) < 1e-4
+        np.testing.assert_allclose(relative_error(probs[i].x_true, X), gold[str(i)]["re"], rtol=1e-4)
     # every problem: reported projected residual = ||S(C - Phi(X))||
     worst = 0.0
     for i, p in enumerate(probs):

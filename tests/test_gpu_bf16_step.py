@@ -8,10 +8,13 @@ the checks are properties of the stored basis that hold at any size:
 * the sketches S(V_i) the GPU kept are the sketches of the stored V_i (the
   bfloat16 path sketches with Om1 rounded to bfloat16; exact bfloat16
   products, float32 accumulation: relative 1e-4);
-* column j of H is what classical Gram-Schmidt with one reorthogonalisation
-  in sketch space gives for s = S(Phi(V_j)) against those sketches
-  (Sec. 4.3), evaluated here in float64 (1e-3 of the column, from the
-  high/low bfloat16 split of the composed matrix Om1 A1);
+* column j of H is what the oracle's orthogonalisation of Sec. 4.3
+  (modified Gram-Schmidt in sketch space with one reorthogonalisation pass,
+  oracle.arnoldi.orthogonalise) gives for W = Phi(V_j), s = S(W) against
+  the stored V_1..V_j and their sketches, in float64 (1e-3 of the column,
+  from the high/low bfloat16 split of the composed matrix Om1 A1); the GPU
+  evaluates the same column by classical Gram-Schmidt through the sketched
+  Gram matrix, equal in exact arithmetic for a Theta-orthonormal basis;
 * the Arnoldi relation Phi(V_j) = sum_{i<=j+1} h_ij V_i holds up to the
   rounding of h_{j+1,j} V_{j+1} to bfloat16 (unit roundoff 2^-9, bound
   taken as 2^-7 of ||h_{j+1,j} V_{j+1}|| plus float32 noise).
@@ -30,6 +33,8 @@ import pytest
 from paper_2603_00839_amd import synth
 from oracle.operator import Operator
 from oracle.sketch import Sketch
+from oracle.arnoldi import orthogonalise
+from oracle.tensor_algebra import fro_norm
 import _util as U
 
 pytestmark = pytest.mark.gpu
@@ -90,16 +95,13 @@ def _check_step(case, toeplitz):
     # stored sketches are the sketches of the stored basis
     for i in range(m):
         assert U.rel(SVg[i], SV[i]) < 1e-4, ("S(V_i)", i)
+    SVt = [sk_b(V[i]) for i in range(m + 1)]                            # oracle layout
     for j in range(m):
         W = op_o(V[j])
-        # column j of H from sketch-space CGS2 on the stored basis
-        s = sk_b(W).ravel()
-        S = SV[:j + 1]
-        G = S @ S.T
-        h1 = S @ s
-        h = h1 + (h1 - G @ h1)
-        hn2 = s @ s - 2.0 * h @ h1 + h @ G @ h
-        ref = np.concatenate([h, [np.sqrt(max(hn2, 0.0))]])
+        # column j of H: the oracle's sketch-space MGS + reorthogonalisation
+        # against the stored basis
+        h, s_orth, _ = orthogonalise(SVt[:j + 1], V[:j + 1], sk_b(W), W, reorth=True)
+        ref = np.concatenate([h, [fro_norm(s_orth)]])
         got = H[:j + 2, j]
         assert np.linalg.norm(got - ref) <= 1e-3 * np.linalg.norm(ref), ("H column", j, got, ref)
         # Arnoldi relation on the stored basis

@@ -156,3 +156,29 @@ def test_training_reduces_the_loss():
         losses.append(float(net.train_step(C, Y.contiguous(), 3e-3).item()))
     print("losses", losses[0], losses[-1], file=sys.stderr)
     assert losses[-1] < 0.5 * losses[0]
+
+
+def test_adam_four_steps_match_reference():
+    """Four k_adam steps with a different gradient each (new data per step)
+    and a changing learning rate, against the float64 Adam fed with the same
+    gradients: the moments must decay and bias-correct across steps (from
+    step 2 on the update is no longer lr g / |g|)."""
+    import torch
+    from paper_2603_00839_amd import rtg
+    banner("cnn adam, four steps")
+    params = random_params(12, last_scale=1.0)
+    net = rtg.WarmStartNet(flat(params))
+    ref = [{k: v.copy() for k, v in p.items()} for p in unflat(flat(params))]
+    opt = cnn.Adam(ref)
+    rng = np.random.default_rng(13)
+    for k, lr in enumerate((1e-3, 2e-3, 5e-4, 1e-3)):
+        C = torch.from_numpy(images(30 + k, 1, 32, 16)).cuda()
+        Y = (C * float(rng.uniform(0.7, 1.1))).contiguous()
+        net.gradients(C, Y)
+        g = unflat(net.read_gradients())
+        net.adam(lr)
+        opt.step(ref, g, lr=lr)
+    after = unflat(net.export())
+    for l in range(6):
+        for k in ("w", "b"):
+            np.testing.assert_allclose(after[l][k], ref[l][k], rtol=1e-5, atol=1e-7)

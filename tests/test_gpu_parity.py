@@ -355,6 +355,53 @@ def test_nonfinite_input_is_flagged():
     assert rtg.read_info(ib).flags & rtg.FLAG_NONFINITE
 
 
+@pytest.mark.parametrize("basis", ["f32", "bf16"])
+def test_nonfinite_at_step_two_returns_the_one_step_solve(basis):
+    """A coefficient that overflows float32 at step 2 stops the solve with
+    the one complete column: X, mu and the projected residual are those of
+    the oracle's one-step solve (in float64 nothing overflows there).
+
+    The bands are tridiagonal (diagonal 1, off-diagonals 0.5) except for
+    A1[5, 5] = 1e20 and A2[7, 7] = 1e25; C is one pixel at (6, 8).  V_1 is
+    zero on row 5 and column 7, so Phi(V_1) is finite; V_2 has an entry of
+    about 0.2 at (5, 7), where Phi(V_2) and its sketch reach 1e44."""
+    from paper_2603_00839_amd import rtg
+    banner("edge: overflow at step 2", basis)
+    I1, I2, J = 16, 16, 1
+
+    def band(I, hot, big):
+        b = np.zeros((I, 3), np.float32)
+        b[:, 0] = 0.5
+        b[:, 1] = 1.0
+        b[:, 2] = 0.5
+        b[hot, 1] = big
+        return b
+
+    a1, a2, bb = band(I1, 5, 1e20), band(I2, 7, 1e25), np.ones((1, 1), np.float32)
+    rng = np.random.default_rng(8)
+    o1 = (rng.standard_normal((8, I1)) / np.sqrt(8)).astype(np.float32)
+    o2 = (rng.standard_normal((8, I2)) / np.sqrt(8)).astype(np.float32)
+    C = np.zeros((I1, I2, J), np.float32)
+    C[6, 8, 0] = 1.0
+    op_o, sk_o = Operator(a1, a2, bb), Sketch(o1, o2, None)
+    ref = rtg_gmres(op_o, sk_o, C, 1, mu=1e-3)
+    full = rtg_gmres(op_o, sk_o, C, 2, mu=1e-3)
+    assert full.m_eff == 2 and np.abs(full.arnoldi.V[1][5, 7, 0]) > 0.1     # the premise: V_2 at (5, 7)
+    op_g = rtg.setup_operator(I1, I2, J, a1, a2, bb)
+    sk_g = rtg.setup_sketch(I1, I2, J, o1, o2, None)
+    prm = rtg.make_params(5, rtg.BF16 if basis == "bf16" else rtg.F32, mu=1e-3)
+    Xg, ib = rtg.solve(op_g, sk_g, U.to_dev(C), None, prm)
+    info = rtg.read_info(ib)
+    assert info.flags & rtg.FLAG_NONFINITE and info.iters == 1, (info.flags, info.iters)
+    assert np.all(np.isfinite(U.from_dev(Xg)))
+    tol = 2e-2 if basis == "bf16" else 1e-4      # one bfloat16 rounding of V_1
+    assert U.rel(U.from_dev(Xg), ref.X) < tol
+    assert abs(info.res_proj - ref.res_proj) <= tol * ref.res_proj, (info.res_proj, ref.res_proj)
+    # (the bfloat16 path sketches with Om1 rounded to bfloat16, so its beta
+    # differs from the oracle's at that rounding)
+    assert abs(info.beta - ref.beta) <= (1e-2 if basis == "bf16" else 1e-5) * ref.beta
+
+
 def test_batched_uneven_problems_match_oracle():
     """Problems of different sizes, operators, m, mu rules and X0 in one batch."""
     import torch
