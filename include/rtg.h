@@ -175,6 +175,19 @@ size_t rtg_sketch_workspace_bytes(rtg_sk sk);
  * bfloat16 X and uses bfloat16 MFMA with float32 accumulation. */
 int rtg_sketch(rtg_sk sk, int x_dtype, const void* X, float* SX,
                void* ws, size_t ws_bytes, void* stream);
+/* rtg_sketch without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc).  The descriptor and the partial sketches live in
+ * a device array of RTG_SKETCH_NOALLOC_MAX_BYTES that the library keeps on
+ * every GPU it runs on until the process ends; the call allocates nothing.
+ * RTG_E_WORKSPACE when rtg_sketch_workspace_bytes(sk) exceeds that size
+ * (J * ceil(I2 / 32) * l1 * l2 * 4 bytes plus a few hundred, e.g. 0.8 MB for
+ * a 512x512x3 tensor with a 64x64x3 sketch); other argument errors as
+ * rtg_sketch.  All calls on one GPU share its array: calls that overlap in
+ * time on one GPU (several streams, several host threads) race and must be
+ * serialised by the caller.  Results are identical to rtg_sketch's. */
+#define RTG_SKETCH_NOALLOC_MAX_BYTES (8u << 20)
+int rtg_sketch_noalloc(rtg_sk sk, int x_dtype, const void* X, float* SX, void* stream);
 int rtg_destroy_sketch(rtg_sk sk);
 
 /* ---- Arnoldi and solve ----------------------------------------------------- */

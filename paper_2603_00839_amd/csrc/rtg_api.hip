@@ -861,6 +861,60 @@ int rtg_sketch(rtg_sk sk, int x_dtype, const void* X, float* SX, void* ws, size_
     return RTG_OK;
 }
 
+}  // extern "C"
+
+// ---- the sketch without a caller workspace (rtg_sketch_noalloc)
+// Its descriptor, prefix table and per-tile partial sketches live in a
+// file-scope device array: every GPU the library runs on holds its own copy
+// from the load of the code object to the end of the process.  Host code
+// never passes the array's name to a kernel (on the host it only stands in
+// for the symbol); it passes the device address that hipGetSymbolAddress
+// returns, looked up once per device with that device current.
+namespace {
+constexpr size_t SKETCH_SCRATCH_BYTES = (size_t)RTG_SKETCH_NOALLOC_MAX_BYTES;
+__device__ __align__(256) unsigned char scratch[SKETCH_SCRATCH_BYTES];
+
+struct ScratchTable {
+    std::mutex mu;
+    std::vector<void*> ptr;   // device address of scratch, per device ordinal
+};
+
+ScratchTable& scratch_table() {
+    static ScratchTable t;
+    return t;
+}
+
+int scratch_of_current_device(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return RTG_E_HIP;
+    ScratchTable& t = scratch_table();
+    std::lock_guard<std::mutex> lock(t.mu);
+    if ((size_t)dev >= t.ptr.size()) t.ptr.resize((size_t)dev + 1, nullptr);
+    if (!t.ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return RTG_E_HIP;
+        t.ptr[dev] = p;
+    }
+    *out = t.ptr[dev];
+    return RTG_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int rtg_sketch_noalloc(rtg_sk sk, int x_dtype, const void* X, float* SX, void* stream) {
+    if (!sk || !X || !SX) return RTG_E_ARG;
+    if (x_dtype != RTG_F32 && x_dtype != RTG_BF16) return RTG_E_ARG;
+    if (rtg_sketch_workspace_bytes(sk) > SKETCH_SCRATCH_BYTES) return RTG_E_WORKSPACE;
+    void* ws = nullptr;
+    const int rc = scratch_of_current_device(&ws);
+    if (rc) return rc;
+    // the same launches as rtg_sketch, on the device array: nothing in it
+    // has to start at zero (the descriptor and the prefix table are uploaded
+    // by every call, and every tile writes its whole partial sketch)
+    return rtg_sketch(sk, x_dtype, X, SX, ws, SKETCH_SCRATCH_BYTES, stream);
+}
+
 size_t rtg_workspace_bytes(rtg_op op, rtg_sk sk, int m, int basis_dtype) {
     if (check_pair(op, sk) || check_m(sk, m)) return 0;
     // (room for the restart-cycle descriptor copy of rtg_solve with restarts)

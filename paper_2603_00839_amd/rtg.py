@@ -7,7 +7,7 @@ device layout of the library: a C-contiguous torch tensor of shape
 
 The functions keep the names of the C entry points without the ``rtg_``
 prefix: setup_operator, setup_operator_psf, apply_operator, setup_sketch, sketch,
-workspace_bytes, gk_workspace_bytes, arnoldi, golub_kahan, workspace_layout,
+sketch_noalloc, workspace_bytes, gk_workspace_bytes, arnoldi, golub_kahan, workspace_layout,
 gk_workspace_layout, solve, solve_batched.
 """
 from __future__ import annotations
@@ -92,6 +92,7 @@ def load_library():
         "rtg_setup_sketch": (c_int, [c_int, c_int, c_int, c_int, c_int, c_int, fp, fp, fp, ctypes.POINTER(c_vp)]),
         "rtg_sketch_workspace_bytes": (c_sz, [c_vp]),
         "rtg_sketch": (c_int, [c_vp, c_int, c_vp, c_vp, c_vp, c_sz, c_vp]),
+        "rtg_sketch_noalloc": (c_int, [c_vp, c_int, c_vp, c_vp, c_vp]),
         "rtg_destroy_sketch": (c_int, [c_vp]),
         "rtg_workspace_bytes": (c_sz, [c_vp, c_vp, c_int, c_int]),
         "rtg_setup_operator_psf": (c_int, [c_int, c_int, c_int, c_vp, c_int, c_vp, c_int, c_vp]),
@@ -315,6 +316,17 @@ def sketch(sk: Sketch, X, ws=None):
     out = torch.empty((sk.l[2], sk.l[1], sk.l[0]), dtype=torch.float32, device=X.device)
     _check(lib().rtg_sketch(sk.handle, _dtype_code(X), _ptr(X), _ptr(out), _ptr(ws), ws.numel(), _stream()),
            "rtg_sketch")
+    return out
+
+
+def sketch_noalloc(sk: Sketch, X, out):
+    """S(X) into the caller's float32 device tensor out (shape (l3, l2, l1))
+    through rtg_sketch_noalloc: no workspace, nothing allocated."""
+    I1, I2, J = sk.shape
+    _check_tensor(X, (J, I2, I1), "X")
+    _check_tensor(out, (sk.l[2], sk.l[1], sk.l[0]), "out")
+    _check(lib().rtg_sketch_noalloc(sk.handle, _dtype_code(X), _ptr(X), _ptr(out), _stream()),
+           "rtg_sketch_noalloc")
     return out
 
 
