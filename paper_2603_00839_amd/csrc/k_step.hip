@@ -38,6 +38,7 @@ typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
 constexpr int STEP_T1 = 64;                 // rows per block
 constexpr int STEP_NKR = 3;                 // input channels per raw slab
+constexpr int STEP_PF = 4;                  // basis terms of a block requested before the operator is applied
 // Byte offset that lies past every buffer range used here: the host only
 // launches this kernel when a basis vector is under 2^31 bytes.
 constexpr unsigned STEP_OOB = 0x80000000u;
@@ -52,14 +53,18 @@ template <int R, int RPW>
 struct StepSmem {
     static constexpr int T1 = STEP_T1, TC = TILE_TC;
     static constexpr int R8 = (R + 7) / 8 * 8;          // row halo in whole 16-byte chunks
-    static constexpr int CHR = (T1 + 2 * R8) / 8;       // chunks per raw column
+    static constexpr int SR = T1 + 2 * R8;              // slab rows
+    static constexpr int CHR = SR / 8;                  // chunks per raw column
     static constexpr int CHP = CHR | 1;                 // column stride in chunks (odd: no bank conflicts)
     static constexpr int SC = TC + 2 * R;               // slab columns
+    static constexpr int NT = (SC + 15) / 16;           // column tiles of the i1 product
+    static constexpr int NKB = (15 + R8 + R) / 32 + 1;  // 32-row K-blocks per 16-row tile of the i1 product
     static constexpr int NSLOT = STEP_NKR * SC * CHP;   // 16-byte slots of the raw slab
     static constexpr int RAWB = NSLOT * 16;
-    static constexpr int ZRP = T1 + 1;
+    static constexpr int ZRP = T1 + 4;                  // Z column stride (16-byte aligned)
     static constexpr int WP = ((2 * R + 1) + 3) / 4 * 4;
     static constexpr int XP = T1 + 8;
+    static constexpr int WTP = T1 + 4;                  // stride of the transposed W tile
     static constexpr int YP = TC + 1;
     static constexpr int YB = 64 * RPW * YP * 4;
     static constexpr int UB = RAWB > YB ? RAWB : YB;
@@ -67,25 +72,27 @@ struct StepSmem {
 
 // TOEP: both spatial bands are Toeplitz on their in-range entries (a
 // convolution with zero boundary conditions, as for the blurs of Sec. 5).
-// The i1 and i2 passes then read each group of four taps once for all eight
-// outputs of a lane, instead of per output row or column, and the band rows
-// are not streamed into LDS.  Outputs of rows past I1 come out nonzero in
-// this form; they are never stored.
+// The i1 product's coefficient fragments are then the same for every block
+// (computed once per workgroup) and the i2 pass reads each group of four
+// taps once for all eight outputs of a lane; otherwise the block's band rows
+// are streamed into LDS and the fragments are formed per block.  Outputs of
+// rows past I1 come out nonzero in either form; they are never stored.
 template <int R, int RPW, bool TOEP>
-__global__ void __launch_bounds__(256) k_step(const Desc* __restrict__ descs, const int* __restrict__ starts,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_step(const Desc* __restrict__ descs, const int* __restrict__ starts,
                                               int count, int j) {
     using SM = StepSmem<R, RPW>;
-    constexpr int T1 = SM::T1, TC = SM::TC, R8 = SM::R8, CHR = SM::CHR, CHP = SM::CHP, SC = SM::SC;
-    constexpr int NSLOT = SM::NSLOT, ZRP = SM::ZRP, WP = SM::WP, XP = SM::XP, YP = SM::YP;
+    constexpr int T1 = SM::T1, TC = SM::TC, R8 = SM::R8, SR = SM::SR, CHR = SM::CHR, CHP = SM::CHP, SC = SM::SC;
+    constexpr int NT = SM::NT, NKB = SM::NKB;
+    constexpr int NSLOT = SM::NSLOT, ZRP = SM::ZRP, WP = SM::WP, XP = SM::XP, WTP = SM::WTP, YP = SM::YP;
     constexpr int NKR = STEP_NKR;
-    constexpr int NIN = 8 + 2 * R;                      // i1-pass window (rows) per eight outputs
-    constexpr int NRD = (R8 - R + NIN + 7) / 8;         // 16-byte reads covering it from an aligned row
+    constexpr int NIN = 8 + 2 * R;                      // i2-pass window (columns) per eight outputs
 
     // Separate LDS arrays: reads of one are not held back by the compiler
     // for asynchronous loads still in flight into another.
     __shared__ float coef_s[MMAX + 2];
     __shared__ __attribute__((aligned(16))) unsigned char su[SM::UB];
-    __shared__ float Z[SC * ZRP];                       // [col][row] after the i1 pass
+    __shared__ __attribute__((aligned(16))) float Z[SC * ZRP];    // [col][row] after the i1 product
+    __shared__ __attribute__((aligned(16))) float Wt[TC * WTP];   // [col][row]: the W tile, for the multi-AXPY
     __shared__ __attribute__((aligned(16))) float A1c[TOEP ? WP : T1 * WP];   // TOEP: the taps of A1
     __shared__ __attribute__((aligned(16))) float A2c[TOEP ? WP : TC * WP];   // TOEP: the taps of A2
     __shared__ __attribute__((aligned(16))) bf16_t Xh[TC * XP];
@@ -188,96 +195,137 @@ __global__ void __launch_bounds__(256) k_step(const Desc* __restrict__ descs, co
         return k < khi ? bkc : 0.f;
     };
 
+    // ---- the i1 product on MFMA.  Wave w owns output rows 16 w .. 16 w + 15
+    // of every block; their inputs are slab rows [16 w + R8 - R, 16 w + 15 +
+    // R8 + R], covered by NKB K-blocks of 32 rows starting at kstart(q)
+    // (clamped to the slab; rows an earlier K-block covers get coefficient
+    // zero).  A operand: the A1 coefficient of output row 16 w + m16 and slab
+    // row kstart(q) + 8 kq + e, split into three bfloat16 terms (high, middle,
+    // low: their sum is the float32 coefficient to about 2^-24); B operand:
+    // 8 consecutive slab rows of one column, one 16-byte LDS chunk of the raw
+    // bfloat16 slab.  The products are exact and accumulate in float32.
+    auto kstart = [&](int q) { return min(16 * wave + 32 * q, SR - 32); };
+    u4 afr[NKB][3];
+    auto make_frags = [&]() {
+#pragma unroll
+        for (int q = 0; q < NKB; ++q) {
+            const int s0 = kstart(q);
+            const int covered = q > 0 ? kstart(q - 1) + 32 : 0;   // rows below this are an earlier K-block's
+            unsigned hw[4] = {0u, 0u, 0u, 0u}, mw[4] = {0u, 0u, 0u, 0u}, lw[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int sr = s0 + 8 * kq + e;
+                const int orow = 16 * wave + m16;
+                const int dd = sr - R8 - orow;
+                const bool ok = (dd >= -R) & (dd <= R) & (sr >= covered);
+                const int tix = min(max(dd + R, 0), 2 * R);
+                float cf;
+                if constexpr (TOEP) cf = A1c[tix];
+                else cf = A1c[orow * WP + tix];
+                cf = ok ? cf : 0.f;
+                const bf16_t h = f2bf(cf);
+                const float r1v = cf - bf2f(h);
+                const bf16_t mm = f2bf(r1v);
+                const bf16_t lo = f2bf(r1v - bf2f(mm));
+                const int sh = (e & 1) * 16;
+                hw[e >> 1] |= (unsigned)h << sh;
+                mw[e >> 1] |= (unsigned)mm << sh;
+                lw[e >> 1] |= (unsigned)lo << sh;
+            }
+            afr[q][0] = u4{hw[0], hw[1], hw[2], hw[3]};
+            afr[q][1] = u4{mw[0], mw[1], mw[2], mw[3]};
+            afr[q][2] = u4{lw[0], lw[1], lw[2], lw[3]};
+        }
+    };
+    if constexpr (TOEP) {
+        __syncthreads();                                   // taps in LDS
+        make_frags();
+    }
+
     const int nrb = (I1 + T1 - 1) / T1;
     dma_slab(0, klo);
     if constexpr (!TOEP) dma_bands(0);
+    // the multi-AXPY's share of a thread: eight consecutive rows of one
+    // column of the block (16-byte accesses)
+    const int acol = tid >> 3, arow = 8 * (tid & 7);
+    auto load_term = [&](int i, unsigned aoff) {
+        const auto rv = step_rsrc((const bf16_t*)d.V + (size_t)i * d.n + tile_off, tile_elems * 2);
+        return __builtin_amdgcn_raw_buffer_load_b128(rv, aoff, 0, 0);
+    };
     for (int rb = 0; rb < nrb; ++rb) {
         const int i10 = rb * T1;
-        // ---- i1 pass, over groups of NKR input channels:
-        //      Z[col][row] = sum_d A1[i1, i1 + d] U[col][row + d]
+        const bool aok = (i10 + arow < I1) & (acol < ncol);
+        const unsigned aoff = aok ? (unsigned)(acol * I1 + i10 + arow) * 2u : STEP_OOB;
+        // the block's first STEP_PF basis terms are requested now, so that they
+        // arrive while the operator is applied
+        u4 pre[STEP_PF];
+#pragma unroll
+        for (int i = 0; i < STEP_PF; ++i) pre[i] = i < nterms ? load_term(i, aoff) : u4{0u, 0u, 0u, 0u};
+        // ---- i1 product over groups of NKR input channels, each channel's
+        // product mixed in with its weight B[k, c] (mode products commute):
+        //      Z[col][row] = sum_k B[k, c] sum_i' A1[i1, i'] V_j[k][i'][col]
+        f4 zacc[NT];
+#pragma unroll
+        for (int n = 0; n < NT; ++n) zacc[n] = f4{0.f, 0.f, 0.f, 0.f};
         for (int k0 = klo; k0 < khi; k0 += NKR) {
             if (k0 > klo) {
                 __syncthreads();                           // previous group's slab reads done
                 dma_slab(rb, k0);
             }
-            __builtin_amdgcn_s_waitcnt(0x0F70);            // vmcnt(0): this wave's loads into LDS landed
+            // this wave's loads into LDS have landed once at most nv younger
+            // vector-memory instructions are outstanding (the counter runs in
+            // issue order): the basis terms requested above and, after the
+            // first block, the previous block's store stay in flight
+            const int nv = (k0 > klo) ? 0 : (rb > 0 ? 1 : 0) + min(nterms, STEP_PF);
+            switch (nv) {
+                case 0: __builtin_amdgcn_s_waitcnt(0x0F70); break;
+                case 1: __builtin_amdgcn_s_waitcnt(0x0F71); break;
+                case 2: __builtin_amdgcn_s_waitcnt(0x0F72); break;
+                case 3: __builtin_amdgcn_s_waitcnt(0x0F73); break;
+                case 4: __builtin_amdgcn_s_waitcnt(0x0F74); break;
+                default: __builtin_amdgcn_s_waitcnt(0x0F75); break;
+            }
             __syncthreads();
-            float wk[NKR];
+            if constexpr (!TOEP)
+                if (k0 == klo) make_frags();               // this block's band rows
 #pragma unroll
-            for (int kk = 0; kk < NKR; ++kk) wk[kk] = bweight(k0 + kk);
-            if (lane < SC) {
+            for (int kk = 0; kk < NKR; ++kk) {
+                if (k0 + kk >= khi) break;
+                const float wk = bweight(k0 + kk);
+                u4 bv[NKB][NT];
 #pragma unroll
-                for (int blk = 0; blk < 2; ++blk) {
-                    const int rbase = wave * 16 + blk * 8;
-                    // in[e] = U at slab row rbase + (R8 - R) + e of this column
-                    float in[NIN];
+                for (int q = 0; q < NKB; ++q)
 #pragma unroll
-                    for (int e = 0; e < NIN; ++e) in[e] = 0.f;
-#pragma unroll
-                    for (int kk = 0; kk < NKR; ++kk) {
-                        const bf16_t* colp = raw + ((kk * SC + lane) * CHP) * 8 + rbase;
-                        u4 rv[NRD];
-#pragma unroll
-                        for (int q = 0; q < NRD; ++q) rv[q] = *(const u4*)(colp + 8 * q);
-#pragma unroll
-                        for (int e = 0; e < NIN; ++e) {
-                            const int qq = R8 - R + e;
-                            const unsigned w = rv[qq / 8][(qq % 8) / 2];
-                            const float v = __uint_as_float((qq & 1) ? (w & 0xffff0000u) : (w << 16));
-                            in[e] = fmaf(wk[kk], v, in[e]);
-                        }
+                    for (int n = 0; n < NT; ++n) {
+                        const int colc = min(16 * n + m16, SC - 1);
+                        bv[q][n] = *(const u4*)(raw + ((kk * SC + colc) * CHP + kstart(q) / 8 + kq) * 8);
                     }
-                    if constexpr (TOEP) {
-                        float s2[8];
 #pragma unroll
-                        for (int o = 0; o < 8; ++o) s2[o] = (k0 > klo) ? Z[lane * ZRP + rbase + o] : 0.f;
+                for (int n = 0; n < NT; ++n) {
+                    f4 a = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                        for (int t4 = 0; t4 < WP; t4 += 4) {
-                            const f4 cv = *(const f4*)(A1c + t4);
+                    for (int q = 0; q < NKB; ++q)
 #pragma unroll
-                            for (int q = 0; q < 4; ++q) {
-                                if (t4 + q > 2 * R) break;
+                        for (int t = 0; t < 3; ++t)
+                            a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, afr[q][t]),
+                                                                         __builtin_bit_cast(bf8, bv[q][n]), a, 0, 0, 0);
 #pragma unroll
-                                for (int o = 0; o < 8; ++o) s2[o] = fmaf(cv[q], in[o + t4 + q], s2[o]);
-                            }
-                        }
-#pragma unroll
-                        for (int o = 0; o < 8; ++o) Z[lane * ZRP + rbase + o] = s2[o];
-                    } else {
-#pragma unroll
-                        for (int o = 0; o < 8; ++o) {
-                            const float* cr = A1c + (rbase + o) * WP;
-                            float s2 = (k0 > klo) ? Z[lane * ZRP + rbase + o] : 0.f;
-#pragma unroll
-                            for (int t = 0; t <= 2 * R; ++t) s2 = fmaf(cr[t], in[o + t], s2);
-                            Z[lane * ZRP + rbase + o] = s2;
-                        }
-                    }
+                    for (int i = 0; i < 4; ++i) zacc[n][i] = fmaf(wk, a[i], zacc[n][i]);
                 }
             }
+        }
+        // lane: rows 16 w + 4 kq .. + 3 of slab column 16 n + m16
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+            const int col = 16 * n + m16;
+            if (col < SC) *(f4*)(Z + col * ZRP + 16 * wave + 4 * kq) = zacc[n];
         }
         __syncthreads();                                   // Z complete; slab and band rows free
         if (rb + 1 < nrb) {
             dma_slab(rb + 1, klo);
             if constexpr (!TOEP) dma_bands(rb + 1);
         }
-        // ---- the first two multi-AXPY terms (lane = row, eight columns per wave)
-        const int row = i10 + lane;
-        unsigned aoff[8];
-#pragma unroll
-        for (int o = 0; o < 8; ++o) {
-            const int col = wave * 8 + o;
-            aoff[o] = (row < I1 && col < ncol) ? (unsigned)(col * I1 + row) * 2u : STEP_OOB;
-        }
-        auto load_term = [&](int i, unsigned* v) {
-            const auto rv = step_rsrc((const bf16_t*)d.V + (size_t)i * d.n + tile_off, tile_elems * 2);
-#pragma unroll
-            for (int o = 0; o < 8; ++o) v[o] = __builtin_amdgcn_raw_buffer_load_b16(rv, aoff[o], 0, 0);
-        };
-        unsigned va[8], vb[8];
-        if (nterms > 0) load_term(0, va);
-        if (nterms > 1) load_term(1, vb);
-        // ---- i2 pass: the W tile in registers
+        // ---- i2 pass (lane = row, eight columns per wave): the W tile
         float x[8];
         {
             float in2[NIN];
@@ -307,6 +355,14 @@ __global__ void __launch_bounds__(256) k_step(const Desc* __restrict__ descs, co
                 }
             }
         }
+        // ---- the W tile to LDS, read back as eight consecutive rows of one
+        // column per thread: the multi-AXPY, the store and the sketch operand
+        // are then 16-byte accesses
+#pragma unroll
+        for (int o = 0; o < 8; ++o) Wt[(wave * 8 + o) * WTP + lane] = x[o];
+        u4 va = u4{0u, 0u, 0u, 0u}, vb = u4{0u, 0u, 0u, 0u};
+        if (nterms > STEP_PF) va = load_term(STEP_PF, aoff);
+        if (nterms > STEP_PF + 1) vb = load_term(STEP_PF + 1, aoff);
         // ---- operands of this block's mode-1 contraction (stacked rows
         // [Om1 ; Om1 A1]), requested before the stores so that they arrive
         // while the tile is stored
@@ -330,30 +386,49 @@ __global__ void __launch_bounds__(256) k_step(const Desc* __restrict__ descs, co
                 A[u2].l = half ? __builtin_amdgcn_raw_buffer_load_b128(rs, off + om1_lo, 0, 0) : u4{0u, 0u, 0u, 0u};
             }
         };
-        // ---- multi-AXPY, two terms in flight
-        auto apply_term = [&](float ci, const unsigned* v) {
-#pragma unroll
-            for (int o = 0; o < 8; ++o) x[o] = fmaf(-ci, __uint_as_float(v[o] << 16), x[o]);
-        };
-        for (int i = 0; i < nterms; i += 2) {
-            apply_term(coef_s[i], va);
-            if (i + 2 < nterms) load_term(i + 2, va);
-            if (i + 1 < nterms) {
-                apply_term(coef_s[i + 1], vb);
-                if (i + 3 < nterms) load_term(i + 3, vb);
-            }
-        }
         AF A0[RPW], A1[RPW];
         load_a(0, A0);
         if (nkb > 1) load_a(1, A1);
-        // ---- scale, round, store V_{j+1}; the tile to LDS for the sketch
-        const auto rd = step_rsrc((const bf16_t*)d.V + (size_t)j * d.n + tile_off, tile_elems * 2);
+        __syncthreads();                                   // the W tile is in LDS
+        float w8[8];
+        {
+            const f4 lo4 = *(const f4*)(Wt + acol * WTP + arow);
+            const f4 hi4 = *(const f4*)(Wt + acol * WTP + arow + 4);
 #pragma unroll
-        for (int o = 0; o < 8; ++o) {
-            const bf16_t h = f2bf(aoff[o] != STEP_OOB ? x[o] * scale : 0.f);
-            __builtin_amdgcn_raw_buffer_store_b16(h, rd, aoff[o], 0, 0);
-            Xh[(wave * 8 + o) * XP + lane] = h;
+            for (int r = 0; r < 4; ++r) {
+                w8[r] = lo4[r];
+                w8[4 + r] = hi4[r];
+            }
         }
+        // ---- multi-AXPY, two terms in flight
+        auto apply_term = [&](float ci, u4 v) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                w8[2 * q] = fmaf(-ci, __uint_as_float(v[q] << 16), w8[2 * q]);
+                w8[2 * q + 1] = fmaf(-ci, __uint_as_float(v[q] & 0xffff0000u), w8[2 * q + 1]);
+            }
+        };
+#pragma unroll
+        for (int i = 0; i < STEP_PF; ++i)
+            if (i < nterms) apply_term(coef_s[i], pre[i]);
+        for (int i = STEP_PF; i < nterms; i += 2) {
+            apply_term(coef_s[i], va);
+            if (i + 2 < nterms) va = load_term(i + 2, aoff);
+            if (i + 1 < nterms) {
+                apply_term(coef_s[i + 1], vb);
+                if (i + 3 < nterms) vb = load_term(i + 3, aoff);
+            }
+        }
+        // ---- scale, round, store V_{j+1}; the tile to LDS for the sketch
+        // (zeros outside the tensor: the sketch operands' padding is zero too)
+        u4 pk;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            pk[q] = (unsigned)f2bf(w8[2 * q] * scale) | ((unsigned)f2bf(w8[2 * q + 1] * scale) << 16);
+        if (!aok) pk = u4{0u, 0u, 0u, 0u};
+        const auto rd = step_rsrc((const bf16_t*)d.V + (size_t)j * d.n + tile_off, tile_elems * 2);
+        __builtin_amdgcn_raw_buffer_store_b128(pk, rd, aoff, 0, 0);
+        *(u4*)(Xh + acol * XP + arow) = pk;
         __syncthreads();
         // ---- mode-1 contraction of this block on MFMA (a block is at most two K-blocks)
         auto mfma_block = [&](int kb, const AF* A) {
