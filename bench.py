@@ -31,6 +31,9 @@ Variants (each timed over the same number of steps):
                  those 256 problems per step.  (A bfloat16 basis from X0 = 0
                  misses the oracle's restoration error on this batch: some
                  problems do not reach the discrepancy level in 40 steps.)
+  mixed_uneven   the same batch in the mixed form RTG_F32_BF16: float32 basis,
+                 sketch contractions on bfloat16 MFMA operands with float32
+                 accumulation
   fp32_video     --video-batch 256x256x64 grayscale videos (spatial sigma 2,
                  temporal box blur of width 5, noise 1e-3, sketch 48x48x16),
                  float32 basis, X0 = 0, m = 80
@@ -76,7 +79,7 @@ sys.path.insert(0, ROOT)
 METRIC = "RTG-GMRES solves/s at 512²×3, m=50: plain FP32 vs BF16+learned X₀ at equal rel err"
 HBM_PEAK_GBS = 8000.0
 VARIANTS = ["fp32_plain", "bf16_warm", "bf16_obs", "fp32_unsketched", "fp32_gk", "fp32_psf", "fp32_uneven",
-            "fp32_video", "bf16_video"]
+            "mixed_uneven", "fp32_video", "bf16_video"]
 # the plain solver that re-solves failed warm starts: X0 = 0, m = 50, float32 basis
 FALLBACK_M = 50
 GOLDEN_RE = os.path.join(ROOT, "tests", "golden", "oracle_re.json")
@@ -381,7 +384,7 @@ def oracle_ratios(results, cb, gold):
             pairs = [(r["re"][k], cb["re"][k]) for k in (0, 1) if k < len(r["re"])]
         elif v == "fp32_psf":
             pairs = [(r["re"][0], cb["re_psf0"])]
-        elif v == "fp32_uneven" and gold:
+        elif v in ("fp32_uneven", "mixed_uneven") and gold:
             pairs = [(r["re"][int(k)], g["re"]) for k, g in gold["uneven"].items() if int(k) < len(r["re"])]
         elif v in ("fp32_video", "bf16_video") and gold:
             pairs = [(r["re"][0], gold["video"]["0"]["re"])]
@@ -480,10 +483,11 @@ def main():
                 r["kernel"] = ("k_tile", "k_tile.hip", "multi-AXPY + store + MFMA sketch, 256x256x64 videos")
             res = [rel_err(plan.outs[b], probs_v[b]["xt"]) for b in range(Bv)]
             r["solves_per_step"] = Bv
-        elif v == "fp32_uneven":
+        elif v in ("fp32_uneven", "mixed_uneven"):
             probs_u = make_uneven_batch(dev)
             Bu = len(probs_u)
-            prm = [rtg.make_params(40, rtg.F32, delta=q["delta"], eta=1.01) for q in probs_u]
+            bt = rtg.F32 if v == "fp32_uneven" else rtg.F32_BF16
+            prm = [rtg.make_params(40, bt, delta=q["delta"], eta=1.01) for q in probs_u]
             plan = rtg.BatchPlan([q["op"] for q in probs_u], [q["sk"] for q in probs_u], [q["C"] for q in probs_u],
                                  [None] * Bu, prm)
             ns = [q["n"] for q in probs_u]
@@ -496,7 +500,8 @@ def main():
             tune = tune_plan(plan, args)
             r = time_variant(plan, args.steps, args.warmup, rtg, torch, rtg.KIND_TILE, bytes_u)
             r["kernel"] = ("k_tile", "k_tile.hip", "multi-AXPY + store + MFMA sketch, float32 basis, "
-                                                   "256 uneven problems")
+                                                   + ("float32" if v == "fp32_uneven" else "bfloat16")
+                                                   + " products, 256 uneven problems")
             res = [rel_err(plan.outs[b], probs_u[b]["xt"]) for b in range(Bu)]
             r["solves_per_step"] = Bu
         elif v == "fp32_psf":
@@ -556,7 +561,7 @@ def main():
             r["kernel"] = ("k_step", "k_step.hip", "Arnoldi step: operator per tile + multi-AXPY + store + "
                                                    "dual MFMA sketch (bfloat16 basis)")
             r["fallbacks_per_step"] = plan.n_fallback
-        if v not in ("fp32_psf", "fp32_uneven", "fp32_video", "bf16_video"):
+        if v not in ("fp32_psf", "fp32_uneven", "mixed_uneven", "fp32_video", "bf16_video"):
             res = [rel_err(plan.outs[b], probs[b]["xt"]) for b in range(B)]
         r["tune"] = tune
         r["re"] = res

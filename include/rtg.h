@@ -53,8 +53,12 @@ extern "C" {
 typedef struct rtg_op_s* rtg_op;
 typedef struct rtg_sk_s* rtg_sk;
 
-/* element types of tensors the library reads (X inputs, the Krylov basis) */
-enum { RTG_F32 = 0, RTG_BF16 = 1 };
+/* element types of tensors the library reads (X inputs, the Krylov basis);
+ * RTG_F32_BF16 (basis only): the basis is stored in float32 and the sketch
+ * contractions take bfloat16 MFMA operands with float32 accumulation (each
+ * new basis tensor rounded to bfloat16 for the products; Om1 rounded to
+ * bfloat16, its composition with A1 kept in two bfloat16 terms) */
+enum { RTG_F32 = 0, RTG_BF16 = 1, RTG_F32_BF16 = 2 };
 
 /* return codes */
 enum {
@@ -84,7 +88,9 @@ enum {
 typedef struct {
     int m;            /* maximum number of Arnoldi steps (Golub-Kahan: columns),
                          1 <= m <= 96                                            */
-    int basis_dtype;  /* RTG_F32 or RTG_BF16: storage of V_j (and MFMA precision) */
+    int basis_dtype;  /* RTG_F32, RTG_BF16 (storage of V_j and MFMA precision) or
+                         RTG_F32_BF16 (float32 storage, bfloat16 sketch products;
+                         RTG-GMRES only)                                         */
     double mu;        /* >= 0: fixed Tikhonov parameter; < 0: chosen by mu_rule    */
     double delta;     /* absolute noise-norm estimate ||E||_F (discrepancy)       */
     double eta;       /* discrepancy safety factor (1.01 is customary)            */

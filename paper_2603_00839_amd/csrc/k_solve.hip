@@ -380,7 +380,7 @@ __global__ void k_compose(const Desc* __restrict__ descs, int nbc) {
         for (int dd = -r1; dd <= r1; ++dd) {
             const int ip = i - dd;
             const int ipc = min(max(ip, 0), I1 - 1);
-            const float om = d.bf16 ? bf2f(d.om1h[(size_t)ac * I1 + ipc]) : d.om1[(size_t)ac * I1 + ipc];
+            const float om = d.skbf ? bf2f(d.om1h[(size_t)ac * I1 + ipc]) : d.om1[(size_t)ac * I1 + ipc];
             const float w = d.a1t[(size_t)(r1 + dd) * I1 + ipc];
             acc = fmaf((ip >= 0 && ip < I1) ? om : 0.f, w, acc);
         }

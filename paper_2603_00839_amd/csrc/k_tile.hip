@@ -40,6 +40,7 @@ namespace rtg {
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u2v __attribute__((ext_vector_type(2)));
 
 constexpr int TILE_SBR = 256;   // rows per super-block: 256 lanes x 32 elements / 32 columns
 // element offset of a chunk outside the tile: its byte offset lies past every
@@ -54,29 +55,33 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, in
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, 0x00020000);
 }
 
-template <bool BB, bool SPLIT, int RPW>
+template <bool MB, bool SPLIT, int RPW>
 struct TileSmem {
     static constexpr int TC = TILE_TC;
     static constexpr int CSB = TILE_SBR + 8;    // bfloat16 plane column stride (elements)
     static constexpr int CSF = TILE_SBR + 4;    // float32 column stride (elements)
-    static constexpr int XBYTES = BB ? (SPLIT ? 2 : 1) * TC * CSB * 2 : TC * CSF * 4;
+    static constexpr int XBYTES = MB ? (SPLIT ? 2 : 1) * TC * CSB * 2 : TC * CSF * 4;
     static constexpr int YP = TC + 1;
     static constexpr int YBYTES = 64 * RPW * YP * 4;   // stacked sketch rows x columns
     static constexpr int BYTES = XBYTES > YBYTES ? XBYTES : YBYTES;
 };
 
-// BB: basis stored as bfloat16 (bfloat16 MFMA); SPLIT: the sketched tile is
-// float32 in bfloat16 mode (two planes); RPW: sketch row tiles of 16 per wave.
-template <bool BB, bool SPLIT, int RPW>
+// BB: basis stored as bfloat16; MB: the sketch contractions take bfloat16
+// MFMA operands (float32 accumulation) -- a bfloat16 basis always does, a
+// float32 basis in the mixed form (RTG_F32_BF16) does with its tile rounded
+// to bfloat16 for the products; SPLIT: the sketched tile is float32 in
+// bfloat16 mode, split into two planes; RPW: sketch row tiles of 16 per wave.
+template <bool BB, bool MB, bool SPLIT, int RPW>
 __global__ void __launch_bounds__(256) k_tile(const Desc* __restrict__ descs,
                                               const int* __restrict__ starts, int count,
                                               int mode, int nterms_arg, int dst_index, int t0) {
-    using SM = TileSmem<BB, SPLIT, RPW>;
+    static_assert(MB || !BB, "a bfloat16 basis uses bfloat16 products");
+    using SM = TileSmem<MB, SPLIT, RPW>;
     constexpr int TC = TILE_TC;
     constexpr int SBR = TILE_SBR;
     constexpr int CK = BB ? 8 : 4;             // elements per lane chunk (16 bytes of basis)
     constexpr int NCK = SBR * TC / 256 / CK;   // chunks per lane
-    constexpr int KBR = BB ? 32 : 16;          // rows per MFMA K-block
+    constexpr int KBR = MB ? 32 : 16;          // rows per MFMA K-block
     constexpr int CSB = SM::CSB, CSF = SM::CSF, YP = SM::YP;
 
     __shared__ float coef_s[MMAX + 2];
@@ -133,9 +138,9 @@ __global__ void __launch_bounds__(256) k_tile(const Desc* __restrict__ descs,
     // sketch matrices in operand order: Om1, and Om1 A1 (bfloat16: high
     // plane then low plane)
     const int nkbf = frag_nkb(I1, KBR);
-    const unsigned fbytes = (unsigned)frag_elems(l1, I1, KBR) * (unsigned)es;
-    const auto rom1 = make_rsrc(BB ? (const void*)d.om1hf : (const void*)d.om1f, (int)fbytes);
-    const auto rom1c = make_rsrc(BB ? (const void*)d.om1th : (const void*)d.om1t, (int)(BB ? 2 * fbytes : fbytes));
+    const unsigned fbytes = (unsigned)frag_elems(l1, I1, KBR) * (MB ? 2u : 4u);
+    const auto rom1 = make_rsrc(MB ? (const void*)d.om1hf : (const void*)d.om1f, (int)fbytes);
+    const auto rom1c = make_rsrc(MB ? (const void*)d.om1th : (const void*)d.om1t, (int)(MB ? 2 * fbytes : fbytes));
     f4 acc[RPW][2];
 #pragma unroll
     for (int u = 0; u < RPW; ++u)
@@ -267,7 +272,26 @@ __global__ void __launch_bounds__(256) k_tile(const Desc* __restrict__ descs,
         if (sb > 0) __syncthreads();          // the previous super-block's MFMA reads are done
 #pragma unroll
         for (int u = 0; u < NCK; ++u) {
-            if constexpr (BB) {
+            if constexpr (MB && !BB && !SPLIT) {
+                // float32 basis, bfloat16 products: the chunk's four values rounded
+                u2v hi;
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+                    hi[q] = (unsigned)f2bf(x[u][2 * q]) | ((unsigned)f2bf(x[u][2 * q + 1]) << 16);
+                *(u2v*)(Xh + colu[u] * CSB + rowu[u]) = hi;
+            } else if constexpr (MB && !BB) {
+                // float32 source split into high and low planes
+                u2v hi, lo;
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const bf16_t h0 = f2bf(x[u][2 * q]), h1 = f2bf(x[u][2 * q + 1]);
+                    hi[q] = (unsigned)h0 | ((unsigned)h1 << 16);
+                    const bf16_t g0 = f2bf(x[u][2 * q] - bf2f(h0)), g1 = f2bf(x[u][2 * q + 1] - bf2f(h1));
+                    lo[q] = (unsigned)g0 | ((unsigned)g1 << 16);
+                }
+                *(u2v*)(Xh + colu[u] * CSB + rowu[u]) = hi;
+                *(u2v*)(Xl + colu[u] * CSB + rowu[u]) = lo;
+            } else if constexpr (BB) {
                 u4 hi, lo;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
@@ -292,7 +316,7 @@ __global__ void __launch_bounds__(256) k_tile(const Desc* __restrict__ descs,
         const int rows_sb = min(SBR, I1 - sb * SBR);
         const int nkb = (rows_sb + KBR - 1) / KBR;
         struct AF {
-            u4 h, l;     // bfloat16: Om1 (h), or Om1 A1 high / low; float32: h as f4 bits
+            u4 h, l;     // bfloat16 products: Om1 (h), or Om1 A1 high / low; float32: h as f4 bits
         };
         // A fragments in operand order: one contiguous 1 KB read per wave and
         // tile; padding rows and columns are stored zeros, and unused tiles
@@ -307,7 +331,7 @@ __global__ void __launch_bounds__(256) k_tile(const Desc* __restrict__ descs,
                 const unsigned off = (t < NRT) ? (unsigned)((tl * nkbf + kbg) * 64 + lane) * 16u : OOB_A;
                 const auto& rs = half ? rom1c : rom1;
                 A[u].h = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
-                if constexpr (BB)
+                if constexpr (MB)
                     A[u].l = half ? __builtin_amdgcn_raw_buffer_load_b128(rs, off + fbytes, 0, 0) : u4{0u, 0u, 0u, 0u};
             }
         };
@@ -315,7 +339,7 @@ __global__ void __launch_bounds__(256) k_tile(const Desc* __restrict__ descs,
 #pragma unroll
             for (int g = 0; g < 2; ++g) {
                 const int col = 16 * g + m16;
-                if constexpr (BB) {
+                if constexpr (MB) {
                     const u4 bh = *(const u4*)(Xh + col * CSB + kb * KBR + 8 * kq);
                     u4 bl = u4{0u, 0u, 0u, 0u};
                     if constexpr (SPLIT) bl = *(const u4*)(Xl + col * CSB + kb * KBR + 8 * kq);
@@ -382,18 +406,23 @@ __global__ void __launch_bounds__(256) k_tile(const Desc* __restrict__ descs,
 
 hipError_t launch_tile(const Desc* d, const int* starts, int count, int total_tiles, int mode,
                        int nterms, int dst_index, int basis_bf16, int src_bf16, int l1max, hipStream_t s,
-                       int first_term, int rows) {
-#define RTG_TILE(BBV, SPV, RPV)                                                                   \
-    hipLaunchKernelGGL((k_tile<BBV, SPV, RPV>), dim3(total_tiles), dim3(256), 0, s, d, starts, count, \
+                       int first_term, int rows, int sketch_bf16) {
+#define RTG_TILE(BBV, MBV, SPV, RPV)                                                              \
+    hipLaunchKernelGGL((k_tile<BBV, MBV, SPV, RPV>), dim3(total_tiles), dim3(256), 0, s, d, starts, count, \
                        mode, nterms, dst_index, first_term)
     const int rtiles = ((l1max + 15) / 16) * ((mode == TM_NEWV || mode == TM_GKNEW) ? 2 : 1);
     const bool small = rtiles <= 8 && rows != 4;
+    const bool split = (mode == TM_SKETCH_SRC || mode == TM_SKETCH_W) && !src_bf16;
     if (basis_bf16) {
-        const bool split = (mode == TM_SKETCH_SRC || mode == TM_SKETCH_W) && !src_bf16;
-        if (split) { if (small) RTG_TILE(true, true, 2); else RTG_TILE(true, true, 4); }
-        else { if (small) RTG_TILE(true, false, 2); else RTG_TILE(true, false, 4); }
+        if (split) { if (small) RTG_TILE(true, true, true, 2); else RTG_TILE(true, true, true, 4); }
+        else { if (small) RTG_TILE(true, true, false, 2); else RTG_TILE(true, true, false, 4); }
+    } else if (sketch_bf16) {
+        // float32 basis with bfloat16 products: sources that are not a basis
+        // tensor (R0, W) keep the two-plane split, new basis tensors one plane
+        if (split) { if (small) RTG_TILE(false, true, true, 2); else RTG_TILE(false, true, true, 4); }
+        else { if (small) RTG_TILE(false, true, false, 2); else RTG_TILE(false, true, false, 4); }
     } else {
-        if (small) RTG_TILE(false, false, 2); else RTG_TILE(false, false, 4);
+        if (small) RTG_TILE(false, false, false, 2); else RTG_TILE(false, false, false, 4);
     }
 #undef RTG_TILE
     return hipGetLastError();

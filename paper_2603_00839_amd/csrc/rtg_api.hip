@@ -188,6 +188,7 @@ void fill_desc(Desc& d, const rtg_op_s* op, const rtg_sk_s* sk, int m, int bf16,
     d.r1 = op->r1; d.r2 = op->r2; d.rB = op->rB;
     d.m = m;
     d.bf16 = bf16;
+    d.skbf = bf16;
     d.has_om3 = sk->has_om3;
     d.n_i2t = L.n_i2t;
     d.ntile[KIND_PHI] = L.ntile_phi;
@@ -266,6 +267,7 @@ struct Plan {
     int step_toep;     // fused step: Toeplitz taps
     int tile_rows;     // sketch tiles per wave of the tile kernel (2 where they fit, or 4)
     int step_rows;     // the same for the fused step
+    int skbf;          // sketch contractions on bfloat16 operands (every problem's descriptor says so)
     Desc* d_desc_r;    // restart cycles: the descriptors with X0 = X (null without restarts)
 };
 
@@ -328,6 +330,7 @@ int build_plan(std::vector<Desc>& descs, void* ws, hipStream_t s, Plan& plan, in
     plan.step_toep = plan.toeplitz;
     plan.tile_rows = 2;
     plan.step_rows = 2;
+    plan.skbf = descs.empty() ? 0 : descs[0].skbf;
     if (tune) {
         if (tune->phi_slab >= 0) plan.phi_dma = std::min(plan.phi_dma, tune->phi_slab);
         if (tune->phi_toeplitz >= 0) plan.phi_toep = plan.toeplitz && tune->phi_toeplitz;
@@ -428,19 +431,19 @@ int run_solver(const Plan& plan, int count, int mmax, int bf16, bool any_x0, boo
             RTG_TIMED(0, launch_phi(dd, sp, count, plan.total[KIND_PHI], PS_X0, 0, plan.rmax, plan.phi_jt, 0,
                                     s, plan.stencil, plan.phi_dma, plan.phi_toep));
         RTG_TIMED(2, launch_gram(dd, sg, count, plan.total[KIND_GRAM], GM_START, cycle, nullptr, s, us));
-        RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_NEWV, 0, 0, bf16, 0, plan.l1max, s, 0, plan.tile_rows));
+        RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_NEWV, 0, 0, bf16, 0, plan.l1max, s, 0, plan.tile_rows, plan.skbf));
         for (int j = 1; j <= mmax; ++j) {
             RTG_TIMED(0, launch_phi(dd, sp, count, plan.total[KIND_PHI], PS_BASIS, j - 1, plan.rmax,
                                     plan.phi_jt, bf16, s, plan.stencil, plan.phi_dma, plan.phi_toep));
             RTG_TIMED(2, launch_gram(dd, sg, count, plan.total[KIND_GRAM], GM_STEP, j, nullptr, s, us));
             if (j < mmax || last_newv)
                 RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_NEWV, j, j, bf16, 0,
-                                         plan.l1max, s, 0, plan.tile_rows));
+                                         plan.l1max, s, 0, plan.tile_rows, plan.skbf));
         }
         if (solve) {
             RTG_TIMED(3, launch_solve(dd, count, mmax, s));
             RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_ASSEMBLE, 0, 0, bf16, 0,
-                                     plan.l1max, s, 0, plan.tile_rows));
+                                     plan.l1max, s, 0, plan.tile_rows, plan.skbf));
         }
         return RTG_OK;
     }
@@ -451,31 +454,31 @@ int run_solver(const Plan& plan, int count, int mmax, int bf16, bool any_x0, boo
             RTG_TIMED(0, launch_phi(dd, sp, count, plan.total[KIND_PHI], PS_X0, 0, plan.rmax, plan.phi_jt, 0,
                                     s, 1, plan.phi_dma, plan.phi_toep));
         RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_SKETCH_SRC, 0, 0, bf16, 0,
-                                 plan.l1max, s, 0, plan.tile_rows));
+                                 plan.l1max, s, 0, plan.tile_rows, plan.skbf));
         RTG_TIMED(2, launch_gram(dd, sg, count, plan.total[KIND_GRAM], GM_START, cycle, nullptr, s));
-        RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_NEWV, 0, 0, bf16, 0, plan.l1max, s, 0, plan.tile_rows));
+        RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_NEWV, 0, 0, bf16, 0, plan.l1max, s, 0, plan.tile_rows, plan.skbf));
         for (int j = 1; j <= mmax; ++j) {
             RTG_TIMED(0, launch_phi(dd, sp, count, plan.total[KIND_PHI], PS_BASIS, j - 1, plan.rmax,
                                     plan.phi_jt, bf16, s, 1, plan.phi_dma, plan.phi_toep));
             RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_SKETCH_W, 0, 0, bf16, 0,
-                                     plan.l1max, s, 0, plan.tile_rows));
+                                     plan.l1max, s, 0, plan.tile_rows, plan.skbf));
             RTG_TIMED(2, launch_gram(dd, sg, count, plan.total[KIND_GRAM], GM_STEP, j, nullptr, s));
             if (j < mmax || last_newv)
                 RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_NEWV, j, j, bf16, 0,
-                                         plan.l1max, s, 0, plan.tile_rows));
+                                         plan.l1max, s, 0, plan.tile_rows, plan.skbf));
         }
         if (solve) {
             RTG_TIMED(3, launch_solve(dd, count, mmax, s));
             RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_ASSEMBLE, 0, 0, bf16, 0,
-                                     plan.l1max, s, 0, plan.tile_rows));
+                                     plan.l1max, s, 0, plan.tile_rows, plan.skbf));
         }
         return RTG_OK;
     }
     if (cycle == 0) RTG_HIP(launch_compose(dd, count, plan.compose_max, s));   // restart cycles reuse them
     if (any_x0) RTG_TIMED(0, launch_phi(dd, sp, count, plan.total[KIND_PHI], PS_X0, 0, plan.rmax, plan.phi_jt, 0, s, 0, plan.phi_dma, plan.phi_toep));
-    RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_SKETCH_SRC, 0, 0, bf16, 0, plan.l1max, s, 0, plan.tile_rows));
+    RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_SKETCH_SRC, 0, 0, bf16, 0, plan.l1max, s, 0, plan.tile_rows, plan.skbf));
     RTG_TIMED(2, launch_gram(dd, sg, count, plan.total[KIND_GRAM], GM_START, cycle, nullptr, s));
-    RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_NEWV, 0, 0, bf16, 0, plan.l1max, s, 0, plan.tile_rows));
+    RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_NEWV, 0, 0, bf16, 0, plan.l1max, s, 0, plan.tile_rows, plan.skbf));
     for (int j = 1; j <= mmax; ++j) {
         // S(V_j) and S(Phi(V_j)) come from the pass that formed V_j.  With a
         // bfloat16 basis the step kernel recomputes Phi(V_j) tile by tile (W
@@ -493,13 +496,13 @@ int run_solver(const Plan& plan, int count, int mmax, int bf16, bool any_x0, boo
                 RTG_TIMED(0, launch_phi(dd, sp, count, plan.total[KIND_PHI], PS_BASIS, j - 1, plan.rmax,
                                         plan.phi_jt, bf16, s, 0, plan.phi_dma, plan.phi_toep));
                 RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_NEWV, j, j, bf16, 0,
-                                         plan.l1max, s, 0, plan.tile_rows));
+                                         plan.l1max, s, 0, plan.tile_rows, plan.skbf));
             }
         }
     }
     if (solve) {
         RTG_TIMED(3, launch_solve(dd, count, mmax, s));
-        RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_ASSEMBLE, 0, 0, bf16, 0, plan.l1max, s, 0, plan.tile_rows));
+        RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_ASSEMBLE, 0, 0, bf16, 0, plan.l1max, s, 0, plan.tile_rows, plan.skbf));
     }
     return RTG_OK;
 }
@@ -547,7 +550,10 @@ int run_gk(const Plan& plan, int count, int mmax, int bf16, bool any_x0, bool so
 
 int validate_params(const rtg_params* prm) {
     if (!prm) return RTG_E_ARG;
-    if (prm->basis_dtype != RTG_F32 && prm->basis_dtype != RTG_BF16) return RTG_E_ARG;
+    if (prm->basis_dtype != RTG_F32 && prm->basis_dtype != RTG_BF16 && prm->basis_dtype != RTG_F32_BF16)
+        return RTG_E_ARG;
+    // the mixed form (float32 basis, bfloat16 sketch products) is RTG-GMRES only
+    if (prm->basis_dtype == RTG_F32_BF16 && prm->method != RTG_METHOD_GMRES) return RTG_E_ARG;
     if (prm->mu_rule != RTG_MU_DISCREPANCY && prm->mu_rule != RTG_MU_GCV) return RTG_E_ARG;
     if (prm->method != RTG_METHOD_GMRES && prm->method != RTG_METHOD_GOLUB_KAHAN) return RTG_E_ARG;
     // restarts: a tolerance eps (stop_res) is what ends them; RTG-GMRES only
@@ -937,7 +943,7 @@ int rtg_arnoldi(rtg_op op, rtg_sk sk, const float* R0, int m, int basis_dtype, d
     if (rc) return rc;
     if ((rc = check_m(sk, m))) return rc;
     if (!R0 || !ws || !H || !beta || !m_done) return RTG_E_ARG;
-    if (basis_dtype != RTG_F32 && basis_dtype != RTG_BF16) return RTG_E_ARG;
+    if (basis_dtype != RTG_F32 && basis_dtype != RTG_BF16 && basis_dtype != RTG_F32_BF16) return RTG_E_ARG;
     if (!aligned16(R0) || !aligned16(ws) || !(bd_tol >= 0.0)) return RTG_E_ARG;
     const int bf16 = basis_dtype == RTG_BF16;
     if (ws_bytes < rtg_workspace_bytes(op, sk, m, basis_dtype)) return RTG_E_WORKSPACE;
@@ -949,6 +955,7 @@ int rtg_arnoldi(rtg_op op, rtg_sk sk, const float* R0, int m, int basis_dtype, d
     descs[0].bd_tol = bd_tol;
     descs[0].m = m;
     descs[0].keep_last = 1;
+    descs[0].skbf = basis_dtype != RTG_F32;
     Plan plan;
     if ((rc = build_plan(descs, ws, s, plan))) return rc;
     // the last step also forms V_{m+1} (used by the Arnoldi relation):
@@ -1025,13 +1032,13 @@ namespace {
 // rtg_solve_batched.
 struct Batch {
     std::vector<Desc> descs;
-    int nsides = 1, rmax = 0, mmax = 0, bf16 = 0;
+    int nsides = 1, rmax = 0, mmax = 0, bf16 = 0, skbf = 0;
     bool gk = false, any_x0 = false;
 };
 
 int prepare_batch(int count, const rtg_problem* probs, void* ws, size_t ws_bytes, Batch& bt) {
     if (count < 1 || !probs || !ws || !aligned16(ws)) return RTG_E_ARG;
-    int bf16 = -1;
+    int basis = -1;
     const int method = probs[0].params.method;
     const bool gk = method == RTG_METHOD_GOLUB_KAHAN;
     for (int p = 0; p < count; ++p) {
@@ -1044,15 +1051,16 @@ int prepare_batch(int count, const rtg_problem* probs, void* ws, size_t ws_bytes
         if (gk && (q.sk->identity || !q.op->adj)) return RTG_E_ARG;
         if (!q.C || !q.X || !q.info) return RTG_E_ARG;
         if (!aligned16(q.C) || !aligned16(q.X) || (q.X0 && !aligned16(q.X0))) return RTG_E_ARG;
-        const int b = q.params.basis_dtype == RTG_BF16;
-        if (bf16 >= 0 && b != bf16) return RTG_E_ARG;     // one basis type per batch
-        bf16 = b;
+        if (basis >= 0 && q.params.basis_dtype != basis) return RTG_E_ARG;     // one basis type per batch
+        basis = q.params.basis_dtype;
     }
+    const int bf16 = basis == RTG_BF16;
     const size_t need = rtg_batch_workspace_bytes(count, probs);
     if (need == 0) return RTG_E_SHAPE;
     if (ws_bytes < need) return RTG_E_WORKSPACE;
     bt.gk = gk;
     bt.bf16 = bf16;
+    bt.skbf = basis != RTG_F32;
     bt.nsides = gk ? 2 : 1;
     bt.rmax = 0;
     for (int p = 0; p < count; ++p) bt.rmax = std::max(bt.rmax, probs[p].params.restarts);
@@ -1066,6 +1074,7 @@ int prepare_batch(int count, const rtg_problem* probs, void* ws, size_t ws_bytes
         char* base = (char*)ws + off;
         Desc& d = bt.descs[p];
         fill_desc(d, q.op, q.sk, q.params.m, bf16, base, L);
+        d.skbf = bt.skbf;
         set_params(d, &q.params);
         d.C = q.C;
         d.X0 = q.X0;

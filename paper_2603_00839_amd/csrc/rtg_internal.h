@@ -46,6 +46,8 @@ struct Desc {
     int r1, r2, rB;
     int m;              // max steps for this problem
     int bf16;           // basis stored as bfloat16
+    int skbf;           // sketch contractions on bfloat16 MFMA operands (a bfloat16 basis, or the
+                        // float32 basis of the mixed form RTG_F32_BF16)
     int has_om3;        // Om3 given (else identity, l3 == J)
     int n_i2t;          // ceil(I2 / TILE_TC)
     int ntile[NKIND];   // tiles of this problem per kernel kind
@@ -275,7 +277,7 @@ hipError_t launch_phi_single(int I1, int I2, int J, int r1, int r2, int rB, cons
                              const void* src, int bf16_in, const float* C, float* dst, hipStream_t s);
 hipError_t launch_tile(const Desc* d, const int* starts, int count, int total_tiles,
                        int mode, int nterms, int dst_index, int basis_bf16, int src_bf16,
-                       int l1max, hipStream_t s, int first_term = 0, int rows = 2);
+                       int l1max, hipStream_t s, int first_term = 0, int rows = 2, int sketch_bf16 = 0);
 // rows (tile and step kernels): 16-row sketch tiles per wave, 2 where the
 // stacked sketch rows fit (the default), or 4
 hipError_t launch_step(const Desc* d, const int* starts, int count, int total_tiles, int j, int rmax,

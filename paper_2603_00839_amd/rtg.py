@@ -24,6 +24,7 @@ LIB_PATH = os.path.join(HERE, "librtg.so")
 HEADER = os.path.join(HERE, "..", "include", "rtg.h")
 
 F32, BF16 = 0, 1
+F32_BF16 = 2      # basis type: float32 storage, bfloat16 sketch products
 FLAG_BREAKDOWN, FLAG_DISCREP_UNREACHABLE, FLAG_MU_INF, FLAG_NONFINITE, FLAG_NOT_CONVERGED = 1, 2, 4, 8, 16
 FLAG_FALLBACK = 32
 
