@@ -229,6 +229,18 @@ def tile_bytes(n, es, m_eff, has_x0):
     return b
 
 
+def arnoldi_bytes(n, es, m_eff):
+    """Algorithmic HBM bytes of the persistent launch of one float32-basis
+    solve (the Arnoldi process without the assembly): the sketch of R0 and
+    V1 = R0/beta (read R0 twice, write V1), then steps j = 1 .. m_eff - 1
+    (read V_1..V_j, write V_{j+1}).  The operator's W is not counted: the
+    method does not need it in memory."""
+    b = 2 * 4 * n + es * n
+    for j in range(1, m_eff):
+        b += (j + 1) * es * n
+    return b
+
+
 def phi_bytes(n, es, m_eff):
     """Algorithmic bytes of the operator launches of one solve whose W is
     formed in memory: step j reads V_j and writes W = Phi(V_j)."""
@@ -493,15 +505,24 @@ def main():
             ns = [q["n"] for q in probs_u]
             it = {"i": 0}
 
+            tune = tune_plan(plan, args)
+            persist = tune.get("persist") == 1
+
             def bytes_u(inf, it=it):
-                b = tile_bytes(ns[it["i"] % Bu], 4, inf.iters, False)
+                n_i = ns[it["i"] % Bu]
+                b = arnoldi_bytes(n_i, 4, inf.iters) if persist else tile_bytes(n_i, 4, inf.iters, False)
                 it["i"] += 1
                 return b
-            tune = tune_plan(plan, args)
-            r = time_variant(plan, args.steps, args.warmup, rtg, torch, rtg.KIND_TILE, bytes_u)
-            r["kernel"] = ("k_tile", "k_tile.hip", "multi-AXPY + store + MFMA sketch, float32 basis, "
-                                                   + ("float32" if v == "fp32_uneven" else "bfloat16")
-                                                   + " products, 256 uneven problems")
+            prod = "float32" if v == "fp32_uneven" else "bfloat16"
+            if persist:
+                r = time_variant(plan, args.steps, args.warmup, rtg, torch, rtg.KIND_PERSIST, bytes_u)
+                r["kernel"] = ("k_persist", "k_persist.hip", "the Arnoldi process of all 256 uneven problems in "
+                               "one persistent launch (operator, multi-AXPY + MFMA sketch, sketched Gram), "
+                               "float32 basis, " + prod + " products")
+            else:
+                r = time_variant(plan, args.steps, args.warmup, rtg, torch, rtg.KIND_TILE, bytes_u)
+                r["kernel"] = ("k_tile", "k_tile.hip", "multi-AXPY + store + MFMA sketch, float32 basis, "
+                                                       + prod + " products, 256 uneven problems")
             res = [rel_err(plan.outs[b], probs_u[b]["xt"]) for b in range(Bu)]
             r["solves_per_step"] = Bu
         elif v == "fp32_psf":

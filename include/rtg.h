@@ -80,8 +80,11 @@ enum {
     RTG_F_MU_INF = 4,              /* eta*delta >= beta: y = 0, X = X0                  */
     RTG_F_NONFINITE = 8,           /* NaN/Inf met in a coefficient                     */
     RTG_F_NOT_CONVERGED = 16,      /* stop_res requested and not reached within m      */
-    RTG_F_FALLBACK = 32            /* rtg_solve_batched_fallback: the result is the
+    RTG_F_FALLBACK = 32,           /* rtg_solve_batched_fallback: the result is the
                                       plain solver's re-solve of this problem          */
+    RTG_F_TIMEOUT = 64             /* the persistent batched launch was abandoned (a
+                                      wait between its workgroups exceeded the limit
+                                      of rtg_set_wait_limit): no steps, X = X0         */
 };
 
 /* Solver parameters. */
@@ -308,7 +311,15 @@ int rtg_solve_batched_fallback(int count, const rtg_problem* probs, int fb_m,
  *   step_toeplitz fused step: 1 Toeplitz taps (all bands Toeplitz), 0 band rows
  *   gram_pairs    sketched inner products: (a, b) sketch pairs per workgroup,
  *                 256, 512 or 1024 (capped at 4096 / l3 finished values; never
- *                 below the library's own choice for the problem) */
+ *                 below the library's own choice for the problem)
+ *   persist       1: the Arnoldi process of the whole batch (the start and
+ *                 every step of every problem) as one persistent launch whose
+ *                 workgroups take the stages' tiles in order from a device-side
+ *                 counter, each stage of a problem waiting only for that
+ *                 problem's earlier stages (RTG-GMRES with a sketch, a
+ *                 separable operator, a float32 basis in either product form,
+ *                 J <= 4 and inputs under 2^31 bytes); 0: one launch per stage
+ *                 over all problems */
 typedef struct {
     int phi_jt;
     int phi_slab;
@@ -317,7 +328,7 @@ typedef struct {
     int step_rows;
     int step_toeplitz;
     int gram_pairs;
-    int reserved;     /* zero */
+    int persist;
 } rtg_tune;           /* 32 bytes */
 
 /* Time the batch's solve (the Arnoldi or Golub-Kahan loop; no projected
@@ -336,12 +347,23 @@ int rtg_autotune_batched(int count, const rtg_problem* probs, void* ws,
 /* Record a choice for the batch's key (RTG_E_ARG for a field outside the
  * values above or one the batch cannot use: phi_slab 1 or 2 for inputs of
  * 2^31 bytes or more, phi_slab 2 for a separable operator or J > 3,
- * toeplitz fields for non-Toeplitz bands or a general PSF, nonzero reserved). */
+ * toeplitz fields for non-Toeplitz bands or a general PSF, persist 1 for a
+ * batch that cannot take it or with phi_jt 8 or phi_slab 0). */
 int rtg_tune_set(int count, const rtg_problem* probs, const rtg_tune* tune);
 /* The choice a solve of this batch would use, every field resolved. */
 int rtg_tune_get(int count, const rtg_problem* probs, rtg_tune* tune);
 /* Forget every recorded choice. */
 int rtg_tune_clear(void);
+
+/* Bound on every wait between workgroups of the persistent launch
+ * (rtg_tune.persist = 1): a workgroup that finds a dependency unmet after
+ * this many polls (about a microsecond each) abandons the launch; every
+ * workgroup then stops taking work, and every problem of the batch ends
+ * with RTG_F_TIMEOUT in its info flags, no steps and X = X0 (zero when X0
+ * is NULL).  Process-wide, read at each launch; polls >= 0 (RTG_E_ARG
+ * otherwise), default 4194304.  A limit that low waits never pass is what
+ * tests of the failure path use. */
+int rtg_set_wait_limit(int polls);
 
 /* ---- learned warm start ----------------------------------------------------
  * X0 = C + f(C), f = six 3x3 zero-padded convolutions 3 -> 32 -> 32 -> 32 ->
@@ -378,7 +400,8 @@ int rtg_cnn_adam(void* state, float lr, int step, void* stream);
  * When enabled, every launch of the selected kernel kinds made by the solver
  * calls (bit k of kind_mask: 0 operator Phi, 1 multi-AXPY + sketch tile,
  * 2 sketched Gram / Hessenberg update, 3 projected Tikhonov solve, 4 Arnoldi
- * step with the operator applied on the fly) is
+ * step with the operator applied on the fly, 5 the persistent launch of the
+ * Arnoldi process) is
  * bracketed by two hipEvents recorded on the launch stream.
  * rtg_event_timing_read waits for those events and returns, per kind, the
  * summed duration in milliseconds and the number of launches, then clears

@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librtg.so")
 OBJ_DIR = os.path.join(HERE, "..", "_build")
-SOURCES = ["rtg_api.hip", "k_operator.hip", "k_tile.hip", "k_step.hip", "k_gram.hip", "k_solve.hip", "k_cnn.hip"]
+SOURCES = ["rtg_api.hip", "k_operator.hip", "k_tile.hip", "k_step.hip", "k_gram.hip", "k_solve.hip", "k_cnn.hip",
+           "k_persist.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -318,9 +318,10 @@ __global__ void __launch_bounds__(1024) k_solve(const Desc* __restrict__ descs) 
 // cycle (its residual was below eps), sits this one out too; the others
 // keep their step count and flags (but for NOT_CONVERGED, which the cycle
 // decides anew).
-__global__ void k_init(const Desc* __restrict__ descs, int cycle) {
+__global__ void k_init(const Desc* __restrict__ descs, int cycle, int* sched) {
     const Desc& d = descs[blockIdx.x];
     const int tid = threadIdx.x;
+    if (sched && blockIdx.x == 0 && tid < SCH_WORDS) sched[tid] = 0;
     if (cycle > 0) {
         const bool sit_out = cycle > d.restarts || d.state[ST_SKIP] != 0;
         __syncthreads();                      // every thread has read the state
@@ -329,6 +330,7 @@ __global__ void k_init(const Desc* __restrict__ descs, int cycle) {
                 d.state[ST_SKIP] = 1;
                 d.state[ST_ACTIVE] = 0;
             }
+            if (tid < NKIND) d.state[ST_DONE + tid] = 0;
             return;
         }
         if (tid < NSTATE) {
@@ -436,8 +438,8 @@ hipError_t launch_solve(const Desc* d, int count, int mmax, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_init(const Desc* d, int count, hipStream_t s, int cycle) {
-    hipLaunchKernelGGL(k_init, dim3(count), dim3(256), 0, s, d, cycle);
+hipError_t launch_init(const Desc* d, int count, hipStream_t s, int cycle, int* sched) {
+    hipLaunchKernelGGL(k_init, dim3(count), dim3(256), 0, s, d, cycle, sched);
     return hipGetLastError();
 }
 

@@ -21,6 +21,7 @@
 #include "rtg_internal.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -165,7 +166,7 @@ size_t problem_bytes(const rtg_op_s* op, const rtg_sk_s* sk, int m, int bf16, in
 // per-kernel tile prefix tables
 size_t plan_bytes(int count, int nsides = 1, bool restart = false) {
     return align_up((size_t)count * nsides * (restart ? 2 : 1) * sizeof(Desc)) +
-           align_up((size_t)NKIND * (count + 1) * sizeof(int));
+           align_up((size_t)NKIND * (count + 1) * sizeof(int)) + align_up(SCH_WORDS * sizeof(int));
 }
 
 int check_pair(const rtg_op_s* op, const rtg_sk_s* sk) {
@@ -269,6 +270,8 @@ struct Plan {
     int step_rows;     // the same for the fused step
     int skbf;          // sketch contractions on bfloat16 operands (every problem's descriptor says so)
     Desc* d_desc_r;    // restart cycles: the descriptors with X0 = X (null without restarts)
+    int persist;       // the Arnoldi process as one persistent launch
+    int* d_sched;      // its scheduling words (SCH_WORDS ints)
 };
 
 // descs holds nsides groups of count problems (the same shapes in each group);
@@ -338,11 +341,17 @@ int build_plan(std::vector<Desc>& descs, void* ws, hipStream_t s, Plan& plan, in
         if (tune->tile_rows == 4) plan.tile_rows = 4;
         if (tune->step_rows == 4) plan.step_rows = 4;
     }
+    // the persistent launch: sketched separable RTG-GMRES with a float32
+    // basis (either product form), 16-byte operator slabs, one tile for all
+    // channels
+    plan.persist = tune && tune->persist == 1 && nsides == 1 && !plan.unsketched && !plan.stencil &&
+                   plan.phi_jt == 4 && plan.phi_dma >= 1 && !descs.empty() && !descs[0].bf16;
     char* base = (char*)ws;
     plan.d_desc = (Desc*)base;
     plan.d_desc_r = nullptr;
     const size_t nd = descs.size();
     plan.d_starts = (int*)(base + align_up(nd * (restart ? 2 : 1) * sizeof(Desc)));
+    plan.d_sched = (int*)((char*)plan.d_starts + align_up((size_t)NKIND * (count + 1) * sizeof(int)));
     int rc = upload(plan.d_desc, descs.data(), nd * sizeof(Desc), s);
     if (rc) return rc;
     if (restart) {
@@ -367,7 +376,7 @@ const int* starts_of(const Plan& plan, int kind, int count) {
     } while (0)
 
 // ---- optional event timing of launches (measurement facility)
-constexpr int NTIMED = 5;   // 0 operator, 1 tile, 2 gram, 3 solve, 4 step
+constexpr int NTIMED = 6;   // 0 operator, 1 tile, 2 gram, 3 solve, 4 step, 5 persistent Arnoldi
 struct EventTiming {
     int mask = 0;
     std::vector<hipEvent_t> pool;
@@ -384,6 +393,9 @@ struct EventTiming {
     }
 };
 EventTiming g_timing;
+
+// polls of a cross-workgroup wait in the persistent launch before it is abandoned
+std::atomic<int> g_wait_limit{1 << 22};
 
 struct TimedLaunch {
     int kind;
@@ -420,7 +432,7 @@ int run_solver(const Plan& plan, int count, int mmax, int bf16, bool any_x0, boo
     const int* sp = starts_of(plan, KIND_PHI, count);
     const int* st = starts_of(plan, KIND_TILE, count);
     const int* sg = starts_of(plan, KIND_GRAM, count);
-    RTG_HIP(launch_init(dd, count, s, cycle));
+    RTG_HIP(launch_init(dd, count, s, cycle, plan.persist ? plan.d_sched : nullptr));
     if (plan.unsketched) {
         // Identity sketch (unsketched global GMRES, the Omega = I form of the
         // method): W = Phi(V_j) is formed first, the Gram kernel takes the
@@ -475,6 +487,34 @@ int run_solver(const Plan& plan, int count, int mmax, int bf16, bool any_x0, boo
         return RTG_OK;
     }
     if (cycle == 0) RTG_HIP(launch_compose(dd, count, plan.compose_max, s));   // restart cycles reuse them
+    if (plan.persist) {
+        // the start and every step of every problem: one launch
+        PersistArgs a{};
+        a.descs = dd;
+        a.starts[KIND_PHI] = sp;
+        a.starts[KIND_TILE] = st;
+        a.starts[KIND_GRAM] = sg;
+        a.count = count;
+        a.tp = plan.total[KIND_PHI];
+        a.tt = plan.total[KIND_TILE];
+        a.tg = plan.total[KIND_GRAM];
+        a.any_x0 = any_x0 ? 1 : 0;
+        a.cycle = cycle;
+        a.sched = plan.d_sched;
+        a.wait_limit = g_wait_limit.load();
+        const long long full = last_newv ? mmax : mmax - 1;   // steps that form V_{j+1}
+        const long long total = (any_x0 ? (long long)a.tp : 0) + 2LL * a.tt + a.tg + (long long)mmax * a.tg +
+                                full * ((long long)a.tp + a.tt);
+        if (total > 0x3FFFFFFFLL) return RTG_E_SHAPE;
+        a.total = (int)total;
+        RTG_TIMED(5, launch_persist(a, plan.rmax, plan.phi_toep, plan.skbf, s));
+        if (solve) {
+            RTG_TIMED(3, launch_solve(dd, count, mmax, s));
+            RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_ASSEMBLE, 0, 0, bf16, 0, plan.l1max, s, 0,
+                                     plan.tile_rows, plan.skbf));
+        }
+        return RTG_OK;
+    }
     if (any_x0) RTG_TIMED(0, launch_phi(dd, sp, count, plan.total[KIND_PHI], PS_X0, 0, plan.rmax, plan.phi_jt, 0, s, 0, plan.phi_dma, plan.phi_toep));
     RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_SKETCH_SRC, 0, 0, bf16, 0, plan.l1max, s, 0, plan.tile_rows, plan.skbf));
     RTG_TIMED(2, launch_gram(dd, sg, count, plan.total[KIND_GRAM], GM_START, cycle, nullptr, s));
@@ -1124,6 +1164,7 @@ struct TuneCaps {
     int maxJ = 1, slab_cap = 2;
     bool toep_ok = true, stencil = false, phi_runs = true, step_runs = false;
     bool gram_runs = false;   // some problem's Gram chunk follows gram_pairs
+    bool persist_ok = false;  // the persistent launch applies (given phi_jt 4 and 16-byte slabs)
 };
 
 TuneCaps tune_caps(int count, const rtg_problem* probs) {
@@ -1147,6 +1188,7 @@ TuneCaps tune_caps(int count, const rtg_problem* probs) {
     c.slab_cap = big ? 0 : ((c.stencil && c.maxJ <= 3) ? 2 : 1);
     const bool gk = probs[0].params.method == RTG_METHOD_GOLUB_KAHAN;
     c.step_runs = bf16 && step_ok && !c.stencil && !unsk && !gk;
+    c.persist_ok = !bf16 && !c.stencil && !unsk && !gk && c.maxJ <= 4 && c.slab_cap >= 1;
     c.phi_runs = !c.step_runs || x0;
     return c;
 }
@@ -1154,7 +1196,7 @@ TuneCaps tune_caps(int count, const rtg_problem* probs) {
 // Every -1 replaced by the default; RTG_E_ARG for a value outside the
 // documented set or one the batch cannot use.
 int resolve_tune(const TuneCaps& c, const rtg_tune& in, rtg_tune& out) {
-    if (in.reserved != 0) return RTG_E_ARG;
+    if (in.persist < -1 || in.persist > 1) return RTG_E_ARG;
     if (in.gram_pairs != -1 && in.gram_pairs != 256 && in.gram_pairs != 512 && in.gram_pairs != 1024) return RTG_E_ARG;
     auto one_of = [](int v, int a, int b) { return v == -1 || v == a || v == b; };
     if (!one_of(in.phi_jt, 4, 8) || !one_of(in.tile_rows, 2, 4) || !one_of(in.step_rows, 2, 4)) return RTG_E_ARG;
@@ -1170,13 +1212,15 @@ int resolve_tune(const TuneCaps& c, const rtg_tune& in, rtg_tune& out) {
     out.step_rows = in.step_rows >= 0 ? in.step_rows : 2;
     out.step_toeplitz = in.step_toeplitz >= 0 ? in.step_toeplitz : (c.toep_ok ? 1 : 0);
     out.gram_pairs = in.gram_pairs >= 0 ? in.gram_pairs : GRAM_CH;
+    if (in.persist == 1 && (!c.persist_ok || out.phi_jt != 4 || out.phi_slab < 1)) return RTG_E_ARG;
+    out.persist = in.persist >= 0 ? in.persist : 0;
     return RTG_OK;
 }
 
 rtg_tune tune_unset() {
     rtg_tune t;
     t.phi_jt = t.phi_slab = t.phi_toeplitz = t.tile_rows = t.step_rows = t.step_toeplitz = t.gram_pairs = -1;
-    t.reserved = 0;
+    t.persist = -1;
     return t;
 }
 
@@ -1333,6 +1377,12 @@ int rtg_tune_get(int count, const rtg_problem* probs, rtg_tune* tune) {
     return resolve_tune(tune_caps(count, probs), lookup_tune(count, probs), *tune);
 }
 
+int rtg_set_wait_limit(int polls) {
+    if (polls < 0) return RTG_E_ARG;
+    g_wait_limit.store(polls);
+    return RTG_OK;
+}
+
 int rtg_tune_clear(void) {
     TuneTable& tt = tune_table();
     std::lock_guard<std::mutex> lock(tt.mu);
@@ -1432,6 +1482,19 @@ int rtg_autotune_batched(int count, const rtg_problem* probs, void* ws, size_t w
                 c.step_toeplitz = tp;
                 cands.push_back(c);
             }
+        rc = try_group(cands);
+    }
+    // one persistent launch (with the shapes so far, and each Gram chunk:
+    // its latency now overlaps other problems' work)
+    if (!rc && caps.persist_ok && best.phi_jt == 4 && best.phi_slab >= 1) {
+        std::vector<rtg_tune> cands;
+        for (int gp : {256, 512, 1024}) {
+            if (!caps.gram_runs && gp != best.gram_pairs) continue;
+            rtg_tune c = best;
+            c.persist = 1;
+            c.gram_pairs = caps.gram_runs ? gp : best.gram_pairs;
+            cands.push_back(c);
+        }
         rc = try_group(cands);
     }
     (void)hipEventDestroy(e0);

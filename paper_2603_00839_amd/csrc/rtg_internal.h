@@ -35,7 +35,10 @@ enum KernelKind { KIND_PHI = 0, KIND_TILE = 1, KIND_GRAM = 2, NKIND = 3 };
 // state[] slots (int)
 // (ST_ITERS: steps of the finished restart cycles; ST_SKIP: this problem sits
 // out the current restart cycle, X and its info stay as they are)
-enum { ST_ACTIVE = 0, ST_MEFF = 1, ST_FLAGS = 2, ST_COUNTER = 3, ST_ITERS = 4, ST_SKIP = 5, NSTATE = 16 };
+// (ST_DONE + kind: tasks of that kind finished for this problem in the
+// persistent launch, one slot per KernelKind)
+enum { ST_ACTIVE = 0, ST_MEFF = 1, ST_FLAGS = 2, ST_COUNTER = 3, ST_ITERS = 4, ST_SKIP = 5, ST_DONE = 6, NSTATE = 16 };
+static_assert(ST_DONE + NKIND <= NSTATE, "state slots");
 // scal[] slots (double)
 enum { SC_BETA = 0, SC_MU = 1, SC_RESPROJ = 2, SC_RESLS = 3, SC_RHO = 4, NSCAL = 16 };
 
@@ -118,6 +121,18 @@ struct Desc {
 // ---------------------------------------------------------------------------
 // small device helpers
 // ---------------------------------------------------------------------------
+// The workitem's index in its workgroup, read through an opaque register
+// copy.  A stage body inlined into the loop of the persistent launch would
+// otherwise have its per-lane index arithmetic hoisted out of the loop and
+// kept in registers through every other stage (the stand-alone kernels
+// compile to the same registers either way).
+__device__ __forceinline__ int block_tid() {
+    int t;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(t) : "v"((int)threadIdx.x));
+    __builtin_assume(t >= 0 && t < 1024);
+    return t;
+}
+
 __device__ __forceinline__ int find_problem(const int* __restrict__ starts, int count, int b) {
     // largest p with starts[p] <= b (starts has count+1 entries, starts[0] = 0)
     int lo = 0, hi = count - 1;
@@ -285,10 +300,27 @@ hipError_t launch_step(const Desc* d, const int* starts, int count, int total_ti
 hipError_t launch_gram(const Desc* d, const int* starts, int count, int total_tiles,
                        int mode, int j, float* sketch_out, hipStream_t s, int unsketched = 0);
 hipError_t launch_solve(const Desc* d, int count, int mmax, hipStream_t s);
-hipError_t launch_init(const Desc* d, int count, hipStream_t s, int cycle = 0);
+// sched (may be null): the persistent launch's words, zeroed by block 0
+hipError_t launch_init(const Desc* d, int count, hipStream_t s, int cycle = 0, int* sched = nullptr);
 hipError_t launch_compose(const Desc* d, int count, int max_entries, hipStream_t s);
 hipError_t launch_finish_arnoldi(const Desc* d, double* H, double* beta, int* m_done,
                                  int m, hipStream_t s);
+
+// The persistent launch of a batch's Arnoldi process: its scheduling words
+// (next task, error, workgroups that have left) and arguments.
+enum { SCH_NEXT = 0, SCH_ERROR = 1, SCH_EXITED = 2, SCH_WORDS = 4 };
+struct PersistArgs {
+    const Desc* descs;
+    const int* starts[NKIND];   // prefix tables of the problems' tiles per kernel kind
+    int count;
+    int tp, tt, tg;             // tiles of one operator, tile and Gram stage over the batch
+    int total;                  // tasks
+    int any_x0;                 // the operator on X0 comes first
+    int cycle;                  // restart cycle (the start stage's argument)
+    int* sched;                 // SCH_WORDS ints, zeroed before the launch
+    int wait_limit;             // polls before a wait gives up
+};
+hipError_t launch_persist(const PersistArgs& a, int rmax, int toeplitz, int sketch_bf16, hipStream_t s);
 
 // k_tile modes
 // (TM_GKNEW: a new Golub-Kahan basis tensor from W and the terms

@@ -27,6 +27,7 @@ F32, BF16 = 0, 1
 F32_BF16 = 2      # basis type: float32 storage, bfloat16 sketch products
 FLAG_BREAKDOWN, FLAG_DISCREP_UNREACHABLE, FLAG_MU_INF, FLAG_NONFINITE, FLAG_NOT_CONVERGED = 1, 2, 4, 8, 16
 FLAG_FALLBACK = 32
+FLAG_TIMEOUT = 64
 
 
 class RTGError(RuntimeError):
@@ -55,9 +56,10 @@ class Tune(ctypes.Structure):
     """Launch shapes of a batch (rtg_tune); -1 = the library default."""
     _fields_ = [("phi_jt", ctypes.c_int), ("phi_slab", ctypes.c_int), ("phi_toeplitz", ctypes.c_int),
                 ("tile_rows", ctypes.c_int), ("step_rows", ctypes.c_int), ("step_toeplitz", ctypes.c_int),
-                ("gram_pairs", ctypes.c_int), ("reserved", ctypes.c_int)]
+                ("gram_pairs", ctypes.c_int), ("persist", ctypes.c_int)]
 
-    FIELDS = ("phi_jt", "phi_slab", "phi_toeplitz", "tile_rows", "step_rows", "step_toeplitz", "gram_pairs")
+    FIELDS = ("phi_jt", "phi_slab", "phi_toeplitz", "tile_rows", "step_rows", "step_toeplitz", "gram_pairs",
+              "persist")
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f in self.FIELDS}
@@ -114,6 +116,7 @@ def load_library():
         "rtg_tune_set": (c_int, [c_int, ctypes.POINTER(Problem), ctypes.POINTER(Tune)]),
         "rtg_tune_get": (c_int, [c_int, ctypes.POINTER(Problem), ctypes.POINTER(Tune)]),
         "rtg_tune_clear": (c_int, []),
+        "rtg_set_wait_limit": (c_int, [c_int]),
         "rtg_cnn_state_bytes": (c_sz, []),
         "rtg_cnn_workspace_bytes": (c_sz, [c_int, c_int, c_int]),
         "rtg_cnn_init": (c_int, [c_vp, fp, c_vp]),
@@ -544,6 +547,12 @@ def tune_clear():
     _check(lib().rtg_tune_clear(), "rtg_tune_clear")
 
 
+def set_wait_limit(polls: int):
+    """Bound on the waits between workgroups of the persistent launch
+    (rtg_set_wait_limit)."""
+    _check(lib().rtg_set_wait_limit(int(polls)), "rtg_set_wait_limit")
+
+
 def solve_batched(ops, sks, Cs, X0s, params, outs=None) -> BatchPlan:
     plan = BatchPlan(ops, sks, Cs, X0s, params, outs)
     plan.run()
@@ -553,8 +562,8 @@ def solve_batched(ops, sks, Cs, X0s, params, outs=None) -> BatchPlan:
 # ---------------------------------------------------------------------------
 # measurement
 # ---------------------------------------------------------------------------
-KIND_PHI, KIND_TILE, KIND_GRAM, KIND_SOLVE, KIND_STEP = 0, 1, 2, 3, 4
-N_KINDS = 5
+KIND_PHI, KIND_TILE, KIND_GRAM, KIND_SOLVE, KIND_STEP, KIND_PERSIST = 0, 1, 2, 3, 4, 5
+N_KINDS = 6
 
 
 def event_timing_enable(kind_mask: int):

@@ -82,10 +82,10 @@ def test_tune_struct_layout_matches_header():
     assert ctypes.sizeof(rtg.Tune) == 32
     for i, f in enumerate(rtg.Tune.FIELDS):
         assert getattr(rtg.Tune, f).offset == 4 * i
-    assert rtg.Tune.reserved.offset == 28
+    assert rtg.Tune.persist.offset == 28
     t = rtg.make_tune(tile_rows=4)
     assert t.as_dict() == dict(phi_jt=-1, phi_slab=-1, phi_toeplitz=-1, tile_rows=4, step_rows=-1, step_toeplitz=-1,
-                               gram_pairs=-1)
+                               gram_pairs=-1, persist=-1)
     with pytest.raises(rtg.RTGError):
         rtg.make_tune(rows=2)
 
@@ -102,3 +102,14 @@ def test_tune_calls_check_arguments_on_the_host(lib):
     assert lib.rtg_tune_set(1, arr, ctypes.byref(t)) == -1
     assert lib.rtg_tune_get(1, arr, None) == -1
     assert lib.rtg_autotune_batched(1, arr, None, 0, 0, ctypes.byref(t), None, None) == -1
+
+
+def test_wait_limit_and_timeout_flag(lib):
+    """rtg_set_wait_limit takes any count >= 0 (host state only); the flag
+    that an abandoned persistent launch leaves is the header's value."""
+    assert lib.rtg_set_wait_limit(-1) == -1
+    assert lib.rtg_set_wait_limit(0) == 0
+    assert lib.rtg_set_wait_limit(1 << 22) == 0
+    with open(os.path.join(ROOT, "include", "rtg.h")) as f:
+        hdr = f.read()
+    assert "RTG_F_TIMEOUT = 64" in hdr and rtg.FLAG_TIMEOUT == 64

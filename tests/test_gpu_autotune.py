@@ -170,7 +170,7 @@ def test_tune_set_refuses_impossible_choices():
         with pytest.raises(rtg.RTGError):
             plan.set_tune(rtg.make_tune(**c))
     t = rtg.make_tune()
-    t.reserved = 1
+    t.persist = 2
     with pytest.raises(rtg.RTGError):
         plan.set_tune(t)
     # random (non-Toeplitz) bands: no Toeplitz forms
