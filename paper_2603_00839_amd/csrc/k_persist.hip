@@ -5,10 +5,14 @@
 // beta = ||S(R0)|| (Gram), V_1 (tile), then per step j the sketched inner
 // products with the Hessenberg update (Gram), W = Phi(V_j) (operator) and
 // V_{j+1} with its two sketches (tile) -- become tasks of one grid of
-// resident workgroups.  Tasks are numbered stage after stage exactly as the
-// launches would run them (every problem's tiles of a stage, problem after
-// problem), and a workgroup claims the next number from a global counter.
-// Each stage of a problem waits only for that problem's own earlier stages:
+// resident workgroups.  The problems are cut into eight contiguous groups
+// of about equal size (tensor elements), one per XCD (workgroups reach the
+// XCDs round-robin, and each XCD has its own L2: neighbouring operator
+// tiles share halos, one problem's tiles share its sketch matrices); the
+// queue of XCD x holds the tiles of its problems of every stage, stage after
+// stage in launch order, and the workgroups of that XCD claim its tasks in
+// order from the queue's counter.  Each stage of a
+// problem waits only for that problem's own earlier stages:
 //
 //   sketch of R0   after the operator on X0 (R0 = C - Phi(X0), when given)
 //   beta           after the sketch of R0
@@ -25,15 +29,19 @@
 // stage's last workgroup counts itself only after the step's small float64
 // part, so a finished Gram count means the step's coefficients are stored.
 //
-// No deadlock: numbers are claimed in increasing order and every dependency
-// has a smaller number, so the smallest unfinished claimed task always has
-// its dependencies finished and belongs to a running workgroup.  Each
-// workgroup claims its next task while running the current one.
+// No deadlock: take the unfinished task that comes first in stage order.
+// Its dependencies (earlier stages) are finished.  Every task before it in
+// its queue comes earlier in stage order, so is finished too: either a
+// workgroup holds it, or the queue's next claim returns it, and every queue
+// has workgroups (the grid is a multiple of eight).  A workgroup claims its
+// next task while running the current one; the one it holds ahead comes
+// after its current task, so the argument stands.
 //
 // Memory ordering across workgroups (and across the chip's XCDs, whose L2
-// caches are separate): every wave releases its stores at agent scope before
-// the workgroup counts the task in; a waiting workgroup acquires at agent
-// scope after the count is met.  Every wait is bounded: after wait_limit
+// caches are separate): every wave waits until its stores are complete, and
+// after the workgroup's barrier one release at agent scope (a write-back of
+// the XCD's L2) precedes the counts it publishes; a waiting workgroup
+// acquires at agent scope after the count is met.  Every wait is bounded: after wait_limit
 // polls the workgroup raises the batch's error word, every workgroup stops
 // claiming, and the last one to leave marks every problem with
 // RTG_F_TIMEOUT, no steps and no further work (the solve that follows
@@ -65,54 +73,67 @@ struct Task {
     int dep_n[NKIND];   // finished stages of each kind it waits for (0: none)
 };
 
-// Task t of the batch (t < total).  Stages: [operator on X0], sketch of R0,
-// beta, V_1, then per step j = 1..mmax the Gram step and, unless it is the
-// last step without V_{m+1}, the operator and the new basis tensor.
-__device__ __forceinline__ Task decode(const PersistArgs& a, int t) {
+// The tiles of a stage of kind k that queue x takes: those of its problems,
+// [qfirst[k][x], qfirst[k][x + 1]).
+__device__ __forceinline__ int q_first(const PersistArgs& a, int k, int x) { return a.qfirst[k][x]; }
+__device__ __forceinline__ int q_len(const PersistArgs& a, int k, int x) { return a.qfirst[k][x + 1] - a.qfirst[k][x]; }
+
+// Tasks of queue x in their order: [operator on X0], sketch of R0, beta, V_1,
+// then per step j = 1..steps the Gram step and, for the first `full` steps,
+// the operator and the new basis tensor.
+__device__ __forceinline__ int queue_tasks(const PersistArgs& a, int x) {
+    const int tp = q_len(a, KIND_PHI, x), tt = q_len(a, KIND_TILE, x), tg = q_len(a, KIND_GRAM, x);
+    return (a.any_x0 ? tp : 0) + 2 * tt + tg + a.steps * tg + a.full * (tp + tt);
+}
+
+// Task u of queue x (u < queue_tasks(a, x)).
+__device__ __forceinline__ Task decode(const PersistArgs& a, int x, int u) {
     Task k;
     k.dep_n[KIND_PHI] = k.dep_n[KIND_TILE] = k.dep_n[KIND_GRAM] = 0;
+    const int tp = q_len(a, KIND_PHI, x), tt = q_len(a, KIND_TILE, x), tg = q_len(a, KIND_GRAM, x);
+    const int fp = q_first(a, KIND_PHI, x), ft = q_first(a, KIND_TILE, x), fg = q_first(a, KIND_GRAM, x);
     const int x0 = a.any_x0 ? 1 : 0;
     if (x0) {
-        if (t < a.tp) {
-            k.kind = KIND_PHI; k.mode = PS_X0; k.arg = 0; k.b = t;
+        if (u < tp) {
+            k.kind = KIND_PHI; k.mode = PS_X0; k.arg = 0; k.b = fp + u;
             return k;
         }
-        t -= a.tp;
+        u -= tp;
     }
-    if (t < a.tt) {
-        k.kind = KIND_TILE; k.mode = TM_SKETCH_SRC; k.arg = 0; k.b = t;
+    if (u < tt) {
+        k.kind = KIND_TILE; k.mode = TM_SKETCH_SRC; k.arg = 0; k.b = ft + u;
         k.dep_n[KIND_PHI] = x0;
         return k;
     }
-    t -= a.tt;
-    if (t < a.tg) {
-        k.kind = KIND_GRAM; k.mode = GM_START; k.arg = a.cycle; k.b = t;
+    u -= tt;
+    if (u < tg) {
+        k.kind = KIND_GRAM; k.mode = GM_START; k.arg = a.cycle; k.b = fg + u;
         k.dep_n[KIND_TILE] = 1;
         return k;
     }
-    t -= a.tg;
-    if (t < a.tt) {
-        k.kind = KIND_TILE; k.mode = TM_NEWV; k.arg = 0; k.b = t;
+    u -= tg;
+    if (u < tt) {
+        k.kind = KIND_TILE; k.mode = TM_NEWV; k.arg = 0; k.b = ft + u;
         k.dep_n[KIND_GRAM] = 1;
         return k;
     }
-    t -= a.tt;
-    const int per = a.tg + a.tp + a.tt;
-    const int j = 1 + t / per;
-    t -= (j - 1) * per;
-    if (t < a.tg) {
-        k.kind = KIND_GRAM; k.mode = GM_STEP; k.arg = j; k.b = t;
+    u -= tt;
+    const int per = tg + tp + tt;
+    const int j = 1 + u / per;
+    u -= (j - 1) * per;
+    if (u < tg) {
+        k.kind = KIND_GRAM; k.mode = GM_STEP; k.arg = j; k.b = fg + u;
         k.dep_n[KIND_TILE] = j + 1;
         return k;
     }
-    t -= a.tg;
-    if (t < a.tp) {
-        k.kind = KIND_PHI; k.mode = PS_BASIS; k.arg = j - 1; k.b = t;
+    u -= tg;
+    if (u < tp) {
+        k.kind = KIND_PHI; k.mode = PS_BASIS; k.arg = j - 1; k.b = fp + u;
         k.dep_n[KIND_TILE] = j + 1;
         return k;
     }
-    t -= a.tp;
-    k.kind = KIND_TILE; k.mode = TM_NEWV; k.arg = j; k.b = t;
+    u -= tp;
+    k.kind = KIND_TILE; k.mode = TM_NEWV; k.arg = j; k.b = ft + u;
     k.dep_n[KIND_GRAM] = j + 1;
     k.dep_n[KIND_PHI] = x0 + j;
     return k;
@@ -139,32 +160,70 @@ __device__ __forceinline__ bool wait_count(const int* counter, int target, int* 
 
 // two workgroups per CU (the Gram stage's LDS allows no more; the tile
 // stage's registers need as many as two waves per SIMD leave)
+// Completed tasks whose count is not yet published: each workgroup holds
+// up to PEND of them (per counter, how many tasks it gets) and publishes
+// them together after one release -- when it holds PEND, before any wait
+// that is not already met, and before it leaves.  A workgroup never waits
+// while holding unpublished tasks, so the order argument above still holds;
+// one L2 write-back then covers several tasks.
+constexpr int PEND = 4;
+
+struct Pending {
+    int* ctr[PEND];
+    int n[PEND];
+    int used;   // distinct counters
+    int held;   // tasks
+};
+
+// one thread: publish every pending count after one release at agent scope
+__device__ __forceinline__ void publish(Pending& pd) {
+    if (pd.used == 0) return;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    for (int i = 0; i < pd.used; ++i)
+        __hip_atomic_fetch_add(pd.ctr[i], pd.n[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    pd.used = 0;
+    pd.held = 0;
+}
+
 template <int R, bool TP, bool MB>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) k_persist(PersistArgs a) {
     using LY = PersistLds<R, TP, MB>;
     __shared__ __attribute__((aligned(16))) unsigned char lds[LY::BYTES];
     __shared__ int s_task;
+    __shared__ Pending s_pend;   // thread 0's list
     const int tid = threadIdx.x;
     int* sched = a.sched;
+    // queue of this workgroup: its XCD (workgroups are dispatched to the
+    // eight XCDs round-robin), so that a stage's neighbouring tiles -- shared
+    // operator halos, one problem's sketch matrices -- meet in one L2
+    const int x = blockIdx.x & 7;
+    int* next = sched + SCH_QUEUE + SCH_QSTRIDE * x;
+    const int ntask = queue_tasks(a, x);
     int claimed = 0;   // thread 0: the task claimed ahead
-    if (tid == 0) claimed = __hip_atomic_fetch_add(sched + SCH_NEXT, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid == 0) {
+        s_pend.used = 0;
+        s_pend.held = 0;
+        claimed = __hip_atomic_fetch_add(next, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     for (;;) {
         if (tid == 0) {
             int t = claimed;
-            if (t < a.total) claimed = __hip_atomic_fetch_add(sched + SCH_NEXT, 1, __ATOMIC_RELAXED,
-                                                              __HIP_MEMORY_SCOPE_AGENT);
-            if (t >= a.total || ld_agent(sched + SCH_ERROR) != 0) {
+            if (t < ntask) claimed = __hip_atomic_fetch_add(next, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (t >= ntask || ld_agent(sched + SCH_ERROR) != 0) {
                 t = -1;
             } else {
-                const Task k = decode(a, t);
+                const Task k = decode(a, x, t);
                 const int* starts = a.starts[k.kind];
                 const int p = find_problem(starts, a.count, k.b);
                 const Desc& d = a.descs[p];
 #pragma unroll
-                for (int q = 0; q < NKIND; ++q)
-                    if (t >= 0 && k.dep_n[q] > 0 &&
-                        !wait_count(d.state + ST_DONE + q, k.dep_n[q] * d.ntile[q], sched + SCH_ERROR, a.wait_limit))
-                        t = -1;
+                for (int q = 0; q < NKIND; ++q) {
+                    const int* ctr = d.state + ST_DONE + q;
+                    const int target = k.dep_n[q] * d.ntile[q];
+                    if (t < 0 || k.dep_n[q] == 0 || ld_agent(ctr) >= target) continue;
+                    publish(s_pend);   // nothing held while waiting
+                    if (!wait_count(ctr, target, sched + SCH_ERROR, a.wait_limit)) t = -1;
+                }
             }
             s_task = t;
         }
@@ -173,7 +232,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
         if (t < 0) break;
         // the producers' stores (released before they counted in) are seen
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        const Task k = decode(a, t);
+        const Task k = decode(a, x, t);
         const int* starts = a.starts[k.kind];
         if (k.kind == KIND_PHI) {
             phi_batched_task<R, false, 4, false, SL_VEC, TP>(a.descs, starts, a.count, k.mode, k.arg, k.b,
@@ -190,17 +249,29 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
         } else {
             gram_task<false>(a.descs, starts, a.count, k.mode, k.arg, nullptr, k.b, *(GramSmem*)lds);
         }
-        // every wave's stores reach memory before the task is counted in
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        // every wave's stores are complete (in this XCD's L2) before the
+        // barrier; then one write-back of the L2 (wave 0's release at agent
+        // scope) makes all of them visible to the other XCDs before the task
+        // is counted in
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
         __syncthreads();
         if (tid == 0) {
-            const int p = find_problem(starts, a.count, k.b);
-            __hip_atomic_fetch_add(a.descs[p].state + ST_DONE + k.kind, 1, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+            int* ctr = a.descs[find_problem(starts, a.count, k.b)].state + ST_DONE + k.kind;
+            Pending& pd = s_pend;
+            int i = 0;
+            while (i < pd.used && pd.ctr[i] != ctr) ++i;
+            if (i == pd.used) {   // a new counter (held < PEND, so there is room)
+                pd.ctr[i] = ctr;
+                pd.n[i] = 0;
+                pd.used = i + 1;
+            }
+            pd.n[i] += 1;
+            if (++pd.held == PEND) publish(pd);
         }
     }
     // the last workgroup to leave marks every problem of an abandoned batch
     if (tid == 0) {
+        publish(s_pend);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         const int left = __hip_atomic_fetch_add(sched + SCH_EXITED, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         if (left == (int)gridDim.x - 1 && ld_agent(sched + SCH_ERROR) != 0) {
@@ -245,7 +316,8 @@ hipError_t launch_one(const PersistArgs& a, hipStream_t s) {
             gc.blocks[{dev, fn}] = resident;
         }
     }
-    const int grid = std::max(1, std::min(resident, a.total));
+    // every queue needs a workgroup: a multiple of eight, at least eight
+    const int grid = std::max(8, resident & ~7);
     hipLaunchKernelGGL((k_persist<R, TP, MB>), dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError();
 }

@@ -321,7 +321,8 @@ __global__ void __launch_bounds__(1024) k_solve(const Desc* __restrict__ descs) 
 __global__ void k_init(const Desc* __restrict__ descs, int cycle, int* sched) {
     const Desc& d = descs[blockIdx.x];
     const int tid = threadIdx.x;
-    if (sched && blockIdx.x == 0 && tid < SCH_WORDS) sched[tid] = 0;
+    if (sched && blockIdx.x == 0)
+        for (int w = tid; w < SCH_WORDS; w += blockDim.x) sched[w] = 0;
     if (cycle > 0) {
         const bool sit_out = cycle > d.restarts || d.state[ST_SKIP] != 0;
         __syncthreads();                      // every thread has read the state

@@ -272,6 +272,7 @@ struct Plan {
     Desc* d_desc_r;    // restart cycles: the descriptors with X0 = X (null without restarts)
     int persist;       // the Arnoldi process as one persistent launch
     int* d_sched;      // its scheduling words (SCH_WORDS ints)
+    int qfirst[NKIND][9];   // its XCD queues: first tile of each queue's problems per kind
 };
 
 // descs holds nsides groups of count problems (the same shapes in each group);
@@ -308,6 +309,19 @@ int build_plan(std::vector<Desc>& descs, void* ws, hipStream_t s, Plan& plan, in
         }
         starts[(size_t)k * (count + 1) + count] = acc;
         plan.total[k] = acc;
+    }
+    // the persistent launch's XCD queues: problems in eight contiguous
+    // groups of about equal element counts
+    {
+        long long ntot = 0;
+        for (int p = 0; p < count; ++p) ntot += descs[p].n;
+        int p = 0;
+        long long acc = 0;
+        for (int x = 0; x <= 8; ++x) {
+            const long long cut = ntot * x / 8;
+            while (p < count && (x == 8 || acc + descs[p].n / 2 < cut)) acc += descs[p++].n;
+            for (int k = 0; k < NKIND; ++k) plan.qfirst[k][x] = starts[(size_t)k * (count + 1) + p];
+        }
     }
     plan.l1max = 1;
     plan.compose_max = 1;
@@ -495,18 +509,16 @@ int run_solver(const Plan& plan, int count, int mmax, int bf16, bool any_x0, boo
         a.starts[KIND_TILE] = st;
         a.starts[KIND_GRAM] = sg;
         a.count = count;
-        a.tp = plan.total[KIND_PHI];
-        a.tt = plan.total[KIND_TILE];
-        a.tg = plan.total[KIND_GRAM];
+        std::memcpy(a.qfirst, plan.qfirst, sizeof(a.qfirst));
         a.any_x0 = any_x0 ? 1 : 0;
         a.cycle = cycle;
         a.sched = plan.d_sched;
         a.wait_limit = g_wait_limit.load();
-        const long long full = last_newv ? mmax : mmax - 1;   // steps that form V_{j+1}
-        const long long total = (any_x0 ? (long long)a.tp : 0) + 2LL * a.tt + a.tg + (long long)mmax * a.tg +
-                                full * ((long long)a.tp + a.tt);
+        a.steps = mmax;
+        a.full = last_newv ? mmax : mmax - 1;   // steps that form V_{j+1}
+        const long long tp = plan.total[KIND_PHI], tt = plan.total[KIND_TILE], tg = plan.total[KIND_GRAM];
+        const long long total = (any_x0 ? tp : 0) + 2 * tt + tg + (long long)mmax * tg + (long long)a.full * (tp + tt);
         if (total > 0x3FFFFFFFLL) return RTG_E_SHAPE;
-        a.total = (int)total;
         RTG_TIMED(5, launch_persist(a, plan.rmax, plan.phi_toep, plan.skbf, s));
         if (solve) {
             RTG_TIMED(3, launch_solve(dd, count, mmax, s));

@@ -308,13 +308,15 @@ hipError_t launch_finish_arnoldi(const Desc* d, double* H, double* beta, int* m_
 
 // The persistent launch of a batch's Arnoldi process: its scheduling words
 // (next task, error, workgroups that have left) and arguments.
-enum { SCH_NEXT = 0, SCH_ERROR = 1, SCH_EXITED = 2, SCH_WORDS = 4 };
+// (one task counter per XCD queue, each on its own 128-byte line)
+enum { SCH_ERROR = 0, SCH_EXITED = 1, SCH_QUEUE = 32, SCH_QSTRIDE = 32, SCH_WORDS = SCH_QUEUE + 8 * SCH_QSTRIDE };
 struct PersistArgs {
     const Desc* descs;
     const int* starts[NKIND];   // prefix tables of the problems' tiles per kernel kind
     int count;
-    int tp, tt, tg;             // tiles of one operator, tile and Gram stage over the batch
-    int total;                  // tasks
+    int qfirst[NKIND][9];       // per kernel kind, the first tile of each XCD queue's problems (and the total)
+    int steps;                  // Arnoldi steps (the largest m)
+    int full;                   // steps that form V_{j+1} (the operator and tile stages)
     int any_x0;                 // the operator on X0 comes first
     int cycle;                  // restart cycle (the start stage's argument)
     int* sched;                 // SCH_WORDS ints, zeroed before the launch
