@@ -34,6 +34,9 @@ Variants (each timed over the same number of steps):
   mixed_uneven   the same batch in the mixed form RTG_F32_BF16: float32 basis,
                  sketch contractions on bfloat16 MFMA operands with float32
                  accumulation
+  mixed_uneven_persist  mixed_uneven with its Arnoldi process in one
+                 persistent launch (rtg_tune.persist = 1; the other shapes
+                 autotuned)
   fp32_video     --video-batch 256x256x64 grayscale videos (spatial sigma 2,
                  temporal box blur of width 5, noise 1e-3, sketch 48x48x16),
                  float32 basis, X0 = 0, m = 80
@@ -79,7 +82,7 @@ sys.path.insert(0, ROOT)
 METRIC = "RTG-GMRES solves/s at 512²×3, m=50: plain FP32 vs BF16+learned X₀ at equal rel err"
 HBM_PEAK_GBS = 8000.0
 VARIANTS = ["fp32_plain", "bf16_warm", "bf16_obs", "fp32_unsketched", "fp32_gk", "fp32_psf", "fp32_uneven",
-            "mixed_uneven", "fp32_video", "bf16_video"]
+            "mixed_uneven", "mixed_uneven_persist", "fp32_video", "bf16_video"]
 # the plain solver that re-solves failed warm starts: X0 = 0, m = 50, float32 basis
 FALLBACK_M = 50
 GOLDEN_RE = os.path.join(ROOT, "tests", "golden", "oracle_re.json")
@@ -396,7 +399,7 @@ def oracle_ratios(results, cb, gold):
             pairs = [(r["re"][k], cb["re"][k]) for k in (0, 1) if k < len(r["re"])]
         elif v == "fp32_psf":
             pairs = [(r["re"][0], cb["re_psf0"])]
-        elif v in ("fp32_uneven", "mixed_uneven") and gold:
+        elif v in ("fp32_uneven", "mixed_uneven", "mixed_uneven_persist") and gold:
             pairs = [(r["re"][int(k)], g["re"]) for k, g in gold["uneven"].items() if int(k) < len(r["re"])]
         elif v in ("fp32_video", "bf16_video") and gold:
             pairs = [(r["re"][0], gold["video"]["0"]["re"])]
@@ -495,7 +498,7 @@ def main():
                 r["kernel"] = ("k_tile", "k_tile.hip", "multi-AXPY + store + MFMA sketch, 256x256x64 videos")
             res = [rel_err(plan.outs[b], probs_v[b]["xt"]) for b in range(Bv)]
             r["solves_per_step"] = Bv
-        elif v in ("fp32_uneven", "mixed_uneven"):
+        elif v in ("fp32_uneven", "mixed_uneven", "mixed_uneven_persist"):
             probs_u = make_uneven_batch(dev)
             Bu = len(probs_u)
             bt = rtg.F32 if v == "fp32_uneven" else rtg.F32_BF16
@@ -506,6 +509,11 @@ def main():
             it = {"i": 0}
 
             tune = tune_plan(plan, args)
+            if v == "mixed_uneven_persist" and tune.get("persist") != 1:
+                t = plan.tune()
+                t.persist = 1
+                plan.set_tune(t)
+                tune = {**tune, "persist": 1}
             persist = tune.get("persist") == 1
 
             def bytes_u(inf, it=it):
@@ -582,7 +590,7 @@ def main():
             r["kernel"] = ("k_step", "k_step.hip", "Arnoldi step: operator per tile + multi-AXPY + store + "
                                                    "dual MFMA sketch (bfloat16 basis)")
             r["fallbacks_per_step"] = plan.n_fallback
-        if v not in ("fp32_psf", "fp32_uneven", "mixed_uneven", "fp32_video", "bf16_video"):
+        if v not in ("fp32_psf", "fp32_uneven", "mixed_uneven", "mixed_uneven_persist", "fp32_video", "bf16_video"):
             res = [rel_err(plan.outs[b], probs[b]["xt"]) for b in range(B)]
         r["tune"] = tune
         r["re"] = res
