@@ -34,6 +34,7 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+typedef float f16v __attribute__((ext_vector_type(16)));
 
 enum ConvMode { CV_HIDDEN = 0, CV_LAST_INFER = 1, CV_LAST_TRAIN = 2, CV_BWD_DATA = 3 };
 
@@ -279,6 +280,11 @@ struct WgradArgs {
 // zero padding layer B sees -- and layer B (32 -> COUT) reads it from LDS, so
 // the activation between the two layers never goes to memory.  Layer A's
 // weights stay in registers for the whole kernel, layer B's in LDS.
+// Both layers of a hidden pair run on v_mfma_f32_32x32x16_bf16 (32 output
+// channels x 32 pixels per product): each 16-byte activation fragment read
+// from LDS feeds twice the products of a 16x16x32 tile, which halves the
+// LDS reads per product -- the bound of this kernel.  The last pair's
+// layer B (3 output channels) keeps 16x16x32 tiles.
 // Persistent grid: a workgroup streams the next tile's input (with its
 // two-pixel halo) into LDS by asynchronous loads while it computes layer B of
 // the current tile.
@@ -305,7 +311,9 @@ __global__ void __launch_bounds__(C2_THREADS) k_conv2(Conv2Args a) {
     constexpr int IH = TH + 4, IW = TW + 4;            // input tile (two-pixel halo)
     constexpr int MH = TH + 2, MW = TW + 2;            // layer-A tile (one-pixel halo)
     constexpr int MP = MH * MW;                         // layer-A pixels
-    constexpr int MNT = (MP + 15) / 16;                 // layer-A N-tiles of 16 pixels
+    constexpr int MNT = (MP + 31) / 32;                 // layer-A N-tiles of 32 pixels
+    constexpr int KSA = (9 * CIN_S + 15) / 16;          // layer-A K steps of 16 (taps x channels)
+    constexpr int DA = KSA % 3 == 0 ? 3 : KSA;          // layer-A operand reads ahead
     constexpr int PSA = CIN_S + 8, PSB = 32 + 8;        // padded channels per pixel in LDS
     constexpr int KPA = kpad_of(CIN_S), KQA = KPA / 32;
     constexpr int KPB = kpad_of(32), KQB = KPB / 32;
@@ -313,35 +321,39 @@ __global__ void __launch_bounds__(C2_THREADS) k_conv2(Conv2Args a) {
     constexpr int NCH = CIN_S / 8;
     constexpr int KLB = KPB + 8;                        // padded LDS row of layer-B weights
     __shared__ __attribute__((aligned(16))) bf16_t Xs[IH * IW * PSA];
-    __shared__ __attribute__((aligned(16))) bf16_t Ms[MNT * 16 * PSB];   // whole N-tiles: unconditional stores
+    __shared__ __attribute__((aligned(16))) bf16_t Ms[MNT * 32 * PSB];   // whole N-tiles: unconditional stores
     __shared__ __attribute__((aligned(16))) bf16_t WlB[COUTB_M * KLB];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n16 = lane & 15, s = lane >> 4;
+    const int n32 = lane & 31, g = lane >> 5;
     const int I1 = a.I1, I2 = a.I2;
     const size_t plane = (size_t)I1 * I2;
     const int nt1 = (I1 + TW - 1) / TW, nt2 = (I2 + TH - 1) / TH;
     const int ntiles = a.N * nt1 * nt2;
 
-    // layer-A weights (MFMA A operands, reused by every N-tile) in registers;
-    // layer-B weights in LDS (each fragment serves four N-tiles); biases in registers
-    bf8 AfA[KQA][2];
+    // layer-A weights (MFMA A operands of 32x32x16 products, reused by every
+    // N-tile) in registers; layer-B weights in LDS; biases in registers (the
+    // lane's 16 output channels of a 32x32 result: 8 (v / 4) + 4 g + v % 4)
+    bf8 AfA[KSA];
 #pragma unroll
-    for (int q = 0; q < KQA; ++q)
-#pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
-            AfA[q][mt] = __builtin_bit_cast(bf8, *gptr((const u4*)(a.wA + (size_t)(16 * mt + n16) * KPA + 32 * q + 8 * s)));
+    for (int q = 0; q < KSA; ++q)
+        AfA[q] = __builtin_bit_cast(bf8, *gptr((const u4*)(a.wA + (size_t)n32 * KPA + 16 * q + 8 * g)));
     for (int e = tid; e < COUTB_M * (KPB / 8); e += NTH) {
         const int row = e / (KPB / 8), c8 = e % (KPB / 8);
         *(u4*)(WlB + row * KLB + c8 * 8) = *gptr((const u4*)(a.wB + (size_t)row * KPB + c8 * 8));
     }
-    float biasA[2][4], biasB[MTB][4];
+    float biasA[16], biasB[LASTB ? 4 * MTB : 16];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int v = 0; v < 16; ++v) biasA[v] = *gptr(a.bA + 8 * (v / 4) + 4 * g + v % 4);
+    if constexpr (LASTB) {
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt) biasA[mt][i] = *gptr(a.bA + 16 * mt + 4 * s + i);
+        for (int mt = 0; mt < MTB; ++mt)
 #pragma unroll
-        for (int mt = 0; mt < MTB; ++mt) biasB[mt][i] = *gptr(a.bB + 16 * mt + 4 * s + i);
+            for (int i = 0; i < 4; ++i) biasB[4 * mt + i] = *gptr(a.bB + 16 * mt + 4 * s + i);
+    } else {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) biasB[v] = *gptr(a.bB + 8 * (v / 4) + 4 * g + v % 4);
     }
 
     // The input tile (two-pixel halo) reaches Xs by asynchronous global-to-
@@ -393,16 +405,17 @@ __global__ void __launch_bounds__(C2_THREADS) k_conv2(Conv2Args a) {
         }
 
 
-        // ---- layer A on the grown tile: N-tiles of 16 pixels, wave w takes w, w + 8, ...
-        // Operand reads run three taps ahead of the matrix cores, across the
-        // end of an N-tile into the wave's next one (KQA is a multiple of 3,
-        // so tap q always sits in slot q % 3).
-        constexpr int DA = 3;
-        static_assert(KQA % DA == 0, "tap window");
+        // ---- layer A on the grown tile: N-tiles of 32 pixels (32x32x16
+        // products: lane l holds pixel nt 32 + l % 32 and, of each K step of
+        // 16, the 8 channels 8 (l / 32) ..), wave w takes w, w + 8, ...
+        // Operand reads run DA steps ahead of the matrix cores, across the
+        // end of an N-tile into the wave's next one (DA divides KSA, so step
+        // q always sits in slot q % DA).
+        static_assert(KSA % DA == 0, "operand window");
         auto readA = [&](int nt, int q) {
-            const int pc = min(nt * 16 + n16, MP - 1);
+            const int pc = min(nt * 32 + n32, MP - 1);
             const int mr = pc / MW, mc = pc % MW;
-            const int k = 32 * q + 8 * s;
+            const int k = 16 * q + 8 * g;
             const int tap = k / CIN_S, ci0 = k % CIN_S;
             const int tp = tap < 9 ? tap : 0;
             const u4 v = *(const u4*)(Xs + ((mr + tp % 3) * IW + mc + tp / 3) * PSA + ci0);
@@ -414,103 +427,148 @@ __global__ void __launch_bounds__(C2_THREADS) k_conv2(Conv2Args a) {
             for (int q = 0; q < DA; ++q) Bw[q] = readA(min(wave, MNT - 1), q);
             for (int nt = wave; nt < MNT; nt += TH) {
                 const int ntn = min(nt + TH, MNT - 1);          // past the last tile: a valid tile again, unused
-                f4 acc[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
+                f16v acc = {};
 #pragma unroll
-                for (int q = 0; q < KQA; ++q) {
+                for (int q = 0; q < KSA; ++q) {
                     const u4 cur = Bw[q % DA];
-                    Bw[q % DA] = (q + DA < KQA) ? readA(nt, q + DA) : readA(ntn, q + DA - KQA);
-                    __builtin_amdgcn_sched_barrier(0);       // keep the read ahead of these products
-#pragma unroll
-                    for (int mt = 0; mt < 2; ++mt)
-                        acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AfA[q][mt], __builtin_bit_cast(bf8, cur), acc[mt],
-                                                                          0, 0, 0);
+                    Bw[q % DA] = (q + DA < KSA) ? readA(nt, q + DA) : readA(ntn, q + DA - KSA);
+                    __builtin_amdgcn_sched_barrier(0);       // keep the read ahead of this product
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(AfA[q], __builtin_bit_cast(bf8, cur), acc, 0, 0, 0);
                 }
                 // epilogue without branches: pixels outside the image (the
                 // zero padding of layer B's input) get a factor 0, and the
                 // pixels past MP of the last N-tile land in Ms's tail
-                const int p = nt * 16 + n16;
+                const int p = nt * 32 + n32;
                 const int pc = min(p, MP - 1);
                 const int mr = pc / MW, mc = pc % MW;
                 const int y2 = i20 - 1 + mr, y1 = i10 - 1 + mc;
                 const float inimg = ((y1 >= 0) & (y1 < I1) & (y2 >= 0) & (y2 < I2)) ? 1.f : 0.f;
 #pragma unroll
-                for (int mt = 0; mt < 2; ++mt) {
+                for (int r = 0; r < 4; ++r) {
                     float v[4];
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) v[i] = fmaxf(acc[mt][i] + biasA[mt][i], 0.f) * inimg;
+                    for (int i = 0; i < 4; ++i) v[i] = fmaxf(acc[4 * r + i] + biasA[4 * r + i], 0.f) * inimg;
                     u2 pk;
                     pk[0] = (unsigned)f2bf(v[0]) | ((unsigned)f2bf(v[1]) << 16);
                     pk[1] = (unsigned)f2bf(v[2]) | ((unsigned)f2bf(v[3]) << 16);
-                    *(u2*)(Ms + p * PSB + 16 * mt + 4 * s) = pk;
+                    *(u2*)(Ms + p * PSB + 8 * r + 4 * g) = pk;
                 }
             }
         }
         __syncthreads();                     // layer A done: Ms complete, Xs free
         if (t + (int)gridDim.x < ntiles) dma_tile(t + (int)gridDim.x);
-        // ---- layer B: wave w takes output row w, four N-tiles of 16 pixels;
-        // the operands (weights and activations) of tap q + 1 are read while
-        // tap q is on the matrix cores
-        f4 acc[4][MTB];
+        if constexpr (!LASTB) {
+            // ---- layer B (hidden pair): wave w takes output row w, two
+            // N-tiles of 32 pixels, 32x32x16 products; the operands (weights
+            // and activations) of step q + 1 are read while step q is on the
+            // matrix cores
+            f16v accB[2] = {};
+            auto loadB2 = [&](int q, u4* Bq, u4& Wq) {
+                const int k = 16 * q + 8 * g;
+                const int tap = k / 32, ci0 = k % 32;
+                Wq = *(const u4*)(WlB + n32 * KLB + k);
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt)
+                for (int nt = 0; nt < 2; ++nt)
+                    Bq[nt] = *(const u4*)(Ms + ((wave + tap % 3) * MW + nt * 32 + n32 + tap / 3) * PSB + ci0);
+            };
+            constexpr int KSB = 9 * 32 / 16;
+            u4 Bb[2][2], Wb[2];
+            loadB2(0, Bb[0], Wb[0]);
 #pragma unroll
-            for (int mt = 0; mt < MTB; ++mt) acc[nt][mt] = f4{0.f, 0.f, 0.f, 0.f};
-        auto loadB = [&](int q, u4* Bq, u4* Wq) {
-            const int k = 32 * q + 8 * s;
-            const int tap = k / 32, ci0 = k % 32;
-            const int tp = tap < 9 ? tap : 0;
+            for (int q = 0; q < KSB; ++q) {
+                if (q + 1 < KSB) loadB2(q + 1, Bb[(q + 1) & 1], Wb[(q + 1) & 1]);
 #pragma unroll
-            for (int mt = 0; mt < MTB; ++mt) Wq[mt] = *(const u4*)(WlB + (16 * mt + n16) * KLB + 32 * q + 8 * s);
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
-                const int il = nt * 16 + n16;
-                const u4 v = *(const u4*)(Ms + ((wave + tp % 3) * MW + il + tp / 3) * PSB + ci0);
-                Bq[nt] = tap < 9 ? v : u4{0u, 0u, 0u, 0u};
+                for (int nt = 0; nt < 2; ++nt)
+                    accB[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf8, Wb[q & 1]),
+                                                                       __builtin_bit_cast(bf8, Bb[q & 1][nt]), accB[nt],
+                                                                       0, 0, 0);
             }
-        };
-        {
-            u4 Bb[2][4], Wb[2][MTB];
-            loadB(0, Bb[0], Wb[0]);
+            const bool row_ok = i2 < I2;
 #pragma unroll
-            for (int q = 0; q < KQB; ++q) {
-                if (q + 1 < KQB) loadB(q + 1, Bb[(q + 1) & 1], Wb[(q + 1) & 1]);
-#pragma unroll
-                for (int nt = 0; nt < 4; ++nt)
-#pragma unroll
-                    for (int mt = 0; mt < MTB; ++mt)
-                        acc[nt][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                            __builtin_bit_cast(bf8, Wb[q & 1][mt]), __builtin_bit_cast(bf8, Bb[q & 1][nt]), acc[nt][mt],
-                            0, 0, 0);
-            }
-        }
-        const bool row_ok = i2 < I2;
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            const int i1 = i10 + nt * 16 + n16;
-            const bool ok = row_ok && i1 < I1;
-            if constexpr (!LASTB) {
+            for (int nt = 0; nt < 2; ++nt) {
+                const int i1 = i10 + nt * 32 + n32;
+                const bool ok = row_ok && i1 < I1;
                 const size_t pix = ((size_t)img * I2 + i2c) * I1 + min(i1, I1 - 1);
-                u2 pk[MTB];
+                u2 pk[4];
 #pragma unroll
-                for (int mt = 0; mt < MTB; ++mt) {
+                for (int r = 0; r < 4; ++r) {
                     float v[4];
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) v[i] = fmaxf(acc[nt][mt][i] + biasB[mt][i], 0.f);
-                    pk[mt][0] = (unsigned)f2bf(v[0]) | ((unsigned)f2bf(v[1]) << 16);
-                    pk[mt][1] = (unsigned)f2bf(v[2]) | ((unsigned)f2bf(v[3]) << 16);
+                    for (int i = 0; i < 4; ++i) v[i] = fmaxf(accB[nt][4 * r + i] + biasB[4 * r + i], 0.f);
+                    pk[r][0] = (unsigned)f2bf(v[0]) | ((unsigned)f2bf(v[1]) << 16);
+                    pk[r][1] = (unsigned)f2bf(v[2]) | ((unsigned)f2bf(v[3]) << 16);
                 }
                 if (ok) {
 #pragma unroll
-                    for (int mt = 0; mt < MTB; ++mt) *gptr_w((u2*)(a.out + pix * COUTB_S + 16 * mt + 4 * s)) = pk[mt];
+                    for (int r = 0; r < 4; ++r) *gptr_w((u2*)(a.out + pix * COUTB_S + 8 * r + 4 * g)) = pk[r];
                 }
-            } else {
-                // rows 0..2 of the first M tile (lanes with s = 0) are the three output channels
-                float x0[3];
-#pragma unroll
-                for (int c = 0; c < 3; ++c) x0[c] = cin[nt][c] + acc[nt][0][c] + biasB[0][c];
-                if (ok && s == 0) {
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) *gptr_w(a.X0 + ((size_t)img * 3 + c) * plane + (size_t)i2 * I1 + i1) = x0[c];
+            }
+        } else {
+            // ---- layer B: wave w takes output row w, four N-tiles of 16 pixels;
+            // the operands (weights and activations) of tap q + 1 are read while
+            // tap q is on the matrix cores
+            f4 acc[4][MTB];
+    #pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+    #pragma unroll
+                for (int mt = 0; mt < MTB; ++mt) acc[nt][mt] = f4{0.f, 0.f, 0.f, 0.f};
+            auto loadB = [&](int q, u4* Bq, u4* Wq) {
+                const int k = 32 * q + 8 * s;
+                const int tap = k / 32, ci0 = k % 32;
+                const int tp = tap < 9 ? tap : 0;
+    #pragma unroll
+                for (int mt = 0; mt < MTB; ++mt) Wq[mt] = *(const u4*)(WlB + (16 * mt + n16) * KLB + 32 * q + 8 * s);
+    #pragma unroll
+                for (int nt = 0; nt < 4; ++nt) {
+                    const int il = nt * 16 + n16;
+                    const u4 v = *(const u4*)(Ms + ((wave + tp % 3) * MW + il + tp / 3) * PSB + ci0);
+                    Bq[nt] = tap < 9 ? v : u4{0u, 0u, 0u, 0u};
+                }
+            };
+            {
+                u4 Bb[2][4], Wb[2][MTB];
+                loadB(0, Bb[0], Wb[0]);
+    #pragma unroll
+                for (int q = 0; q < KQB; ++q) {
+                    if (q + 1 < KQB) loadB(q + 1, Bb[(q + 1) & 1], Wb[(q + 1) & 1]);
+    #pragma unroll
+                    for (int nt = 0; nt < 4; ++nt)
+    #pragma unroll
+                        for (int mt = 0; mt < MTB; ++mt)
+                            acc[nt][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                __builtin_bit_cast(bf8, Wb[q & 1][mt]), __builtin_bit_cast(bf8, Bb[q & 1][nt]), acc[nt][mt],
+                                0, 0, 0);
+                }
+            }
+            const bool row_ok = i2 < I2;
+    #pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const int i1 = i10 + nt * 16 + n16;
+                const bool ok = row_ok && i1 < I1;
+                if constexpr (!LASTB) {
+                    const size_t pix = ((size_t)img * I2 + i2c) * I1 + min(i1, I1 - 1);
+                    u2 pk[MTB];
+    #pragma unroll
+                    for (int mt = 0; mt < MTB; ++mt) {
+                        float v[4];
+    #pragma unroll
+                        for (int i = 0; i < 4; ++i) v[i] = fmaxf(acc[nt][mt][i] + biasB[4 * mt + i], 0.f);
+                        pk[mt][0] = (unsigned)f2bf(v[0]) | ((unsigned)f2bf(v[1]) << 16);
+                        pk[mt][1] = (unsigned)f2bf(v[2]) | ((unsigned)f2bf(v[3]) << 16);
+                    }
+                    if (ok) {
+    #pragma unroll
+                        for (int mt = 0; mt < MTB; ++mt) *gptr_w((u2*)(a.out + pix * COUTB_S + 16 * mt + 4 * s)) = pk[mt];
+                    }
+                } else {
+                    // rows 0..2 of the first M tile (lanes with s = 0) are the three output channels
+                    float x0[3];
+    #pragma unroll
+                    for (int c = 0; c < 3; ++c) x0[c] = cin[nt][c] + acc[nt][0][c] + biasB[c];
+                    if (ok && s == 0) {
+    #pragma unroll
+                        for (int c = 0; c < 3; ++c) *gptr_w(a.X0 + ((size_t)img * 3 + c) * plane + (size_t)i2 * I1 + i1) = x0[c];
+                    }
                 }
             }
         }
