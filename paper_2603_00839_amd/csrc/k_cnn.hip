@@ -35,6 +35,14 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u2 __attribute__((ext_vector_type(2)));
 typedef float f16v __attribute__((ext_vector_type(16)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
+
+// two floats to bfloat16 (round to nearest even) in one 32-bit word, the
+// first in the low half: one packed conversion instead of two
+__device__ __forceinline__ unsigned bf2pack(float lo, float hi) {
+    return __builtin_bit_cast(unsigned, __builtin_convertvector(f2v{lo, hi}, bf2v));
+}
 
 enum ConvMode { CV_HIDDEN = 0, CV_LAST_INFER = 1, CV_LAST_TRAIN = 2, CV_BWD_DATA = 3 };
 
@@ -324,7 +332,8 @@ __global__ void __launch_bounds__(C2_THREADS) k_conv2(Conv2Args a) {
     __shared__ __attribute__((aligned(16))) bf16_t Ms[MNT * 32 * PSB];   // whole N-tiles: unconditional stores
     __shared__ __attribute__((aligned(16))) bf16_t WlB[COUTB_M * KLB];
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: a scalar N-tile loop
     const int n16 = lane & 15, s = lane >> 4;
     const int n32 = lane & 31, g = lane >> 5;
     const int I1 = a.I1, I2 = a.I2;
@@ -343,14 +352,15 @@ __global__ void __launch_bounds__(C2_THREADS) k_conv2(Conv2Args a) {
         const int row = e / (KPB / 8), c8 = e % (KPB / 8);
         *(u4*)(WlB + row * KLB + c8 * 8) = *gptr((const u4*)(a.wB + (size_t)row * KPB + c8 * 8));
     }
-    float biasA[16], biasB[LASTB ? 4 * MTB : 16];
+    f16v biasA, biasB = {};                             // 32x32 results (hidden layers)
+    float biasL[4 * MTB];                               // last pair's layer B (16x16 results)
 #pragma unroll
     for (int v = 0; v < 16; ++v) biasA[v] = *gptr(a.bA + 8 * (v / 4) + 4 * g + v % 4);
     if constexpr (LASTB) {
 #pragma unroll
         for (int mt = 0; mt < MTB; ++mt)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) biasB[4 * mt + i] = *gptr(a.bB + 16 * mt + 4 * s + i);
+            for (int i = 0; i < 4; ++i) biasL[4 * mt + i] = *gptr(a.bB + 16 * mt + 4 * s + i);
     } else {
 #pragma unroll
         for (int v = 0; v < 16; ++v) biasB[v] = *gptr(a.bB + 8 * (v / 4) + 4 * g + v % 4);
@@ -361,35 +371,47 @@ __global__ void __launch_bounds__(C2_THREADS) k_conv2(Conv2Args a) {
     // s % NTH of pass s / NTH (a wave's instruction fills 1 KB, lane i at
     // bytes 16 i).  Padding slots and pixels outside the image are fetched
     // from past the buffer range and read as zeros.  The next tile's loads
-    // are issued once layer A no longer reads Xs, so they overlap layer B.
+    // are issued once layer A no longer reads Xs, one pass every other step
+    // of layer B's products.
     constexpr int SPP = PSA / 8;                        // slots per pixel
     constexpr int NSL = IH * IW * SPP;
+    constexpr int NPASS = (NSL + NTH - 1) / NTH;        // passes; the last one may be partial
     const auto rx = __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16_t*>(a.x), (short)0,
                                                       (int)((size_t)a.N * plane * CIN_S * 2), 0x00020000);
-    auto dma_tile = [&](int tt) {
+    const auto ro = __builtin_amdgcn_make_buffer_rsrc(a.out, (short)0, (int)((size_t)a.N * plane * COUTB_S * 2),
+                                                      0x00020000);
+    constexpr int NSTB = 8;                             // hidden pair: stores per wave and tile
+    static_assert(NSTB < 16, "vmcnt field");
+    struct Origin { int i10, i20, img; };
+    auto origin = [&](int tt) {
         const int t1 = tt % nt1, r = tt / nt1;
-        const int i10 = t1 * TW, i20 = (r % nt2) * TH, img = r / nt2;
-        auto one = [&](int it) {
-            const int sl = it * NTH + tid;
-            const int pxl = sl / SPP, c = sl % SPP;
-            const int y1 = i10 - 2 + pxl % IW, y2 = i20 - 2 + pxl / IW;
-            const bool ok = (c < NCH) & (y1 >= 0) & (y1 < I1) & (y2 >= 0) & (y2 < I2);
-            const unsigned off =
-                ok ? (unsigned)(((((size_t)img * I2 + y2) * I1 + y1) * CIN_S + c * 8) * 2) : 0x80000000u;
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                rx, (__attribute__((address_space(3))) void*)(Xs + (size_t)(it * NTH + wave * 64) * 8), 16, off, 0, 0, 0);
-        };
-#pragma unroll
-        for (int it = 0; it < NSL / NTH; ++it) one(it);
-        if constexpr (NSL % NTH != 0)
-            if (tid < NSL % NTH) one(NSL / NTH);
+        return Origin{t1 * TW, (r % nt2) * TH, r / nt2};
+    };
+    auto dma_pass = [&](const Origin& o, int it) {
+        const int sl = it * NTH + tid;
+        if (NSL % NTH != 0 && it == NPASS - 1 && sl >= NSL) return;
+        const int pxl = sl / SPP, c = sl % SPP;
+        const int y1 = o.i10 - 2 + pxl % IW, y2 = o.i20 - 2 + pxl / IW;
+        const bool ok = (c < NCH) & (y1 >= 0) & (y1 < I1) & (y2 >= 0) & (y2 < I2);
+        const unsigned off =
+            ok ? (unsigned)(((((size_t)o.img * I2 + y2) * I1 + y1) * CIN_S + c * 8) * 2) : 0x80000000u;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            rx, (__attribute__((address_space(3))) void*)(Xs + (size_t)(it * NTH + wave * 64) * 8), 16, off, 0, 0, 0);
     };
     int t = blockIdx.x;
-    if (t < ntiles) dma_tile(t);
+    if (t < ntiles) {
+        const Origin o0 = origin(t);
+#pragma unroll
+        for (int it = 0; it < NPASS; ++it) dma_pass(o0, it);
+    }
     for (; t < ntiles; t += gridDim.x) {
         const int t1 = t % nt1, rr = t / nt1;
         const int i10 = t1 * TW, i20 = (rr % nt2) * TH, img = rr / nt2;
-        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's loads of the tile have landed
+        // this wave's loads of the tile have landed: memory operations
+        // complete in issue order, and after the input loads a hidden pair's
+        // wave has issued exactly NSTB stores, which need not be waited for
+        if (LASTB || t == (int)blockIdx.x) __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+        else __builtin_amdgcn_s_waitcnt(0x0F70 | NSTB);                         // vmcnt(NSTB)
         __syncthreads();                     // all of them; the previous tile's reads of Ms are done
         // epilogue operands of layer B (last pair)
         float cin[4][3];
@@ -427,7 +449,7 @@ __global__ void __launch_bounds__(C2_THREADS) k_conv2(Conv2Args a) {
             for (int q = 0; q < DA; ++q) Bw[q] = readA(min(wave, MNT - 1), q);
             for (int nt = wave; nt < MNT; nt += TH) {
                 const int ntn = min(nt + TH, MNT - 1);          // past the last tile: a valid tile again, unused
-                f16v acc = {};
+                f16v acc = biasA;                           // the bias enters as the first accumulator
 #pragma unroll
                 for (int q = 0; q < KSA; ++q) {
                     const u4 cur = Bw[q % DA];
@@ -435,34 +457,34 @@ __global__ void __launch_bounds__(C2_THREADS) k_conv2(Conv2Args a) {
                     __builtin_amdgcn_sched_barrier(0);       // keep the read ahead of this product
                     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(AfA[q], __builtin_bit_cast(bf8, cur), acc, 0, 0, 0);
                 }
-                // epilogue without branches: pixels outside the image (the
-                // zero padding of layer B's input) get a factor 0, and the
-                // pixels past MP of the last N-tile land in Ms's tail
+                // epilogue without branches: ReLU as a clamp to [0, lim], with
+                // lim = 0 for pixels outside the image (the zero padding of
+                // layer B's input); the pixels past MP of the last N-tile land
+                // in Ms's tail
                 const int p = nt * 32 + n32;
                 const int pc = min(p, MP - 1);
                 const int mr = pc / MW, mc = pc % MW;
                 const int y2 = i20 - 1 + mr, y1 = i10 - 1 + mc;
-                const float inimg = ((y1 >= 0) & (y1 < I1) & (y2 >= 0) & (y2 < I2)) ? 1.f : 0.f;
+                const float lim = ((y1 >= 0) & (y1 < I1) & (y2 >= 0) & (y2 < I2)) ? __builtin_inff() : 0.f;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    float v[4];
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) v[i] = fmaxf(acc[4 * r + i] + biasA[4 * r + i], 0.f) * inimg;
                     u2 pk;
-                    pk[0] = (unsigned)f2bf(v[0]) | ((unsigned)f2bf(v[1]) << 16);
-                    pk[1] = (unsigned)f2bf(v[2]) | ((unsigned)f2bf(v[3]) << 16);
+                    pk[0] = bf2pack(__builtin_amdgcn_fmed3f(acc[4 * r], 0.f, lim),
+                                    __builtin_amdgcn_fmed3f(acc[4 * r + 1], 0.f, lim));
+                    pk[1] = bf2pack(__builtin_amdgcn_fmed3f(acc[4 * r + 2], 0.f, lim),
+                                    __builtin_amdgcn_fmed3f(acc[4 * r + 3], 0.f, lim));
                     *(u2*)(Ms + p * PSB + 8 * r + 4 * g) = pk;
                 }
             }
         }
         __syncthreads();                     // layer A done: Ms complete, Xs free
-        if (t + (int)gridDim.x < ntiles) dma_tile(t + (int)gridDim.x);
+        const bool nxt = t + (int)gridDim.x < ntiles;
+        const Origin on = origin(min(t + (int)gridDim.x, ntiles - 1));
         if constexpr (!LASTB) {
             // ---- layer B (hidden pair): wave w takes output row w, two
             // N-tiles of 32 pixels, 32x32x16 products; the operands (weights
-            // and activations) of step q + 1 are read while step q is on the
+            // and activations) of step q + 2 are read while step q is on the
             // matrix cores
-            f16v accB[2] = {};
             auto loadB2 = [&](int q, u4* Bq, u4& Wq) {
                 const int k = 16 * q + 8 * g;
                 const int tap = k / 32, ci0 = k % 32;
@@ -472,40 +494,44 @@ __global__ void __launch_bounds__(C2_THREADS) k_conv2(Conv2Args a) {
                     Bq[nt] = *(const u4*)(Ms + ((wave + tap % 3) * MW + nt * 32 + n32 + tap / 3) * PSB + ci0);
             };
             constexpr int KSB = 9 * 32 / 16;
-            u4 Bb[2][2], Wb[2];
-            loadB2(0, Bb[0], Wb[0]);
+            static_assert(2 * NPASS <= KSB + 1, "input passes per layer-B step");
+            constexpr int PD = 2;                       // operand reads run PD steps ahead
+            u4 Bb[PD + 1][2], Wb[PD + 1];
+#pragma unroll
+            for (int q = 0; q < PD; ++q) loadB2(q, Bb[q], Wb[q]);
+            f16v accB[2] = {biasB, biasB};              // the bias enters as the first accumulator
 #pragma unroll
             for (int q = 0; q < KSB; ++q) {
-                if (q + 1 < KSB) loadB2(q + 1, Bb[(q + 1) & 1], Wb[(q + 1) & 1]);
+                if (q + PD < KSB) loadB2(q + PD, Bb[(q + PD) % (PD + 1)], Wb[(q + PD) % (PD + 1)]);
+                if ((q & 1) == 0 && q / 2 < NPASS && nxt) dma_pass(on, q / 2);
+                __builtin_amdgcn_sched_barrier(0);       // keep the reads ahead of these products
 #pragma unroll
                 for (int nt = 0; nt < 2; ++nt)
-                    accB[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf8, Wb[q & 1]),
-                                                                       __builtin_bit_cast(bf8, Bb[q & 1][nt]), accB[nt],
-                                                                       0, 0, 0);
+                    accB[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf8, Wb[q % (PD + 1)]),
+                                                                       __builtin_bit_cast(bf8, Bb[q % (PD + 1)][nt]),
+                                                                       accB[nt], 0, 0, 0);
             }
             const bool row_ok = i2 < I2;
 #pragma unroll
             for (int nt = 0; nt < 2; ++nt) {
                 const int i1 = i10 + nt * 32 + n32;
                 const bool ok = row_ok && i1 < I1;
-                const size_t pix = ((size_t)img * I2 + i2c) * I1 + min(i1, I1 - 1);
-                u2 pk[4];
+                // buffer stores, issued by every lane (past the range for
+                // pixels outside the image, which the hardware drops): each
+                // wave issues exactly NSTB stores per tile after its input loads
+                const unsigned off = ok ? (unsigned)(((((size_t)img * I2 + i2) * I1 + i1) * COUTB_S + 4 * g) * 2)
+                                        : 0x80000000u;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    float v[4];
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) v[i] = fmaxf(accB[nt][4 * r + i] + biasB[4 * r + i], 0.f);
-                    pk[r][0] = (unsigned)f2bf(v[0]) | ((unsigned)f2bf(v[1]) << 16);
-                    pk[r][1] = (unsigned)f2bf(v[2]) | ((unsigned)f2bf(v[3]) << 16);
-                }
-                if (ok) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) *gptr_w((u2*)(a.out + pix * COUTB_S + 8 * r + 4 * g)) = pk[r];
+                    u2 pk;
+                    pk[0] = bf2pack(fmaxf(accB[nt][4 * r], 0.f), fmaxf(accB[nt][4 * r + 1], 0.f));
+                    pk[1] = bf2pack(fmaxf(accB[nt][4 * r + 2], 0.f), fmaxf(accB[nt][4 * r + 3], 0.f));
+                    __builtin_amdgcn_raw_buffer_store_b64(pk, ro, off + 16u * r, 0, 0);
                 }
             }
         } else {
             // ---- layer B: wave w takes output row w, four N-tiles of 16 pixels;
-            // the operands (weights and activations) of tap q + 1 are read while
+            // the operands (weights and activations) of tap q + 2 are read while
             // tap q is on the matrix cores
             f4 acc[4][MTB];
     #pragma unroll
@@ -526,18 +552,23 @@ __global__ void __launch_bounds__(C2_THREADS) k_conv2(Conv2Args a) {
                 }
             };
             {
-                u4 Bb[2][4], Wb[2][MTB];
-                loadB(0, Bb[0], Wb[0]);
+                constexpr int PD = 2;                   // operand reads run PD taps ahead
+                u4 Bb[PD + 1][4], Wb[PD + 1][MTB];
+    #pragma unroll
+                for (int q = 0; q < PD; ++q) loadB(q, Bb[q], Wb[q]);
     #pragma unroll
                 for (int q = 0; q < KQB; ++q) {
-                    if (q + 1 < KQB) loadB(q + 1, Bb[(q + 1) & 1], Wb[(q + 1) & 1]);
+                    if (q + PD < KQB) loadB(q + PD, Bb[(q + PD) % (PD + 1)], Wb[(q + PD) % (PD + 1)]);
+                    static_assert(NPASS <= KQB, "input passes per layer-B tap");
+                    if (q < NPASS && nxt) dma_pass(on, q);
+                    __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of these products
     #pragma unroll
                     for (int nt = 0; nt < 4; ++nt)
     #pragma unroll
                         for (int mt = 0; mt < MTB; ++mt)
                             acc[nt][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                                __builtin_bit_cast(bf8, Wb[q & 1][mt]), __builtin_bit_cast(bf8, Bb[q & 1][nt]), acc[nt][mt],
-                                0, 0, 0);
+                                __builtin_bit_cast(bf8, Wb[q % (PD + 1)][mt]), __builtin_bit_cast(bf8, Bb[q % (PD + 1)][nt]),
+                                acc[nt][mt], 0, 0, 0);
                 }
             }
             const bool row_ok = i2 < I2;
@@ -552,7 +583,7 @@ __global__ void __launch_bounds__(C2_THREADS) k_conv2(Conv2Args a) {
                     for (int mt = 0; mt < MTB; ++mt) {
                         float v[4];
     #pragma unroll
-                        for (int i = 0; i < 4; ++i) v[i] = fmaxf(acc[nt][mt][i] + biasB[4 * mt + i], 0.f);
+                        for (int i = 0; i < 4; ++i) v[i] = fmaxf(acc[nt][mt][i] + biasL[4 * mt + i], 0.f);
                         pk[mt][0] = (unsigned)f2bf(v[0]) | ((unsigned)f2bf(v[1]) << 16);
                         pk[mt][1] = (unsigned)f2bf(v[2]) | ((unsigned)f2bf(v[3]) << 16);
                     }
@@ -564,7 +595,7 @@ __global__ void __launch_bounds__(C2_THREADS) k_conv2(Conv2Args a) {
                     // rows 0..2 of the first M tile (lanes with s = 0) are the three output channels
                     float x0[3];
     #pragma unroll
-                    for (int c = 0; c < 3; ++c) x0[c] = cin[nt][c] + acc[nt][0][c] + biasB[c];
+                    for (int c = 0; c < 3; ++c) x0[c] = cin[nt][c] + acc[nt][0][c] + biasL[c];
                     if (ok && s == 0) {
     #pragma unroll
                         for (int c = 0; c < 3; ++c) *gptr_w(a.X0 + ((size_t)img * 3 + c) * plane + (size_t)i2 * I1 + i1) = x0[c];
