@@ -228,9 +228,12 @@ void fill_desc(Desc& d, const rtg_op_s* op, const rtg_sk_s* sk, int m, int bf16,
     }
 }
 
-// Kernel arguments are copied at launch, so host-side staging can be
-// released as soon as the launch call returns (and the copies are
-// capturable in a graph).
+// Host-to-device copies of a plan's descriptors, in stream order.  Under
+// stream capture they travel by value as kernel arguments (3 KB per launch),
+// so that every replay of the graph writes the captured contents.  Otherwise
+// one asynchronous copy from a pinned staging buffer: four buffers per
+// device in turn, each reused only once the event recorded behind its last
+// copy has completed.
 struct Blob {
     unsigned char b[3072];
 };
@@ -239,7 +242,20 @@ __global__ void k_store(Blob blob, unsigned char* dst, int nbytes) {
     for (int i = threadIdx.x; i < nbytes; i += blockDim.x) dst[i] = blob.b[i];
 }
 
-int upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
+constexpr int STAGE_DEVICES = 16, STAGE_SLOTS = 4;
+struct Staging {
+    std::mutex mu;
+    void* host[STAGE_DEVICES][STAGE_SLOTS] = {};
+    size_t cap[STAGE_DEVICES][STAGE_SLOTS] = {};
+    hipEvent_t ev[STAGE_DEVICES][STAGE_SLOTS] = {};
+    int next[STAGE_DEVICES] = {};
+};
+Staging g_staging;
+// set around the calls of an entry point that may not allocate (the staging
+// buffers are allocated on first use): its uploads go by value
+thread_local bool t_upload_by_value = false;
+
+int upload_by_value(void* dst, const void* src, size_t bytes, hipStream_t s) {
     const unsigned char* p = (const unsigned char*)src;
     for (size_t off = 0; off < bytes; off += sizeof(Blob)) {
         Blob blob;
@@ -248,6 +264,33 @@ int upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
         hipLaunchKernelGGL(k_store, dim3(1), dim3(256), 0, s, blob, (unsigned char*)dst + off, (int)nb);
     }
     return hipGetLastError() == hipSuccess ? RTG_OK : RTG_E_HIP;
+}
+
+int upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess) return RTG_E_HIP;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return RTG_E_HIP;
+    if (t_upload_by_value || cs != hipStreamCaptureStatusNone || dev < 0 || dev >= STAGE_DEVICES)
+        return upload_by_value(dst, src, bytes, s);
+    std::lock_guard<std::mutex> lock(g_staging.mu);
+    const int k = g_staging.next[dev];
+    g_staging.next[dev] = (k + 1) % STAGE_SLOTS;
+    hipEvent_t& ev = g_staging.ev[dev][k];
+    if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return RTG_E_HIP;
+    if (hipEventSynchronize(ev) != hipSuccess) return RTG_E_HIP;   // the buffer's previous copy is done
+    void*& h = g_staging.host[dev][k];
+    if (g_staging.cap[dev][k] < bytes) {
+        if (h) (void)hipHostFree(h);
+        h = nullptr;
+        g_staging.cap[dev][k] = 0;
+        const size_t cap = std::max<size_t>(bytes, 64 << 10);
+        if (hipHostMalloc(&h, cap, hipHostMallocDefault) != hipSuccess) return RTG_E_HIP;
+        g_staging.cap[dev][k] = cap;
+    }
+    std::memcpy(h, src, bytes);
+    if (hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, s) != hipSuccess) return RTG_E_HIP;
+    return hipEventRecord(ev, s) == hipSuccess ? RTG_OK : RTG_E_HIP;
 }
 
 struct Plan {
@@ -366,8 +409,11 @@ int build_plan(std::vector<Desc>& descs, void* ws, hipStream_t s, Plan& plan, in
     const size_t nd = descs.size();
     plan.d_starts = (int*)(base + align_up(nd * (restart ? 2 : 1) * sizeof(Desc)));
     plan.d_sched = (int*)((char*)plan.d_starts + align_up((size_t)NKIND * (count + 1) * sizeof(int)));
-    int rc = upload(plan.d_desc, descs.data(), nd * sizeof(Desc), s);
-    if (rc) return rc;
+    // descriptors, the restart cycles' copies and the prefix tables as one
+    // image of the region they occupy: a single upload
+    const size_t starts_off = (size_t)((char*)plan.d_starts - base);
+    std::vector<unsigned char> image(starts_off + starts.size() * sizeof(int), 0);
+    std::memcpy(image.data(), descs.data(), nd * sizeof(Desc));
     if (restart) {
         std::vector<Desc> rd(descs);
         for (auto& d : rd) {
@@ -375,9 +421,10 @@ int build_plan(std::vector<Desc>& descs, void* ws, hipStream_t s, Plan& plan, in
             d.R0src = d.W;
         }
         plan.d_desc_r = plan.d_desc + nd;
-        if ((rc = upload(plan.d_desc_r, rd.data(), nd * sizeof(Desc), s))) return rc;
+        std::memcpy(image.data() + nd * sizeof(Desc), rd.data(), nd * sizeof(Desc));
     }
-    return upload(plan.d_starts, starts.data(), starts.size() * sizeof(int), s);
+    std::memcpy(image.data() + starts_off, starts.data(), starts.size() * sizeof(int));
+    return upload(base, image.data(), image.size(), s);
 }
 
 const int* starts_of(const Plan& plan, int kind, int count) {
@@ -401,8 +448,11 @@ struct EventTiming {
             pool.pop_back();
             return e;
         }
+        // timing-only events: recording one needs no system-scope release
+        // (a cache write-back and invalidation before the next launch, which
+        // would otherwise sit between every pair of timed launches)
         hipEvent_t e = nullptr;
-        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
         return e;
     }
 };
@@ -969,7 +1019,12 @@ int rtg_sketch_noalloc(rtg_sk sk, int x_dtype, const void* X, float* SX, void* s
     if (rc) return rc;
     // the same launches as rtg_sketch, on the device array: nothing in it
     // has to start at zero (the descriptor and the prefix table are uploaded
-    // by every call, and every tile writes its whole partial sketch)
+    // by every call, as kernel arguments, and every tile writes its whole
+    // partial sketch)
+    struct ByValue {
+        ByValue() { t_upload_by_value = true; }
+        ~ByValue() { t_upload_by_value = false; }
+    } by_value;
     return rtg_sketch(sk, x_dtype, X, SX, ws, SKETCH_SCRATCH_BYTES, stream);
 }
 
