@@ -256,15 +256,22 @@ __device__ __forceinline__ void mode2_partials(const float* Ys, int wave, int la
                 Bv[ks] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
             }
         }
+        // the transposed tile (Om2 rows as the A operand): lane (m16, kq)
+        // then holds P[a = m16][b = 4 kq .. 4 kq + 3] of the 16 x 16 block,
+        // four consecutive floats of one row -- one 16-byte store
         f4v pacc = f4v{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ks = 0; ks < TC / 4; ++ks)
-            pacc = __builtin_amdgcn_mfma_f32_16x16x4f32(Ys[(16 * t + m16) * YP + 4 * ks + kq], Bv[ks], pacc, 0, 0, 0);
+            pacc = __builtin_amdgcn_mfma_f32_16x16x4f32(Bv[ks], Ys[(16 * t + m16) * YP + 4 * ks + kq], pacc, 0, 0, 0);
         float* P = half ? P1 : P0;
+        const int ar = 16 * (t - half * RT) + m16;
+        const int b0 = 16 * rt2 + 4 * kq;
+        if ((l2 & 3) == 0) {
+            if (ar < l1 && b0 < l2) *gptr_w((f4v*)(P + (size_t)ar * l2 + b0)) = pacc;
+        } else {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int ar = 16 * (t - half * RT) + 4 * kq + i;
-            if (ar < l1 && bcol < l2) *gptr_w(P + (size_t)ar * l2 + bcol) = pacc[i];
+            for (int i = 0; i < 4; ++i)
+                if (ar < l1 && b0 + i < l2) *gptr_w(P + (size_t)ar * l2 + b0 + i) = pacc[i];
         }
     }
 }
