@@ -346,15 +346,26 @@ __device__ __forceinline__ void gram_task(const Desc* __restrict__ descs, const 
     // (a general PSF: the W partials are those of W itself, mode 3 is Om3)
     // (the split form reduces through the LDS of the G block, which only the
     // tail fills, after the barrier below)
+    // (the start step of an unnormalised V_1 reads that tensor's partials)
+    const float* p_start = (mode == GM_START && d.lazy_v1) ? d.PV : d.PW;
     if (split) {
         if (mode == GM_STEP || mode == GM_GK)
             finish_sketches_split<2>(d, q0, qn, d.PW, d.st ? om3 : d.om3t, s_s, d.PV, om3, s_v, (float*)sG);
-        else finish_sketches_split<1>(d, q0, qn, d.PW, om3, s_s, nullptr, nullptr, nullptr, (float*)sG);
+        else finish_sketches_split<1>(d, q0, qn, p_start, om3, s_s, nullptr, nullptr, nullptr, (float*)sG);
     } else if (mode == GM_STEP || mode == GM_GK)
         finish_sketches<2>(d, q0, qn, d.PW, d.st ? om3 : d.om3t, (d.st || d.has_om3) ? -1 : d.rB, s_s, d.PV, om3,
                            -1, s_v);
-    else finish_sketches<1>(d, q0, qn, d.PW, om3, -1, s_s, nullptr, nullptr, -1, nullptr);
+    else finish_sketches<1>(d, q0, qn, p_start, om3, -1, s_s, nullptr, nullptr, -1, nullptr);
     __syncthreads();
+    if (mode == GM_STEP && j == 1 && d.lazy_v1) {
+        // V_1 is stored unnormalised: S(V_1) and S(Phi(V_1)) scale by 1 / beta
+        const float ib = (float)(1.0 / d.scal[SC_BETA]);
+        for (int e = tid; e < E; e += 256) {
+            s_s[e] *= ib;
+            s_v[e] *= ib;
+        }
+        __syncthreads();
+    }
 
     if (mode == GM_SKETCH_OUT) {
         const int l1 = d.l1, l2 = d.l2;
@@ -763,9 +774,13 @@ __device__ __forceinline__ void gram_task(const Desc* __restrict__ descs, const 
         gvec[j] = -sj * gj;
         const double res_ls = fabs(gvec[j]);
         sc[SC_RESLS] = res_ls;
-        // coefficients of the orthogonalisation / normalisation
-        for (int i = 0; i < j; ++i) d.coef[i] = (float)hs[i];
-        d.coef[MMAX + 1] = hn > 0.0 ? (float)(1.0 / hn) : 0.f;
+        // coefficients of the orthogonalisation / normalisation (an
+        // unnormalised stored V_1 = beta V_1 takes 1 / beta: in the scale at
+        // step 1, where it is also the tensor the operator is applied to, and
+        // in its own coefficient later)
+        const double ib = d.lazy_v1 ? 1.0 / sc[SC_BETA] : 1.0;
+        for (int i = 0; i < j; ++i) d.coef[i] = (float)(hs[i] * ((i == 0 && j >= 2) ? ib : 1.0));
+        d.coef[MMAX + 1] = hn > 0.0 ? (float)((j == 1 ? ib : 1.0) / hn) : 0.f;
         // stopping decisions
         if (hn <= d.bd_tol * rho) {
             st[ST_FLAGS] |= RTG_F_BREAKDOWN;

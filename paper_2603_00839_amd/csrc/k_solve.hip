@@ -286,7 +286,8 @@ __global__ void __launch_bounds__(1024) k_solve(const Desc* __restrict__ descs) 
         double yv = 0.0;
         for (int i = 0; i < k; ++i) yv += Ws[i * LD + tid] * fco[i];
         d.y[tid] = yv;
-        d.coef[tid] = (float)(-yv);
+        // (a V_1 stored unnormalised carries its 1 / beta in its coefficient)
+        d.coef[tid] = (float)(-yv * ((d.lazy_v1 && tid == 0) ? 1.0 / beta : 1.0));
         ok = isfinite(yv);
     }
     const int allok = __syncthreads_and(ok ? 1 : 0);
@@ -346,6 +347,7 @@ __global__ void k_init(const Desc* __restrict__ descs, int cycle, int* sched) {
         d.state[tid] = (tid == ST_ACTIVE) ? 1 : ((tid == ST_FLAGS && d.fallback) ? RTG_F_FALLBACK : 0);
     }
     if (tid < NSCAL) d.scal[tid] = 0.0;
+    if (tid == 0) d.coef[MMAX + 1] = 1.f;   // the scale of a V_1 formed before the start step
     const int m = d.m;
     for (int e = tid; e < (m + 1) * m; e += blockDim.x) d.H[e] = 0.0;
     for (int e = tid; e < 3 * m + 1; e += blockDim.x) d.gv[e] = 0.0;

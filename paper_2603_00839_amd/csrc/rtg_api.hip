@@ -302,6 +302,7 @@ struct Plan {
     int compose_max;   // largest entry count of the composed matrices (mode 1 padded to operand tiles)
     int phi_jt;        // output channels per operator tile (one choice per batch)
     bool step_ok;      // the fused step kernel applies (32-bit byte offsets into a basis vector)
+    bool lazy_v1;      // V_1 stored unnormalised (Desc::lazy_v1)
     int toeplitz;      // every problem's bands are Toeplitz
     int unsketched;    // every problem's sketch is the identity (a batch is all one or all the other)
     int stencil;       // every problem's operator is a general PSF (all or none)
@@ -323,7 +324,7 @@ struct Plan {
 // tune: the launch shapes (resolved, no -1), clamped to what the batch can
 // use; null for the library defaults.
 int build_plan(std::vector<Desc>& descs, void* ws, hipStream_t s, Plan& plan, int nsides = 1,
-               bool restart = false, const rtg_tune* tune = nullptr) {
+               bool restart = false, const rtg_tune* tune = nullptr, bool solve = false) {
     const int count = (int)descs.size() / nsides;
     std::vector<int> starts((size_t)NKIND * (count + 1), 0);
     int maxJ = 1;
@@ -386,6 +387,12 @@ int build_plan(std::vector<Desc>& descs, void* ws, hipStream_t s, Plan& plan, in
         if (!d.unsketched) plan.l1max = std::max(plan.l1max, d.l1);
         plan.compose_max = std::max(plan.compose_max, (int)compose_mode1_entries(d.l1, d.I1) + d.l2 * d.I2 + d.l3 * d.J);
     }
+    // one pass over R0 forms and sketches V_1 (unnormalised) where the
+    // basis stays internal (a solve) and the fused step forms the rest
+    plan.lazy_v1 = solve && nsides == 1 && !restart && !plan.unsketched && !plan.stencil && plan.step_ok &&
+                   !descs.empty();
+    for (auto& d : descs) plan.lazy_v1 = plan.lazy_v1 && d.bf16 && !d.gk;
+    for (auto& d : descs) d.lazy_v1 = plan.lazy_v1 ? 1 : 0;
     plan.phi_toep = plan.toeplitz;
     plan.step_toep = plan.toeplitz;
     plan.tile_rows = 2;
@@ -578,9 +585,16 @@ int run_solver(const Plan& plan, int count, int mmax, int bf16, bool any_x0, boo
         return RTG_OK;
     }
     if (any_x0) RTG_TIMED(0, launch_phi(dd, sp, count, plan.total[KIND_PHI], PS_X0, 0, plan.rmax, plan.phi_jt, 0, s, 0, plan.phi_dma, plan.phi_toep));
-    RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_SKETCH_SRC, 0, 0, bf16, 0, plan.l1max, s, 0, plan.tile_rows, plan.skbf));
-    RTG_TIMED(2, launch_gram(dd, sg, count, plan.total[KIND_GRAM], GM_START, cycle, nullptr, s));
-    RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_NEWV, 0, 0, bf16, 0, plan.l1max, s, 0, plan.tile_rows, plan.skbf));
+    if (plan.lazy_v1 && cycle == 0) {
+        // V_1 = R0 (scale 1, set by the init kernel) with both its sketches
+        // in one pass; the start step takes beta from S(V_1)
+        RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_NEWV, 0, 0, bf16, 0, plan.l1max, s, 0, plan.tile_rows, plan.skbf));
+        RTG_TIMED(2, launch_gram(dd, sg, count, plan.total[KIND_GRAM], GM_START, cycle, nullptr, s));
+    } else {
+        RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_SKETCH_SRC, 0, 0, bf16, 0, plan.l1max, s, 0, plan.tile_rows, plan.skbf));
+        RTG_TIMED(2, launch_gram(dd, sg, count, plan.total[KIND_GRAM], GM_START, cycle, nullptr, s));
+        RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_NEWV, 0, 0, bf16, 0, plan.l1max, s, 0, plan.tile_rows, plan.skbf));
+    }
     for (int j = 1; j <= mmax; ++j) {
         // S(V_j) and S(Phi(V_j)) come from the pass that formed V_j.  With a
         // bfloat16 basis the step kernel recomputes Phi(V_j) tile by tile (W
@@ -1319,7 +1333,7 @@ int solve_batched(int count, const rtg_problem* probs, void* ws, size_t ws_bytes
     rtg_tune tune;
     if ((rc = resolve_tune(tune_caps(count, probs), lookup_tune(count, probs), tune))) return rc;
     Plan plan;
-    if ((rc = build_plan(bt.descs, ws, s, plan, bt.nsides, bt.rmax > 0, &tune))) return rc;
+    if ((rc = build_plan(bt.descs, ws, s, plan, bt.nsides, bt.rmax > 0, &tune, true))) return rc;
     if (bt.gk) return run_gk(plan, count, bt.mmax, bt.bf16, bt.any_x0, true, s);
     if ((rc = run_solver(plan, count, bt.mmax, bt.bf16, bt.any_x0, true, false, s))) return rc;
     // restarted RTG-GMRES: every cycle is launched for the whole batch; a

@@ -65,6 +65,10 @@ struct Desc {
                         // (operator Phi^T, transposed bands); 0 = RTG-GMRES
     int fallback;       // a re-solve by the plain solver after a failed warm-started solve:
                         // RTG_F_FALLBACK is set in its flags from the start
+    int lazy_v1;        // V_1 is stored as R0 itself (bfloat16), not R0 / beta: the pass that
+                        // forms it also sketches it, and beta = ||S(V_1)|| is applied where
+                        // V_1 is used (its sketches, its multi-AXPY coefficient and the
+                        // assembly); bfloat16-basis solves with the fused step only
     long long n;        // I1*I2*J
     long long L;        // l1*l2*l3
     // operator / sketch (device)
