@@ -300,22 +300,44 @@ def time_variant(plan, steps, warmup, rtg, torch, kind, bytes_of, pre=None):
     }
 
 
+def source_digest(kernel_src):
+    """SHA-256 of a kernel source followed by the local headers it includes
+    (recursively, each once, in the order met; paths relative to the
+    including file), so that a change to a shared header also counts."""
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    seen = set()
+
+    def add(path):
+        path = os.path.normpath(path)
+        if path in seen or not os.path.exists(path):
+            return
+        seen.add(path)
+        with open(path, "rb") as f:
+            data = f.read()
+        h.update(data)
+        for inc in re.findall(rb'#include\s+"([^"]+)"', data):
+            add(os.path.join(os.path.dirname(path), inc.decode()))
+
+    add(os.path.join(ROOT, "paper_2603_00839_amd", "csrc", kernel_src))
+    return h.hexdigest()
+
+
 def recorded_traffic(kernel_src, variant, tune, batch):
     """HBM traffic per launch measured with rocprofv3 counters (FETCH_SIZE and
     WRITE_SIZE, scaled by a copy-kernel calibration) and recorded with the
-    SHA-256 of the kernel source it was measured on; None when the kernel
-    source has changed since, when nothing was recorded, when the record is
-    of another workload (the record names the variant and the batch size) or
-    of other launch shapes than this run's (the record names them)."""
-    import hashlib
+    digest of the kernel source and its headers it was measured on
+    (source_digest); None when either has changed since, when nothing was
+    recorded, when the record is of another workload (the record names the
+    variant and the batch size) or of other launch shapes than this run's
+    (the record names them)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    src = os.path.join(ROOT, "paper_2603_00839_amd", "csrc", kernel_src)
-    with open(src, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
+    sha = source_digest(kernel_src)
     ent = rec.get(kernel_src)
     if not ent or ent.get("source_sha256") != sha or ent.get("variant", "bf16_warm") != variant:
         return None

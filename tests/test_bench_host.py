@@ -51,7 +51,11 @@ def test_recorded_traffic_needs_the_same_source_variant_batch_and_shapes(tmp_pat
     shutil.copy(src, tmp_path / "paper_2603_00839_amd" / "csrc" / "k_step.hip")
     shutil.copy(os.path.join(ROOT, "paper_2603_00839_amd", "csrc", "k_tile.hip"),
                 tmp_path / "paper_2603_00839_amd" / "csrc" / "k_tile.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    hdr = os.path.join(ROOT, "paper_2603_00839_amd", "csrc", "rtg_internal.h")
+    shutil.copy(hdr, tmp_path / "paper_2603_00839_amd" / "csrc" / "rtg_internal.h")
+    # the step kernel's source followed by the one local header it includes
+    # (the public header it reaches through "../../include" is absent here)
+    sha = hashlib.sha256(open(src, "rb").read() + open(hdr, "rb").read()).hexdigest()
     shapes = dict(phi_jt=4, phi_slab=1, phi_toeplitz=1, tile_rows=2, step_rows=2, step_toeplitz=1)
     rec = {"k_step.hip": {"source_sha256": sha, "variant": "bf16_warm", "batch": 32, "launch_shapes": shapes,
                           "bytes_per_launch": 123.0}}
@@ -63,6 +67,11 @@ def test_recorded_traffic_needs_the_same_source_variant_batch_and_shapes(tmp_pat
     assert bench.recorded_traffic("k_step.hip", "bf16_warm", tune, 16) is None
     assert bench.recorded_traffic("k_step.hip", "bf16_warm", {**tune, "step_rows": 4}, 32) is None
     assert bench.recorded_traffic("k_tile.hip", "bf16_warm", tune, 32) is None     # nothing recorded for it
+    with open(tmp_path / "paper_2603_00839_amd" / "csrc" / "rtg_internal.h", "a") as f:
+        f.write("\n// changed\n")
+    assert bench.recorded_traffic("k_step.hip", "bf16_warm", tune, 32) is None   # a header of the kernel changed
+    shutil.copy(hdr, tmp_path / "paper_2603_00839_amd" / "csrc" / "rtg_internal.h")
+    assert bench.recorded_traffic("k_step.hip", "bf16_warm", tune, 32) == 123.0
     with open(tmp_path / "paper_2603_00839_amd" / "csrc" / "k_step.hip", "a") as f:
         f.write("\n// changed\n")
     assert bench.recorded_traffic("k_step.hip", "bf16_warm", tune, 32) is None
