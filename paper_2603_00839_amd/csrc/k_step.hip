@@ -16,9 +16,10 @@
 //    asynchronous global-to-LDS loads issued while the previous block is
 //    processed.  Chunks outside the tensor are fetched from past the end of
 //    the buffer range, which reads zeros (the zero boundary condition);
-//  * i1 pass: a lane per slab column mixes the input channels,
-//    U = sum_k B[k, c] V_j[k] (mode products commute), and blurs along i1
-//    with wave-uniform band coefficients, into Z (LDS, float);
+//  * i1 pass on MFMA: each input channel's slab is blurred along i1 (band
+//    coefficients as a bfloat16 high + middle pair, float32 accumulation)
+//    and mixed in with its weight, Z = sum_k B[k, c] A1 V_j[k] (mode products
+//    commute), into LDS as float;
 //  * i2 pass: a lane per row blurs eight columns of Z, which leaves the W
 //    tile in registers in the basis' own layout (lane = row);
 //  * multi-AXPY with V_1..V_j (two terms in flight), scale, round to
@@ -27,7 +28,9 @@
 //    stacked rows [Om1 ; Om1 A1] (the composed matrix split into high and
 //    low bfloat16 parts).
 // After the last block the mode-2 contraction with Om2 / Om2 A2 writes two
-// l1 x l2 partials per tile, which the sketched-Gram kernel reduces.
+// l1 x l2 partials per tile, which the sketched-Gram kernel reduces; for
+// l2 <= 64 the wave's Om2 columns are requested before the mode-1 results
+// go to LDS.
 #include "rtg_internal.h"
 
 namespace rtg {
@@ -200,18 +203,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     // R8 + R], covered by NKB K-blocks of 32 rows starting at kstart(q)
     // (clamped to the slab; rows an earlier K-block covers get coefficient
     // zero).  A operand: the A1 coefficient of output row 16 w + m16 and slab
-    // row kstart(q) + 8 kq + e, split into three bfloat16 terms (high, middle,
-    // low: their sum is the float32 coefficient to about 2^-24); B operand:
+    // row kstart(q) + 8 kq + e, split into two bfloat16 terms (high and
+    // middle: their sum is the float32 coefficient to about 2^-17 of its
+    // size, far below the bfloat16 rounding of the stored basis); B operand:
     // 8 consecutive slab rows of one column, one 16-byte LDS chunk of the raw
     // bfloat16 slab.  The products are exact and accumulate in float32.
     auto kstart = [&](int q) { return min(16 * wave + 32 * q, SR - 32); };
-    u4 afr[NKB][3];
+    u4 afr[NKB][2];
     auto make_frags = [&]() {
 #pragma unroll
         for (int q = 0; q < NKB; ++q) {
             const int s0 = kstart(q);
             const int covered = q > 0 ? kstart(q - 1) + 32 : 0;   // rows below this are an earlier K-block's
-            unsigned hw[4] = {0u, 0u, 0u, 0u}, mw[4] = {0u, 0u, 0u, 0u}, lw[4] = {0u, 0u, 0u, 0u};
+            unsigned hw[4] = {0u, 0u, 0u, 0u}, mw[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const int sr = s0 + 8 * kq + e;
@@ -226,15 +230,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
                 const bf16_t h = f2bf(cf);
                 const float r1v = cf - bf2f(h);
                 const bf16_t mm = f2bf(r1v);
-                const bf16_t lo = f2bf(r1v - bf2f(mm));
                 const int sh = (e & 1) * 16;
                 hw[e >> 1] |= (unsigned)h << sh;
                 mw[e >> 1] |= (unsigned)mm << sh;
-                lw[e >> 1] |= (unsigned)lo << sh;
             }
             afr[q][0] = u4{hw[0], hw[1], hw[2], hw[3]};
             afr[q][1] = u4{mw[0], mw[1], mw[2], mw[3]};
-            afr[q][2] = u4{lw[0], lw[1], lw[2], lw[3]};
         }
     };
     if constexpr (TOEP) {
@@ -306,7 +307,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
 #pragma unroll
                     for (int q = 0; q < NKB; ++q)
 #pragma unroll
-                        for (int t = 0; t < 3; ++t)
+                        for (int t = 0; t < 2; ++t)
                             a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, afr[q][t]),
                                                                          __builtin_bit_cast(bf8, bv[q][n]), a, 0, 0, 0);
 #pragma unroll
@@ -453,6 +454,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     }
 
     // ---- mode-1 results to LDS, then the mode-2 contraction
+    const bool m2fast = ((l2 + 15) >> 4) == 4;
+    float B0[TC / 4], B1[TC / 4];
+    if (m2fast) mode2_load4<TC>(wave, lane, l2, I2, i20, ncol, d.om2, d.om2t, B0, B1);
     __syncthreads();
 #pragma unroll
     for (int u2 = 0; u2 < RPW; ++u2) {
@@ -464,8 +468,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
             for (int i = 0; i < 4; ++i) Ys[(16 * t + 4 * kq + i) * YP + 16 * g + m16] = acc[u2][g][i];
     }
     __syncthreads();
-    mode2_partials<TC, YP>(Ys, wave, lane, NRT, RT, l1, l2, I2, i20, ncol, d.om2, d.om2t,
-                           d.PV + (size_t)tile * l1 * l2, d.PW + (size_t)tile * l1 * l2);
+    if (m2fast)
+        mode2_partials4<TC, YP>(Ys, wave, lane, RT, l1, l2, B0, B1, d.PV + (size_t)tile * l1 * l2,
+                                d.PW + (size_t)tile * l1 * l2);
+    else
+        mode2_partials<TC, YP>(Ys, wave, lane, NRT, RT, l1, l2, I2, i20, ncol, d.om2, d.om2t,
+                               d.PV + (size_t)tile * l1 * l2, d.PW + (size_t)tile * l1 * l2);
 }
 
 // Only bfloat16-basis variants exist: with a float32 basis the solver forms
