@@ -259,9 +259,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
         const unsigned aoff = aok ? (unsigned)(acol * I1 + i10 + arow) * 2u : STEP_OOB;
         // the block's first STEP_PF basis terms are requested now, so that they
         // arrive while the operator is applied
+        // Wave priorities (s_setprio) among the three workgroups of a CU: a
+        // wave issuing its memory requests goes first (2), so that their
+        // latency starts early; a wave in a run of matrix products next (1);
+        // the rest at 0.
         u4 pre[STEP_PF];
+        __builtin_amdgcn_s_setprio(2);
 #pragma unroll
         for (int i = 0; i < STEP_PF; ++i) pre[i] = i < nterms ? load_term(i, aoff) : u4{0u, 0u, 0u, 0u};
+        __builtin_amdgcn_s_setprio(0);
         // ---- i1 product over groups of NKR input channels, each channel's
         // product mixed in with its weight B[k, c] (mode products commute):
         //      Z[col][row] = sum_k B[k, c] sum_i' A1[i1, i'] V_j[k][i'][col]
@@ -289,6 +295,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
             __syncthreads();
             if constexpr (!TOEP)
                 if (k0 == klo) make_frags();               // this block's band rows
+            __builtin_amdgcn_s_setprio(1);
 #pragma unroll
             for (int kk = 0; kk < NKR; ++kk) {
                 if (k0 + kk >= khi) break;
@@ -315,6 +322,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
                 }
             }
         }
+        __builtin_amdgcn_s_setprio(0);
         // lane: rows 16 w + 4 kq .. + 3 of slab column 16 n + m16
 #pragma unroll
         for (int n = 0; n < NT; ++n) {
@@ -322,10 +330,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
             if (col < SC) *(f4*)(Z + col * ZRP + 16 * wave + 4 * kq) = zacc[n];
         }
         __syncthreads();                                   // Z complete; slab and band rows free
+        __builtin_amdgcn_s_setprio(2);
         if (rb + 1 < nrb) {
             dma_slab(rb + 1, klo);
             if constexpr (!TOEP) dma_bands(rb + 1);
         }
+        __builtin_amdgcn_s_setprio(0);
         // ---- i2 pass (lane = row, eight columns per wave): the W tile
         float x[8];
         {
@@ -449,8 +459,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
                 }
             }
         };
+        __builtin_amdgcn_s_setprio(1);
         mfma_block(0, A0);
         if (nkb > 1) mfma_block(1, A1);
+        __builtin_amdgcn_s_setprio(0);
     }
 
     // ---- mode-1 results to LDS, then the mode-2 contraction
