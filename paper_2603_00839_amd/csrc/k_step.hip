@@ -468,7 +468,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     // ---- mode-1 results to LDS, then the mode-2 contraction
     const bool m2fast = ((l2 + 15) >> 4) == 4;
     float B0[TC / 4], B1[TC / 4];
-    if (m2fast) mode2_load4<TC>(wave, lane, l2, I2, i20, ncol, d.om2, d.om2t, B0, B1);
+    if (m2fast) mode2_load4<TC>(wave, lane, l2, I2, i20, ncol, NRT, RT, d.om2, d.om2t, B0, B1);
     __syncthreads();
 #pragma unroll
     for (int u2 = 0; u2 < RPW; ++u2) {
@@ -481,7 +481,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     }
     __syncthreads();
     if (m2fast)
-        mode2_partials4<TC, YP>(Ys, wave, lane, RT, l1, l2, B0, B1, d.PV + (size_t)tile * l1 * l2,
+        mode2_partials4<TC, YP>(Ys, wave, lane, NRT, RT, l1, l2, B0, B1, d.PV + (size_t)tile * l1 * l2,
                                 d.PW + (size_t)tile * l1 * l2);
     else
         mode2_partials<TC, YP>(Ys, wave, lane, NRT, RT, l1, l2, I2, i20, ncol, d.om2, d.om2t,

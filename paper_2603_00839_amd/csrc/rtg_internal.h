@@ -284,26 +284,36 @@ __device__ __forceinline__ void mode2_partials(const float* Ys, int wave, int la
 // of Om2, one per wave): the wave's Om2 and Om2 A2 columns are requested
 // together, before the mode-1 results reach LDS, so that one memory latency
 // overlaps the barriers instead of two following them.
+// B1 (the Om2 A2 columns) is loaded only for a dual sketch (NRT > RT): a
+// sketch-only descriptor has no composed matrices.
 template <int TC>
-__device__ __forceinline__ void mode2_load4(int wave, int lane, int l2, int I2, int i20, int ncol,
-                                            const float* om2, const float* om2t, float (&B0)[TC / 4],
+__device__ __forceinline__ void mode2_load4(int wave, int lane, int l2, int I2, int i20, int ncol, int NRT,
+                                            int RT, const float* om2, const float* om2t, float (&B0)[TC / 4],
                                             float (&B1)[TC / 4]) {
     const int m16 = lane & 15, kq = lane >> 4;
     const int obytes = l2 * I2 * 4;
     const int bcol = 16 * wave + m16;
     const auto r0 = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(om2), (short)0, obytes, 0x00020000);
-    const auto r1 = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(om2t), (short)0, obytes, 0x00020000);
 #pragma unroll
     for (int ks = 0; ks < TC / 4; ++ks) {
         const int k = 4 * ks + kq;
         const unsigned off = (bcol < l2 && k < ncol) ? (unsigned)(bcol * I2 + i20 + k) * 4u : 0x80000000u;
         B0[ks] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r0, off, 0, 0));
-        B1[ks] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r1, off, 0, 0));
+        B1[ks] = 0.f;
+    }
+    if (NRT > RT) {
+        const auto r1 = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(om2t), (short)0, obytes, 0x00020000);
+#pragma unroll
+        for (int ks = 0; ks < TC / 4; ++ks) {
+            const int k = 4 * ks + kq;
+            const unsigned off = (bcol < l2 && k < ncol) ? (unsigned)(bcol * I2 + i20 + k) * 4u : 0x80000000u;
+            B1[ks] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r1, off, 0, 0));
+        }
     }
 }
 
 template <int TC, int YP>
-__device__ __forceinline__ void mode2_partials4(const float* Ys, int wave, int lane, int RT, int l1, int l2,
+__device__ __forceinline__ void mode2_partials4(const float* Ys, int wave, int lane, int NRT, int RT, int l1, int l2,
                                                 const float (&B0)[TC / 4], const float (&B1)[TC / 4], float* P0,
                                                 float* P1) {
     typedef float f4v __attribute__((ext_vector_type(4)));
@@ -323,7 +333,8 @@ __device__ __forceinline__ void mode2_partials4(const float* Ys, int wave, int l
         }
     };
     for (int t = 0; t < RT; ++t) one(t, B0, P0, 16 * t + m16);
-    for (int t = 0; t < RT; ++t) one(RT + t, B1, P1, 16 * t + m16);
+    if (NRT > RT)
+        for (int t = 0; t < RT; ++t) one(RT + t, B1, P1, 16 * t + m16);
 }
 
 template <typename T>
