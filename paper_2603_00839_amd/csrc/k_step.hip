@@ -93,6 +93,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     // Separate LDS arrays: reads of one are not held back by the compiler
     // for asynchronous loads still in flight into another.
     __shared__ float coef_s[MMAX + 2];
+    __shared__ float bw_s[2 * RMAX_B + 1];              // B[k, c] for the input channels klo .. khi - 1
     __shared__ __attribute__((aligned(16))) unsigned char su[SM::UB];
     __shared__ __attribute__((aligned(16))) float Z[SC * ZRP];    // [col][row] after the i1 product
     __shared__ __attribute__((aligned(16))) float Wt[TC * WTP];   // [col][row]: the W tile, for the multi-AXPY
@@ -132,6 +133,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
 
     const int nterms = j;
     for (int i = tid; i < nterms; i += 256) coef_s[i] = d.coef[i];
+    if (tid < khi - klo) bw_s[tid] = *gptr(d.bb + (size_t)(klo + tid) * wB + rB + (c - klo - tid));
     const float scale = d.coef[MMAX + 1];
     if constexpr (TOEP) {
         if (tid < WP) {
@@ -192,11 +194,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
         if constexpr (NA % 256 != 0)
             if (tid < NA % 256) one(NA / 256);
     };
-    auto bweight = [&](int k) {
-        const int kc = min(k, khi - 1);
-        const float bkc = *gptr(d.bb + (size_t)kc * wB + rB + (c - kc));
-        return k < khi ? bkc : 0.f;
-    };
+    // the channel weights come from LDS: a vector-memory load here would make
+    // the i1 pass wait for every load issued before it (the counter runs in
+    // issue order), the block's basis terms included
+    auto bweight = [&](int k) { return k < khi ? bw_s[k - klo] : 0.f; };
 
     // ---- the i1 product on MFMA.  Wave w owns output rows 16 w .. 16 w + 15
     // of every block; their inputs are slab rows [16 w + R8 - R, 16 w + 15 +
@@ -330,12 +331,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
             if (col < SC) *(f4*)(Z + col * ZRP + 16 * wave + 4 * kq) = zacc[n];
         }
         __syncthreads();                                   // Z complete; slab and band rows free
-        __builtin_amdgcn_s_setprio(2);
-        if (rb + 1 < nrb) {
-            dma_slab(rb + 1, klo);
-            if constexpr (!TOEP) dma_bands(rb + 1);
-        }
-        __builtin_amdgcn_s_setprio(0);
         // ---- i2 pass (lane = row, eight columns per wave): the W tile
         float x[8];
         {
@@ -401,6 +396,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
         load_a(0, A0);
         if (nkb > 1) load_a(1, A1);
         __syncthreads();                                   // the W tile is in LDS
+        // the next block's slab and band rows: requested here rather than
+        // after the previous barrier, since a barrier's release fence makes
+        // every asynchronous load to LDS still in flight land first
+        __builtin_amdgcn_s_setprio(2);
+        if (rb + 1 < nrb) {
+            dma_slab(rb + 1, klo);
+            if constexpr (!TOEP) dma_bands(rb + 1);
+        }
+        __builtin_amdgcn_s_setprio(0);
         float w8[8];
         {
             const f4 lo4 = *(const f4*)(Wt + acol * WTP + arow);
