@@ -49,6 +49,9 @@ CASES = [
     (96, 64, 8, 6, 6, 2, 24, 24, 4, True, True, 6),
     # more steps than the Gram kernel stages in LDS (G read from global memory)
     (48, 32, 2, 3, 3, 1, 16, 8, 2, False, True, 70),
+    # the widest channel band (rB = 8: up to 17 input channels per output
+    # channel, staged in six groups of three)
+    (48, 40, 20, 3, 3, 8, 16, 16, 4, True, True, 4),
 ]
 
 
