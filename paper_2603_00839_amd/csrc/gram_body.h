@@ -269,7 +269,7 @@ __device__ __forceinline__ void gram_task(const Desc* __restrict__ descs, const 
 
     const int p = find_problem(starts, count, b);
     const Desc& d = descs[p];
-    const int wgi = b - starts[p];
+    const int wgi = uniform_int(b - starts[p]);
     const int nwg = d.ntile[KIND_GRAM];
     if ((mode == GM_STEP || mode == GM_GK) && d.state[ST_ACTIVE] == 0) return;
 

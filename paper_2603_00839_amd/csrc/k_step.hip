@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     const int b = xcd_tile(blockIdx.x, gridDim.x);
     const int p = find_problem(starts, count, b);
     const Desc& d = descs[p];
-    const int tile = b - starts[p];
+    const int tile = uniform_int(b - starts[p]);
     if (d.state[ST_ACTIVE] == 0) return;
 
     const int tid = threadIdx.x, lane = tid & 63;

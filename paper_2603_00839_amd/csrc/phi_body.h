@@ -410,7 +410,7 @@ __device__ __forceinline__ void phi_batched_task(const Desc* __restrict__ descs,
         a.C = d.C;
     }
     a.dst = d.W;
-    phi_tile<R, BF16IN, JT, ST, SL, TP>(a, b - starts[p], smem);
+    phi_tile<R, BF16IN, JT, ST, SL, TP>(a, uniform_int(b - starts[p]), smem);
 }
 
 }  // namespace rtg

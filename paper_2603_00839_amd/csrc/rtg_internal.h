@@ -137,14 +137,30 @@ __device__ __forceinline__ int block_tid() {
     return t;
 }
 
+// Lane 0's value, known to the compiler to be the same in every lane.  A
+// value that is uniform but comes from a vector memory load (a descriptor
+// field, a problem's state word) otherwise lives in vector registers, and
+// every buffer access whose resource is built from it is wrapped in a loop
+// over the distinct values of the wave's lanes.
+__device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+template <typename T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+    const unsigned long long v = (unsigned long long)p;
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return (T*)(((unsigned long long)hi << 32) | lo);
+}
+
 __device__ __forceinline__ int find_problem(const int* __restrict__ starts, int count, int b) {
-    // largest p with starts[p] <= b (starts has count+1 entries, starts[0] = 0)
+    // largest p with starts[p] <= b (starts has count+1 entries, starts[0] = 0);
+    // every lane of a wave asks for the same b, and the answer is made
+    // wave-uniform
     int lo = 0, hi = count - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
-        if (starts[mid] <= b) lo = mid; else hi = mid - 1;
+        if (uniform_int(starts[mid]) <= b) lo = mid; else hi = mid - 1;
     }
-    return lo;
+    return uniform_int(lo);
 }
 
 // Operand order of the mode-1 sketch matrices for the MFMA contractions.

@@ -102,7 +102,7 @@ __device__ __forceinline__ void tile_task(const Desc* __restrict__ descs, const 
 
     const int p = find_problem(starts, count, b);
     const Desc& d = descs[p];
-    const int tile = b - starts[p];
+    const int tile = uniform_int(b - starts[p]);
     const bool newv = (mode == TM_NEWV || mode == TM_GKNEW);
     if ((newv || mode == TM_SKETCH_W) && d.state[ST_ACTIVE] == 0) return;
     if (mode == TM_ASSEMBLE && d.state[ST_SKIP] != 0) return;   // X stays (restart cycle sat out)
@@ -123,7 +123,7 @@ __device__ __forceinline__ void tile_task(const Desc* __restrict__ descs, const 
 
     int nterms = 0;
     if (newv) nterms = nterms_arg;
-    else if (mode == TM_ASSEMBLE) nterms = d.state[ST_MEFF];
+    else if (mode == TM_ASSEMBLE) nterms = uniform_int(d.state[ST_MEFF]);
     const int first = (mode == TM_GKNEW) ? t0 : 0;   // terms [first, nterms)
     const bool do_store = (newv || mode == TM_ASSEMBLE);
     const bool do_sketch = (mode != TM_ASSEMBLE) && !d.unsketched;   // an identity sketch keeps no partials
@@ -136,6 +136,7 @@ __device__ __forceinline__ void tile_task(const Desc* __restrict__ descs, const 
     else if (mode == TM_NEWV) src = (nterms == 0) ? d.R0src : (const void*)d.W;
     else if (mode == TM_GKNEW) src = d.W;
     else src = d.X0;     // may be null: zero
+    src = uniform_ptr(src);
 
     for (int i = tid; i < nterms; i += 256) coef_s[i] = d.coef[i];
     const float scale = do_store ? d.coef[MMAX + 1] : 1.f;
