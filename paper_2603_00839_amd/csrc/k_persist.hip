@@ -185,8 +185,14 @@ __device__ __forceinline__ void publish(Pending& pd) {
     pd.held = 0;
 }
 
+// The descriptors come as a kernel argument of their own, declared
+// __restrict__ (the kernel writes through the pointers they hold, never into
+// them): their fields are then read by scalar loads, and the buffer resources
+// built from them stay in scalar registers.  Read through the argument
+// struct, they were vector loads, and every buffer access was wrapped in a
+// loop over the lanes' distinct resources.
 template <int R, bool TP, bool MB>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) k_persist(PersistArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) k_persist(PersistArgs a, const Desc* __restrict__ descs) {
     using LY = PersistLds<R, TP, MB>;
     __shared__ __attribute__((aligned(16))) unsigned char lds[LY::BYTES];
     __shared__ int s_task;
@@ -215,7 +221,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
                 const Task k = decode(a, x, t);
                 const int* starts = a.starts[k.kind];
                 const int p = find_problem(starts, a.count, k.b);
-                const Desc& d = a.descs[p];
+                const Desc& d = descs[p];
 #pragma unroll
                 for (int q = 0; q < NKIND; ++q) {
                     const int* ctr = d.state + ST_DONE + q;
@@ -232,22 +238,26 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
         if (t < 0) break;
         // the producers' stores (released before they counted in) are seen
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        const Task k = decode(a, x, t);
-        const int* starts = a.starts[k.kind];
+        Task k = decode(a, x, t);
+        k.kind = uniform_int(k.kind);
+        k.mode = uniform_int(k.mode);
+        k.arg = uniform_int(k.arg);
+        k.b = uniform_int(k.b);
+        const int* starts = uniform_ptr(a.starts[k.kind]);
         if (k.kind == KIND_PHI) {
-            phi_batched_task<R, false, 4, false, SL_VEC, TP>(a.descs, starts, a.count, k.mode, k.arg, k.b,
+            phi_batched_task<R, false, 4, false, SL_VEC, TP>(descs, starts, a.count, k.mode, k.arg, k.b,
                                                              (float*)lds);
         } else if (k.kind == KIND_TILE) {
             // a float32 source in the mixed form is split into two bfloat16
             // planes (R0); new basis tensors take one plane
             if (MB && k.mode == TM_SKETCH_SRC)
-                tile_task<false, MB, MB, 4>(a.descs, starts, a.count, k.mode, 0, 0, 0, k.b,
+                tile_task<false, MB, MB, 4>(descs, starts, a.count, k.mode, 0, 0, 0, k.b,
                                             *(TileShared<MB, MB, 4>*)lds);
             else
-                tile_task<false, MB, false, 4>(a.descs, starts, a.count, k.mode, k.arg, k.arg, 0, k.b,
+                tile_task<false, MB, false, 4>(descs, starts, a.count, k.mode, k.arg, k.arg, 0, k.b,
                                                *(TileShared<MB, false, 4>*)lds);
         } else {
-            gram_task<false>(a.descs, starts, a.count, k.mode, k.arg, nullptr, k.b, *(GramSmem*)lds);
+            gram_task<false>(descs, starts, a.count, k.mode, k.arg, nullptr, k.b, *(GramSmem*)lds);
         }
         // every wave's stores are complete (in this XCD's L2) before the
         // barrier; then one write-back of the L2 (wave 0's release at agent
@@ -256,7 +266,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
         __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
         __syncthreads();
         if (tid == 0) {
-            int* ctr = a.descs[find_problem(starts, a.count, k.b)].state + ST_DONE + k.kind;
+            int* ctr = descs[find_problem(starts, a.count, k.b)].state + ST_DONE + k.kind;
             Pending& pd = s_pend;
             int i = 0;
             while (i < pd.used && pd.ctr[i] != ctr) ++i;
@@ -276,7 +286,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
         const int left = __hip_atomic_fetch_add(sched + SCH_EXITED, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         if (left == (int)gridDim.x - 1 && ld_agent(sched + SCH_ERROR) != 0) {
             for (int p = 0; p < a.count; ++p) {
-                int* st = a.descs[p].state;
+                int* st = descs[p].state;
                 st[ST_FLAGS] |= RTG_F_TIMEOUT;
                 st[ST_MEFF] = 0;
                 st[ST_ACTIVE] = 0;
@@ -318,7 +328,7 @@ hipError_t launch_one(const PersistArgs& a, hipStream_t s) {
     }
     // every queue needs a workgroup: a multiple of eight, at least eight
     const int grid = std::max(8, resident & ~7);
-    hipLaunchKernelGGL((k_persist<R, TP, MB>), dim3(grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_persist<R, TP, MB>), dim3(grid), dim3(256), 0, s, a, a.descs);
     return hipGetLastError();
 }
 
