@@ -385,16 +385,16 @@ __global__ void k_compose(const Desc* __restrict__ descs, int nbc) {
         for (int dd = -r1; dd <= r1; ++dd) {
             const int ip = i - dd;
             const int ipc = min(max(ip, 0), I1 - 1);
-            const float om = d.skbf ? bf2f(d.om1h[(size_t)ac * I1 + ipc]) : d.om1[(size_t)ac * I1 + ipc];
-            const float w = d.a1t[(size_t)(r1 + dd) * I1 + ipc];
+            const float om = d.skbf ? bf2f(*gptr(d.om1h + (size_t)ac * I1 + ipc)) : *gptr(d.om1 + (size_t)ac * I1 + ipc);
+            const float w = *gptr(d.a1t + (size_t)(r1 + dd) * I1 + ipc);
             acc = fmaf((ip >= 0 && ip < I1) ? om : 0.f, w, acc);
         }
         acc = real ? acc : 0.f;
-        if (i < nkf * FRAG_K_F32) ((float*)d.om1t)[frag_index(a, i, nkf, FRAG_K_F32)] = acc;
+        if (i < nkf * FRAG_K_F32) *gptr_w((float*)d.om1t + frag_index(a, i, nkf, FRAG_K_F32)) = acc;
         const bf16_t hi = f2bf(acc);
         const size_t fh = frag_index(a, i, nkh, FRAG_K_BF16);
-        ((bf16_t*)d.om1th)[fh] = hi;
-        ((bf16_t*)d.om1th)[lo_plane + fh] = f2bf(acc - bf2f(hi));
+        *gptr_w((bf16_t*)d.om1th + fh) = hi;
+        *gptr_w((bf16_t*)d.om1th + lo_plane + fh) = f2bf(acc - bf2f(hi));
     } else if (e < E1 + E2) {
         const int e2 = e - E1;
         const int b = e2 / I2, i = e2 % I2;
@@ -403,20 +403,20 @@ __global__ void k_compose(const Desc* __restrict__ descs, int nbc) {
         for (int dd = -r2; dd <= r2; ++dd) {
             const int ip = i - dd;
             const int ipc = min(max(ip, 0), I2 - 1);
-            const float om = d.om2[(size_t)b * I2 + ipc];
-            const float w = d.a2t[(size_t)(r2 + dd) * I2 + ipc];
+            const float om = *gptr(d.om2 + (size_t)b * I2 + ipc);
+            const float w = *gptr(d.a2t + (size_t)(r2 + dd) * I2 + ipc);
             acc = fmaf((ip >= 0 && ip < I2) ? om : 0.f, w, acc);
         }
-        ((float*)d.om2t)[e2] = acc;
+        *gptr_w((float*)d.om2t + e2) = acc;
     } else if (e < E1 + E2 + E3) {
         const int e3 = e - E1 - E2;
         const int c3 = e3 / J, k = e3 % J;
         float acc = 0.f;
         for (int j = max(0, k - rB); j <= min(J - 1, k + rB); ++j) {
-            const float o3 = d.has_om3 ? d.om3[(size_t)c3 * J + j] : (c3 == j ? 1.f : 0.f);
-            acc = fmaf(o3, d.bb[(size_t)k * wB + rB + (j - k)], acc);
+            const float o3 = d.has_om3 ? *gptr(d.om3 + (size_t)c3 * J + j) : (c3 == j ? 1.f : 0.f);
+            acc = fmaf(o3, *gptr(d.bb + (size_t)k * wB + rB + (j - k)), acc);
         }
-        ((float*)d.om3t)[e3] = acc;
+        *gptr_w((float*)d.om3t + e3) = acc;
     }
 }
 
