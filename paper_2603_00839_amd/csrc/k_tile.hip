@@ -17,7 +17,7 @@ hipError_t launch_tile(const Desc* d, const int* starts, int count, int total_ti
 #define RTG_TILE(BBV, MBV, SPV, RPV)                                                              \
     hipLaunchKernelGGL((k_tile<BBV, MBV, SPV, RPV>), dim3(total_tiles), dim3(256), 0, s, d, starts, count, \
                        mode, nterms, dst_index, first_term)
-    const int rtiles = ((l1max + 15) / 16) * ((mode == TM_NEWV || mode == TM_GKNEW) ? 2 : 1);
+    const int rtiles = ((l1max + 15) / 16) * ((mode == TM_NEWV || mode == TM_GKNEW || mode == TM_NEWV1) ? 2 : 1);
     const bool small = rtiles <= 8 && rows != 4;
     const bool split = (mode == TM_SKETCH_SRC || mode == TM_SKETCH_W) && !src_bf16;
     if (basis_bf16) {

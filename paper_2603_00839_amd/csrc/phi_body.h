@@ -59,6 +59,7 @@ struct PhiArgs {
     const float* st;  // stencil ((2 r1 + 1)^2, [a + r1][b + r1]) of a general PSF, else null
     const float* taps;  // Toeplitz bands (convolutions): A1 taps at [r1 + dd], A2 taps at
                         // [2 RMAX_SPATIAL + 1 + r2 + dd]; null for general bands
+    bf16_t* dst_bf;     // non-null: the result goes there, rounded to bfloat16, instead of dst
 };
 
 __device__ __forceinline__ int xcd_remap(int b, int G) {
@@ -381,7 +382,11 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int tile, float* smem
 #pragma unroll
             for (int o = 0; o < 8; ++o) {
                 const int i2 = i20 + wave * 8 + o;
-                if (i2 < I2) *gptr_w(a.dst + (size_t)(j0 + jj) * plane + (size_t)i2 * I1 + i1) = acc[jj][o];
+                if (i2 < I2) {
+                    const size_t e = (size_t)(j0 + jj) * plane + (size_t)i2 * I1 + i1;
+                    if (a.dst_bf) *gptr_w(a.dst_bf + e) = f2bf(acc[jj][o]);
+                    else *gptr_w(a.dst + e) = acc[jj][o];
+                }
             }
         }
     }
@@ -410,6 +415,7 @@ __device__ __forceinline__ void phi_batched_task(const Desc* __restrict__ descs,
         a.C = d.C;
     }
     a.dst = d.W;
+    a.dst_bf = (src_sel == PS_X0_V1) ? (bf16_t*)d.V : nullptr;
     phi_tile<R, BF16IN, JT, ST, SL, TP>(a, uniform_int(b - starts[p]), smem);
 }
 

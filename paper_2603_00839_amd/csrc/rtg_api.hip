@@ -584,11 +584,15 @@ int run_solver(const Plan& plan, int count, int mmax, int bf16, bool any_x0, boo
         }
         return RTG_OK;
     }
-    if (any_x0) RTG_TIMED(0, launch_phi(dd, sp, count, plan.total[KIND_PHI], PS_X0, 0, plan.rmax, plan.phi_jt, 0, s, 0, plan.phi_dma, plan.phi_toep));
-    if (plan.lazy_v1 && cycle == 0) {
+    const bool lazy = plan.lazy_v1 && cycle == 0;
+    // (a bfloat16 basis stored unnormalised: the operator kernel stores R0 =
+    // C - Phi(X0) rounded to bfloat16 as V_1 itself)
+    if (any_x0) RTG_TIMED(0, launch_phi(dd, sp, count, plan.total[KIND_PHI], lazy ? PS_X0_V1 : PS_X0, 0, plan.rmax, plan.phi_jt, 0, s, 0, plan.phi_dma, plan.phi_toep));
+    if (lazy) {
         // V_1 = R0 (scale 1, set by the init kernel) with both its sketches
-        // in one pass; the start step takes beta from S(V_1)
-        RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_NEWV, 0, 0, bf16, 0, plan.l1max, s, 0, plan.tile_rows, plan.skbf));
+        // in one pass (stored there too where X0 is absent, R0 = C); the
+        // start step takes beta from S(V_1)
+        RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_NEWV1, 0, 0, bf16, 0, plan.l1max, s, 0, plan.tile_rows, plan.skbf));
         RTG_TIMED(2, launch_gram(dd, sg, count, plan.total[KIND_GRAM], GM_START, cycle, nullptr, s));
     } else {
         RTG_TIMED(1, launch_tile(dd, st, count, plan.total[KIND_TILE], TM_SKETCH_SRC, 0, 0, bf16, 0, plan.l1max, s, 0, plan.tile_rows, plan.skbf));

@@ -413,9 +413,14 @@ hipError_t launch_persist(const PersistArgs& a, int rmax, int toeplitz, int sket
 // [first_term, nterms) of this side's basis)
 // (TM_SKETCH_W: the sketch of the stored W, for operators without composed
 // sketch matrices)
-enum TileMode { TM_NEWV = 1, TM_ASSEMBLE = 2, TM_SKETCH_SRC = 3, TM_GKNEW = 4, TM_SKETCH_W = 5 };
-// k_phi source selection
-enum PhiSrc { PS_BASIS = 0, PS_X0 = 1 };
+// (TM_NEWV1: V_1 = R0 of a bfloat16 basis stored unnormalised: where X0 is
+// given, the operator kernel (PS_X0_V1) has stored R0 = C - Phi(X0) in
+// bfloat16 as V_1 already and the pass only sketches it; otherwise R0 = C is
+// rounded, stored and sketched as TM_NEWV does)
+enum TileMode { TM_NEWV = 1, TM_ASSEMBLE = 2, TM_SKETCH_SRC = 3, TM_GKNEW = 4, TM_SKETCH_W = 5, TM_NEWV1 = 6 };
+// k_phi source selection (PS_X0_V1: R0 = C - Phi(X0) rounded to bfloat16
+// into the basis' first slot)
+enum PhiSrc { PS_BASIS = 0, PS_X0 = 1, PS_X0_V1 = 2 };
 // k_gram modes
 // (GM_GK: one Golub-Kahan half-step, the sketched norm of the next tensor)
 enum GramMode { GM_START = 0, GM_STEP = 1, GM_SKETCH_OUT = 2, GM_GK = 3 };

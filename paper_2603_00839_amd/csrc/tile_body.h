@@ -103,7 +103,9 @@ __device__ __forceinline__ void tile_task(const Desc* __restrict__ descs, const 
     const int p = find_problem(starts, count, b);
     const Desc& d = descs[p];
     const int tile = uniform_int(b - starts[p]);
-    const bool newv = (mode == TM_NEWV || mode == TM_GKNEW);
+    const bool newv = (mode == TM_NEWV || mode == TM_GKNEW || mode == TM_NEWV1);
+    // V_1 stored by the operator kernel already: sketched from the basis
+    const bool v1_stored = (mode == TM_NEWV1) && d.X0 != nullptr;
     if ((newv || mode == TM_SKETCH_W) && d.state[ST_ACTIVE] == 0) return;
     if (mode == TM_ASSEMBLE && d.state[ST_SKIP] != 0) return;   // X stays (restart cycle sat out)
 
@@ -125,15 +127,16 @@ __device__ __forceinline__ void tile_task(const Desc* __restrict__ descs, const 
     if (newv) nterms = nterms_arg;
     else if (mode == TM_ASSEMBLE) nterms = uniform_int(d.state[ST_MEFF]);
     const int first = (mode == TM_GKNEW) ? t0 : 0;   // terms [first, nterms)
-    const bool do_store = (newv || mode == TM_ASSEMBLE);
+    const bool do_store = (newv || mode == TM_ASSEMBLE) && !v1_stored;
     const bool do_sketch = (mode != TM_ASSEMBLE) && !d.unsketched;   // an identity sketch keeps no partials
     const bool dual = newv && d.st == nullptr;   // a general PSF has no composed sketch matrices
-    const bool src_is_bf = BB && !SPLIT && (mode == TM_SKETCH_SRC);
+    const bool src_is_bf = BB && !SPLIT && (mode == TM_SKETCH_SRC || v1_stored);
 
     const void* src;
     if (mode == TM_SKETCH_SRC) src = d.R0src;
     else if (mode == TM_SKETCH_W) src = d.W;
     else if (mode == TM_NEWV) src = (nterms == 0) ? d.R0src : (const void*)d.W;
+    else if (mode == TM_NEWV1) src = v1_stored ? (const void*)d.V : d.R0src;
     else if (mode == TM_GKNEW) src = d.W;
     else src = d.X0;     // may be null: zero
     src = uniform_ptr(src);
@@ -254,7 +257,7 @@ __device__ __forceinline__ void tile_task(const Desc* __restrict__ descs, const 
         for (int u = 0; u < NCK; ++u)
 #pragma unroll
             for (int q = 0; q < CK; ++q) x[u][q] *= scale;
-        if (newv && BB) {
+        if (newv && BB && do_store) {
             const auto rd = make_rsrc((const char*)d.V + ((size_t)dst_index * d.n + tile_off) * 2, tile_elems * 2);
 #pragma unroll
             for (int u = 0; u < NCK; ++u) {
