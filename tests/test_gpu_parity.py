@@ -270,6 +270,49 @@ def test_solve_bf16_from_observation_cfg2():
     assert re_g <= 1.01 * re_o
 
 
+def test_bf16_batch_mixing_x0_and_none():
+    """A bfloat16-basis batch in which some problems start from X0 and one
+    from zero: where X0 is given the operator kernel stores R0 = C - Phi(X0)
+    rounded to bfloat16 as V_1 and the first tile pass only sketches it;
+    where it is absent the pass stores R0 = C itself.  Every problem holds
+    what its own single-problem solve returns (to 1e-6), beta agrees
+    with the float64 oracle's ||S(R0)|| to the bfloat16 rounding of R0, and
+    the restoration error is within 1% of the oracle's from the same X0."""
+    from paper_2603_00839_amd import rtg
+    banner("bf16 batch, X0 given and absent")
+    probs = [synth.cfg1(s) for s in range(3)]
+    ops, sks, Cs, X0s, prm, x0_host, refs = [], [], [], [], [], [], []
+    rng = np.random.default_rng(5)
+    for k, p in enumerate(probs):
+        C, delta = U.observation(p)
+        x0 = None if k == 0 else (C if k == 1 else
+                                  (0.5 * p.x_true + 0.01 * rng.standard_normal(C.shape)).astype(np.float32))
+        og, sg = U.gpu_pair(p)
+        ops.append(og)
+        sks.append(sg)
+        Cs.append(U.to_dev(C))
+        X0s.append(None if x0 is None else U.to_dev(x0))
+        x0_host.append(x0)
+        prm.append(rtg.make_params(20, rtg.BF16, delta=delta, eta=1.01))
+        op_o, sk_o = U.oracle_pair(p)
+        refs.append(rtg_gmres(op_o, sk_o, C, 20, X0=x0, delta=delta, eta=1.01))
+    plan = rtg.BatchPlan(ops, sks, Cs, X0s, prm)
+    plan.run()
+    infos = plan.infos()
+    for k, p in enumerate(probs):
+        X = U.from_dev(plan.outs[k])
+        Xs, ib = rtg.solve(ops[k], sks[k], Cs[k], X0s[k], prm[k])
+        inf1 = rtg.read_info(ib)
+        re_g = relative_error(p.x_true, X)
+        re_o = relative_error(p.x_true, refs[k].X)
+        print(f"problem {k} (X0 {'none' if x0_host[k] is None else 'given'}): iters {infos[k].iters} "
+              f"beta {infos[k].beta:.6e} (oracle {refs[k].beta:.6e}) RE {re_g:.5f} (oracle {re_o:.5f})",
+              file=sys.stderr)
+        assert U.rel(X, U.from_dev(Xs)) < 1e-6 and infos[k].iters == inf1.iters
+        np.testing.assert_allclose(infos[k].beta, refs[k].beta, rtol=4e-3)
+        assert re_g <= 1.01 * re_o
+
+
 def test_bf16_from_zero_reports_unreachable_discrepancy():
     """From X0 = 0 at nu = 1e-3 the bfloat16 rounding of the basis (relative
     2^-9) exceeds the noise level: the projected least-squares residual
