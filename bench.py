@@ -100,6 +100,8 @@ def parse():
                     help="warm-started solve: run --m-warm steps, or stop at the first step whose projected "
                          "least-squares residual is within the discrepancy level eta*delta (at most --m-warm)")
     ap.add_argument("--x0", choices=["learned", "observation"], default="learned")
+    ap.add_argument("--overlap", choices=["on", "off"], default="on",
+                    help="bf16_warm: run the next batch's network while the host waits for the fallback flags")
     ap.add_argument("--headline", choices=["auto", "fp32_plain", "bf16_warm"], default="auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--video-batch", type=int, default=4, help="videos per step of the video variants")
@@ -265,16 +267,28 @@ def gk_tile_bytes(n, es, m_eff):
     return b + m_eff * es * n + 4 * n
 
 
-def time_variant(plan, steps, warmup, rtg, torch, kind, bytes_of, pre=None):
+def time_variant(plan, steps, warmup, rtg, torch, kind, bytes_of, pre=None, overlap=False):
     """Time `steps` batch solves; `pre` (the warm-start network forward that
     produces the X0 of the batch) runs inside every timed step.  Launches of
     kernel kind `kind` are bracketed by HIP events on their stream inside the
     library; `bytes_of(info)` gives the algorithmic bytes of those launches for
-    one problem."""
-    def one():
-        if pre is not None:
+    one problem.  With `overlap` (a plan with a fallback and a `pre`) each step
+    queues the solve and the copy of its flags, then the network of the next
+    batch, and only then waits for the flags and queues the re-solves, so the
+    GPU runs the network while the host waits; the network of the first batch
+    runs in the warm-up, and every timed step still holds one network and one
+    solve."""
+    if overlap and pre is not None:
+        def one():
+            plan.begin()
             pre()
-        plan.run()
+            plan.end()
+        pre()
+    else:
+        def one():
+            if pre is not None:
+                pre()
+            plan.run()
     for _ in range(warmup):
         one()
     torch.cuda.synchronize()
@@ -608,10 +622,11 @@ def main():
                 # of its warm attempt only (the re-solve runs the tile kernel)
                 return step_bytes(n, 2, args.m_warm if inf.flags & rtg.FLAG_FALLBACK else inf.iters)
             r = time_variant(plan, args.steps, args.warmup, rtg, torch, rtg.KIND_STEP, warm_bytes,
-                             pre=None if obs else pre)
+                             pre=None if obs else pre, overlap=args.overlap == "on")
             r["kernel"] = ("k_step", "k_step.hip", "Arnoldi step: operator per tile + multi-AXPY + store + "
                                                    "dual MFMA sketch (bfloat16 basis)")
             r["fallbacks_per_step"] = plan.n_fallback
+            r["overlap"] = args.overlap == "on" and not obs
         if v not in ("fp32_psf", "fp32_uneven", "mixed_uneven", "mixed_uneven_persist", "fp32_video", "bf16_video"):
             res = [rel_err(plan.outs[b], probs[b]["xt"]) for b in range(B)]
         r["tune"] = tune
@@ -675,6 +690,7 @@ def main():
                          "re_mean": v["re_mean"], "re_problem0": v["re_p0"], "iters_mean": v["iters_mean"],
                          "flags": v["flags"], "flag_counts": v["flag_counts"],
                          "fallbacks_per_step": v.get("fallbacks_per_step"),
+                         "overlap": v.get("overlap"),
                          "kernel": v["kernel"][0], "tune": v["tune"],
                          "kernel_gbs": (v["k_bytes"] / (v["k_ms"] * 1e-3) / 1e9 if v["k_ms"] > 0 else 0.0)}
                      for k, v in results.items()},

@@ -288,6 +288,30 @@ int rtg_solve_batched_fallback(int count, const rtg_problem* probs, int fb_m,
                                int fb_basis, int fail_mask, void* ws,
                                size_t ws_bytes, int* n_fallback, void* stream);
 
+/* The same fallback in two calls, so that the stream can take other work
+ * (the next batch's warm start, say) while the flags travel: the host waits
+ * only for the flag copy, not for what was queued after it.
+ * rtg_solve_batched_fallback_begin solves the batch as rtg_solve_batched
+ * does and queues the copy of every problem's flags to flags_host (count
+ * ints of caller-owned host memory, page-locked for the copy to run
+ * asynchronously; it must not be touched before the matching _end);
+ * asynchronous.  rtg_solve_batched_fallback_end, called with the same
+ * arguments and the same flags_host, waits for that copy, re-solves the
+ * problems whose flags meet fail_mask exactly as rtg_solve_batched_fallback
+ * does, and returns once the re-solves are queued; *n_fallback receives their
+ * number.  Errors as rtg_solve_batched_fallback; _end without a pending
+ * _begin for flags_host returns RTG_E_ARG.  Calls for different flags_host
+ * buffers may be in flight together. */
+int rtg_solve_batched_fallback_begin(int count, const rtg_problem* probs,
+                                     int fb_m, int fb_basis, int fail_mask,
+                                     void* ws, size_t ws_bytes,
+                                     int* flags_host, void* stream);
+int rtg_solve_batched_fallback_end(int count, const rtg_problem* probs,
+                                   int fb_m, int fb_basis, int fail_mask,
+                                   void* ws, size_t ws_bytes,
+                                   const int* flags_host, int* n_fallback,
+                                   void* stream);
+
 /* ---- tile autotuner (the batching form's launch shapes) --------------------
  * The launch shapes of a batch: every combination that the fields allow is
  * a correct solve of the same problems (they change which thread computes

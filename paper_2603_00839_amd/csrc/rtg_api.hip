@@ -1376,6 +1376,64 @@ __global__ void k_gather_flags(const Desc* __restrict__ descs, int count, int* _
 constexpr int FALLBACK_MASK_ALL = RTG_F_BREAKDOWN | RTG_F_DISCREP_UNREACHABLE | RTG_F_MU_INF | RTG_F_NONFINITE |
                                   RTG_F_NOT_CONVERGED;
 
+// The fallback in two halves.  fallback_begin validates, solves the batch and
+// queues the copy of every problem's flags to flags_host (host memory);
+// fallback_resolve reads them there and re-solves the failed problems with
+// the plain solver, as many at a time as the workspace holds.
+int fallback_begin(int count, const rtg_problem* probs, int fb_m, int fb_basis, int fail_mask, void* ws,
+                   size_t ws_bytes, int* flags_host, void* stream) {
+    if ((fail_mask & ~FALLBACK_MASK_ALL) != 0) return RTG_E_ARG;
+    if (fb_basis != RTG_F32 && fb_basis != RTG_BF16) return RTG_E_ARG;
+    if (count < 1 || !probs || !ws) return RTG_E_ARG;
+    for (int p = 0; p < count; ++p) {
+        const rtg_params q = plain_params(probs[p].params, fb_m, fb_basis);
+        int rc = validate_params(&q);
+        if (rc) return rc;
+    }
+    const size_t need = rtg_fallback_workspace_bytes(count, probs, fb_m, fb_basis);
+    if (need == 0) return RTG_E_SHAPE;
+    if (ws_bytes < need) return RTG_E_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = solve_batched(count, probs, ws, ws_bytes, s, 0);
+    if (rc) return rc;
+    // the flags of every problem, gathered through the batch's descriptors
+    // (at the start of the workspace) into its last bytes, then copied out
+    int* dflags = (int*)((char*)ws + need - align_up((size_t)count * sizeof(int)));
+    hipLaunchKernelGGL(k_gather_flags, dim3((count + 255) / 256), dim3(256), 0, s, (const Desc*)ws, count, dflags);
+    RTG_HIP(hipGetLastError());
+    RTG_HIP(hipMemcpyAsync(flags_host, dflags, (size_t)count * sizeof(int), hipMemcpyDeviceToHost, s));
+    return RTG_OK;
+}
+
+int fallback_resolve(int count, const rtg_problem* probs, int fb_m, int fb_basis, int fail_mask, void* ws,
+                     size_t ws_bytes, const int* flags, int* n_fallback, hipStream_t s) {
+    std::vector<rtg_problem> redo;
+    for (int p = 0; p < count; ++p)
+        if (flags[p] & fail_mask) redo.push_back(plain_problem(probs[p], fb_m, fb_basis));
+    *n_fallback = (int)redo.size();
+    // re-solve them with the plain solver, as many at a time as the
+    // workspace holds (each one alone fits: checked by fallback_begin)
+    size_t first = 0;
+    while (first < redo.size()) {
+        size_t n = 1;
+        while (first + n < redo.size() && rtg_batch_workspace_bytes((int)(n + 1), redo.data() + first) <= ws_bytes) ++n;
+        int rc = solve_batched((int)n, redo.data() + first, ws, ws_bytes, s, 1);
+        if (rc) return rc;
+        first += n;
+    }
+    return RTG_OK;
+}
+
+// Events of rtg_solve_batched_fallback_begin, by the host buffer they guard
+struct FallbackEvents {
+    std::mutex mu;
+    std::map<const int*, hipEvent_t> ev;
+};
+FallbackEvents& fallback_events() {
+    static FallbackEvents fe;
+    return fe;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1399,43 +1457,54 @@ size_t rtg_fallback_workspace_bytes(int count, const rtg_problem* probs, int fb_
 
 int rtg_solve_batched_fallback(int count, const rtg_problem* probs, int fb_m, int fb_basis, int fail_mask,
                                void* ws, size_t ws_bytes, int* n_fallback, void* stream) {
-    if (!n_fallback || (fail_mask & ~FALLBACK_MASK_ALL) != 0) return RTG_E_ARG;
+    if (!n_fallback) return RTG_E_ARG;
     *n_fallback = 0;
-    if (fb_basis != RTG_F32 && fb_basis != RTG_BF16) return RTG_E_ARG;
-    if (count < 1 || !probs || !ws) return RTG_E_ARG;
-    for (int p = 0; p < count; ++p) {
-        const rtg_params q = plain_params(probs[p].params, fb_m, fb_basis);
-        int rc = validate_params(&q);
-        if (rc) return rc;
-    }
-    const size_t need = rtg_fallback_workspace_bytes(count, probs, fb_m, fb_basis);
-    if (need == 0) return RTG_E_SHAPE;
-    if (ws_bytes < need) return RTG_E_WORKSPACE;
-    hipStream_t s = (hipStream_t)stream;
-    int rc = solve_batched(count, probs, ws, ws_bytes, s, 0);
+    std::vector<int> flags((size_t)count > 0 ? (size_t)count : 1, 0);
+    int rc = fallback_begin(count, probs, fb_m, fb_basis, fail_mask, ws, ws_bytes, flags.data(), stream);
     if (rc) return rc;
-    // the flags of every problem, gathered through the batch's descriptors
-    // (at the start of the workspace) into its last bytes, then read back
-    int* dflags = (int*)((char*)ws + need - align_up((size_t)count * sizeof(int)));
-    hipLaunchKernelGGL(k_gather_flags, dim3((count + 255) / 256), dim3(256), 0, s, (const Desc*)ws, count, dflags);
-    RTG_HIP(hipGetLastError());
-    std::vector<int> flags((size_t)count, 0);
-    RTG_HIP(hipMemcpyAsync(flags.data(), dflags, (size_t)count * sizeof(int), hipMemcpyDeviceToHost, s));
-    RTG_HIP(hipStreamSynchronize(s));
-    std::vector<rtg_problem> redo;
-    for (int p = 0; p < count; ++p)
-        if (flags[p] & fail_mask) redo.push_back(plain_problem(probs[p], fb_m, fb_basis));
-    *n_fallback = (int)redo.size();
-    // re-solve them with the plain solver, as many at a time as the
-    // workspace holds (each one alone fits: checked above)
-    size_t first = 0;
-    while (first < redo.size()) {
-        size_t n = 1;
-        while (first + n < redo.size() && rtg_batch_workspace_bytes((int)(n + 1), redo.data() + first) <= ws_bytes) ++n;
-        if ((rc = solve_batched((int)n, redo.data() + first, ws, ws_bytes, s, 1))) return rc;
-        first += n;
+    RTG_HIP(hipStreamSynchronize((hipStream_t)stream));
+    return fallback_resolve(count, probs, fb_m, fb_basis, fail_mask, ws, ws_bytes, flags.data(), n_fallback,
+                            (hipStream_t)stream);
+}
+
+int rtg_solve_batched_fallback_begin(int count, const rtg_problem* probs, int fb_m, int fb_basis, int fail_mask,
+                                     void* ws, size_t ws_bytes, int* flags_host, void* stream) {
+    if (!flags_host) return RTG_E_ARG;
+    int rc = fallback_begin(count, probs, fb_m, fb_basis, fail_mask, ws, ws_bytes, flags_host, stream);
+    if (rc) return rc;
+    hipEvent_t ev = nullptr;
+    RTG_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    if (hipEventRecord(ev, (hipStream_t)stream) != hipSuccess) {
+        (void)hipEventDestroy(ev);
+        return RTG_E_HIP;
     }
+    FallbackEvents& fe = fallback_events();
+    std::lock_guard<std::mutex> lock(fe.mu);
+    auto it = fe.ev.find(flags_host);
+    if (it != fe.ev.end()) (void)hipEventDestroy(it->second);   // an earlier begin never ended
+    fe.ev[flags_host] = ev;
     return RTG_OK;
+}
+
+int rtg_solve_batched_fallback_end(int count, const rtg_problem* probs, int fb_m, int fb_basis, int fail_mask,
+                                   void* ws, size_t ws_bytes, const int* flags_host, int* n_fallback,
+                                   void* stream) {
+    if (!n_fallback || !flags_host) return RTG_E_ARG;
+    *n_fallback = 0;
+    hipEvent_t ev = nullptr;
+    {
+        FallbackEvents& fe = fallback_events();
+        std::lock_guard<std::mutex> lock(fe.mu);
+        auto it = fe.ev.find(flags_host);
+        if (it == fe.ev.end()) return RTG_E_ARG;                 // no begin for this buffer
+        ev = it->second;
+        fe.ev.erase(it);
+    }
+    const hipError_t e = hipEventSynchronize(ev);
+    (void)hipEventDestroy(ev);
+    if (e != hipSuccess) return RTG_E_HIP;
+    return fallback_resolve(count, probs, fb_m, fb_basis, fail_mask, ws, ws_bytes, flags_host, n_fallback,
+                            (hipStream_t)stream);
 }
 
 int rtg_tune_set(int count, const rtg_problem* probs, const rtg_tune* tune) {

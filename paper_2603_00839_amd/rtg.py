@@ -111,6 +111,10 @@ def load_library():
         "rtg_fallback_workspace_bytes": (c_sz, [c_int, ctypes.POINTER(Problem), c_int, c_int]),
         "rtg_solve_batched_fallback": (c_int, [c_int, ctypes.POINTER(Problem), c_int, c_int, c_int, c_vp, c_sz,
                                                ctypes.POINTER(c_int), c_vp]),
+        "rtg_solve_batched_fallback_begin": (c_int, [c_int, ctypes.POINTER(Problem), c_int, c_int, c_int, c_vp,
+                                                     c_sz, c_vp, c_vp]),
+        "rtg_solve_batched_fallback_end": (c_int, [c_int, ctypes.POINTER(Problem), c_int, c_int, c_int, c_vp,
+                                                   c_sz, c_vp, ctypes.POINTER(c_int), c_vp]),
         "rtg_autotune_batched": (c_int, [c_int, ctypes.POINTER(Problem), c_vp, c_sz, c_int, ctypes.POINTER(Tune),
                                          ctypes.POINTER(c_d), c_vp]),
         "rtg_tune_set": (c_int, [c_int, ctypes.POINTER(Problem), ctypes.POINTER(Tune)]),
@@ -514,6 +518,34 @@ class BatchPlan:
             return self.outs
         _check(lib().rtg_solve_batched(self.count, self.arr, _ptr(self.ws), self.ws.numel(), _stream()),
                "rtg_solve_batched")
+        return self.outs
+
+    def begin(self):
+        """First half of run() with a fallback (rtg_solve_batched_fallback_begin):
+        solves the batch and queues the copy of the flags to a page-locked
+        host buffer; returns without waiting, so the stream can take other
+        work before end()."""
+        if self.fallback is None:
+            raise RTGError("begin(): the batch was made without a fallback")
+        if getattr(self, "flags_host", None) is None:
+            self.flags_host = _torch().zeros(self.count, dtype=_torch().int32, pin_memory=True)
+        fb_m, fb_basis, mask = self.fallback
+        _check(lib().rtg_solve_batched_fallback_begin(self.count, self.arr, fb_m, fb_basis, mask, _ptr(self.ws),
+                                                      self.ws.numel(), self.flags_host.data_ptr(), _stream()),
+               "rtg_solve_batched_fallback_begin")
+
+    def end(self):
+        """Second half (rtg_solve_batched_fallback_end): waits for the flags,
+        queues the re-solves and sets n_fallback; returns the outputs."""
+        if self.fallback is None or getattr(self, "flags_host", None) is None:
+            raise RTGError("end(): no begin() on this batch")
+        n = ctypes.c_int(0)
+        fb_m, fb_basis, mask = self.fallback
+        _check(lib().rtg_solve_batched_fallback_end(self.count, self.arr, fb_m, fb_basis, mask, _ptr(self.ws),
+                                                    self.ws.numel(), self.flags_host.data_ptr(), ctypes.byref(n),
+                                                    _stream()),
+               "rtg_solve_batched_fallback_end")
+        self.n_fallback = n.value
         return self.outs
 
     def infos(self) -> List[Info]:

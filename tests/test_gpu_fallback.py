@@ -26,10 +26,8 @@ import _util as U
 pytestmark = pytest.mark.gpu
 
 
-def test_fallback_resolves_failed_warm_starts_with_the_plain_solver():
-    import torch
+def _warm_batch():
     from paper_2603_00839_amd import rtg
-    print("[case] fallback: 4 x cfg1, bf16 warm start, m' = 5", file=sys.stderr, flush=True)
     probs = [synth.cfg1(s) for s in range(4)]
     ops, sks, Cs, X0s, prm, refs = [], [], [], [], [], []
     rng = np.random.default_rng(21)
@@ -52,6 +50,13 @@ def test_fallback_resolves_failed_warm_starts_with_the_plain_solver():
         Cs.append(U.to_dev(C))
         X0s.append(U.to_dev(x0))
         prm.append(rtg.make_params(5, rtg.BF16, delta=delta, eta=1.01, stop_res=1.01 * delta))
+    return ops, sks, Cs, X0s, prm, refs
+
+
+def test_fallback_resolves_failed_warm_starts_with_the_plain_solver():
+    from paper_2603_00839_amd import rtg
+    print("[case] fallback: 4 x cfg1, bf16 warm start, m' = 5", file=sys.stderr, flush=True)
+    ops, sks, Cs, X0s, prm, refs = _warm_batch()
     # the warm-started batch alone
     plain = rtg.BatchPlan(ops, sks, Cs, X0s, prm)
     plain.run()
@@ -94,3 +99,34 @@ def test_fallback_argument_errors():
     # an fb_m the 16x16x3 sketch cannot take (m + 1 > L) has no workspace size
     with pytest.raises(rtg.RTGError):
         rtg.BatchPlan([og], [sg], [U.to_dev(C)], [None], prm, fallback=(1000, rtg.F32))
+
+
+def test_fallback_in_two_calls_matches_the_single_call():
+    """rtg_solve_batched_fallback_begin/_end give bit for bit what
+    rtg_solve_batched_fallback gives, also with other work queued on the
+    stream between the two calls (here the single-call solve of a second
+    plan), and _end with no pending _begin is an argument error."""
+    import torch
+    from paper_2603_00839_amd import rtg
+    print("[case] fallback begin/end: 4 x cfg1", file=sys.stderr, flush=True)
+    ops, sks, Cs, X0s, prm, _ = _warm_batch()
+    one = rtg.BatchPlan(ops, sks, Cs, X0s, prm, fallback=(20, rtg.F32))
+    one.run()
+    want = [U.from_dev(x) for x in one.outs]
+    want_flags = [i.flags for i in one.infos()]
+    two = rtg.BatchPlan(ops, sks, Cs, X0s, prm, fallback=(20, rtg.F32))
+    other = rtg.BatchPlan(ops, sks, Cs, X0s, prm, fallback=(20, rtg.F32))
+    for rep in range(2):
+        for x in two.outs:
+            x.fill_(float("nan"))
+        two.begin()
+        other.run()               # queued between the two halves
+        two.end()
+        torch.cuda.synchronize()
+        assert two.n_fallback == one.n_fallback
+        assert [i.flags for i in two.infos()] == want_flags
+        for k in range(4):
+            np.testing.assert_array_equal(U.from_dev(two.outs[k]), want[k])
+    # a second end() has no begin() to finish
+    with pytest.raises(rtg.RTGError, match="invalid argument"):
+        two.end()
